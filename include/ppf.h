@@ -1,0 +1,304 @@
+/*
+ * ppf.h — C ABI of the MI355X (gfx950) SIR particle-filter library.
+ *
+ * The library runs one step of the sequential importance resampling (SIR)
+ * filter of Algorithm 1 (Section 2 of "PPF – A Parallel Particle Filtering
+ * Library", Demirel et al., arXiv:1310.5045) per call, entirely in HIP kernels:
+ *
+ *   propagate   bootstrap proposal under the near-constant-velocity model of
+ *               Section 6.1, state x = (x, y, vx, vy, I0);
+ *   weight      Gaussian-spot observation model of Eq. 3 evaluated on a local
+ *               P x P image patch (Eq. 4, Section 5.5 "Image Patches");
+ *   normalise   weight normalisation and effective sample size of Algorithm 1,
+ *               done in the log domain; MMSE estimate of Section 2;
+ *   resample    when ESS < threshold (Algorithm 1): either global systematic
+ *               resampling, or RNA — distributed resampling with
+ *               non-proportional allocation (Section 3) with one GPU workgroup
+ *               standing in for each process and a ring exchange of a fixed
+ *               fraction of each group's particles.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns int: PPF_OK (0) or a negative PPF_E* code. None
+ *     aborts, none lets a C++ exception escape.
+ *   - "_dev" pointers are HIP device pointers on the current device; "_host"
+ *     pointers are ordinary host memory. The library never frees memory it did
+ *     not allocate. Nothing here allocates device memory: state lives in the
+ *     caller's workspace.
+ *   - A handle is used by one host thread at a time. All device work of a
+ *     handle is enqueued on the hipStream_t given to ppf_create (NULL = the
+ *     null stream). Functions documented as "async" return before the GPU has
+ *     finished; functions documented as "syncs" wait for that stream.
+ *   - Random numbers come from Philox4x32-10 (Salmon et al., SC'11), keyed by
+ *     the 64-bit seed. Counter words are (particle or group index, frame k,
+ *     purpose << 24 | block, track_id) with purposes INIT=1, PROPAGATE=2,
+ *     RESAMPLE=3, RNA=4, so every draw of a run is a pure function of
+ *     (seed, track_id, k, index): a run is reproducible and restartable.
+ */
+#ifndef PPF_H
+#define PPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+enum {
+  PPF_OK = 0,
+  PPF_EINVAL = -1,    /* bad argument or parameter                          */
+  PPF_ENOMEM = -2,    /* workspace / scratch smaller than required          */
+  PPF_EDEVICE = -3,   /* a HIP runtime call failed                          */
+  PPF_ESTATE = -4,    /* null, destroyed or otherwise unusable handle       */
+  PPF_ENUMERIC = -5,  /* a step produced no finite normaliser; rolled back   */
+  PPF_ENOTIMPL = -6   /* option recognised but not built                    */
+};
+
+enum { PPF_RESAMPLE_SYSTEMATIC = 0, PPF_RESAMPLE_RNA = 1 };
+enum { PPF_OBS_SPOT = 0, PPF_OBS_LINEAR_GAUSSIAN = 1 };
+enum { PPF_INIT_UNIFORM = 0, PPF_INIT_GAUSSIAN = 1 };
+
+/* Largest patch edge P the kernels are built for. */
+#define PPF_MAX_PATCH 25
+
+typedef struct ppf_ctx* ppf_handle;
+
+/*
+ * Filter parameters. Field meanings follow the paper's notation.
+ *
+ * state_dim     must be 5: x = (x, y, vx, vy, I0), Section 6.1.
+ * obs_model     PPF_OBS_SPOT: the frame is a W x H image, Eq. 3 + Eq. 4.
+ *               PPF_OBS_LINEAR_GAUSSIAN: the observation is three floats
+ *               (x, y, I0) + N(0, diag(lg_r^2)); a linear-Gaussian variant of
+ *               the same state-space model whose exact posterior is the Kalman
+ *               filter (Eqs. 1-2), used to validate the whole recursion.
+ * n_particles   N, 1 <= N <= 2^31 - 1.
+ * width,height  frame size in pixels; frames are row-major fp32 Z[y][x]
+ *               (spot model only; ignored for the linear-Gaussian model).
+ * psf_sigma     sigma_PSF of Eq. 3 in pixels (> 0).
+ * background    I_bg of Eq. 3.
+ * noise_sigma   sigma_xi of Eq. 4 (> 0).
+ * patch         P, the edge of the square pixel set S_x of Eq. 4, odd,
+ *               1..PPF_MAX_PATCH; 0 selects 2*floor(3*psf_sigma)+1, the
+ *               integer reading of the +-3 sigma_PSF box.
+ * q[5]          process-noise standard deviations of (x, y, vx, vy, I0).
+ * init_kind     PPF_INIT_UNIFORM: x0[d] ~ U[init_a[d], init_b[d]) (the paper
+ *               initialises uniformly at random, Section 6.3);
+ *               PPF_INIT_GAUSSIAN: x0[d] ~ N(init_a[d], init_b[d]^2).
+ * lg_r[3]       observation noise sds of the linear-Gaussian model (> 0).
+ * resample      PPF_RESAMPLE_SYSTEMATIC or PPF_RESAMPLE_RNA.
+ * ess_threshold resample iff ESS < ess_threshold (Algorithm 1); +INFINITY
+ *               resamples every step, 0 never.
+ * rna_group     n, particles per RNA group (one workgroup each); N % n == 0,
+ *               1 <= n <= 1024. Ignored for systematic resampling.
+ * rna_exchange  rho in [0, 1): after local resampling the last floor(rho * n)
+ *               slots of group g take the particles (and weight) of the same
+ *               slots of group g-1 mod G (Section 3, ring of processes).
+ * seed          Philox key.
+ * track_id      Philox counter word 3 (distinguishes independent filters).
+ */
+typedef struct ppf_params {
+  int32_t state_dim;
+  int32_t obs_model;
+  int64_t n_particles;
+  int32_t width;
+  int32_t height;
+  float psf_sigma;
+  float background;
+  float noise_sigma;
+  int32_t patch;
+  float q[5];
+  int32_t init_kind;
+  float init_a[5];
+  float init_b[5];
+  float lg_r[3];
+  int32_t resample;
+  double ess_threshold;
+  int32_t rna_group;
+  float rna_exchange;
+  uint64_t seed;
+  uint32_t track_id;
+  int32_t reserved; /* must be 0 */
+} ppf_params;
+
+/* Scalars of the last committed step (see ppf_stats). */
+typedef struct ppf_stats_t {
+  int64_t k;           /* committed steps since create/reset                  */
+  int32_t resampled;   /* 1 if the last committed step resampled              */
+  int32_t rolled_back; /* steps rolled back (PPF_ENUMERIC) since last report  */
+  double ess;          /* 1 / sum w^2 of the last step, pre-resampling        */
+  double max_logw;     /* m = max_i log w~_i (unnormalised log weight)        */
+  double log_sum;      /* log sum_i exp(log w~_i - m)                         */
+  double delta;        /* log p^(z_k | z_1:k-1) = m + log_sum                 */
+  double cum;          /* sum over committed steps of delta                   */
+  double mean[5];      /* MMSE estimate sum_i w_i x~_i (Section 2)           */
+} ppf_stats_t;
+
+/* Per-kernel timing accumulated while profiling is enabled. */
+typedef struct ppf_kernel_time {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} ppf_kernel_time;
+
+/* Library version string, static storage. */
+const char* ppf_version(void);
+
+/* sizeof(ppf_params) as compiled, so bindings can check their layout. */
+size_t ppf_params_size(void);
+
+/* Fill *p with the defaults of a single-spot 128x128 tracking problem
+ * (s = 1.5, b = 10, sigma_xi = 3, N = 4096, systematic every step).
+ * EINVAL if p is NULL. */
+int ppf_params_default(ppf_params* p);
+
+/* Bytes of device workspace a filter with parameters *p needs (256-byte
+ * aligned start required). EINVAL for invalid parameters (see ppf_create). */
+int ppf_workspace_bytes(const ppf_params* p, size_t* bytes);
+
+/*
+ * Validate *p, carve the caller's device workspace and draw x0 (Algorithm 1,
+ * initialisation, k = 0: w0 = 1/N, x0 ~ pi(x0)); async on hip_stream.
+ *   workspace   device pointer, 256-byte aligned, at least
+ *               ppf_workspace_bytes bytes; owned by the caller and must
+ *               outlive the handle.
+ *   hip_stream  hipStream_t used for all device work of the handle.
+ *   out         receives the handle (host memory owned by the library, freed
+ *               by ppf_destroy).
+ * EINVAL: state_dim != 5, N out of range, even/too large patch, a sigma <= 0,
+ *   N % rna_group != 0 under RNA, rho outside [0, 1), null pointers, a patch
+ *   too wide for psf_sigma (edge beyond 37 sigma), frame size <= 0.
+ * ENOMEM: bytes too small. EDEVICE: a HIP call failed.
+ */
+int ppf_create(const ppf_params* p, void* workspace, size_t bytes, void* hip_stream,
+               ppf_handle* out);
+
+/* Re-draw x0 and zero the step counter and log-likelihood; async. */
+int ppf_reset(ppf_handle h);
+
+/*
+ * One SIR step k (Algorithm 1, SIS step + normalisation + ESS + optional
+ * resampling) on the observation obs_dev; async.
+ *   obs_dev  spot model: device frame, H*W fp32 row-major Z[y][x];
+ *            linear-Gaussian model: 3 fp32 (x, y, I0) on the device.
+ *            Must stay valid until the stream has passed the step.
+ * Nothing is synchronised: the resampling decision is taken on the device.
+ * When the step finds no finite normaliser (e.g. NaN pixels under every
+ * particle) it is rolled back on the device (state and k unchanged) and the
+ * next synchronising call reports PPF_ENUMERIC.
+ * ESTATE for a null handle; EDEVICE if a launch fails.
+ */
+int ppf_step(ppf_handle h, const float* obs_dev);
+
+/* Wait for the handle's stream. Returns PPF_ENUMERIC if any step enqueued
+ * since the last report was rolled back (and clears the report), else OK. */
+int ppf_sync(ppf_handle h);
+
+/* MMSE estimate x^ = sum_i w_i x~_i of the last committed step (weights
+ * before resampling, Section 2) and its ESS; syncs. mean: 5 doubles. Either
+ * pointer may be NULL. Returns PPF_ENUMERIC like ppf_sync. */
+int ppf_estimate(ppf_handle h, double mean[5], double* ess);
+
+/* cum = sum_k log p^(z_k | z_1:k-1), last = the term of the last committed
+ * step: the normaliser of Eq. 1 estimated by the particles (log of the sum of
+ * the normalised previous weights times the likelihood); syncs. Either
+ * pointer may be NULL. Returns PPF_ENUMERIC like ppf_sync. */
+int ppf_loglik(ppf_handle h, double* cum, double* last);
+
+/* All scalars of the last committed step; syncs and clears the roll-back
+ * report (returns PPF_OK even if steps were rolled back: see rolled_back). */
+int ppf_stats(ppf_handle h, ppf_stats_t* out);
+
+/*
+ * Copy the particle system of the last committed step to the host; syncs.
+ *   state_host  5*N fp32, SoA [x | y | vx | vy | I0], the propagated states
+ *               x~_k (before resampling);
+ *   logw_host   N fp64, normalised log weights log w_k (before resampling);
+ *   anc_host    N int32, the ancestors s(i) drawn at step k, or the identity
+ *               when step k did not resample (or no step ran yet).
+ * Any pointer may be NULL.
+ */
+int ppf_get_particles(ppf_handle h, float* state_host, double* logw_host, int32_t* anc_host);
+
+/*
+ * Replace the particle system (checkpoint restore, test injection); syncs.
+ *   state_host  5*N fp32 SoA as above; logw_host N fp64 log weights,
+ *   normalised (log-sum-exp 0) for ppf_loglik to keep its meaning.
+ * The next step propagates particle i from state i with log weight logw[i]
+ * (no resampling in between). The step counter k is kept.
+ */
+int ppf_set_particles(ppf_handle h, const float* state_host, const double* logw_host);
+
+/* Write the resampled particle states x_k^i = x~_k^{s(i)} (Algorithm 1,
+ * resampling copy) as 5*N fp32 SoA to out_dev; async. Equals the state of
+ * ppf_get_particles when the last step did not resample. */
+int ppf_gather(ppf_handle h, float* out_dev);
+
+/* Enable (1) / disable (0) per-kernel HIP-event timing of the handle's
+ * launches; enabling clears the accumulated times. */
+int ppf_profile_enable(ppf_handle h, int on);
+
+/* Read accumulated kernel times; syncs. Writes at most max_entries entries
+ * and the number written to *n_entries. */
+int ppf_profile_read(ppf_handle h, ppf_kernel_time* out, int max_entries, int* n_entries);
+
+/* Release the handle (host memory only; the workspace stays the caller's).
+ * Waits for the handle's outstanding work first. NULL is accepted. */
+int ppf_destroy(ppf_handle h);
+
+/* Static text for a return code. */
+const char* ppf_error_string(int code);
+
+/* Text of the last error recorded on the handle ("" if none). */
+const char* ppf_last_error(ppf_handle h);
+
+/* ------------------------------------------------ standalone primitives */
+
+/*
+ * Philox4x32-10 (Salmon et al., SC'11) over n counters: out[4i..4i+3] =
+ * Philox(ctr[4i..4i+3], key = (seed & 0xffffffff, seed >> 32)); async on
+ * hip_stream. ctr_dev and out_dev: 4*n uint32 on the device. EINVAL for
+ * n < 0 or null pointers with n > 0.
+ */
+int ppf_philox4x32_10(uint64_t seed, const uint32_t* ctr_dev, uint32_t* out_dev, int64_t n,
+                      void* hip_stream);
+
+/* Device scratch bytes needed by the standalone resamplers for n weights. */
+int ppf_resample_scratch_bytes(int64_t n, size_t* bytes);
+
+/*
+ * Systematic resampling of the resampling step of Algorithm 1 on arbitrary
+ * log weights; async.
+ *   logw_dev  n fp32 unnormalised log weights (-inf allowed, not all -inf);
+ *   u         the single uniform in [0, 1); slot i uses (i + u) / n;
+ *   anc_dev   n int32 out: s(i) = min{ j : (i + u)/n < C_j }, C the CDF of
+ *             the normalised weights (C_{n-1} taken as 1);
+ *   scratch   device scratch of ppf_resample_scratch_bytes(n), 256-aligned.
+ * EINVAL / ENOMEM as usual. Non-finite normaliser: anc is left unwritten and
+ * the call returns OK (no sync happens); callers validate inputs.
+ */
+int ppf_resample_systematic(const float* logw_dev, int64_t n, double u, int32_t* anc_dev,
+                            void* scratch, size_t scratch_bytes, void* hip_stream);
+
+/*
+ * RNA resampling (Section 3): groups g of `group` consecutive weights are
+ * resampled locally and systematically with uniform u_dev[g]; group g's slot
+ * weight becomes W_g / group (W_g its share of the normalised weight); then
+ * the last `moved` slots of each group take the ancestors and weight of the
+ * same slots of group g-1 mod G. Async.
+ *   u_dev    G = n / group doubles in [0, 1) on the device;
+ *   anc_dev  n int32 out (global indices);
+ *   lwg_dev  G doubles out: log(W_g / group) (-inf for an empty group, which
+ *            keeps the identity map).
+ * EINVAL: n % group != 0, group outside 1..1024, moved outside 0..group.
+ */
+int ppf_resample_rna(const float* logw_dev, int64_t n, int32_t group, int32_t moved,
+                     const double* u_dev, int32_t* anc_dev, double* lwg_dev, void* scratch,
+                     size_t scratch_bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPF_H */

@@ -1,0 +1,29 @@
+"""Build the FP64 oracle's shared library with gcc (test infrastructure).
+
+Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may use
+anything under oracle/.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ppf_oracle.c")
+LIB = os.path.join(HERE, "_liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile ppf_oracle.c into oracle/_liboracle.so (always recompiles)."""
+    tmp = LIB + ".tmp"
+    # -ffp-contract=off: no fused multiply-add, so every operation rounds as written.
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fPIC", "-shared",
+           "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,408 @@
+/*
+ * FP64 CPU oracle of the SIR filter step — TEST INFRASTRUCTURE.
+ *
+ * Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may
+ * import, call, link or execute anything under oracle/.
+ *
+ * Plain, slow, sequential double-precision code that follows Algorithm 1
+ * (SIR, Section 2) with the dynamics of Section 6.1 and the observation
+ * model of Eqs. 3-4 (Section 6.2), and the RNA scheme of Section 3. Every
+ * loop runs in index order; every sum is sequential. The random numbers come
+ * from this file's own Philox4x32-10 written from its published definition
+ * (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as easy as 1, 2, 3",
+ * SC'11).
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   - proposal: bootstrap, pi = p(x_k | x_{k-1}), so the weight update of
+ *     Algorithm 1 reduces to w_{k-1} * p(z_k | x~_k);
+ *   - dynamics: unit frame interval, positions advance by the previous
+ *     velocity, independent Gaussian noise per state component;
+ *   - S_x: the P x P pixel block centred on the pixel nearest to (x^, y^);
+ *     pixels outside the frame contribute Z - I_bg = 0;
+ *   - Eq. 4 keeps its Gaussian normaliser, so the per-step normaliser of
+ *     Eq. 1 (the log-likelihood increment) is an absolute quantity;
+ *   - resampling scheme: systematic, s(i) = min{ j : (i+u)/N < C_j };
+ *   - RNA: contiguous groups, local systematic resampling, slot weight W_g/n,
+ *     the last floor(rho n) slots of group g replaced by those of g-1 mod G.
+ */
+#include "ppf_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { PURPOSE_INIT = 1, PURPOSE_PROPAGATE = 2, PURPOSE_RESAMPLE = 3, PURPOSE_RNA = 4 };
+
+/* ------------------------------------------------------------- Philox */
+
+/* One Philox round: two 32x32->64 products, their halves xored with the
+ * other counter words and the round key, then a fixed word permutation. */
+static void philox_round(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c[0];
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c[2];
+  const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+  const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+  const uint32_t n0 = hi1 ^ c[1] ^ k0;
+  const uint32_t n1 = lo1;
+  const uint32_t n2 = hi0 ^ c[3] ^ k1;
+  const uint32_t n3 = lo0;
+  c[0] = n0;
+  c[1] = n1;
+  c[2] = n2;
+  c[3] = n3;
+}
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { /* Weyl key schedule between rounds */
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    philox_round(c, k0, k1);
+  }
+  memcpy(out, c, sizeof c);
+}
+
+void orc_philox_many(uint64_t seed, int64_t n, const uint32_t* ctr, uint32_t* out) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int64_t i = 0; i < n; ++i) orc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
+static void draw(const orc_model* m, uint32_t index, uint32_t k, uint32_t purpose, uint32_t block,
+                 uint32_t out[4]) {
+  const uint32_t ctr[4] = {index, k, (purpose << 24) | block, m->track};
+  const uint32_t key[2] = {(uint32_t)m->seed, (uint32_t)(m->seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+/* --------------------------------------------------------- conversions */
+
+double orc_u24_open_hi(uint32_t a) { return ldexp((double)(a >> 8), -24); }
+
+double orc_u24_open_lo(uint32_t a) { return ldexp((double)(a >> 8) + 1.0, -24); }
+
+double orc_u53(uint32_t a, uint32_t b) {
+  return ldexp((double)a * 2097152.0 + (double)(b >> 11), -53);
+}
+
+/* Box-Muller: radius from a uniform in (0, 1], angle from one in [0, 1). */
+void orc_box_muller(uint32_t a, uint32_t b, double* z0, double* z1) {
+  const double radius = sqrt(-2.0 * log(orc_u24_open_lo(a)));
+  const double angle = 2.0 * M_PI * orc_u24_open_hi(b);
+  *z0 = radius * cos(angle);
+  *z1 = radius * sin(angle);
+}
+
+double orc_resample_uniform(const orc_model* m, int64_t k) {
+  uint32_t r[4];
+  draw(m, 0u, (uint32_t)k, PURPOSE_RESAMPLE, 0u, r);
+  return orc_u53(r[0], r[1]);
+}
+
+double orc_rna_uniform(const orc_model* m, int64_t g, int64_t k) {
+  uint32_t r[4];
+  draw(m, (uint32_t)g, (uint32_t)k, PURPOSE_RNA, 0u, r);
+  return orc_u53(r[0], r[1]);
+}
+
+/* Five standard normals for (index, k, purpose): words 0,1 and 2,3 of block
+ * 0 give two pairs; words 0,1 of block 1 give the fifth (cosine branch). */
+static void five_normals(const orc_model* m, uint32_t index, uint32_t k, uint32_t purpose,
+                         double z[5]) {
+  uint32_t r0[4], r1[4];
+  double unused;
+  draw(m, index, k, purpose, 0u, r0);
+  draw(m, index, k, purpose, 1u, r1);
+  orc_box_muller(r0[0], r0[1], &z[0], &z[1]);
+  orc_box_muller(r0[2], r0[3], &z[2], &z[3]);
+  orc_box_muller(r1[0], r1[1], &z[4], &unused);
+}
+
+/* ------------------------------------------------------ initialisation */
+
+/* Stratified uniform initialisation over the (x, y) box: 2^t cells, t =
+ * max(0, floor(log2 N) - 2), x taking ceil(t/2) bits and y floor(t/2);
+ * particle i lies in cell c = floor(i 2^t / N), whose bits alternate x, y
+ * from the lowest (Z order), at a uniform position inside the cell. */
+static int strat_bits(int64_t n) {
+  int t = 0;
+  while (((int64_t)1 << (t + 1)) <= n) ++t;
+  t -= 2;
+  return t < 0 ? 0 : t;
+}
+
+static void strat_cell(int64_t i, int64_t n, int t, uint32_t* cx, uint32_t* cy) {
+  const uint64_t c = ((uint64_t)i << t) / (uint64_t)n;
+  uint32_t x = 0, y = 0;
+  int bx = 0, by = 0;
+  for (int j = 0; j < t; ++j) {
+    const uint32_t bit = (uint32_t)(c >> j) & 1u;
+    if (j % 2 == 0)
+      x |= bit << bx++;
+    else
+      y |= bit << by++;
+  }
+  *cx = x;
+  *cy = y;
+}
+
+/* Algorithm 1, k = 0: w_0 = 1/N and x_0 drawn from the initial density. */
+void orc_init(const orc_model* m, double* x, double* lw) {
+  const int64_t n = m->n;
+  const int t = strat_bits(n);
+  const int ax = (t + 1) / 2, ay = t / 2;
+  for (int64_t i = 0; i < n; ++i) {
+    if (m->init_kind == 2) {
+      uint32_t r0[4], r1[4], cx, cy;
+      draw(m, (uint32_t)i, 0u, PURPOSE_INIT, 0u, r0);
+      draw(m, (uint32_t)i, 0u, PURPOSE_INIT, 1u, r1);
+      strat_cell(i, n, t, &cx, &cy);
+      const double fx = ((double)cx + orc_u24_open_hi(r0[0])) / ldexp(1.0, ax);
+      const double fy = ((double)cy + orc_u24_open_hi(r0[1])) / ldexp(1.0, ay);
+      x[0 * n + i] = m->init_a[0] + (m->init_b[0] - m->init_a[0]) * fx;
+      x[1 * n + i] = m->init_a[1] + (m->init_b[1] - m->init_a[1]) * fy;
+      const uint32_t word[3] = {r0[2], r0[3], r1[0]};
+      for (int d = 2; d < 5; ++d)
+        x[d * n + i] = m->init_a[d] + (m->init_b[d] - m->init_a[d]) * orc_u24_open_hi(word[d - 2]);
+    } else if (m->init_kind == 0) {
+      uint32_t r0[4], r1[4];
+      draw(m, (uint32_t)i, 0u, PURPOSE_INIT, 0u, r0);
+      draw(m, (uint32_t)i, 0u, PURPOSE_INIT, 1u, r1);
+      const uint32_t word[5] = {r0[0], r0[1], r0[2], r0[3], r1[0]};
+      for (int d = 0; d < 5; ++d)
+        x[d * n + i] = m->init_a[d] + (m->init_b[d] - m->init_a[d]) * orc_u24_open_hi(word[d]);
+    } else {
+      double z[5];
+      five_normals(m, (uint32_t)i, 0u, PURPOSE_INIT, z);
+      for (int d = 0; d < 5; ++d) x[d * n + i] = m->init_a[d] + m->init_b[d] * z[d];
+    }
+    lw[i] = -log((double)n);
+  }
+}
+
+/* ---------------------------------------------------------- propagate */
+
+/* Near-constant-velocity dynamics (Section 6.1) with unit time step:
+ * position += velocity, then Gaussian noise with sds q on every component. */
+void orc_propagate(const orc_model* m, int64_t k, const double* x_prev, const int32_t* parent,
+                   double* x_new) {
+  const int64_t n = m->n;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t p = parent ? (int64_t)parent[i] : i;
+    double z[5];
+    five_normals(m, (uint32_t)i, (uint32_t)k, PURPOSE_PROPAGATE, z);
+    const double px = x_prev[0 * n + p], py = x_prev[1 * n + p];
+    const double pvx = x_prev[2 * n + p], pvy = x_prev[3 * n + p];
+    const double pI = x_prev[4 * n + p];
+    x_new[0 * n + i] = px + pvx + m->q[0] * z[0];
+    x_new[1 * n + i] = py + pvy + m->q[1] * z[1];
+    x_new[2 * n + i] = pvx + m->q[2] * z[2];
+    x_new[3 * n + i] = pvy + m->q[3] * z[3];
+    x_new[4 * n + i] = pI + m->q[4] * z[4];
+  }
+}
+
+/* --------------------------------------------------------- likelihood */
+
+/* Eq. 4 on the P x P pixel block around the particle, with the spot of Eq. 3
+ * evaluated per pixel (one exp per pixel, no separable shortcut). */
+void orc_loglik_spot(const orc_model* m, const float* frame, const double* x, double* ll) {
+  const int64_t n = m->n;
+  const int h = (m->patch - 1) / 2;
+  const double two_s2 = 2.0 * m->s * m->s;
+  const double two_sigma2 = 2.0 * m->sigma * m->sigma;
+  const double log_norm =
+      (double)m->patch * (double)m->patch * log(m->sigma * sqrt(2.0 * M_PI));
+  for (int64_t i = 0; i < n; ++i) {
+    const double xt = x[0 * n + i], yt = x[1 * n + i], It = x[4 * n + i];
+    const double cx = floor(xt + 0.5), cy = floor(yt + 0.5);
+    double acc = 0.0;
+    for (int dy = -h; dy <= h; ++dy) {
+      for (int dx = -h; dx <= h; ++dx) {
+        const double u = cx + dx, v = cy + dy;
+        double D = 0.0;
+        if (u >= 0.0 && u < (double)m->width && v >= 0.0 && v < (double)m->height)
+          D = (double)frame[(int64_t)v * m->width + (int64_t)u] - m->b;
+        const double g = exp(-((u - xt) * (u - xt) + (v - yt) * (v - yt)) / two_s2);
+        const double r = D - It * g;
+        acc += r * r;
+      }
+    }
+    ll[i] = -acc / two_sigma2 - log_norm;
+  }
+}
+
+/* Linear-Gaussian observation of (x, y, I0) with independent noise. */
+void orc_loglik_lg(const orc_model* m, const float* obs3, const double* x, double* ll) {
+  const int64_t n = m->n;
+  static const int comp[3] = {0, 1, 4};
+  for (int64_t i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double e = (double)obs3[d] - x[comp[d] * n + i];
+      const double r = m->lg_r[d];
+      acc += -e * e / (2.0 * r * r) - log(r * sqrt(2.0 * M_PI));
+    }
+    ll[i] = acc;
+  }
+}
+
+/* ------------------------------------------------------ normalisation */
+
+/* w_i = exp(l_i - m) / S with m = max l, S = sum exp(l - m); ESS = 1/sum w^2;
+ * the normaliser log sum_i exp(l_i) = m + log S. */
+int orc_normalize(int64_t n, const double* lwt, double* w, double stats[4]) {
+  double mx = -INFINITY;
+  for (int64_t i = 0; i < n; ++i)
+    if (lwt[i] > mx) mx = lwt[i];
+  double S = 0.0;
+  for (int64_t i = 0; i < n; ++i) S += exp(lwt[i] - mx);
+  if (!isfinite(mx) || !isfinite(S) || !(S > 0.0)) return -1;
+  double sum_w2 = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    w[i] = exp(lwt[i] - mx) / S;
+    sum_w2 += w[i] * w[i];
+  }
+  stats[0] = mx;
+  stats[1] = log(S);
+  stats[2] = 1.0 / sum_w2;
+  stats[3] = mx + log(S);
+  return 0;
+}
+
+void orc_estimate(int64_t n, const double* w, const double* x, double mean[5]) {
+  for (int d = 0; d < 5; ++d) {
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) acc += w[i] * x[d * n + i];
+    mean[d] = acc;
+  }
+}
+
+/* ---------------------------------------------------------- resampling */
+
+void orc_resample_systematic(int64_t n, const double* w, double u, int32_t* anc) {
+  int64_t j = 0;
+  double C = w[0];
+  for (int64_t i = 0; i < n; ++i) {
+    const double ui = ((double)i + u) / (double)n;
+    while (j < n - 1 && C <= ui) {
+      ++j;
+      C += w[j];
+    }
+    anc[i] = (int32_t)j;
+  }
+}
+
+void orc_resample_rna(int64_t n, int32_t group, int32_t moved, const double* w,
+                      const double* u_g, int32_t* anc, double* lwg, double* lw_slot) {
+  const int64_t G = n / group;
+  int32_t* local = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  for (int64_t g = 0; g < G; ++g) {
+    const int64_t base = g * group;
+    double W = 0.0;
+    for (int32_t l = 0; l < group; ++l) W += w[base + l];
+    lwg[g] = log(W / (double)group);
+    if (!(W > 0.0)) {
+      for (int32_t l = 0; l < group; ++l) local[base + l] = (int32_t)(base + l);
+      continue;
+    }
+    int32_t j = 0;
+    double cum = w[base];
+    for (int32_t l = 0; l < group; ++l) {
+      const double ul = ((double)l + u_g[g]) / (double)group;
+      while (j < group - 1 && cum / W <= ul) {
+        ++j;
+        cum += w[base + j];
+      }
+      local[base + l] = (int32_t)(base + j);
+    }
+  }
+  for (int64_t g = 0; g < G; ++g) {
+    const int64_t prev = (g + G - 1) % G;
+    for (int32_t l = 0; l < group; ++l) {
+      const int64_t i = g * group + l;
+      if (l >= group - moved) {
+        anc[i] = local[prev * group + l];
+        lw_slot[i] = lwg[prev];
+      } else {
+        anc[i] = local[i];
+        lw_slot[i] = lwg[g];
+      }
+    }
+  }
+  free(local);
+}
+
+/* ------------------------------------------------------------ the filter */
+
+int orc_run(const orc_model* m, int32_t T, const float* obs, double* mean, double* ess,
+            double* delta, int32_t* resampled, double* x_out, double* lw_out, int32_t* anc_out) {
+  const int64_t n = m->n;
+  double* x = (double*)malloc((size_t)(5 * n) * sizeof(double));
+  double* xn = (double*)malloc((size_t)(5 * n) * sizeof(double));
+  double* lw = (double*)malloc((size_t)n * sizeof(double));
+  double* ll = (double*)malloc((size_t)n * sizeof(double));
+  double* w = (double*)malloc((size_t)n * sizeof(double));
+  int32_t* parent = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  double* lwg = (double*)malloc((size_t)n * sizeof(double));
+  double* ug = (double*)malloc((size_t)n * sizeof(double));
+  int have_parent = 0, status = 0;
+  const int64_t frame_len = m->obs_model == 0 ? (int64_t)m->width * m->height : 3;
+
+  orc_init(m, x, lw);
+  for (int32_t k = 1; k <= T; ++k) {
+    const float* z = obs + (int64_t)(k - 1) * frame_len;
+    orc_propagate(m, k, x, have_parent ? parent : NULL, xn);
+    if (m->obs_model == 0)
+      orc_loglik_spot(m, z, xn, ll);
+    else
+      orc_loglik_lg(m, z, xn, ll);
+    for (int64_t i = 0; i < n; ++i) ll[i] += lw[i]; /* w_{k-1} p(z|x~) in logs */
+    double st[4], mu[5];
+    if (orc_normalize(n, ll, w, st) != 0) {
+      status = -k;
+      break;
+    }
+    orc_estimate(n, w, xn, mu);
+    if (mean) memcpy(mean + 5 * (k - 1), mu, sizeof mu);
+    if (ess) ess[k - 1] = st[2];
+    if (delta) delta[k - 1] = st[3];
+    const int do_resample = st[2] < m->ess_threshold;
+    if (resampled) resampled[k - 1] = do_resample;
+    if (lw_out && k == T)
+      for (int64_t i = 0; i < n; ++i) lw_out[i] = ll[i] - st[3];
+    if (do_resample) {
+      if (m->resample == 0) {
+        orc_resample_systematic(n, w, orc_resample_uniform(m, k), parent);
+        for (int64_t i = 0; i < n; ++i) lw[i] = -log((double)n);
+      } else {
+        const int64_t G = n / m->rna_group;
+        for (int64_t g = 0; g < G; ++g) ug[g] = orc_rna_uniform(m, g, k);
+        orc_resample_rna(n, m->rna_group, m->rna_moved, w, ug, parent, lwg, lw);
+      }
+      have_parent = 1;
+    } else {
+      for (int64_t i = 0; i < n; ++i) lw[i] = ll[i] - st[3];
+      have_parent = 0;
+    }
+    double* t = x;
+    x = xn;
+    xn = t;
+  }
+  if (status == 0) {
+    if (x_out) memcpy(x_out, x, (size_t)(5 * n) * sizeof(double));
+    if (anc_out)
+      for (int64_t i = 0; i < n; ++i) anc_out[i] = have_parent ? parent[i] : (int32_t)i;
+  }
+  free(x);
+  free(xn);
+  free(lw);
+  free(ll);
+  free(w);
+  free(parent);
+  free(lwg);
+  free(ug);
+  return status;
+}

@@ -1,0 +1,101 @@
+/*
+ * FP64 CPU oracle of the SIR filter step — TEST INFRASTRUCTURE.
+ *
+ * Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may
+ * import, call, link or execute anything under oracle/. The product library
+ * never links it and shares no code, header or constant table with it.
+ *
+ * This header is the oracle's own; it does not include or mirror the
+ * library's public header.
+ */
+#ifndef PPF_ORACLE_H
+#define PPF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Model of Sections 6.1-6.2 plus the filter options of Algorithm 1 and
+ * Section 3, all in double precision. */
+typedef struct orc_model {
+  int64_t n;            /* N particles                                        */
+  int32_t obs_model;    /* 0 = Gaussian spot on an image, 1 = linear-Gaussian */
+  int32_t width;        /* W                                                  */
+  int32_t height;       /* H                                                  */
+  int32_t patch;        /* P, odd                                             */
+  double s;             /* sigma_PSF (Eq. 3)                                  */
+  double b;             /* I_bg (Eq. 3)                                       */
+  double sigma;         /* sigma_xi (Eq. 4)                                   */
+  double q[5];          /* process-noise sds of (x, y, vx, vy, I0)            */
+  int32_t init_kind;    /* 0 uniform [a,b), 1 Gaussian N(a,b^2), 2 stratified  */
+  int32_t resample;     /* 0 = systematic, 1 = RNA                            */
+  double init_a[5];
+  double init_b[5];
+  double lg_r[3];       /* linear-Gaussian observation sds of (x, y, I0)      */
+  double ess_threshold; /* resample iff ESS < threshold                       */
+  int32_t rna_group;    /* n particles per RNA group                          */
+  int32_t rna_moved;    /* slots moved to the ring neighbour per group        */
+  uint64_t seed;        /* Philox key                                         */
+  uint32_t track;       /* Philox counter word 3                              */
+  int32_t pad;
+} orc_model;
+
+/* Philox4x32-10 block function. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* The same over n counters (4n words each), key from a 64-bit seed. */
+void orc_philox_many(uint64_t seed, int64_t n, const uint32_t* ctr, uint32_t* out);
+
+/* Conversions of Philox words to uniforms and normals. */
+double orc_u24_open_hi(uint32_t a);   /* (a >> 8) / 2^24, in [0, 1)        */
+double orc_u24_open_lo(uint32_t a);   /* ((a >> 8) + 1) / 2^24, in (0, 1]  */
+double orc_u53(uint32_t a, uint32_t b); /* 53-bit uniform in [0, 1)        */
+void orc_box_muller(uint32_t a, uint32_t b, double* z0, double* z1);
+
+/* Uniform of the systematic resampling at frame k; of RNA group g at k. */
+double orc_resample_uniform(const orc_model* m, int64_t k);
+double orc_rna_uniform(const orc_model* m, int64_t g, int64_t k);
+
+/* Algorithm 1 initialisation: x (5*n, SoA), lw (n) = -log N. */
+void orc_init(const orc_model* m, double* x, double* lw);
+
+/* SIS draw of frame k under the bootstrap proposal: x_new[i] from parent
+ * x_prev[parent[i]] (parent NULL: identity). SoA 5*n. */
+void orc_propagate(const orc_model* m, int64_t k, const double* x_prev, const int32_t* parent,
+                   double* x_new);
+
+/* log p(z | x) of Eq. 4 with its normalising constant, per particle. */
+void orc_loglik_spot(const orc_model* m, const float* frame, const double* x, double* ll);
+void orc_loglik_lg(const orc_model* m, const float* obs3, const double* x, double* ll);
+
+/* Normalisation of Algorithm 1 on unnormalised log weights lwt (n):
+ * w (n) normalised; stats = {m, log S, ESS, delta = m + log S}. Returns 0,
+ * or -1 when no finite positive normaliser exists. */
+int orc_normalize(int64_t n, const double* lwt, double* w, double stats[4]);
+
+/* MMSE estimate sum_i w_i x_i (5 values). */
+void orc_estimate(int64_t n, const double* w, const double* x, double mean[5]);
+
+/* Systematic resampling: anc[i] = min{ j : (i + u)/n < C_j }, C_{n-1} := 1. */
+void orc_resample_systematic(int64_t n, const double* w, double u, int32_t* anc);
+
+/* RNA: local systematic resampling per group with u_g[g], slot weight W_g/n,
+ * then ring exchange of the last `moved` slots from group g-1. Outputs the
+ * ancestors, log(W_g/n) per group (lwg, G values) and per slot (lw_slot). */
+void orc_resample_rna(int64_t n, int32_t group, int32_t moved, const double* w,
+                      const double* u_g, int32_t* anc, double* lwg, double* lw_slot);
+
+/* A whole filter run of T frames (Algorithm 1). obs: T frames of H*W fp32
+ * (spot) or T*3 fp32 (linear-Gaussian). Per-frame outputs may be NULL.
+ * x_out (5n), lw_out (n: normalised log weights of the last frame before
+ * resampling), anc_out (n: last ancestors or identity) may be NULL.
+ * Returns 0, or -k when frame k had no finite normaliser. */
+int orc_run(const orc_model* m, int32_t T, const float* obs, double* mean, double* ess,
+            double* delta, int32_t* resampled, double* x_out, double* lw_out, int32_t* anc_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

