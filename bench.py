@@ -1,0 +1,169 @@
+"""Benchmark: particle updates/s of the SIR filter step on one MI355X.
+
+Workload (default): one spot tracked through 1024x1024 fp32 frames with
+N = 38,000,000 particles, spot width s = 2 px, 13x13 likelihood patch,
+systematic resampling every step (the paper's 38-million-particle case on a
+single GPU). A step is one frame: gather + propagate + patch likelihood +
+normalisation/ESS + resampling for all N particles. Frames are synthetic
+(paper_1310_5045_amd.synth) and resident on the GPU before timing starts;
+filter initialisation is outside the timed region.
+
+Prints one JSON line. `value` is N * steps / wall time of the timed steps.
+`roofline` covers the dominant kernel (k_step) against the fp64 vector peak;
+`roofline_resample` covers the resampling scan against HBM bandwidth; both
+use algorithmic work per launch / average launch time measured with HIP
+events on the filter's stream. `cpu_baseline` times the FP64 oracle on a
+bounded sample of the same workload on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+WORKLOADS = {
+    # frame size, frames, particles, spot width, patch, resampling threshold
+    "sir_1024x1024_n38m_p13": dict(W=1024, H=1024, T=20, n=38_000_000, s=2.0, P=13,
+                                   thr=float("inf")),
+    "sir_512x512_n1m_p9": dict(W=512, H=512, T=50, n=1 << 20, s=1.5, P=9, thr=float(1 << 19)),
+    "sir_128x128_n4096_p9": dict(W=128, H=128, T=10, n=4096, s=1.5, P=9, thr=float("inf")),
+}
+
+
+def make_params(ppf, w, init_kind):
+    return ppf.params(n_particles=w["n"], width=w["W"], height=w["H"], psf_sigma=w["s"],
+                      background=10.0, noise_sigma=3.0, patch=w["P"], init_kind=init_kind,
+                      init_a=(0, 0, -1, -1, 15), init_b=(w["W"], w["H"], 1, 1, 45),
+                      ess_threshold=w["thr"], seed=1)
+
+
+def cpu_baseline(w, frames, sample_n, sample_t, init_kind):
+    """The oracle as it stands, single-threaded, on a bounded sample: the
+    first `sample_t` frames of the same movie with `sample_n` particles."""
+    import oracle
+    m = oracle.Model(n=sample_n, width=w["W"], height=w["H"], s=w["s"], b=10.0, sigma=3.0,
+                     patch=w["P"], init_kind=init_kind, init_a=(0, 0, -1, -1, 15),
+                     init_b=(w["W"], w["H"], 1, 1, 45), ess_threshold=w["thr"], seed=1)
+    t0 = time.perf_counter()
+    r = oracle.run(m, frames[:sample_t], sample_t)
+    dt = time.perf_counter() - t0
+    assert r.status == 0
+    return {"value": sample_n * sample_t / dt, "unit": "particle updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{sample_t} frames x {sample_n} particles of the same workload "
+                      f"(fp64, one thread, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sir_1024x1024_n38m_p13", choices=sorted(WORKLOADS))
+    ap.add_argument("--init", default="stratified", choices=["stratified", "uniform"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 22)
+    ap.add_argument("--cpu-frames", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1310_5045_amd as ppf
+    from paper_1310_5045_amd import synth
+
+    w = WORKLOADS[args.workload]
+    init_kind = ppf.INIT_STRATIFIED if args.init == "stratified" else ppf.INIT_UNIFORM
+    K, Wm = args.steps, args.warmup
+    T = max(K, w["T"], Wm)
+    mv = synth.render_movie(w["W"], w["H"], T, intensity=30.0, sigma=w["s"], background=10.0,
+                            noise_sd=3.0, seed=1)
+    torch.cuda.set_device(0)
+    frames = torch.from_numpy(mv.frames).cuda()
+    f = ppf.Filter(make_params(ppf, w, init_kind))
+    stream = f.stream
+    # warm-up: a few steps, then a fresh initial cloud for the timed steps
+    for k in range(Wm):
+        f.step(frames[k])
+    f.reset()
+    f.sync()
+    torch.cuda.synchronize()
+    f.profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for k in range(K):
+        f.step(frames[k % T])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    kt = f.kernel_times()
+    st = f.stats()
+    err = float(np.linalg.norm(st["mean"][:2] - mv.truth[(K - 1) % T, 0]))
+    n = w["n"]
+    ms_per_step = gpu_ms / K
+    value = n * K / (gpu_ms / 1e3)
+
+    P = w["P"]
+    step_launches, step_ms = kt.get("k_step", (0, 0.0))
+    step_avg_s = step_ms / max(step_launches, 1) / 1e3
+    flops_per_particle = 4 * P * P  # P^2 residual FMAs + P^2 square-accumulate FMAs
+    achieved_tf = flops_per_particle * n / step_avg_s / 1e12
+    scan_launches, scan_ms = kt.get("k_scan", (0, 0.0))
+    scan_avg_s = scan_ms / max(scan_launches, 1) / 1e3
+    scan_gbs = 8.0 * n / scan_avg_s / 1e9  # read 4 B log weight, write 4 B ancestor
+    step_gbs = 48.0 * n / step_avg_s / 1e9
+
+    out = {
+        "metric": "particle updates/s at N=38M on 1 GPU",
+        "value": value,
+        "unit": "particle updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 state, f64 likelihood/normalisation",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_particles": n, "frame": [w["W"], w["H"]],
+                   "patch": P, "psf_sigma": w["s"], "resampling": "systematic"
+                   if w["thr"] == float("inf") else f"systematic when ESS < {w['thr']:.0f}",
+                   "init": args.init, "frames_timed": K},
+        "roofline": {"bound": "alu", "kernel": "k_step", "achieved": achieved_tf,
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "avg_launch_ms": step_avg_s * 1e3, "flops_per_particle": flops_per_particle,
+                     "hbm_gbs_at_48B_per_particle": step_gbs},
+        "roofline_resample": {"bound": "hbm", "kernel": "k_scan", "achieved": scan_gbs,
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": scan_gbs / HBM_PEAK_GBS,
+                              "avg_launch_ms": scan_avg_s * 1e3, "bytes_per_particle": 8},
+        "kernel_ms_total": {k: v[1] for k, v in kt.items()},
+        "kernel_launches": {k: v[0] for k, v in kt.items()},
+        "wall_s": wall,
+        "tracking_error_px": err,
+        "final_ess": st["ess"],
+    }
+    f.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, mv.frames, min(args.cpu_sample, n), args.cpu_frames,
+                                           init_kind)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -57,7 +57,7 @@ enum {
 
 enum { PPF_RESAMPLE_SYSTEMATIC = 0, PPF_RESAMPLE_RNA = 1 };
 enum { PPF_OBS_SPOT = 0, PPF_OBS_LINEAR_GAUSSIAN = 1 };
-enum { PPF_INIT_UNIFORM = 0, PPF_INIT_GAUSSIAN = 1 };
+enum { PPF_INIT_UNIFORM = 0, PPF_INIT_GAUSSIAN = 1, PPF_INIT_STRATIFIED = 2 };
 
 /* Largest patch edge P the kernels are built for. */
 #define PPF_MAX_PATCH 25
@@ -83,9 +83,15 @@ typedef struct ppf_ctx* ppf_handle;
  *               1..PPF_MAX_PATCH; 0 selects 2*floor(3*psf_sigma)+1, the
  *               integer reading of the +-3 sigma_PSF box.
  * q[5]          process-noise standard deviations of (x, y, vx, vy, I0).
- * init_kind     PPF_INIT_UNIFORM: x0[d] ~ U[init_a[d], init_b[d]) (the paper
- *               initialises uniformly at random, Section 6.3);
- *               PPF_INIT_GAUSSIAN: x0[d] ~ N(init_a[d], init_b[d]^2).
+ * init_kind     PPF_INIT_UNIFORM: x0[d] ~ U[init_a[d], init_b[d]) i.i.d. (the
+ *               paper initialises uniformly at random, Section 6.3);
+ *               PPF_INIT_GAUSSIAN: x0[d] ~ N(init_a[d], init_b[d]^2);
+ *               PPF_INIT_STRATIFIED: uniform as above, but the (x, y) box is
+ *               cut into 2^t cells (t = max(0, floor(log2 N) - 2), x taking
+ *               ceil(t/2) bits, y floor(t/2)) visited in Z order; particle i
+ *               lies uniformly inside cell floor(i 2^t / N). Consecutive
+ *               indices are then neighbours in the image, which keeps the
+ *               first frame's image tiles small.
  * lg_r[3]       observation noise sds of the linear-Gaussian model (> 0).
  * resample      PPF_RESAMPLE_SYSTEMATIC or PPF_RESAMPLE_RNA.
  * ess_threshold resample iff ESS < ess_threshold (Algorithm 1); +INFINITY

@@ -1,0 +1,595 @@
+// Host runtime of the C ABI declared in include/ppf.h: parameter validation,
+// workspace carving, the per-step launch sequence on the caller's stream,
+// synchronising queries, and per-kernel event timing.
+#include "ppf.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ppf_internal.hpp"
+
+using ppf::Buffers;
+using ppf::Ctrl;
+using ppf::Model;
+
+namespace {
+
+enum KernelId { kKStep, kKReduce, kKFinalize, kKScan, kKHeavy, kKRna, kKInit, kKGather, kKLogw,
+                kNumKernels };
+const char* const kKernelNames[kNumKernels] = {"k_step", "k_reduce", "k_finalize",
+                                               "k_scan", "k_heavy",  "k_rna",
+                                               "k_init", "k_gather", "k_logw"};
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int derived_patch(const ppf_params* p) {
+  return p->patch ? p->patch : 2 * (int)std::floor(3.0 * (double)p->psf_sigma) + 1;
+}
+
+// Returns an empty string when *p is acceptable.
+std::string validate(const ppf_params* p) {
+  if (!p) return "null parameters";
+  if (p->state_dim != 5) return "state_dim must be 5";
+  if (p->reserved != 0) return "reserved must be 0";
+  if (p->n_particles < 1 || p->n_particles > 2147483647LL) return "n_particles out of range";
+  if (p->obs_model != PPF_OBS_SPOT && p->obs_model != PPF_OBS_LINEAR_GAUSSIAN)
+    return "unknown obs_model";
+  if (p->init_kind < PPF_INIT_UNIFORM || p->init_kind > PPF_INIT_STRATIFIED)
+    return "unknown init_kind";
+  if (p->resample != PPF_RESAMPLE_SYSTEMATIC && p->resample != PPF_RESAMPLE_RNA)
+    return "unknown resample scheme";
+  for (int d = 0; d < 5; ++d) {
+    if (!std::isfinite(p->q[d]) || p->q[d] < 0.0f) return "q must be finite and >= 0";
+    if (!std::isfinite(p->init_a[d]) || !std::isfinite(p->init_b[d]))
+      return "init box must be finite";
+  }
+  if (std::isnan(p->ess_threshold)) return "ess_threshold is NaN";
+  if (p->obs_model == PPF_OBS_SPOT) {
+    if (p->width < 1 || p->height < 1) return "frame size must be positive";
+    if ((int64_t)p->width * p->height > (int64_t)1 << 31) return "frame too large";
+    if (!(p->psf_sigma > 0.0f) || !std::isfinite(p->psf_sigma)) return "psf_sigma must be > 0";
+    if (!(p->noise_sigma > 0.0f) || !std::isfinite(p->noise_sigma))
+      return "noise_sigma must be > 0";
+    if (!std::isfinite(p->background)) return "background must be finite";
+    const int P = derived_patch(p);
+    if (P < 1 || P > PPF_MAX_PATCH || P % 2 == 0) return "patch must be odd and <= 25";
+    const double s = p->psf_sigma, h = (P - 1) / 2;
+    // the Gaussian recurrence starts at the patch edge: keep exp() normal
+    if ((h + 0.5) * (h + 0.5) / (2.0 * s * s) > 700.0) return "patch too wide for psf_sigma";
+  } else {
+    for (int d = 0; d < 3; ++d)
+      if (!(p->lg_r[d] > 0.0f) || !std::isfinite(p->lg_r[d])) return "lg_r must be > 0";
+  }
+  if (p->resample == PPF_RESAMPLE_RNA) {
+    if (p->rna_group < 1 || p->rna_group > ppf::kMaxGroup) return "rna_group out of range";
+    if (p->n_particles % p->rna_group != 0) return "n_particles must be a multiple of rna_group";
+    if (!(p->rna_exchange >= 0.0f && p->rna_exchange < 1.0f)) return "rna_exchange not in [0,1)";
+  }
+  return "";
+}
+
+int strat_bits(int64_t n) {
+  int t = 0;
+  while (((int64_t)1 << (t + 1)) <= n) ++t;
+  t -= 2;
+  return t < 0 ? 0 : t;
+}
+
+Model make_model(const ppf_params* p) {
+  Model m{};
+  m.n = p->n_particles;
+  m.inv_n = 1.0 / (double)m.n;
+  m.log_n = std::log((double)m.n);
+  m.W = p->width;
+  m.H = p->height;
+  m.P = p->obs_model == PPF_OBS_SPOT ? derived_patch(p) : 1;
+  m.obs = p->obs_model;
+  m.init_kind = p->init_kind;
+  for (int d = 0; d < 5; ++d) {
+    m.q[d] = p->q[d];
+    m.init_a[d] = p->init_a[d];
+    m.init_b[d] = p->init_b[d];
+  }
+  m.bf = p->background;
+  m.b = (double)p->background;
+  const double s = p->psf_sigma, sg = p->noise_sigma;
+  m.inv2s2 = 1.0 / (2.0 * s * s);
+  m.inv2sig2 = 1.0 / (2.0 * sg * sg);
+  m.lognorm_obs = (double)m.P * (double)m.P * std::log(sg * std::sqrt(2.0 * M_PI));
+  m.lg_norm = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double r = p->lg_r[d];
+    m.lg_inv2r2[d] = r > 0.0 ? 1.0 / (2.0 * r * r) : 0.0;
+    m.lg_norm += r > 0.0 ? std::log(r * std::sqrt(2.0 * M_PI)) : 0.0;
+  }
+  m.thr = p->ess_threshold;
+  if (p->resample == PPF_RESAMPLE_RNA) {
+    m.group = p->rna_group;
+    m.moved = (int32_t)std::floor((double)p->rna_exchange * (double)p->rna_group);
+    m.G = (int32_t)(m.n / m.group);
+    m.inv_group = 1.0 / (double)m.group;
+  }
+  m.key0 = (uint32_t)p->seed;
+  m.key1 = (uint32_t)(p->seed >> 32);
+  m.track = p->track_id;
+  m.strat_t = strat_bits(m.n);
+  return m;
+}
+
+int64_t record_blocks(int64_t n) { return (n + ppf::kBlock - 1) / ppf::kBlock; }
+int64_t level2_blocks(int64_t nb) {
+  return nb > ppf::kDirectRecords ? (nb < ppf::kReduceBlocks ? nb : ppf::kReduceBlocks) : 0;
+}
+int64_t scan_tiles(int64_t n) { return (n + ppf::kTile - 1) / ppf::kTile; }
+
+// Carve the filter workspace; base may be null to only compute the size.
+size_t carve(const ppf_params* p, char* base, Buffers* b) {
+  const int64_t n = p->n_particles;
+  Buffers bb{};
+  bb.nb = record_blocks(n);
+  bb.nr2 = level2_blocks(bb.nb);
+  bb.ntiles = scan_tiles(n);
+  const int64_t G = p->resample == PPF_RESAMPLE_RNA ? n / p->rna_group : 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* ptr = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return ptr;
+  };
+  bb.ctrl = reinterpret_cast<Ctrl*>(take(sizeof(Ctrl)));
+  bb.X0 = reinterpret_cast<float*>(take(sizeof(float) * 5 * n));
+  bb.X1 = reinterpret_cast<float*>(take(sizeof(float) * 5 * n));
+  bb.L0 = reinterpret_cast<float*>(take(sizeof(float) * n));
+  bb.L1 = reinterpret_cast<float*>(take(sizeof(float) * n));
+  bb.R0 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nb));
+  bb.R1 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nb));
+  bb.R2 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * (bb.nr2 ? bb.nr2 : 1)));
+  bb.anc = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
+  bb.lw64 = reinterpret_cast<double*>(take(sizeof(double) * n));
+  bb.lwg = reinterpret_cast<double*>(take(sizeof(double) * G));
+  bb.desc = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * bb.ntiles));
+  bb.heavy = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * 2 * bb.ntiles));
+  bb.zeros = nullptr;
+  if (b) *b = bb;
+  return off;
+}
+
+// Scratch of the standalone resamplers.
+size_t carve_scratch(int64_t n, char* base, Buffers* b) {
+  Buffers bb{};
+  bb.nb = record_blocks(n);
+  bb.nr2 = level2_blocks(bb.nb);
+  bb.ntiles = scan_tiles(n);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* ptr = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return ptr;
+  };
+  bb.ctrl = reinterpret_cast<Ctrl*>(take(sizeof(Ctrl)));
+  bb.R0 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nb));
+  bb.R2 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * (bb.nr2 ? bb.nr2 : 1)));
+  bb.zeros = reinterpret_cast<double*>(take(sizeof(double) * bb.nb));
+  bb.desc = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * bb.ntiles));
+  bb.heavy = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * 2 * bb.ntiles));
+  if (b) *b = bb;
+  return off;
+}
+
+}  // namespace
+
+struct ppf_ctx {
+  ppf_params p{};
+  Model m{};
+  Buffers b{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool prof = false;
+  struct Ev {
+    int kernel;
+    hipEvent_t start, stop;
+  };
+  std::vector<Ev> events;
+  double total_ms[kNumKernels] = {};
+  int64_t launches[kNumKernels] = {};
+
+  int fail(int code, const std::string& what) {
+    err = what;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char* where) {
+    err = std::string(where) + ": " + hipGetErrorString(e);
+    return PPF_EDEVICE;
+  }
+  // Launch with optional event timing around it.
+  template <class F>
+  int run(int kernel, F&& launch) {
+    hipEvent_t a = nullptr, z = nullptr;
+    if (prof) {
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&z) != hipSuccess)
+        return fail(PPF_EDEVICE, "hipEventCreate failed");
+      if (hipEventRecord(a, stream) != hipSuccess) return fail(PPF_EDEVICE, "hipEventRecord");
+    }
+    const hipError_t e = launch();
+    if (prof) {
+      const hipError_t ez = hipEventRecord(z, stream);
+      events.push_back({kernel, a, z});
+      if (ez != hipSuccess) return hip_fail(ez, "hipEventRecord");
+    }
+    if (e != hipSuccess) return hip_fail(e, kKernelNames[kernel]);
+    return PPF_OK;
+  }
+  int collect() {
+    for (auto& ev : events) {
+      if (hipEventSynchronize(ev.stop) != hipSuccess) return fail(PPF_EDEVICE, "event sync");
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ev.start, ev.stop) == hipSuccess) {
+        total_ms[ev.kernel] += ms;
+        launches[ev.kernel] += 1;
+      }
+      (void)hipEventDestroy(ev.start);
+      (void)hipEventDestroy(ev.stop);
+    }
+    events.clear();
+    return PPF_OK;
+  }
+  int read_ctrl(Ctrl* c) {
+    hipError_t e = hipMemcpyAsync(c, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "reading control block");
+    return PPF_OK;
+  }
+  ppf::WeightSrc filter_weights() const {
+    ppf::WeightSrc w{};
+    w.val0 = b.L0;
+    w.val1 = b.L1;
+    w.off0 = b.R0;
+    w.off1 = b.R1;
+    w.stride = ppf::kRec;
+    w.use_cur = 1;
+    return w;
+  }
+};
+
+extern "C" {
+
+const char* ppf_version(void) { return "ppf-mi355x 0.1 (gfx950)"; }
+
+size_t ppf_params_size(void) { return sizeof(ppf_params); }
+
+int ppf_params_default(ppf_params* p) {
+  if (!p) return PPF_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->state_dim = 5;
+  p->obs_model = PPF_OBS_SPOT;
+  p->n_particles = 4096;
+  p->width = p->height = 128;
+  p->psf_sigma = 1.5f;
+  p->background = 10.0f;
+  p->noise_sigma = 3.0f;
+  p->patch = 0;
+  const float q[5] = {0.5f, 0.5f, 0.1f, 0.1f, 1.0f};
+  const float a[5] = {0.0f, 0.0f, -1.0f, -1.0f, 15.0f};
+  const float bnd[5] = {128.0f, 128.0f, 1.0f, 1.0f, 45.0f};
+  for (int d = 0; d < 5; ++d) {
+    p->q[d] = q[d];
+    p->init_a[d] = a[d];
+    p->init_b[d] = bnd[d];
+  }
+  p->init_kind = PPF_INIT_UNIFORM;
+  p->lg_r[0] = p->lg_r[1] = p->lg_r[2] = 1.0f;
+  p->resample = PPF_RESAMPLE_SYSTEMATIC;
+  p->ess_threshold = INFINITY;
+  p->rna_group = 256;
+  p->rna_exchange = 0.1f;
+  p->seed = 1;
+  p->track_id = 0;
+  return PPF_OK;
+}
+
+int ppf_workspace_bytes(const ppf_params* p, size_t* bytes) {
+  if (!bytes || !validate(p).empty()) return PPF_EINVAL;
+  *bytes = carve(p, nullptr, nullptr);
+  return PPF_OK;
+}
+
+int ppf_create(const ppf_params* p, void* workspace, size_t bytes, void* hip_stream,
+               ppf_handle* out) {
+  if (!out) return PPF_EINVAL;
+  *out = nullptr;
+  if (!validate(p).empty() || !workspace) return PPF_EINVAL;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return PPF_EINVAL;
+  const size_t need = carve(p, nullptr, nullptr);
+  if (bytes < need) return PPF_ENOMEM;
+  ppf_ctx* h = new (std::nothrow) ppf_ctx();
+  if (!h) return PPF_ENOMEM;
+  h->p = *p;
+  h->m = make_model(p);
+  carve(p, static_cast<char*>(workspace), &h->b);
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  const int rc = h->run(kKInit, [&] { return ppf::launch_init(h->m, h->b, h->stream); });
+  if (rc != PPF_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return PPF_OK;
+}
+
+int ppf_reset(ppf_handle h) {
+  if (!h) return PPF_ESTATE;
+  return h->run(kKInit, [&] { return ppf::launch_init(h->m, h->b, h->stream); });
+}
+
+int ppf_step(ppf_handle h, const float* obs_dev) {
+  if (!h) return PPF_ESTATE;
+  if (!obs_dev) return h->fail(PPF_EINVAL, "null observation");
+  int rc = h->run(kKStep, [&] { return ppf::launch_step(h->m, h->b, obs_dev, h->stream); });
+  if (rc) return rc;
+  if (h->b.nr2) {
+    rc = h->run(kKReduce, [&] { return ppf::launch_reduce(h->m, h->b, 0, h->stream); });
+    if (rc) return rc;
+  }
+  rc = h->run(kKFinalize, [&] { return ppf::launch_finalize(h->m, h->b, 0, 0.0, h->stream); });
+  if (rc) return rc;
+  const ppf::WeightSrc w = h->filter_weights();
+  if (h->p.resample == PPF_RESAMPLE_RNA)
+    return h->run(kKRna, [&] { return ppf::launch_rna(h->m, h->b, w, nullptr, h->stream); });
+  rc = h->run(kKScan, [&] { return ppf::launch_scan(h->m, h->b, w, h->stream); });
+  if (rc) return rc;
+  return h->run(kKHeavy, [&] { return ppf::launch_heavy(h->m, h->b, w, h->stream); });
+}
+
+int ppf_sync(ppf_handle h) {
+  if (!h) return PPF_ESTATE;
+  Ctrl c;
+  int rc = h->read_ctrl(&c);
+  if (rc) return rc;
+  if (c.rolled_back) {
+    const int32_t zero = 0;
+    hipError_t e = hipMemcpyAsync(&h->b.ctrl->rolled_back, &zero, sizeof zero,
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "clearing roll-back report");
+    return h->fail(PPF_ENUMERIC, "a step had no finite normaliser and was rolled back");
+  }
+  return PPF_OK;
+}
+
+int ppf_estimate(ppf_handle h, double mean[5], double* ess) {
+  if (!h) return PPF_ESTATE;
+  const int rc = ppf_sync(h);
+  if (rc != PPF_OK && rc != PPF_ENUMERIC) return rc;
+  Ctrl c;
+  const int rc2 = h->read_ctrl(&c);
+  if (rc2) return rc2;
+  if (mean)
+    for (int d = 0; d < 5; ++d) mean[d] = c.mean[d];
+  if (ess) *ess = c.ess;
+  return rc;
+}
+
+int ppf_loglik(ppf_handle h, double* cum, double* last) {
+  if (!h) return PPF_ESTATE;
+  const int rc = ppf_sync(h);
+  if (rc != PPF_OK && rc != PPF_ENUMERIC) return rc;
+  Ctrl c;
+  const int rc2 = h->read_ctrl(&c);
+  if (rc2) return rc2;
+  if (cum) *cum = c.cum;
+  if (last) *last = c.delta;
+  return rc;
+}
+
+int ppf_stats(ppf_handle h, ppf_stats_t* out) {
+  if (!h) return PPF_ESTATE;
+  if (!out) return PPF_EINVAL;
+  Ctrl c;
+  int rc = h->read_ctrl(&c);
+  if (rc) return rc;
+  out->k = c.k;
+  out->resampled = c.resampled;
+  out->rolled_back = c.rolled_back;
+  out->ess = c.ess;
+  out->max_logw = c.m;
+  out->log_sum = c.log_sum;
+  out->delta = c.delta;
+  out->cum = c.cum;
+  for (int d = 0; d < 5; ++d) out->mean[d] = c.mean[d];
+  if (c.rolled_back) {
+    const int32_t zero = 0;
+    hipError_t e = hipMemcpyAsync(&h->b.ctrl->rolled_back, &zero, sizeof zero,
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "clearing roll-back report");
+  }
+  return PPF_OK;
+}
+
+int ppf_get_particles(ppf_handle h, float* state_host, double* logw_host, int32_t* anc_host) {
+  if (!h) return PPF_ESTATE;
+  Ctrl c;
+  int rc = h->read_ctrl(&c);
+  if (rc) return rc;
+  const int64_t n = h->m.n;
+  hipError_t e = hipSuccess;
+  if (state_host)
+    e = hipMemcpyAsync(state_host, c.cur ? h->b.X1 : h->b.X0, sizeof(float) * 5 * n,
+                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess && logw_host) {
+    rc = h->run(kKLogw, [&] { return ppf::launch_logw(h->m, h->b, h->stream); });
+    if (rc) return rc;
+    e = hipMemcpyAsync(logw_host, h->b.lw64, sizeof(double) * n, hipMemcpyDeviceToHost,
+                       h->stream);
+  }
+  const bool resampled = c.mode == ppf::kModeSys || c.mode == ppf::kModeRna;
+  if (e == hipSuccess && anc_host && resampled)
+    e = hipMemcpyAsync(anc_host, h->b.anc, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
+                       h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "copying particles");
+  if (anc_host && !resampled)
+    for (int64_t i = 0; i < n; ++i) anc_host[i] = (int32_t)i;
+  return PPF_OK;
+}
+
+int ppf_set_particles(ppf_handle h, const float* state_host, const double* logw_host) {
+  if (!h) return PPF_ESTATE;
+  if (!state_host || !logw_host) return h->fail(PPF_EINVAL, "null particles");
+  Ctrl c;
+  int rc = h->read_ctrl(&c);
+  if (rc) return rc;
+  const int64_t n = h->m.n;
+  hipError_t e = hipMemcpyAsync(c.cur ? h->b.X1 : h->b.X0, state_host, sizeof(float) * 5 * n,
+                                hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->b.lw64, logw_host, sizeof(double) * n, hipMemcpyHostToDevice,
+                       h->stream);
+  if (e == hipSuccess) e = ppf::launch_set_mode(h->b, ppf::kModeSet, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "setting particles");
+  return PPF_OK;
+}
+
+int ppf_gather(ppf_handle h, float* out_dev) {
+  if (!h) return PPF_ESTATE;
+  if (!out_dev) return h->fail(PPF_EINVAL, "null output");
+  return h->run(kKGather, [&] { return ppf::launch_gather(h->m, h->b, out_dev, h->stream); });
+}
+
+int ppf_profile_enable(ppf_handle h, int on) {
+  if (!h) return PPF_ESTATE;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(PPF_EDEVICE, "sync");
+  h->collect();
+  h->prof = on != 0;
+  if (h->prof)
+    for (int k = 0; k < kNumKernels; ++k) {
+      h->total_ms[k] = 0.0;
+      h->launches[k] = 0;
+    }
+  return PPF_OK;
+}
+
+int ppf_profile_read(ppf_handle h, ppf_kernel_time* out, int max_entries, int* n_entries) {
+  if (!h) return PPF_ESTATE;
+  if (!n_entries || (max_entries > 0 && !out)) return PPF_EINVAL;
+  const int rc = h->collect();
+  if (rc) return rc;
+  int cnt = 0;
+  for (int k = 0; k < kNumKernels && cnt < max_entries; ++k) {
+    if (!h->launches[k]) continue;
+    std::snprintf(out[cnt].name, sizeof out[cnt].name, "%s", kKernelNames[k]);
+    out[cnt].launches = h->launches[k];
+    out[cnt].total_ms = h->total_ms[k];
+    ++cnt;
+  }
+  *n_entries = cnt;
+  return PPF_OK;
+}
+
+int ppf_destroy(ppf_handle h) {
+  if (!h) return PPF_OK;
+  (void)hipStreamSynchronize(h->stream);
+  h->collect();
+  delete h;
+  return PPF_OK;
+}
+
+const char* ppf_error_string(int code) {
+  switch (code) {
+    case PPF_OK: return "ok";
+    case PPF_EINVAL: return "invalid argument";
+    case PPF_ENOMEM: return "workspace too small";
+    case PPF_EDEVICE: return "HIP device error";
+    case PPF_ESTATE: return "invalid handle state";
+    case PPF_ENUMERIC: return "non-finite normaliser: step rolled back";
+    case PPF_ENOTIMPL: return "not implemented";
+    default: return "unknown error";
+  }
+}
+
+const char* ppf_last_error(ppf_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+int ppf_philox4x32_10(uint64_t seed, const uint32_t* ctr_dev, uint32_t* out_dev, int64_t n,
+                      void* hip_stream) {
+  if (n < 0 || (n > 0 && (!ctr_dev || !out_dev))) return PPF_EINVAL;
+  const hipError_t e =
+      ppf::launch_philox(seed, ctr_dev, out_dev, n, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
+}
+
+int ppf_resample_scratch_bytes(int64_t n, size_t* bytes) {
+  if (!bytes || n < 1 || n > 2147483647LL) return PPF_EINVAL;
+  *bytes = carve_scratch(n, nullptr, nullptr);
+  return PPF_OK;
+}
+
+namespace {
+
+int standalone_prepare(const float* logw_dev, int64_t n, void* scratch, size_t scratch_bytes,
+                       Model* m, Buffers* b) {
+  if (!logw_dev || !scratch || n < 1 || n > 2147483647LL) return PPF_EINVAL;
+  if (reinterpret_cast<uintptr_t>(scratch) % kAlign != 0) return PPF_EINVAL;
+  if (scratch_bytes < carve_scratch(n, nullptr, nullptr)) return PPF_ENOMEM;
+  *m = Model{};
+  m->n = n;
+  m->inv_n = 1.0 / (double)n;
+  m->log_n = std::log((double)n);
+  carve_scratch(n, static_cast<char*>(scratch), b);
+  return PPF_OK;
+}
+
+}  // namespace
+
+int ppf_resample_systematic(const float* logw_dev, int64_t n, double u, int32_t* anc_dev,
+                            void* scratch, size_t scratch_bytes, void* hip_stream) {
+  if (!anc_dev || !(u >= 0.0 && u < 1.0)) return PPF_EINVAL;
+  Model m;
+  Buffers b;
+  const int rc = standalone_prepare(logw_dev, n, scratch, scratch_bytes, &m, &b);
+  if (rc) return rc;
+  b.anc = anc_dev;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  ppf::WeightSrc w{logw_dev, logw_dev, b.zeros, b.zeros, 1, 0};
+  hipError_t e = ppf::launch_records(m, b, logw_dev, s);
+  if (e == hipSuccess && b.nr2) e = ppf::launch_reduce(m, b, 1, s);
+  if (e == hipSuccess) e = ppf::launch_finalize(m, b, 1, u, s);
+  if (e == hipSuccess) e = ppf::launch_scan(m, b, w, s);
+  if (e == hipSuccess) e = ppf::launch_heavy(m, b, w, s);
+  return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
+}
+
+int ppf_resample_rna(const float* logw_dev, int64_t n, int32_t group, int32_t moved,
+                     const double* u_dev, int32_t* anc_dev, double* lwg_dev, void* scratch,
+                     size_t scratch_bytes, void* hip_stream) {
+  if (!anc_dev || !lwg_dev || !u_dev) return PPF_EINVAL;
+  if (group < 1 || group > ppf::kMaxGroup || n % group != 0) return PPF_EINVAL;
+  if (moved < 0 || moved > group) return PPF_EINVAL;
+  Model m;
+  Buffers b;
+  const int rc = standalone_prepare(logw_dev, n, scratch, scratch_bytes, &m, &b);
+  if (rc) return rc;
+  m.group = group;
+  m.moved = moved;
+  m.G = (int32_t)(n / group);
+  m.inv_group = 1.0 / (double)group;
+  b.anc = anc_dev;
+  b.lwg = lwg_dev;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  ppf::WeightSrc w{logw_dev, logw_dev, b.zeros, b.zeros, 1, 0};
+  hipError_t e = ppf::launch_records(m, b, logw_dev, s);
+  if (e == hipSuccess && b.nr2) e = ppf::launch_reduce(m, b, 1, s);
+  if (e == hipSuccess) e = ppf::launch_finalize(m, b, 1, 0.0, s);
+  if (e == hipSuccess) e = ppf::launch_rna(m, b, w, u_dev, s);
+  return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
+}
+
+}  // extern "C"

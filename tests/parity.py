@@ -1,0 +1,114 @@
+"""Teacher-forced comparison of one GPU filter step with the FP64 oracle.
+
+Each check feeds the oracle the GPU's own fp32 inputs (widened exactly), so it
+measures one step's arithmetic only:
+  propagate   oracle propagates the GPU's previous states with the same
+              Philox streams; the GPU state must match to fp32 rounding;
+  weights     oracle evaluates Eq. 4 on the GPU's propagated states with the
+              carried log weights the GPU used; normalised weights within
+              1e-5 relative where l - m >= -40 (else GPU weight < 1e-17),
+              MMSE estimate within 1e-3, log-likelihood increment within 1e-4;
+  ancestors   oracle resamples the GPU's normalised weights with the same
+              uniform; ancestors must be identical for every slot whose
+              uniform is farther than `band` from a CDF step; mismatches
+              inside the band are counted and returned.
+"""
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+import oracle
+
+WEIGHT_RTOL = 1e-5
+MEAN_ATOL = 1e-3
+DELTA_ATOL = 1e-4
+
+
+@dataclass
+class GpuState:
+    x: np.ndarray       # (5, N) float32
+    lw: np.ndarray      # (N,) float64 normalised log weights of the last step
+    anc: np.ndarray     # (N,) int32
+    resampled: bool
+    lw_next: np.ndarray  # carried log weight the next step uses
+
+
+def snapshot(f, n, lw_next):
+    x, lw, anc = f.particles()
+    st = f.stats()
+    return GpuState(x, lw, anc, bool(st["resampled"]), lw_next), st
+
+
+def check_propagate(m, k, prev: GpuState, x_gpu):
+    parent = prev.anc if prev.resampled else None
+    xo = oracle.propagate(m, k, prev.x.astype(np.float64), parent)
+    tol = np.spacing(np.abs(xo).astype(np.float32)).astype(np.float64) + 1e-6
+    err = np.abs(x_gpu.astype(np.float64) - xo)
+    bad = err > tol
+    assert not bad.any(), f"propagate: {bad.sum()} values off, worst {err.max():.3e}"
+    return err.max()
+
+
+def check_weights(m, obs, lw_in, x_gpu, lw_gpu, st):
+    l = lw_in + oracle.loglik(m, obs, x_gpu.astype(np.float64))
+    w, s = oracle.normalize(l)
+    keep = l - s["m"] >= -40.0
+    rel = np.abs(np.exp(lw_gpu[keep]) - w[keep]) / w[keep]
+    assert rel.max() <= WEIGHT_RTOL, f"weights: worst relative error {rel.max():.3e}"
+    assert np.all(np.exp(lw_gpu[~keep]) < 1e-17)
+    mean = oracle.estimate(w, x_gpu.astype(np.float64))
+    assert np.abs(mean - st["mean"]).max() <= MEAN_ATOL, (mean, st["mean"])
+    assert abs(s["delta"] - st["delta"]) <= DELTA_ATOL, (s["delta"], st["delta"])
+    assert math.isclose(s["ess"], st["ess"], rel_tol=1e-6)
+    assert (st["ess"] < m.ess_threshold) == bool(st["resampled"])
+    return rel.max(), s
+
+
+def band_distance(u_slots, C):
+    """Distance of each slot uniform to the nearest CDF step."""
+    j = np.searchsorted(C, u_slots)
+    lo = np.abs(u_slots - C[np.clip(j - 1, 0, C.size - 1)])
+    hi = np.abs(C[np.clip(j, 0, C.size - 1)] - u_slots)
+    return np.minimum(lo, hi)
+
+
+def check_systematic(w_gpu, u, anc_gpu, band=1e-9):
+    """Returns (mismatches inside band, inside 1e-10)."""
+    n = w_gpu.size
+    ao = oracle.resample_systematic(w_gpu, u)
+    mism = ao != anc_gpu
+    if not mism.any():
+        return 0, 0
+    C = np.cumsum(w_gpu)
+    d = band_distance((np.arange(n) + u) / n, C[:-1])
+    outside = mism & (d > band)
+    assert not outside.any(), f"ancestors: {outside.sum()} mismatches outside band {band}"
+    return int(mism.sum()), int((mism & (d > 1e-10)).sum())
+
+
+def check_rna(w_gpu, group, moved, u_g, anc_gpu, band=1e-9):
+    n = w_gpu.size
+    ao, lwg, lws = oracle.resample_rna(w_gpu, group, moved, u_g)
+    mism = ao != anc_gpu
+    if mism.any():
+        G = n // group
+        d = np.full(n, np.inf)
+        local = np.empty(n)
+        for g in range(G):
+            ws = w_gpu[g * group:(g + 1) * group]
+            W = ws.sum()
+            if W > 0:
+                C = np.cumsum(ws) / W
+                ul = (np.arange(group) + u_g[g]) / group
+                local[g * group:(g + 1) * group] = band_distance(ul, C[:-1])
+            else:
+                local[g * group:(g + 1) * group] = np.inf
+        for g in range(G):
+            prev = (g - 1) % G
+            for l in range(group):
+                src = prev if l >= group - moved else g
+                d[g * group + l] = local[src * group + l]
+        outside = mism & (d > band)
+        assert not outside.any(), f"RNA ancestors: {outside.sum()} mismatches outside band"
+    return int(mism.sum()), lws

@@ -1,0 +1,111 @@
+"""The C ABI library loads, exports every function include/ppf.h declares, and
+its host-side logic (parameter validation, sizes, error codes) behaves as
+documented. No test here touches a GPU."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_1310_5045_amd as ppf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ppf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ppf_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ppf.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+    # the binding declares exactly the ABI
+    assert set(names) == set(ppf._SIGS)
+
+
+def test_params_layout_and_defaults():
+    L = ppf.lib()
+    assert L.ppf_params_size() == ctypes.sizeof(ppf.Params) == 152
+    p = ppf.params()
+    assert p.state_dim == 5 and p.n_particles == 4096 and p.width == 128
+    assert math.isinf(p.ess_threshold) and p.resample == ppf.RESAMPLE_SYSTEMATIC
+    assert ppf.patch_size(p) == 9
+    assert ppf.patch_size(ppf.params(psf_sigma=2.0)) == 13
+    assert L.ppf_version().decode().startswith("ppf-mi355x")
+
+
+@pytest.mark.parametrize("bad", [
+    dict(state_dim=4), dict(n_particles=0), dict(n_particles=1 << 31), dict(patch=8),
+    dict(patch=27), dict(psf_sigma=0.0), dict(noise_sigma=-1.0), dict(width=0),
+    dict(resample=1, rna_group=300), dict(resample=1, rna_group=2048, n_particles=4096),
+    dict(resample=1, rna_exchange=1.0), dict(obs_model=7), dict(init_kind=9),
+    dict(q=(0.5, 0.5, -0.1, 0.1, 1.0)), dict(ess_threshold=float("nan")),
+    dict(psf_sigma=0.2, patch=25), dict(obs_model=1, lg_r=(1.0, 0.0, 1.0)), dict(reserved=1),
+])
+def test_invalid_parameters_are_rejected(bad):
+    p = ppf.params(**bad)
+    with pytest.raises(ppf.PPFError) as e:
+        ppf.workspace_bytes(p)
+    assert e.value.code == ppf.PPF_EINVAL
+
+
+def test_workspace_bytes_scale_with_n():
+    small = ppf.workspace_bytes(ppf.params(n_particles=4096))
+    big = ppf.workspace_bytes(ppf.params(n_particles=38_000_000, width=1024, height=1024,
+                                         psf_sigma=2.0))
+    assert small < 1 << 20
+    # two state buffers (40 B) + two log-weight buffers (8 B) + ancestors (4 B)
+    # + fp64 staging (8 B) per particle, plus small per-block records
+    per = big / 38e6
+    assert 60 <= per <= 64, per
+    rna = ppf.workspace_bytes(ppf.params(n_particles=1 << 20, resample=1, rna_group=256))
+    assert rna > ppf.workspace_bytes(ppf.params(n_particles=1 << 20))
+
+
+def test_null_handles_and_error_strings():
+    L = ppf.lib()
+    assert L.ppf_step(None, None) == ppf.PPF_ESTATE
+    assert L.ppf_sync(None) == ppf.PPF_ESTATE
+    assert L.ppf_reset(None) == ppf.PPF_ESTATE
+    assert L.ppf_destroy(None) == ppf.PPF_OK
+    assert L.ppf_last_error(None) == b"null handle"
+    for code in range(0, -7, -1):
+        assert ppf.error_string(code) != "unknown error"
+    assert ppf.error_string(-99) == "unknown error"
+    h = ctypes.c_void_p()
+    assert L.ppf_create(None, None, 0, None, ctypes.byref(h)) == ppf.PPF_EINVAL
+    p = ppf.params()
+    # misaligned or too small workspaces are refused before any device call
+    assert L.ppf_create(ctypes.byref(p), ctypes.c_void_p(0x1001), 1 << 30, None,
+                        ctypes.byref(h)) == ppf.PPF_EINVAL
+    assert L.ppf_create(ctypes.byref(p), ctypes.c_void_p(0x1000), 16, None,
+                        ctypes.byref(h)) == ppf.PPF_ENOMEM
+
+
+def test_standalone_argument_checks():
+    L = ppf.lib()
+    n = ctypes.c_size_t()
+    assert L.ppf_resample_scratch_bytes(1000, ctypes.byref(n)) == 0 and n.value > 0
+    assert L.ppf_resample_scratch_bytes(0, ctypes.byref(n)) == ppf.PPF_EINVAL
+    assert L.ppf_philox4x32_10(1, None, None, -1, None) == ppf.PPF_EINVAL
+    assert L.ppf_philox4x32_10(1, None, None, 0, None) == ppf.PPF_OK
+    assert L.ppf_resample_systematic(None, 10, 0.5, None, None, 0, None) == ppf.PPF_EINVAL
+    assert L.ppf_resample_rna(ctypes.c_void_p(256), 10, 3, 0, ctypes.c_void_p(256),
+                              ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                              1 << 20, None) == ppf.PPF_EINVAL
+
+
+def test_product_package_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1310_5045_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                for needle in ("import oracle", "from oracle", "ppf_oracle", "_liboracle", "orc_"):
+                    assert needle not in text, (f, needle)
