@@ -73,6 +73,8 @@ def lib():
         L.orc_rna_uniform.restype = d
         L.orc_init.argtypes = [P(_Model), vp, vp]
         L.orc_propagate.argtypes = [P(_Model), i64, vp, vp, vp]
+        L.orc_init_indexed.argtypes = [P(_Model), i64, vp, vp]
+        L.orc_propagate_indexed.argtypes = [P(_Model), i64, vp, vp, vp]
         L.orc_loglik_spot.argtypes = [P(_Model), vp, vp, vp]
         L.orc_loglik_lg.argtypes = [P(_Model), vp, vp, vp]
         L.orc_normalize.argtypes = [i64, vp, vp, vp]
@@ -198,6 +200,28 @@ def propagate(m: Model, k: int, x_prev: np.ndarray, parent: Optional[np.ndarray]
     par = None if parent is None else np.ascontiguousarray(parent, dtype=np.int32)
     xn = np.empty((5, m.n))
     lib().orc_propagate(ctypes.byref(c), k, _ptr(xp), _ptr(par), _ptr(xn))
+    return xn
+
+
+def init_indexed(m: Model, n_total: int, index: np.ndarray) -> np.ndarray:
+    """Initial states of particles `index` of a run with n_total particles;
+    m.n must equal len(index)."""
+    c = m.c()
+    idx = np.ascontiguousarray(index, dtype=np.int64)
+    assert idx.size == m.n
+    x = np.empty((5, m.n))
+    lib().orc_init_indexed(ctypes.byref(c), n_total, _ptr(idx), _ptr(x))
+    return x
+
+
+def propagate_indexed(m: Model, k: int, index: np.ndarray, parents: np.ndarray) -> np.ndarray:
+    """Propagate particles `index` (their random numbers) from the given
+    parent states (5, len(index)); m.n must equal len(index)."""
+    c = m.c()
+    idx = np.ascontiguousarray(index, dtype=np.int64)
+    xp = np.ascontiguousarray(parents, dtype=np.float64).reshape(5, m.n)
+    xn = np.empty((5, m.n))
+    lib().orc_propagate_indexed(ctypes.byref(c), k, _ptr(idx), _ptr(xp), _ptr(xn))
     return xn
 
 

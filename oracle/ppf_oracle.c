@@ -148,60 +148,70 @@ static void strat_cell(int64_t i, int64_t n, int t, uint32_t* cx, uint32_t* cy) 
   *cy = y;
 }
 
+/* Initial state of particle i of n (stride: distance between components). */
+static void init_one(const orc_model* m, int64_t i, int64_t n, double* x, int64_t stride) {
+  uint32_t r0[4], r1[4];
+  if (m->init_kind == 1) {
+    double z[5];
+    five_normals(m, (uint32_t)i, 0u, PURPOSE_INIT, z);
+    for (int d = 0; d < 5; ++d) x[d * stride] = m->init_a[d] + m->init_b[d] * z[d];
+    return;
+  }
+  draw(m, (uint32_t)i, 0u, PURPOSE_INIT, 0u, r0);
+  draw(m, (uint32_t)i, 0u, PURPOSE_INIT, 1u, r1);
+  double f[5] = {orc_u24_open_hi(r0[0]), orc_u24_open_hi(r0[1]), orc_u24_open_hi(r0[2]),
+                 orc_u24_open_hi(r0[3]), orc_u24_open_hi(r1[0])};
+  if (m->init_kind == 2) {
+    const int t = strat_bits(n);
+    uint32_t cx, cy;
+    strat_cell(i, n, t, &cx, &cy);
+    f[0] = ((double)cx + f[0]) / ldexp(1.0, (t + 1) / 2);
+    f[1] = ((double)cy + f[1]) / ldexp(1.0, t / 2);
+  }
+  for (int d = 0; d < 5; ++d) x[d * stride] = m->init_a[d] + (m->init_b[d] - m->init_a[d]) * f[d];
+}
+
 /* Algorithm 1, k = 0: w_0 = 1/N and x_0 drawn from the initial density. */
 void orc_init(const orc_model* m, double* x, double* lw) {
   const int64_t n = m->n;
-  const int t = strat_bits(n);
-  const int ax = (t + 1) / 2, ay = t / 2;
   for (int64_t i = 0; i < n; ++i) {
-    if (m->init_kind == 2) {
-      uint32_t r0[4], r1[4], cx, cy;
-      draw(m, (uint32_t)i, 0u, PURPOSE_INIT, 0u, r0);
-      draw(m, (uint32_t)i, 0u, PURPOSE_INIT, 1u, r1);
-      strat_cell(i, n, t, &cx, &cy);
-      const double fx = ((double)cx + orc_u24_open_hi(r0[0])) / ldexp(1.0, ax);
-      const double fy = ((double)cy + orc_u24_open_hi(r0[1])) / ldexp(1.0, ay);
-      x[0 * n + i] = m->init_a[0] + (m->init_b[0] - m->init_a[0]) * fx;
-      x[1 * n + i] = m->init_a[1] + (m->init_b[1] - m->init_a[1]) * fy;
-      const uint32_t word[3] = {r0[2], r0[3], r1[0]};
-      for (int d = 2; d < 5; ++d)
-        x[d * n + i] = m->init_a[d] + (m->init_b[d] - m->init_a[d]) * orc_u24_open_hi(word[d - 2]);
-    } else if (m->init_kind == 0) {
-      uint32_t r0[4], r1[4];
-      draw(m, (uint32_t)i, 0u, PURPOSE_INIT, 0u, r0);
-      draw(m, (uint32_t)i, 0u, PURPOSE_INIT, 1u, r1);
-      const uint32_t word[5] = {r0[0], r0[1], r0[2], r0[3], r1[0]};
-      for (int d = 0; d < 5; ++d)
-        x[d * n + i] = m->init_a[d] + (m->init_b[d] - m->init_a[d]) * orc_u24_open_hi(word[d]);
-    } else {
-      double z[5];
-      five_normals(m, (uint32_t)i, 0u, PURPOSE_INIT, z);
-      for (int d = 0; d < 5; ++d) x[d * n + i] = m->init_a[d] + m->init_b[d] * z[d];
-    }
+    init_one(m, i, n, x + i, n);
     lw[i] = -log((double)n);
   }
+}
+
+void orc_init_indexed(const orc_model* m, int64_t n_total, const int64_t* index, double* x) {
+  for (int64_t j = 0; j < m->n; ++j) init_one(m, index[j], n_total, x + j, m->n);
 }
 
 /* ---------------------------------------------------------- propagate */
 
 /* Near-constant-velocity dynamics (Section 6.1) with unit time step:
  * position += velocity, then Gaussian noise with sds q on every component. */
+static void propagate_one(const orc_model* m, int64_t k, int64_t i, const double* x_prev,
+                          int64_t p, double* x_new, int64_t j) {
+  const int64_t n = m->n;
+  double z[5];
+  five_normals(m, (uint32_t)i, (uint32_t)k, PURPOSE_PROPAGATE, z);
+  const double px = x_prev[0 * n + p], py = x_prev[1 * n + p];
+  const double pvx = x_prev[2 * n + p], pvy = x_prev[3 * n + p];
+  const double pI = x_prev[4 * n + p];
+  x_new[0 * n + j] = px + pvx + m->q[0] * z[0];
+  x_new[1 * n + j] = py + pvy + m->q[1] * z[1];
+  x_new[2 * n + j] = pvx + m->q[2] * z[2];
+  x_new[3 * n + j] = pvy + m->q[3] * z[3];
+  x_new[4 * n + j] = pI + m->q[4] * z[4];
+}
+
 void orc_propagate(const orc_model* m, int64_t k, const double* x_prev, const int32_t* parent,
                    double* x_new) {
-  const int64_t n = m->n;
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t p = parent ? (int64_t)parent[i] : i;
-    double z[5];
-    five_normals(m, (uint32_t)i, (uint32_t)k, PURPOSE_PROPAGATE, z);
-    const double px = x_prev[0 * n + p], py = x_prev[1 * n + p];
-    const double pvx = x_prev[2 * n + p], pvy = x_prev[3 * n + p];
-    const double pI = x_prev[4 * n + p];
-    x_new[0 * n + i] = px + pvx + m->q[0] * z[0];
-    x_new[1 * n + i] = py + pvy + m->q[1] * z[1];
-    x_new[2 * n + i] = pvx + m->q[2] * z[2];
-    x_new[3 * n + i] = pvy + m->q[3] * z[3];
-    x_new[4 * n + i] = pI + m->q[4] * z[4];
-  }
+  for (int64_t i = 0; i < m->n; ++i)
+    propagate_one(m, k, i, x_prev, parent ? (int64_t)parent[i] : i, x_new, i);
+}
+
+void orc_propagate_indexed(const orc_model* m, int64_t k, const int64_t* index,
+                           const double* parents, double* x_new) {
+  for (int64_t j = 0; j < m->n; ++j) propagate_one(m, k, index[j], parents, j, x_new, j);
 }
 
 /* --------------------------------------------------------- likelihood */

@@ -60,10 +60,19 @@ double orc_rna_uniform(const orc_model* m, int64_t g, int64_t k);
 /* Algorithm 1 initialisation: x (5*n, SoA), lw (n) = -log N. */
 void orc_init(const orc_model* m, double* x, double* lw);
 
+/* Initial states of the particles index[0..m->n) of a run with n_total
+ * particles (5 * m->n SoA). */
+void orc_init_indexed(const orc_model* m, int64_t n_total, const int64_t* index, double* x);
+
 /* SIS draw of frame k under the bootstrap proposal: x_new[i] from parent
  * x_prev[parent[i]] (parent NULL: identity). SoA 5*n. */
 void orc_propagate(const orc_model* m, int64_t k, const double* x_prev, const int32_t* parent,
                    double* x_new);
+
+/* The same for the particles index[0..m->n): particle j is index[j] of the
+ * run (its random numbers) and starts from parents[:, j] (5 * m->n SoA). */
+void orc_propagate_indexed(const orc_model* m, int64_t k, const int64_t* index,
+                           const double* parents, double* x_new);
 
 /* log p(z | x) of Eq. 4 with its normalising constant, per particle. */
 void orc_loglik_spot(const orc_model* m, const float* frame, const double* x, double* ll);

@@ -170,7 +170,8 @@ def test_systematic_standalone_brute_force(ppf):
             if k.sum() == 0:
                 k[0] = 1
             fr = [Fraction(int(v), int(k.sum())) for v in k]
-            lw = torch.tensor(np.log(k.astype(np.float64) / k.sum()).astype(np.float32)).cuda()
+            with np.errstate(divide="ignore"):
+                lw = torch.tensor(np.log(k / k.sum()).astype(np.float32)).cuda()
             for lo, hi, anc in brute.systematic_pieces(fr):
                 if hi - lo < Fraction(1, 10**5):
                     continue  # pieces thinner than the fp32 weight rounding
@@ -211,7 +212,8 @@ def test_rna_standalone_vs_oracle(ppf):
     rng = np.random.default_rng(7)
     for n, group, moved in ((4096, 256, 25), (1024, 4, 1), (8192, 1024, 512), (512, 512, 0)):
         l = rng.normal(0, 2, n).astype(np.float32)
-        l[: group] = -np.inf  # an empty group
+        if n > group:
+            l[: group] = -np.inf  # an empty group keeps the identity map
         ug = rng.random(n // group)
         anc, lwg = ppf.resample_rna(torch.from_numpy(l).cuda(), group, moved,
                                     torch.from_numpy(ug).cuda())

@@ -213,3 +213,16 @@ def test_normalize_matches_exact_sums(orc):
     assert math.isclose(st["ess"], ess, rel_tol=1e-12)
     x = rng.normal(size=(5, 5000))
     assert np.allclose(orc.estimate(w, x), np.average(x, axis=1, weights=w), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("init_kind", [0, 1, 2])
+def test_indexed_entry_points_agree_with_whole_run(orc, init_kind):
+    n = 3001
+    m = model(orc, n=n, init_kind=init_kind, init_a=(0, 0, -1, -1, 15), init_b=(64, 32, 1, 1, 45))
+    x, _ = orc.init(m)
+    idx = np.array([0, 1, 255, 256, 2047, 2048, 3000, 1234])
+    ms = model(orc, n=idx.size, init_kind=init_kind, init_a=m.init_a, init_b=m.init_b)
+    assert np.array_equal(orc.init_indexed(ms, n, idx), x[:, idx])
+    parent = np.sort(np.random.default_rng(0).integers(0, n, n)).astype(np.int32)
+    xn = orc.propagate(m, 4, x, parent)
+    assert np.array_equal(orc.propagate_indexed(ms, 4, idx, x[:, parent[idx]]), xn[:, idx])
