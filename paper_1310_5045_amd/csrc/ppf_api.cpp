@@ -20,11 +20,9 @@ using ppf::Model;
 
 namespace {
 
-enum KernelId { kKStep, kKReduce, kKFinalize, kKScan, kKHeavy, kKRna, kKInit, kKGather, kKLogw,
-                kNumKernels };
-const char* const kKernelNames[kNumKernels] = {"k_step", "k_reduce", "k_finalize",
-                                               "k_scan", "k_heavy",  "k_rna",
-                                               "k_init", "k_gather", "k_logw"};
+enum KernelId { kKStep, kKMerge, kKAnc, kKAncHeavy, kKRna, kKInit, kKGather, kKLogw, kNumKernels };
+const char* const kKernelNames[kNumKernels] = {"k_step", "k_merge",  "k_anc",    "k_anc_heavy",
+                                               "k_rna",  "k_init",   "k_gather", "k_logw"};
 
 constexpr size_t kAlign = 256;
 
@@ -104,6 +102,10 @@ Model make_model(const ppf_params* p) {
   m.inv2s2 = 1.0 / (2.0 * s * s);
   m.inv2sig2 = 1.0 / (2.0 * sg * sg);
   m.lognorm_obs = (double)m.P * (double)m.P * std::log(sg * std::sqrt(2.0 * M_PI));
+  // ratio of consecutive 1-D Gaussian factors at unit pixel steps from -h
+  const int h = (m.P - 1) / 2;
+  for (int d = 0; d < ppf::kMaxPatch; ++d)
+    m.gstep[d] = d + 1 < m.P ? std::exp(-(2.0 * (double)(d - h) + 1.0) * m.inv2s2) : 0.0;
   m.lg_norm = 0.0;
   for (int d = 0; d < 3; ++d) {
     const double r = p->lg_r[d];
@@ -125,18 +127,29 @@ Model make_model(const ppf_params* p) {
 }
 
 int64_t record_blocks(int64_t n) { return (n + ppf::kBlock - 1) / ppf::kBlock; }
-int64_t level2_blocks(int64_t nb) {
-  return nb > ppf::kDirectRecords ? (nb < ppf::kReduceBlocks ? nb : ppf::kReduceBlocks) : 0;
+// Records per merge chunk: a multiple of 256, at most 2048 (so a chunk's sum
+// of 2^52-bounded integer weights stays below 2^63), aiming at <= 1024 chunks.
+int64_t merge_chunk(int64_t nb) {
+  int64_t per = (nb + 256 * 1024 - 1) / (256 * 1024);
+  if (per < 1) per = 1;
+  if (per > 8) per = 8;
+  return 256 * per;
 }
-int64_t scan_tiles(int64_t n) { return (n + ppf::kTile - 1) / ppf::kTile; }
+int64_t seg_count(int64_t n) { return (n + ppf::kSegItems - 1) / ppf::kSegItems; }
+int64_t queue_cap(int64_t n) { return (n + ppf::kSlotChunk - 1) / ppf::kSlotChunk + 1; }
+
+void shape(int64_t n, Buffers* bb) {
+  bb->nb = record_blocks(n);
+  bb->chunk = merge_chunk(bb->nb);
+  bb->nch = (bb->nb + bb->chunk - 1) / bb->chunk;
+  bb->nseg = seg_count(n);
+}
 
 // Carve the filter workspace; base may be null to only compute the size.
 size_t carve(const ppf_params* p, char* base, Buffers* b) {
   const int64_t n = p->n_particles;
   Buffers bb{};
-  bb.nb = record_blocks(n);
-  bb.nr2 = level2_blocks(bb.nb);
-  bb.ntiles = scan_tiles(n);
+  shape(n, &bb);
   const int64_t G = p->resample == PPF_RESAMPLE_RNA ? n / p->rna_group : 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -151,13 +164,14 @@ size_t carve(const ppf_params* p, char* base, Buffers* b) {
   bb.L1 = reinterpret_cast<float*>(take(sizeof(float) * n));
   bb.R0 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nb));
   bb.R1 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nb));
-  bb.R2 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * (bb.nr2 ? bb.nr2 : 1)));
+  bb.pfx = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * bb.nb));
+  bb.CR = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nch));
+  bb.cpre = reinterpret_cast<ppf::ChunkPre*>(take(sizeof(ppf::ChunkPre) * bb.nch));
   bb.anc = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
   bb.lw64 = reinterpret_cast<double*>(take(sizeof(double) * n));
   bb.lwg = reinterpret_cast<double*>(take(sizeof(double) * G));
-  bb.desc = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * bb.ntiles));
-  bb.heavy = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * 2 * bb.ntiles));
-  bb.zeros = nullptr;
+  bb.hq = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * queue_cap(n)));
+  bb.hq_cap = queue_cap(n);
   if (b) *b = bb;
   return off;
 }
@@ -165,9 +179,7 @@ size_t carve(const ppf_params* p, char* base, Buffers* b) {
 // Scratch of the standalone resamplers.
 size_t carve_scratch(int64_t n, char* base, Buffers* b) {
   Buffers bb{};
-  bb.nb = record_blocks(n);
-  bb.nr2 = level2_blocks(bb.nb);
-  bb.ntiles = scan_tiles(n);
+  shape(n, &bb);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char* ptr = base ? base + off : nullptr;
@@ -176,10 +188,11 @@ size_t carve_scratch(int64_t n, char* base, Buffers* b) {
   };
   bb.ctrl = reinterpret_cast<Ctrl*>(take(sizeof(Ctrl)));
   bb.R0 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nb));
-  bb.R2 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * (bb.nr2 ? bb.nr2 : 1)));
-  bb.zeros = reinterpret_cast<double*>(take(sizeof(double) * bb.nb));
-  bb.desc = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * bb.ntiles));
-  bb.heavy = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * 2 * bb.ntiles));
+  bb.pfx = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * bb.nb));
+  bb.CR = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nch));
+  bb.cpre = reinterpret_cast<ppf::ChunkPre*>(take(sizeof(ppf::ChunkPre) * bb.nch));
+  bb.hq = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * queue_cap(n)));
+  bb.hq_cap = queue_cap(n);
   if (b) *b = bb;
   return off;
 }
@@ -251,10 +264,10 @@ struct ppf_ctx {
     ppf::WeightSrc w{};
     w.val0 = b.L0;
     w.val1 = b.L1;
-    w.off0 = b.R0;
-    w.off1 = b.R1;
-    w.stride = ppf::kRec;
+    w.rec0 = b.R0;
+    w.rec1 = b.R1;
     w.use_cur = 1;
+    w.relative = 1;
     return w;
   }
 };
@@ -334,18 +347,14 @@ int ppf_step(ppf_handle h, const float* obs_dev) {
   if (!obs_dev) return h->fail(PPF_EINVAL, "null observation");
   int rc = h->run(kKStep, [&] { return ppf::launch_step(h->m, h->b, obs_dev, h->stream); });
   if (rc) return rc;
-  if (h->b.nr2) {
-    rc = h->run(kKReduce, [&] { return ppf::launch_reduce(h->m, h->b, 0, h->stream); });
-    if (rc) return rc;
-  }
-  rc = h->run(kKFinalize, [&] { return ppf::launch_finalize(h->m, h->b, 0, 0.0, h->stream); });
+  rc = h->run(kKMerge, [&] { return ppf::launch_merge(h->m, h->b, 0, 0.0, h->stream); });
   if (rc) return rc;
   const ppf::WeightSrc w = h->filter_weights();
   if (h->p.resample == PPF_RESAMPLE_RNA)
     return h->run(kKRna, [&] { return ppf::launch_rna(h->m, h->b, w, nullptr, h->stream); });
-  rc = h->run(kKScan, [&] { return ppf::launch_scan(h->m, h->b, w, h->stream); });
+  rc = h->run(kKAnc, [&] { return ppf::launch_anc(h->m, h->b, w, h->stream); });
   if (rc) return rc;
-  return h->run(kKHeavy, [&] { return ppf::launch_heavy(h->m, h->b, w, h->stream); });
+  return h->run(kKAncHeavy, [&] { return ppf::launch_anc_heavy(h->m, h->b, w, h->stream); });
 }
 
 int ppf_sync(ppf_handle h) {
@@ -558,12 +567,11 @@ int ppf_resample_systematic(const float* logw_dev, int64_t n, double u, int32_t*
   if (rc) return rc;
   b.anc = anc_dev;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  ppf::WeightSrc w{logw_dev, logw_dev, b.zeros, b.zeros, 1, 0};
+  const ppf::WeightSrc w{logw_dev, logw_dev, b.R0, b.R0, 0, 0};
   hipError_t e = ppf::launch_records(m, b, logw_dev, s);
-  if (e == hipSuccess && b.nr2) e = ppf::launch_reduce(m, b, 1, s);
-  if (e == hipSuccess) e = ppf::launch_finalize(m, b, 1, u, s);
-  if (e == hipSuccess) e = ppf::launch_scan(m, b, w, s);
-  if (e == hipSuccess) e = ppf::launch_heavy(m, b, w, s);
+  if (e == hipSuccess) e = ppf::launch_merge(m, b, 1, u, s);
+  if (e == hipSuccess) e = ppf::launch_anc(m, b, w, s);
+  if (e == hipSuccess) e = ppf::launch_anc_heavy(m, b, w, s);
   return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
 }
 
@@ -584,10 +592,9 @@ int ppf_resample_rna(const float* logw_dev, int64_t n, int32_t group, int32_t mo
   b.anc = anc_dev;
   b.lwg = lwg_dev;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  ppf::WeightSrc w{logw_dev, logw_dev, b.zeros, b.zeros, 1, 0};
+  const ppf::WeightSrc w{logw_dev, logw_dev, b.R0, b.R0, 0, 0};
   hipError_t e = ppf::launch_records(m, b, logw_dev, s);
-  if (e == hipSuccess && b.nr2) e = ppf::launch_reduce(m, b, 1, s);
-  if (e == hipSuccess) e = ppf::launch_finalize(m, b, 1, 0.0, s);
+  if (e == hipSuccess) e = ppf::launch_merge(m, b, 1, 0.0, s);
   if (e == hipSuccess) e = ppf::launch_rna(m, b, w, u_dev, s);
   return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
 }

@@ -11,31 +11,31 @@ namespace ppf {
 // Particles per k_step workgroup; also the granularity of the per-block
 // normalisation records and of the stored log-weight offsets.
 constexpr int kBlock = 256;
-// Systematic-resampling scan tiles: 256 threads x 8 particles.
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kTile = kScanThreads * kScanItems;
-// A tile whose particles own more than kHeavyFactor * kTile output slots is
-// handed to the load-balanced heavy pass instead of writing them itself.
-constexpr int kHeavyFactor = 4;
-constexpr int kHeavyBlocks = 1024;
-constexpr int kHeavyChunk = 8192;  // slots per workgroup iteration (32 per thread)
-// Normalisation record: m, S, S2, sum e*x[5] (doubles).
-constexpr int kRec = 8;
-// Up to this many level-1 records the finalize kernel merges them itself;
-// beyond, a grid-wide first merge produces at most kReduceBlocks records.
-constexpr int64_t kDirectRecords = 4096;
-constexpr int kReduceBlocks = 1024;
-// LDS image tile of one k_step workgroup, in floats.
+// LDS image tile of one k_step workgroup (floats) and its per-centre table of
+// patch sums of squares (doubles: row pass + centre pass).
 constexpr int kTileCap = 4096;
+constexpr int kSqCap = 1536;
 constexpr int kMaxPatch = 25;
 constexpr int kMaxGroup = 1024;
 
-// Fixed-point CDF: weights scaled by 2^60; descriptor words carry a 2-bit
-// status in bits 62-63 and the value in bits 0-61.
-constexpr uint64_t kFlagAggregate = 1ull << 62;
-constexpr uint64_t kFlagPrefix = 2ull << 62;
-constexpr uint64_t kValueMask = (1ull << 62) - 1;
+// Normalisation record of one block of kBlock particles (doubles):
+//   [0] m   maximum log weight of the block
+//   [1] B   sum of the fixed-point weights round(exp(l - m) 2^44) (an exact
+//           integer below 2^52, held in a double)
+//   [2] S2  sum exp(2 (l - m)); NaN marks a non-finite log weight
+//   [3..7]  sum exp(l - m) x_d for the five state components
+constexpr int kRec = 8;
+constexpr double kItemScale = 0x1p44;   // fixed-point weight of one particle
+constexpr double kCdfScale = 0x1p62;    // fixed-point scale of the global CDF
+// Chunk prefixes map 2^44-scaled weights to the 2^62-scaled CDF.
+constexpr double kItemToCdf = 0x1p18;
+
+// Systematic resampling: segments of kSegBlocks blocks; at most kSlotChunk
+// output slots per work item (larger slot ranges are split and queued).
+constexpr int kSegBlocks = 8;
+constexpr int kSegItems = kSegBlocks * kBlock;
+constexpr int kSlotChunk = 4096;
+constexpr int kHeavyGrid = 2048;
 
 enum Purpose : uint32_t { kInit = 1, kPropagate = 2, kResample = 3, kRna = 4 };
 
@@ -56,16 +56,24 @@ struct Ctrl {
   int32_t mode;         // Mode for the next step
   int32_t resampled;    // last committed step resampled
   int32_t rolled_back;  // steps rolled back since the host last read this
-  int32_t do_resample;  // set by finalize for the resampling kernels
-  int32_t heavy_count;  // heavy tiles queued by the scan
-  uint32_t tile_counter;
+  int32_t do_resample;  // set by the merge for the resampling kernels
+  int32_t heavy_count;  // slot chunks queued for k_anc_heavy
+  uint32_t ticket;      // arrival counter of the merge kernel's chunks
   uint32_t pad0;
   double m, log_sum, ess, delta, cum;
   double mean[5];
   double u;             // uniform of the systematic resampling
-  double pad1[16];
+  uint64_t total;       // fixed-point total weight (2^62 scale) of the CDF
+  double pad1[15];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
+
+// Prefix of one chunk of block records: P = fixed-point CDF before the chunk,
+// phi = factor from the chunk's relative integer weights to the CDF scale.
+struct ChunkPre {
+  uint64_t P;
+  double phi;
+};
 
 // Model constants derived on the host from ppf_params (all fp32 parameters
 // widened exactly).
@@ -83,6 +91,7 @@ struct Model {
   double inv2s2;         // 1 / (2 s^2)
   double inv2sig2;       // 1 / (2 sigma_xi^2)
   double lognorm_obs;    // P^2 log(sigma_xi sqrt(2 pi))
+  double gstep[kMaxPatch];  // exp(-(2 (d - h) + 1) / (2 s^2)), h = (P - 1) / 2
   double lg_inv2r2[3];
   double lg_norm;        // sum_d log(r_d sqrt(2 pi))
   double thr;            // ESS threshold
@@ -100,38 +109,41 @@ struct Buffers {
   float* L1;
   double* R0;    // per-block records, double-buffered
   double* R1;
-  double* R2;    // second-level records
+  uint64_t* pfx;    // per block: exclusive prefix of its chunk's relative weights
+  double* CR;       // per chunk: merged record (m, Q bits, S2, sum e x[5])
+  ChunkPre* cpre;   // per chunk: CDF prefix
   int32_t* anc;  // ancestors of the last resampling
   double* lw64;  // fp64 per-particle log weights (caller-set, or output staging)
   double* lwg;   // RNA per-group log(W_g / n)
-  uint64_t* desc;   // scan tile descriptors
-  uint64_t* heavy;  // heavy-tile queue: (tile, exclusive prefix) pairs
-  double* zeros;    // standalone resampling: zero offsets
-  int64_t nb;       // level-1 records = ceil(n / kBlock)
-  int64_t nr2;      // level-2 records (0: merge level 1 directly)
-  int64_t ntiles;   // scan tiles = ceil(n / kTile)
+  uint64_t* hq;  // queued slot chunks: (segment << 32) | chunk index
+  int64_t hq_cap;   // entries of hq
+  int64_t nb;       // block records = ceil(n / kBlock)
+  int64_t chunk;    // records per merge chunk (multiple of 256, at most 2048)
+  int64_t nch;      // merge chunks = ceil(nb / chunk)
+  int64_t nseg;     // resampling segments = ceil(n / kSegItems)
 };
 
-// Where the resampling kernels read log weights: value[i] + off[i / kBlock *
-// stride] - ctrl->delta. Filter: the stored (L, R) pair selected by ctrl->cur;
-// standalone: caller's fp32 log weights with zero offsets.
+// Where the resampling kernels read log weights. Filter: the stored value L
+// selected by ctrl->cur, relative to its block maximum; standalone: the
+// caller's absolute fp32 log weights (relative = 0). The particle's fixed-point
+// weight is round(exp(relative ? L : L - m_block) 2^44).
 struct WeightSrc {
   const float* val0;
   const float* val1;
-  const double* off0;
-  const double* off1;
-  int32_t stride;
+  const double* rec0;
+  const double* rec1;
   int32_t use_cur;
+  int32_t relative;
 };
 
 // Kernel launchers (ppf_kernels.hip). Each returns the launch status.
 hipError_t launch_init(const Model& m, const Buffers& b, hipStream_t s);
 hipError_t launch_step(const Model& m, const Buffers& b, const float* obs, hipStream_t s);
-hipError_t launch_reduce(const Model& m, const Buffers& b, int standalone, hipStream_t s);
-hipError_t launch_finalize(const Model& m, const Buffers& b, int standalone, double u_given,
-                           hipStream_t s);
-hipError_t launch_scan(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s);
-hipError_t launch_heavy(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s);
+hipError_t launch_merge(const Model& m, const Buffers& b, int standalone, double u_given,
+                        hipStream_t s);
+hipError_t launch_anc(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s);
+hipError_t launch_anc_heavy(const Model& m, const Buffers& b, const WeightSrc& w,
+                            hipStream_t s);
 hipError_t launch_rna(const Model& m, const Buffers& b, const WeightSrc& w, const double* u_dev,
                       hipStream_t s);
 hipError_t launch_gather(const Model& m, const Buffers& b, float* out, hipStream_t s);

@@ -1,17 +1,18 @@
 // HIP kernels of the SIR filter step for gfx950 (CDNA4, wave64).
 //
-// One step of Algorithm 1 (Section 2) is four launches on one stream, with
-// every decision taken on the device:
-//   k_step      gather parent + propagate (Section 6.1) + patch likelihood
-//               (Eqs. 3-4, Section 5.5) + per-workgroup log-sum-exp record
-//   k_reduce    first fixed-order merge of the records (large N only)
-//   k_finalize  fixed-order fp64 merge: normaliser, ESS, MMSE estimate,
-//               resampling decision and uniform; commit or roll back
-//   k_scan      systematic resampling: single-pass decoupled look-back scan
-//               of the normalised weights in 2^60 fixed point, and the
-//               ancestor walk for each tile's output slots
-//   k_heavy     load-balanced ancestor writing for tiles owning many slots
-//   (or k_rna   RNA of Section 3: one workgroup per group of particles)
+// One step of Algorithm 1 (Section 2) is three or four launches on one
+// stream, with every decision taken on the device:
+//   k_step       gather parent + propagate (Section 6.1) + patch likelihood
+//                (Eqs. 3-4, Section 5.5) + per-block normalisation record
+//   k_merge      fixed-order merge of the records; its last workgroup takes
+//                the normaliser, ESS, MMSE estimate, resampling decision and
+//                uniform, commits or rolls back the step, and writes the
+//                fixed-point CDF prefixes of the record chunks
+//   k_anc        systematic resampling: per segment of 2048 particles, the
+//                ancestors of the output slots whose uniforms fall in it,
+//                by a merge of slot positions and the segment's CDF
+//   k_anc_heavy  the remaining slot chunks of segments that own many slots
+//   (or k_rna    RNA of Section 3: one workgroup per group of particles)
 #include "ppf_internal.hpp"
 
 #include <cfloat>
@@ -70,105 +71,115 @@ __device__ __forceinline__ void box_muller64(uint32_t a, uint32_t b, double& z0,
   z1 = rad * s;
 }
 
-// -------------------------------------------------------------- reductions
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint64_t t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  return v;
+// ------------------------------------------------------ wave64 primitives
+// Cross-lane moves use DPP row shifts (row_shr:k, within rows of 16 lanes;
+// lanes whose source falls outside the row read 0 and are masked off by the
+// callers) and v_readlane for the four row results. Every helper must be
+// called with all 64 lanes active.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, true);
 }
 
-// Normalisation record: (m, S, S2, sum e x_d) with e = exp(l - m).
-struct Rec {
-  double m, S, S2, ex[5];
+template <int K>
+__device__ __forceinline__ int shr(int v) {
+  return (int)dpp32<0x110 + K>((uint32_t)v);
+}
+template <int K>
+__device__ __forceinline__ uint64_t shr(uint64_t v) {
+  return (uint64_t)dpp32<0x110 + K>((uint32_t)v) |
+         ((uint64_t)dpp32<0x110 + K>((uint32_t)(v >> 32)) << 32);
+}
+template <int K>
+__device__ __forceinline__ double shr(double v) {
+  return __longlong_as_double((long long)shr<K>((uint64_t)__double_as_longlong(v)));
+}
+
+__device__ __forceinline__ int readlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint64_t readlane(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+  return __longlong_as_double((long long)readlane((uint64_t)__double_as_longlong(v), l));
+}
+
+struct OpAdd {
+  template <class T>
+  __device__ __forceinline__ T operator()(T a, T b) const { return a + b; }
+};
+struct OpMax {
+  __device__ __forceinline__ double operator()(double a, double b) const { return fmax(a, b); }
+  __device__ __forceinline__ uint64_t operator()(uint64_t a, uint64_t b) const {
+    return a > b ? a : b;
+  }
+  __device__ __forceinline__ int operator()(int a, int b) const { return a > b ? a : b; }
+};
+struct OpMin {
+  __device__ __forceinline__ int operator()(int a, int b) const { return a < b ? a : b; }
 };
 
-__device__ __forceinline__ Rec rec_empty() {
-  Rec r;
-  r.m = -INFINITY;
-  r.S = r.S2 = 0.0;
-#pragma unroll
-  for (int d = 0; d < 5; ++d) r.ex[d] = 0.0;
-  return r;
+// Inclusive scan within each row of 16 lanes (r = lane & 15).
+template <class T, class Op>
+__device__ __forceinline__ T row_scan(T v, int r, Op op) {
+  T t = shr<1>(v);
+  if (r >= 1) v = op(v, t);
+  t = shr<2>(v);
+  if (r >= 2) v = op(v, t);
+  t = shr<4>(v);
+  if (r >= 4) v = op(v, t);
+  t = shr<8>(v);
+  if (r >= 8) v = op(v, t);
+  return v;
 }
 
-__device__ __forceinline__ Rec rec_load(const double* p) {
-  Rec r;
-  r.m = p[0];
-  r.S = p[1];
-  r.S2 = p[2];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) r.ex[d] = p[3 + d];
-  return r;
+// Reduction over the wave, in a fixed order (result uniform).
+template <class T, class Op>
+__device__ __forceinline__ T wave_reduce(T v, int lane, Op op) {
+  v = row_scan(v, lane & 15, op);
+  return op(op(readlane(v, 15), readlane(v, 31)), op(readlane(v, 47), readlane(v, 63)));
 }
 
-__device__ __forceinline__ void rec_store(double* p, const Rec& r) {
-  p[0] = r.m;
-  p[1] = r.S;
-  p[2] = r.S2;
-#pragma unroll
-  for (int d = 0; d < 5; ++d) p[3 + d] = r.ex[d];
+// Inclusive scan over the wave, in a fixed order.
+template <class T, class Op>
+__device__ __forceinline__ T wave_scan(T v, int lane, Op op) {
+  v = row_scan(v, lane & 15, op);
+  const T r0 = readlane(v, 15), r1 = readlane(v, 31), r2 = readlane(v, 47);
+  const int row = lane >> 4;
+  if (row == 1)
+    v = op(r0, v);
+  else if (row == 2)
+    v = op(op(r0, r1), v);
+  else if (row == 3)
+    v = op(op(op(r0, r1), r2), v);
+  return v;
 }
 
-// Merge of two records onto the larger maximum; NaN sums propagate.
-__device__ __forceinline__ Rec rec_merge(const Rec& a, const Rec& b) {
-  const double m = fmax(a.m, b.m);
-  if (m == -INFINITY) {
-    Rec r = a;
-    r.S = a.S + b.S;  // both empty: keeps a NaN marker if any
-    r.S2 = a.S2 + b.S2;
-    return r;
-  }
-  const double fa = (a.m == -INFINITY) ? 0.0 : exp(a.m - m);
-  const double fb = (b.m == -INFINITY) ? 0.0 : exp(b.m - m);
-  Rec r;
-  r.m = m;
-  r.S = a.S * fa + b.S * fb;
-  r.S2 = a.S2 * fa * fa + b.S2 * fb * fb;
-#pragma unroll
-  for (int d = 0; d < 5; ++d) r.ex[d] = a.ex[d] * fa + b.ex[d] * fb;
-  return r;
-}
-
-// Fixed-order tree merge of one Rec per thread in a 256-thread workgroup.
-__device__ Rec block_merge_256(Rec r, Rec* sh) {
-  const int t = threadIdx.x;
-  sh[t] = r;
+// Reduction over a 256-thread workgroup (sh: 4 entries of LDS scratch).
+template <class T, class Op>
+__device__ __forceinline__ T block_reduce(T v, T* sh, Op op) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  v = wave_reduce(v, lane, op);
+  if (lane == 0) sh[w] = v;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) sh[t] = rec_merge(sh[t], sh[t + s]);
-    __syncthreads();
-  }
-  Rec out = sh[0];
+  const T r = op(op(sh[0], sh[1]), op(sh[2], sh[3]));
   __syncthreads();
-  return out;
+  return r;
+}
+
+// Exclusive prefix sum of exact unsigned integers over a 256-thread
+// workgroup; *total receives the sum of all.
+__device__ __forceinline__ uint64_t block_excl_sum(uint64_t v, uint64_t* sh, uint64_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t inc = wave_scan(v, lane, OpAdd());
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  uint64_t before = 0;
+  for (int j = 0; j < w; ++j) before += sh[j];
+  *total = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return before + inc - v;
 }
 
 // ------------------------------------------------------------ k_init
@@ -185,10 +196,11 @@ __global__ __launch_bounds__(256) void k_init(Model m, Buffers b) {
     c->rolled_back = 0;
     c->do_resample = 0;
     c->heavy_count = 0;
-    c->tile_counter = 0;
+    c->ticket = 0;
     c->m = c->log_sum = c->ess = c->delta = c->cum = 0.0;
     for (int d = 0; d < 5; ++d) c->mean[d] = 0.0;
     c->u = 0.0;
+    c->total = 0;
   }
   if (i >= m.n) return;
   const uint4 r0 = draw(m, (uint32_t)i, 0u, kInit, 0u);
@@ -241,18 +253,16 @@ struct Prop {
   double lw;
 };
 
-__device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, const Ctrl& c,
-                                          int64_t i, uint32_t k) {
-  const int cur = c.cur;
+__device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int cur, int mode,
+                                          double delta, int64_t i, uint32_t k) {
   const float* Xin = cur ? b.X1 : b.X0;
-  const int mode = c.mode;
   int64_t p = i;
   double lw;
   if (mode == kModeSys || mode == kModeRna) p = b.anc[i];
   if (mode == kModeNone) {
     const float* Lin = cur ? b.L1 : b.L0;
     const double* Rin = cur ? b.R1 : b.R0;
-    lw = (double)Lin[i] + Rin[(i / kBlock) * kRec] - c.delta;
+    lw = (double)Lin[i] + Rin[(i / kBlock) * kRec] - delta;
   } else if (mode == kModeRna) {
     const int64_t g = i / m.group;
     const int64_t l = i - g * m.group;
@@ -283,48 +293,9 @@ __device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, cons
   return o;
 }
 
-// Block-wide reduction of the step's log weights into one record, and the
-// stored value l - m_b per particle.
-__device__ __forceinline__ void finish_block(const Model& m, const Buffers& b, const Ctrl& c,
-                                             int64_t i, bool active, double l, const Prop& o,
-                                             double* red) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const double mv = wave_max(active ? l : -INFINITY);
-  if (lane == 0) red[w] = mv;
-  __syncthreads();
-  const double mb = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-  __syncthreads();
-  double e = 0.0;
-  if (active) {
-    if (isnan(l))
-      e = NAN;
-    else if (mb != -INFINITY)
-      e = exp(l - mb);
-  }
-  double v[7] = {e, e * e, e * (double)o.x, e * (double)o.y, e * (double)o.vx, e * (double)o.vy,
-                 e * (double)o.I};
-#pragma unroll
-  for (int j = 0; j < 7; ++j) {
-    v[j] = wave_sum(v[j]);
-    if (lane == 0) red[8 + w * 7 + j] = v[j];
-  }
-  const int nxt = c.cur ^ 1;
-  if (active) {
-    float* Lout = nxt ? b.L1 : b.L0;
-    Lout[i] = (mb == -INFINITY) ? -INFINITY : (float)(l - mb);
-  }
-  __syncthreads();
-  if (t < 7) {
-    const double s = (red[8 + t] + red[8 + 7 + t]) + (red[8 + 14 + t] + red[8 + 21 + t]);
-    double* Rout = nxt ? b.R1 : b.R0;
-    Rout[(int64_t)blockIdx.x * kRec + 1 + t] = s;
-    if (t == 0) Rout[(int64_t)blockIdx.x * kRec] = mb;
-  }
-}
-
-__device__ __forceinline__ void store_state(const Model& m, const Buffers& b, const Ctrl& c,
-                                            int64_t i, const Prop& o) {
-  float* Xout = c.cur ? b.X0 : b.X1;
+__device__ __forceinline__ void store_state(const Model& m, const Buffers& b, int cur, int64_t i,
+                                            const Prop& o) {
+  float* Xout = cur ? b.X0 : b.X1;
   const int64_t n = m.n;
   Xout[i] = o.x;
   Xout[n + i] = o.y;
@@ -333,66 +304,148 @@ __device__ __forceinline__ void store_state(const Model& m, const Buffers& b, co
   Xout[4 * n + i] = o.I;
 }
 
-// Sum over the P x P patch of (D - I g_x g_y)^2 with D = Z - b (0 outside the
-// frame). g_x, g_y are the 1-D Gaussian factors of Eq. 3 at the pixel
-// offsets d - f, built by the exact recurrence
-//   g(d+1) = g(d) exp(-(2d+1)/(2 s^2)) exp(f/s^2).
-template <int P, bool LDS>
-__device__ __forceinline__ double patch_sumsq(const float* __restrict__ src, int64_t row_stride,
-                                              int64_t first, int u0, int v0, int W, int H,
-                                              float bf, double b, const double (&gx)[P],
-                                              double gy, double by, const double* cst,
-                                              double It) {
-  double acc = 0.0;
-  // rows stay rolled (full P x P unrolling hoists every load and spills)
-#pragma unroll 1
-  for (int dy = 0; dy < P; ++dy) {
-    const double my = It * gy;
-    if (LDS) {
-      const float* row = src + first + dy * row_stride;
-#pragma unroll
-      for (int dx = 0; dx < P; ++dx) {
-        const double r = fma(-my, gx[dx], (double)row[dx] - b);
-        acc = fma(r, r, acc);
-      }
-    } else {
-      const int v = v0 + dy;
-      const bool row_in = (unsigned)v < (unsigned)H;
-      const float* row = src + (int64_t)(row_in ? v : 0) * W;
-#pragma unroll
-      for (int dx = 0; dx < P; ++dx) {
-        const int u = u0 + dx;
-        const float z = (row_in && (unsigned)u < (unsigned)W) ? row[u] : bf;
-        const double r = fma(-my, gx[dx], (double)z - b);
-        acc = fma(r, r, acc);
-      }
-    }
-    if (dy + 1 < P) gy *= cst[dy] * by;
-  }
-  return acc;
+// Fixed-point weight of a particle whose weight relative to its block
+// maximum is e in [0, 1]: round(e 2^44), an exact integer held in a double
+// (the fma rounds once, the subtraction is exact).
+__device__ __forceinline__ double item_weight(double e) {
+  return fma(e, kItemScale, 0x1p52) - 0x1p52;
 }
 
+// The block's normalisation record (see kRec) and the stored log weights
+// l - m_b. red: 7 x 256 doubles of LDS, free for reuse by the caller.
+__device__ __forceinline__ void finish_block(const Buffers& b, int cur, int64_t i, bool active,
+                                             double l, const Prop& o, double* red,
+                                             double* dsh) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const bool bad = active && (isnan(l) || l == INFINITY);
+  const double mb = block_reduce((active && !bad) ? l : -INFINITY, dsh, OpMax());
+  double e = 0.0, wi = 0.0;
+  if (active) {
+    float Lf = -INFINITY;
+    if (bad) {
+      Lf = NAN;
+    } else if (mb != -INFINITY && l != -INFINITY) {
+      Lf = (float)(l - mb);
+      e = exp((double)Lf);
+      wi = item_weight(e);
+    }
+    float* Lout = cur ? b.L0 : b.L1;
+    Lout[i] = Lf;
+  }
+  // block_reduce ended with a barrier: every thread is past its reads of
+  // the LDS that red aliases
+  red[t] = wi;
+  red[256 + t] = bad ? NAN : e * e;
+  red[512 + t] = e * (double)o.x;
+  red[768 + t] = e * (double)o.y;
+  red[1024 + t] = e * (double)o.vx;
+  red[1280 + t] = e * (double)o.vy;
+  red[1536 + t] = e * (double)o.I;
+  __syncthreads();
+  double s = 0.0;
+  if (t < 224) {  // value t >> 5, eight consecutive entries (t & 31) * 8 ...
+    const double* p = red + (t >> 5) * 256 + (t & 31) * 8;
+    s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+  }
+  s = row_scan(s, lane & 15, OpAdd());
+  const double h0 = readlane(s, 15) + readlane(s, 31);  // value 2w
+  const double h1 = readlane(s, 47) + readlane(s, 63);  // value 2w + 1
+  if (lane == 0) {
+    double* R = (cur ? b.R0 : b.R1) + (int64_t)blockIdx.x * kRec;
+    R[1 + 2 * w] = h0;
+    if (2 * w + 1 < 7) R[2 + 2 * w] = h1;
+    if (w == 0) R[0] = mb;
+  }
+}
+
+// Patch sums of one particle over P rows of an LDS tile with row stride tw:
+//   X   += sum_dy g_y(dy) sum_dx Z g_x(dx)    (Gaussian-weighted pixel sum)
+//   Gy, G2y: sum of g_y and of g_y^2
+//   sd2 += sum (Z - b)^2 when the per-centre table is not used (!TAB).
+// g_y is advanced by the exact recurrence g(d+1) = g(d) gstep(d) exp(f/s^2).
+template <int P, bool TAB>
+__device__ __forceinline__ void patch_lds(const float* __restrict__ p0, int tw,
+                                          const double (&gx)[P], double gy, double by,
+                                          const double* gstep, double bsub, double& X,
+                                          double& Gy, double& G2y, double& sd2) {
+#pragma unroll 1
+  for (int dy = 0; dy < P; ++dy) {
+    const float* row = p0 + dy * tw;
+    double rd = 0.0;
+#pragma unroll
+    for (int dx = 0; dx < P; ++dx) {
+      const double z = (double)row[dx];
+      rd = fma(z, gx[dx], rd);
+      if (!TAB) {
+        const double d = z - bsub;
+        sd2 = fma(d, d, sd2);
+      }
+    }
+    X = fma(gy, rd, X);
+    Gy += gy;
+    G2y = fma(gy, gy, G2y);
+    gy *= gstep[dy] * by;
+  }
+}
+
+// The same sums read straight from the frame (workgroups whose patches do
+// not fit one LDS tile); pixels outside the frame read as the background.
+template <int P>
+__device__ __forceinline__ void patch_global(const float* __restrict__ obs, int u0, int v0,
+                                             int W, int H, float bf, const double (&gx)[P],
+                                             double gy, double by, const double* gstep,
+                                             double bsub, double& X, double& Gy, double& G2y,
+                                             double& sd2) {
+#pragma unroll 1
+  for (int dy = 0; dy < P; ++dy) {
+    const int v = v0 + dy;
+    const bool row_in = (unsigned)v < (unsigned)H;
+    const float* row = obs + (int64_t)(row_in ? v : 0) * W;
+    double rd = 0.0;
+#pragma unroll
+    for (int dx = 0; dx < P; ++dx) {
+      const int u = u0 + dx;
+      const double z = (double)((row_in && (unsigned)u < (unsigned)W) ? row[u] : bf);
+      rd = fma(z, gx[dx], rd);
+      const double d = z - bsub;
+      sd2 = fma(d, d, sd2);
+    }
+    X = fma(gy, rd, X);
+    Gy += gy;
+    G2y = fma(gy, gy, G2y);
+    gy *= gstep[dy] * by;
+  }
+}
+
+// Propagation and log weight of one particle per thread (Eq. 4 with the spot
+// of Eq. 3 on the P x P patch). The residual sum is expanded as
+//   sum (D - I g)^2 = sum D^2 - 2 I sum D g + I^2 sum g^2,   D = Z - b,
+// with sum D g = sum Z g - b sum g (pixels outside the frame hold Z = b, so
+// D = 0 there) and sum g^2 = (sum g_x^2)(sum g_y^2); everything in fp64. The
+// workgroup stages the bounding box of its patches in LDS and, when small
+// enough, a table of sum D^2 for every patch centre in the box.
 template <int P>
 __global__ __launch_bounds__(256) void k_step_spot(Model m, Buffers b,
                                                    const float* __restrict__ obs) {
-  __shared__ float tile[kTileCap];
-  __shared__ double cst[P];
-  __shared__ double red[8 + 4 * 7];
-  __shared__ int ired[16];
   constexpr int h = (P - 1) / 2;
-  const Ctrl c = *b.ctrl;
-  const uint32_t k = (uint32_t)(c.k + 1);
+  __shared__ __align__(16) float tile[kTileCap];
+  __shared__ double sq[kSqCap];
+  __shared__ double dsh[4];
+  __shared__ int ish[16];
+  const Ctrl* cp = b.ctrl;
+  const int cur = cp->cur, mode = cp->mode;
+  const double cdelta = cp->delta;
+  const uint32_t k = (uint32_t)(cp->k + 1);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t i = (int64_t)blockIdx.x * kBlock + t;
   const bool active = i < m.n;
-  if (t < P - 1) cst[t] = exp(-(2.0 * (double)(t - h) + 1.0) * m.inv2s2);
 
   Prop o{};
   double fx = 0.0, fy = 0.0;
   int cx = 0, cy = 0;
   if (active) {
-    o = propagate(m, b, c, i, k);
-    store_state(m, b, c, i, o);
+    o = propagate(m, b, cur, mode, cdelta, i, k);
+    store_state(m, b, cur, i, o);
     // patch centre: pixel nearest to (x, y); the offset f is exact in fp64
     const double rx = floor((double)o.x + 0.5), ry = floor((double)o.y + 0.5);
     fx = (double)o.x - rx;
@@ -403,34 +456,74 @@ __global__ __launch_bounds__(256) void k_step_spot(Model m, Buffers b,
     cx = (rx >= lox && rx <= hix) ? (int)rx : (rx > hix ? (int)hix : (int)lox);
     cy = (ry >= loy && ry <= hiy) ? (int)ry : (ry > hiy ? (int)hiy : (int)loy);
   }
-  // bounding box of the workgroup's patches
-  int mnx = wave_min_i(active ? cx : INT_MAX), mxx = wave_max_i(active ? cx : INT_MIN);
-  int mny = wave_min_i(active ? cy : INT_MAX), mxy = wave_max_i(active ? cy : INT_MIN);
-  if (lane == 0) {
-    ired[w] = mnx;
-    ired[4 + w] = mxx;
-    ired[8 + w] = mny;
-    ired[12 + w] = mxy;
-  }
-  __syncthreads();
-  mnx = min(min(ired[0], ired[1]), min(ired[2], ired[3]));
-  mxx = max(max(ired[4], ired[5]), max(ired[6], ired[7]));
-  mny = min(min(ired[8], ired[9]), min(ired[10], ired[11]));
-  mxy = max(max(ired[12], ired[13]), max(ired[14], ired[15]));
-  const int64_t tw = (int64_t)mxx - mnx + P, th = (int64_t)mxy - mny + P;
-  const bool use_lds = tw * th <= kTileCap;  // uniform across the workgroup
-  const int tx0 = mnx - h, ty0 = mny - h;
-  if (use_lds) {
-    const int area = (int)(tw * th);
-    for (int j = t; j < area; j += kBlock) {
-      const int ty = j / (int)tw;
-      const int u = tx0 + (j - ty * (int)tw), v = ty0 + ty;
-      tile[j] = ((unsigned)u < (unsigned)m.W && (unsigned)v < (unsigned)m.H)
-                    ? obs[(int64_t)v * m.W + u]
-                    : m.bf;
+  // bounding box of the workgroup's patch centres
+  {
+    const int a0 = wave_reduce(active ? cx : INT_MAX, lane, OpMin());
+    const int a1 = wave_reduce(active ? cx : INT_MIN, lane, OpMax());
+    const int a2 = wave_reduce(active ? cy : INT_MAX, lane, OpMin());
+    const int a3 = wave_reduce(active ? cy : INT_MIN, lane, OpMax());
+    if (lane == 0) {
+      ish[w] = a0;
+      ish[4 + w] = a1;
+      ish[8 + w] = a2;
+      ish[12 + w] = a3;
     }
   }
   __syncthreads();
+  const int mnx = min(min(ish[0], ish[1]), min(ish[2], ish[3]));
+  const int mxx = max(max(ish[4], ish[5]), max(ish[6], ish[7]));
+  const int mny = min(min(ish[8], ish[9]), min(ish[10], ish[11]));
+  const int mxy = max(max(ish[12], ish[13]), max(ish[14], ish[15]));
+  const int64_t tw64 = (int64_t)mxx - mnx + P, th64 = (int64_t)mxy - mny + P;
+  const bool use_lds = tw64 * th64 <= kTileCap;  // uniform across the workgroup
+  const int tw = (int)tw64, th = (int)th64;
+  const int tx0 = mnx - h, ty0 = mny - h;
+  const int64_t acx = (int64_t)mxx - mnx + 1, acy = (int64_t)mxy - mny + 1;
+  const int64_t nH = th64 * acx, nV = acx * acy;
+  const bool use_tab = use_lds && nH + nV <= kSqCap;
+  if (use_lds) {
+    for (int r = w; r < th; r += 4) {
+      const int v = ty0 + r;
+      const bool rin = (unsigned)v < (unsigned)m.H;
+      const float* src = obs + (int64_t)(rin ? v : 0) * m.W;
+      for (int col = lane; col < tw; col += 64) {
+        const int u = tx0 + col;
+        tile[r * tw + col] = (rin && (unsigned)u < (unsigned)m.W) ? src[u] : m.bf;
+      }
+    }
+  }
+  __syncthreads();
+  if (use_tab) {
+    // row pass: sq[r][c] = sum_dx (Z[r][c + dx] - b)^2 for c < acx
+    const int ax = (int)acx, nh = (int)nH, nv = (int)nV;
+    const float rcp = 1.0f / (float)ax;
+    for (int e = t; e < nh; e += 256) {
+      int r = (int)((float)e * rcp);
+      if (r * ax > e) --r;
+      else if ((r + 1) * ax <= e) ++r;
+      const float* row = tile + r * tw + (e - r * ax);
+      double s = 0.0;
+#pragma unroll
+      for (int dx = 0; dx < P; ++dx) {
+        const double d = (double)row[dx] - m.b;
+        s = fma(d, d, s);
+      }
+      sq[e] = s;
+    }
+    __syncthreads();
+    // centre pass: sq[nH + rr * acx + c] = sum_dy sq[(rr + dy) * acx + c]
+    for (int e = t; e < nv; e += 256) {
+      int r = (int)((float)e * rcp);
+      if (r * ax > e) --r;
+      else if ((r + 1) * ax <= e) ++r;
+      const double* col = sq + r * ax + (e - r * ax);
+      double s = 0.0;
+#pragma unroll
+      for (int dy = 0; dy < P; ++dy) s += col[dy * ax];
+      sq[nh + e] = s;
+    }
+    __syncthreads();
+  }
 
   double l = -INFINITY;
   if (active) {
@@ -438,295 +531,513 @@ __global__ __launch_bounds__(256) void k_step_spot(Model m, Buffers b,
     gx[0] = exp(-((double)h + fx) * ((double)h + fx) * m.inv2s2);
     const double bx = exp(2.0 * fx * m.inv2s2);
 #pragma unroll
-    for (int d = 0; d + 1 < P; ++d) gx[d + 1] = gx[d] * (cst[d] * bx);
+    for (int d = 0; d + 1 < P; ++d) gx[d + 1] = gx[d] * (m.gstep[d] * bx);
+    double Gx = 0.0, G2x = 0.0;
+#pragma unroll
+    for (int d = 0; d < P; ++d) {
+      Gx += gx[d];
+      G2x = fma(gx[d], gx[d], G2x);
+    }
     const double gy0 = exp(-((double)h + fy) * ((double)h + fy) * m.inv2s2);
     const double by = exp(2.0 * fy * m.inv2s2);
-    double acc;
-    if (use_lds) {
-      const int64_t first = (int64_t)(cy - h - ty0) * tw + (cx - h - tx0);
-      acc = patch_sumsq<P, true>(tile, tw, first, 0, 0, 0, 0, m.bf, m.b, gx, gy0, by, cst,
-                                 (double)o.I);
+    double X = 0.0, Gy = 0.0, G2y = 0.0, sd2 = 0.0;
+    if (use_tab) {
+      patch_lds<P, true>(tile + (cy - h - ty0) * tw + (cx - h - tx0), tw, gx, gy0, by, m.gstep,
+                         m.b, X, Gy, G2y, sd2);
+      sd2 = sq[nH + (int64_t)(cy - mny) * acx + (cx - mnx)];
+    } else if (use_lds) {
+      patch_lds<P, false>(tile + (cy - h - ty0) * tw + (cx - h - tx0), tw, gx, gy0, by, m.gstep,
+                          m.b, X, Gy, G2y, sd2);
     } else {
-      acc = patch_sumsq<P, false>(obs, 0, 0, cx - h, cy - h, m.W, m.H, m.bf, m.b, gx, gy0, by,
-                                  cst, (double)o.I);
+      patch_global<P>(obs, cx - h, cy - h, m.W, m.H, m.bf, gx, gy0, by, m.gstep, m.b, X, Gy, G2y,
+                      sd2);
     }
-    l = o.lw - acc * m.inv2sig2 - m.lognorm_obs;
+    X -= m.b * (Gx * Gy);
+    const double I = (double)o.I;
+    const double ssq = sd2 - 2.0 * I * X + I * I * (G2x * G2y);
+    l = o.lw - ssq * m.inv2sig2 - m.lognorm_obs;
   }
-  finish_block(m, b, c, i, active, l, o, red);
+  finish_block(b, cur, i, active, l, o, reinterpret_cast<double*>(tile), dsh);
 }
 
 // Linear-Gaussian observation of (x, y, I0): three fp32 values on the device.
 __global__ __launch_bounds__(256) void k_step_lg(Model m, Buffers b,
                                                  const float* __restrict__ obs) {
-  __shared__ double red[8 + 4 * 7];
-  const Ctrl c = *b.ctrl;
-  const uint32_t k = (uint32_t)(c.k + 1);
+  __shared__ double red[7 * 256];
+  __shared__ double dsh[4];
+  const Ctrl* cp = b.ctrl;
+  const int cur = cp->cur, mode = cp->mode;
+  const double cdelta = cp->delta;
+  const uint32_t k = (uint32_t)(cp->k + 1);
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = i < m.n;
   Prop o{};
   double l = -INFINITY;
   if (active) {
-    o = propagate(m, b, c, i, k);
-    store_state(m, b, c, i, o);
+    o = propagate(m, b, cur, mode, cdelta, i, k);
+    store_state(m, b, cur, i, o);
     const double ex = (double)obs[0] - (double)o.x, ey = (double)obs[1] - (double)o.y,
                  eI = (double)obs[2] - (double)o.I;
     l = o.lw - ex * ex * m.lg_inv2r2[0] - ey * ey * m.lg_inv2r2[1] - eI * eI * m.lg_inv2r2[2] -
         m.lg_norm;
   }
-  finish_block(m, b, c, i, active, l, o, red);
+  finish_block(b, cur, i, active, l, o, red, dsh);
 }
 
-// ------------------------------------------------------- records merging
-// First merge level: workgroup j merges a contiguous chunk of level-1
-// records in a fixed order.
-__global__ __launch_bounds__(256) void k_reduce(Buffers b, int standalone) {
-  __shared__ Rec sh[256];
-  // the step wrote its records into the buffer that finalize will make current
-  const double* R = (!standalone && (b.ctrl->cur ^ 1)) ? b.R1 : b.R0;
-  const int64_t chunk = (b.nb + b.nr2 - 1) / b.nr2;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
-  const int64_t hi = min(b.nb, lo + chunk);
-  Rec r = rec_empty();
-  for (int64_t j = lo + threadIdx.x; j < hi; j += 256) r = rec_merge(r, rec_load(R + j * kRec));
-  r = block_merge_256(r, sh);
-  if (threadIdx.x == 0) rec_store(b.R2 + (int64_t)blockIdx.x * kRec, r);
+// Records of caller-supplied absolute fp32 log weights (standalone
+// resampling): the same record layout, with zero state sums.
+__global__ __launch_bounds__(256) void k_records(Model m, Buffers b,
+                                                 const float* __restrict__ logw) {
+  __shared__ double red[2 * 256];
+  __shared__ double dsh[4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+  if (i == 0) {
+    // the standalone scratch starts uninitialised: clear the counters and
+    // flags the following kernels of this call rely on
+    Ctrl* c = b.ctrl;
+    c->ticket = 0u;
+    c->heavy_count = 0;
+    c->do_resample = 0;
+    c->total = 0;
+    c->cur = 0;
+    c->k = 0;
+  }
+  const bool active = i < m.n;
+  const double l = active ? (double)logw[i] : -INFINITY;
+  const bool bad = active && (isnan(l) || l == INFINITY);
+  const double mb = block_reduce((active && !bad) ? l : -INFINITY, dsh, OpMax());
+  double e = 0.0;
+  if (active && !bad && mb != -INFINITY && l != -INFINITY) e = exp(l - mb);
+  red[t] = item_weight(e);
+  red[256 + t] = bad ? NAN : e * e;
+  __syncthreads();
+  double s = 0.0;
+  if (t < 64) {
+    const double* p = red + (t >> 5) * 256 + (t & 31) * 8;
+    s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+  }
+  s = row_scan(s, lane & 15, OpAdd());
+  const double h0 = readlane(s, 15) + readlane(s, 31);
+  const double h1 = readlane(s, 47) + readlane(s, 63);
+  if (t == 0) {
+    double* R = b.R0 + (int64_t)blockIdx.x * kRec;
+    R[0] = mb;
+    R[1] = h0;
+    R[2] = h1;
+    for (int d = 0; d < 5; ++d) R[3 + d] = 0.0;
+  }
+  (void)w;
 }
 
-// Final merge, statistics of Algorithm 1 and the commit of the step.
-__global__ __launch_bounds__(256) void k_finalize(Model m, Buffers b, int standalone,
-                                                  double u_given) {
-  __shared__ Rec sh[256];
+// ------------------------------------------------------------- k_merge
+// Each workgroup merges one chunk of block records relative to the chunk's
+// maximum: the chunk record, and per block the exclusive prefix of the
+// chunk's integer weights q_b = round(B_b exp(m_b - M_c)). The last workgroup
+// to arrive merges the chunk records in a fixed order, takes the statistics
+// of Algorithm 1 (normaliser, ESS, MMSE estimate), decides on resampling,
+// commits or rolls back the step, and for systematic resampling writes each
+// chunk's fixed-point CDF prefix.
+__global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalone,
+                                               double u_given) {
+  __shared__ double dsh[4];
+  __shared__ uint64_t ush[4];
+  __shared__ int sh_last;
+  __shared__ int sh_pre;
+  __shared__ double sh_delta;
   Ctrl* c = b.ctrl;
-  const int which = standalone ? 0 : (c->cur ^ 1);
-  const double* R = b.nr2 ? b.R2 : (which ? b.R1 : b.R0);
-  const int64_t cnt = b.nr2 ? b.nr2 : b.nb;
-  Rec r = rec_empty();
-  for (int64_t j = threadIdx.x; j < cnt; j += 256) r = rec_merge(r, rec_load(R + j * kRec));
-  r = block_merge_256(r, sh);
-  const bool ok = isfinite(r.m) && isfinite(r.S) && r.S > 0.0;
-  if (threadIdx.x == 0) {
+  const int t = threadIdx.x;
+  const int which = standalone ? 0 : (c->cur ^ 1);  // the records this step wrote
+  const double* R = which ? b.R1 : b.R0;
+  const int64_t ch = blockIdx.x;
+  const int64_t lo = ch * b.chunk, hi = min(b.nb, lo + b.chunk);
+  const int per = (int)(b.chunk / 256);
+  const int64_t j0 = lo + (int64_t)t * per;
+
+  double mx = -INFINITY;
+  for (int q = 0; q < per; ++q) {
+    const int64_t j = j0 + q;
+    if (j < hi) mx = fmax(mx, R[j * kRec]);
+  }
+  const double Mc = block_reduce(mx, dsh, OpMax());
+  uint64_t qs = 0;
+  double s2 = 0.0, ex[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < per; ++q) {
+    const int64_t j = j0 + q;
+    if (j < hi) {
+      const double* r = R + j * kRec;
+      const double f = (r[0] == -INFINITY) ? 0.0 : exp(r[0] - Mc);
+      qs += (uint64_t)rint(r[1] * f);
+      s2 += r[2] * (f * f);
+#pragma unroll
+      for (int d = 0; d < 5; ++d) ex[d] += r[3 + d] * f;
+    }
+  }
+  uint64_t qtot;
+  uint64_t run = block_excl_sum(qs, ush, &qtot);
+  for (int q = 0; q < per; ++q) {
+    const int64_t j = j0 + q;
+    if (j < hi) {
+      const double* r = R + j * kRec;
+      const double f = (r[0] == -INFINITY) ? 0.0 : exp(r[0] - Mc);
+      b.pfx[j] = run;
+      run += (uint64_t)rint(r[1] * f);
+    }
+  }
+  const double S2c = block_reduce(s2, dsh, OpAdd());
+  double exc[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) exc[d] = block_reduce(ex[d], dsh, OpAdd());
+  if (t == 0) {
+    double* cr = b.CR + ch * kRec;
+    cr[0] = Mc;
+    cr[1] = __longlong_as_double((long long)qtot);
+    cr[2] = S2c;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) cr[3 + d] = exc[d];
+  }
+  // arrival: the last workgroup finishes the step
+  __threadfence();
+  __syncthreads();
+  if (t == 0) sh_last = (atomicAdd(&c->ticket, 1u) == (uint32_t)(b.nch - 1));
+  __syncthreads();
+  if (!sh_last) return;
+  __threadfence();
+
+  const int64_t nch = b.nch;
+  const int per2 = (int)((nch + 255) / 256);
+  const int64_t c0 = (int64_t)t * per2;
+  auto ld = [&](int64_t idx) {
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<unsigned long long*>(b.CR) + idx, __ATOMIC_RELAXED,
+        __HIP_MEMORY_SCOPE_AGENT));
+  };
+  double mx2 = -INFINITY;
+  for (int q = 0; q < per2; ++q) {
+    const int64_t cc = c0 + q;
+    if (cc < nch) mx2 = fmax(mx2, ld(cc * kRec));
+  }
+  const double M = block_reduce(mx2, dsh, OpMax());
+  double S = 0.0, S2 = 0.0, E[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < per2; ++q) {
+    const int64_t cc = c0 + q;
+    if (cc < nch) {
+      const double mc = ld(cc * kRec);
+      const double f = (mc == -INFINITY) ? 0.0 : exp(mc - M);
+      const uint64_t Q = (uint64_t)__double_as_longlong(ld(cc * kRec + 1));
+      S += (double)Q * f;
+      S2 += ld(cc * kRec + 2) * (f * f);
+#pragma unroll
+      for (int d = 0; d < 5; ++d) E[d] += ld(cc * kRec + 3 + d) * f;
+    }
+  }
+  S = block_reduce(S, dsh, OpAdd()) * (1.0 / kItemScale);
+  S2 = block_reduce(S2, dsh, OpAdd());
+#pragma unroll
+  for (int d = 0; d < 5; ++d) E[d] = block_reduce(E[d], dsh, OpAdd());
+  if (t == 0) {
+    bool ok = isfinite(M) && isfinite(S) && S > 0.0 && isfinite(S2);
+#pragma unroll
+    for (int d = 0; d < 5; ++d) ok = ok && isfinite(E[d]);
+    int pre = 0;
     if (standalone) {
       c->cur = 0;
-      c->delta = ok ? r.m + log(r.S) : 0.0;
+      c->delta = ok ? M + log(S) : 0.0;
       c->u = u_given;
       c->do_resample = ok ? 1 : 0;
       c->k = 0;
+      pre = ok ? 1 : 0;
     } else if (ok) {
       const int64_t k = c->k + 1;
-      const double ess = r.S * r.S / r.S2;
-      const double logS = log(r.S);
+      const double ess = S * S / S2;
+      const double logS = log(S);
       const bool res = ess < m.thr;
       c->k = k;
       c->cur ^= 1;
-      c->m = r.m;
+      c->m = M;
       c->log_sum = logS;
       c->ess = ess;
-      c->delta = r.m + logS;
-      c->cum += r.m + logS;
-      for (int d = 0; d < 5; ++d) c->mean[d] = r.ex[d] / r.S;
+      c->delta = M + logS;
+      c->cum += M + logS;
+#pragma unroll
+      for (int d = 0; d < 5; ++d) c->mean[d] = E[d] / S;
       c->resampled = res ? 1 : 0;
       c->do_resample = res ? 1 : 0;
       c->mode = res ? (m.group > 0 ? kModeRna : kModeSys) : kModeNone;
       const uint4 rr = draw(m, 0u, (uint32_t)k, kResample, 0u);
       c->u = u53(rr.x, rr.y);
+      pre = (res && m.group == 0) ? 1 : 0;
     } else {
       c->rolled_back += 1;
       c->do_resample = 0;
     }
-    c->tile_counter = 0u;
+    sh_pre = pre;
+    sh_delta = c->delta;
+    c->ticket = 0u;
     c->heavy_count = 0;
   }
-  for (int64_t j = threadIdx.x; j < b.ntiles; j += 256) b.desc[j] = 0ull;
+  __syncthreads();
+  if (!sh_pre) return;
+  // chunk prefixes of the fixed-point CDF (2^62 = total weight)
+  const double delta = sh_delta;
+  uint64_t wsum = 0;
+  for (int q = 0; q < per2; ++q) {
+    const int64_t cc = c0 + q;
+    if (cc < nch) {
+      const double mc = ld(cc * kRec);
+      const double phi = (mc == -INFINITY) ? 0.0 : exp(mc - delta) * kItemToCdf;
+      const uint64_t Q = (uint64_t)__double_as_longlong(ld(cc * kRec + 1));
+      wsum += (uint64_t)rint((double)Q * phi);
+    }
+  }
+  uint64_t tot;
+  uint64_t pre = block_excl_sum(wsum, ush, &tot);
+  for (int q = 0; q < per2; ++q) {
+    const int64_t cc = c0 + q;
+    if (cc < nch) {
+      const double mc = ld(cc * kRec);
+      const double phi = (mc == -INFINITY) ? 0.0 : exp(mc - delta) * kItemToCdf;
+      const uint64_t Q = (uint64_t)__double_as_longlong(ld(cc * kRec + 1));
+      b.cpre[cc].P = pre;
+      b.cpre[cc].phi = phi;
+      pre += (uint64_t)rint((double)Q * phi);
+    }
+  }
+  if (t == 0) c->total = tot;
 }
 
 // --------------------------------------------------- systematic resampling
-__device__ __forceinline__ uint64_t slot_u(int64_t s, double u, double inv_n) {
-  const double q = ((double)s + u) * inv_n;
-  return (uint64_t)(q * 0x1p60);
+// Slot s of N takes the particle j whose CDF interval holds (s + u) / N
+// (Algorithm 1's resampling step with one uniform u). Positions and CDF are
+// 2^62 fixed point; positions at or beyond the total are clamped below it,
+// so every slot lands on a particle of positive weight.
+__device__ __forceinline__ uint64_t slot_pos(int64_t s, double u, double inv_n, uint64_t total) {
+  const uint64_t p = (uint64_t)((((double)s + u) * inv_n) * kCdfScale);
+  return p < total ? p : total - 1;
 }
 
-// Number of output slots s in [0, n) with U(s) < C.
-__device__ int64_t slot_count(uint64_t C, double u, double inv_n, int64_t n) {
-  const double est = (double)C * 0x1p-60 * (double)n - u;
+// Number of slots whose position is below P.
+__device__ int64_t first_slot(uint64_t P, double u, double inv_n, uint64_t total, int64_t n) {
+  if (P >= total) return n;
+  const double est = (double)P * (1.0 / kCdfScale) * (double)n - u;
   int64_t s = est <= 0.0 ? 0 : (est >= (double)n ? n : (int64_t)ceil(est));
-  while (s > 0 && slot_u(s - 1, u, inv_n) >= C) --s;
-  while (s < n && slot_u(s, u, inv_n) < C) ++s;
+  while (s > 0 && slot_pos(s - 1, u, inv_n, total) >= P) --s;
+  while (s < n && slot_pos(s, u, inv_n, total) < P) ++s;
   return s;
 }
 
-__device__ __forceinline__ void weight_src(const WeightSrc& w, const Ctrl* c, const float*& val,
-                                           const double*& off) {
-  const int cur = w.use_cur ? c->cur : 0;
-  val = cur ? w.val1 : w.val0;
-  off = cur ? w.off1 : w.off0;
+// CDF position of the start of block blk.
+__device__ __forceinline__ uint64_t block_P(const Buffers& b, int64_t blk) {
+  const ChunkPre cp = b.cpre[blk / b.chunk];
+  return cp.P + (uint64_t)rint((double)b.pfx[blk] * cp.phi);
 }
 
-// Fixed-point weights of one tile, local inclusive CDF into C (blocked:
-// thread t owns items 8t..8t+7). Returns the tile total.
-__device__ uint64_t tile_cdf(const WeightSrc& ws, const Ctrl* c, int64_t base, int64_t n,
-                             double lognorm, uint64_t* C, uint64_t* wsum) {
-  const float* val;
-  const double* off;
-  weight_src(ws, c, val, off);
+// First output slot of segment seg (seg == nseg: n).
+__device__ __forceinline__ int64_t seg_start(const Buffers& b, int64_t seg, double u,
+                                             double inv_n, uint64_t total, int64_t n) {
+  if (seg <= 0) return 0;
+  if (seg >= b.nseg) return n;
+  return first_slot(block_P(b, seg * kSegBlocks), u, inv_n, total, n);
+}
+
+struct SegShared {
+  uint64_t C[kSegItems];      // CDF (upper end) of each loaded particle
+  int32_t stage[kSlotChunk];  // ancestors of the slots, for coalesced stores
+  uint64_t Pb[kSegBlocks + 1];
+  uint64_t u4[4];
+  int i4[4];
+};
+
+// Ancestors of the slots [s_lo, s_hi) (at most kSlotChunk), all of which lie
+// in segment seg. Loads the blocks of the segment that hold these slots,
+// builds their CDF (a running maximum, so particles of zero weight never own
+// an interval), and merges it with the slot positions: each thread takes an
+// equal share of the merged sequence (merge path).
+__device__ void seg_process(const Model& m, const Buffers& b, const WeightSrc& ws, int cur,
+                            double delta, double u, uint64_t total, int64_t seg, int64_t s_lo,
+                            int64_t s_hi, SegShared& sh) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-#pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    const int li = j * kScanThreads + t;
-    const int64_t idx = base + li;
-    uint64_t wf = 0;
-    if (idx < n) {
-      const double lw = (double)val[idx] + off[(idx / kBlock) * ws.stride] - lognorm;
-      wf = __double2ull_rn(exp(lw) * 0x1p60);
-    }
-    C[li] = wf;
+  const int64_t n = m.n;
+  const int M = (int)(s_hi - s_lo);
+  const int64_t b0 = seg * kSegBlocks;
+  const int nbs = (int)min((int64_t)kSegBlocks, b.nb - b0);
+  if (t <= nbs)
+    sh.Pb[t] = (t < nbs) ? block_P(b, b0 + t) : (b0 + nbs < b.nb ? block_P(b, b0 + nbs) : total);
+  __syncthreads();
+  const double inv_n = m.inv_n;
+  const uint64_t U_lo = slot_pos(s_lo, u, inv_n, total);
+  const uint64_t U_hi = slot_pos(s_hi - 1, u, inv_n, total);
+  int ba = 0, bb = 0;
+  for (int q = 1; q < nbs; ++q) {
+    if (sh.Pb[q] <= U_lo) ba = q;
+    if (sh.Pb[q] <= U_hi) bb = q;
   }
-  __syncthreads();
-  uint64_t v[kScanItems];
-  uint64_t run = 0;
-#pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    run += C[t * kScanItems + j];
-    v[j] = run;
-  }
-  const uint64_t incl = wave_incl_scan_u64(run, lane);
-  if (lane == 63) wsum[w] = incl;
-  __syncthreads();
-  uint64_t before = 0;
-  for (int j = 0; j < w; ++j) before += wsum[j];
-  const uint64_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-  const uint64_t texcl = before + incl - run;
-#pragma unroll
-  for (int j = 0; j < kScanItems; ++j) C[t * kScanItems + j] = texcl + v[j];
-  __syncthreads();
-  return total;
-}
+  const int64_t ib0 = (b0 + ba) * kBlock;
+  const int64_t ib1 = min(n, (b0 + bb + 1) * kBlock);
+  const int n_it = (int)(ib1 - ib0);
 
-// Ancestors of slots [s0, s1): the two-pointer walk s(i) = min{ j : U(i) <
-// C_j } over the tile's global inclusive CDF (C + excl), clamped to the last
-// valid item.
-__device__ __forceinline__ void walk_slots(const uint64_t* C, uint64_t excl, int nvalid,
-                                           int64_t base, int64_t s0, int64_t s1, double u,
-                                           double inv_n, int32_t* __restrict__ anc) {
-  if (s0 >= s1) return;
-  uint64_t us = slot_u(s0, u, inv_n);
-  int lo = 0, hi = nvalid - 1;
+  const bool second = ws.use_cur && cur;
+  const float* val = second ? ws.val1 : ws.val0;
+  const double* rec = second ? ws.rec1 : ws.rec0;
+  const int64_t j0 = ib0 + 8 * (int64_t)t;
+  const bool mine = j0 < ib1;
+  double wi[8], kl[8];
+  double tsum = 0.0;
+  uint64_t Pblk = 0;
+  double f = 0.0;
+  if (mine) {
+    const int64_t blk = j0 / kBlock;
+    const double mblk = rec[blk * kRec];
+    const double sub = ws.relative ? 0.0 : mblk;
+    float x[8];
+    // vector loads only from 16-byte aligned bases (callers' views may not be)
+    if (j0 + 8 <= ib1 && (reinterpret_cast<uintptr_t>(val) & 15) == 0) {
+      const float4 v0 = *reinterpret_cast<const float4*>(val + j0);
+      const float4 v1 = *reinterpret_cast<const float4*>(val + j0 + 4);
+      x[0] = v0.x; x[1] = v0.y; x[2] = v0.z; x[3] = v0.w;
+      x[4] = v1.x; x[5] = v1.y; x[6] = v1.z; x[7] = v1.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[q] = (j0 + q < ib1) ? val[j0 + q] : -INFINITY;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      wi[q] = x[q] == -INFINITY ? 0.0 : item_weight(exp((double)x[q] - sub));
+      tsum += wi[q];
+      kl[q] = tsum;
+    }
+    f = (mblk == -INFINITY) ? 0.0 : exp(mblk - delta) * kItemToCdf;
+    Pblk = sh.Pb[blk - b0];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) wi[q] = kl[q] = 0.0;
+  }
+  // prefix of the block's integer weights before this thread's items: the
+  // 32 threads of a block are one half of a wave
+  double inc = row_scan(tsum, lane & 15, OpAdd());
+  const double r0 = readlane(inc, 15), r2 = readlane(inc, 47);
+  if ((lane >> 4) == 1) inc += r0;
+  else if ((lane >> 4) == 3) inc += r2;
+  const double texcl = inc - tsum;  // exact: integers below 2^53
+  uint64_t cq[8];
+  uint64_t tmax = 0;
+  int lp = -1;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    uint64_t v = 0;
+    if (wi[q] > 0.0) {
+      v = Pblk + (uint64_t)rint((texcl + kl[q]) * f);
+      lp = 8 * t + q;
+    }
+    tmax = v > tmax ? v : tmax;
+    cq[q] = v;
+  }
+  // running maximum across the threads, starting at the first block's start
+  const uint64_t winc = wave_scan(tmax, lane, OpMax());
+  uint64_t wex = __shfl_up(winc, 1, 64);
+  if (lane == 0) wex = 0;
+  if (lane == 63) sh.u4[w] = winc;
+  const int lpw = wave_reduce(lp, lane, OpMax());
+  if (lane == 0) sh.i4[w] = lpw;
+  __syncthreads();
+  uint64_t carry = sh.Pb[ba];
+  for (int q = 0; q < w; ++q) carry = sh.u4[q] > carry ? sh.u4[q] : carry;
+  carry = wex > carry ? wex : carry;
+  // the block holding the first slot has positive weight, so last_pos >= 0;
+  // the clamp keeps every written ancestor a valid index regardless
+  const int last_pos = max(max(max(sh.i4[0], sh.i4[1]), max(sh.i4[2], sh.i4[3])), 0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    carry = cq[q] > carry ? cq[q] : carry;
+    if (8 * t + q < n_it) sh.C[8 * t + q] = carry;
+  }
+  __syncthreads();
+
+  // merge path over n_it particles and M slots; a slot precedes particle a
+  // iff its position is below C[a]
+  const int tot_el = n_it + M;
+  const int per = (tot_el + 255) / 256;
+  const int d0 = min(t * per, tot_el), d1 = min(d0 + per, tot_el);
+  int lo = max(0, d0 - M), hi = min(d0, n_it);
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (C[mid] + excl > us)
-      hi = mid;
-    else
+    if (sh.C[mid] <= slot_pos(s_lo + (d0 - mid - 1), u, inv_n, total))
       lo = mid + 1;
+    else
+      hi = mid;
   }
-  int j = lo;
-  for (int64_t s = s0; s < s1; ++s) {
-    us = slot_u(s, u, inv_n);
-    while (j < nvalid - 1 && C[j] + excl <= us) ++j;
-    anc[s] = (int32_t)(base + j);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_scan(Model m, Buffers b, WeightSrc ws) {
-  __shared__ uint64_t C[kTile];
-  __shared__ uint64_t wsum[4];
-  __shared__ uint64_t sh_excl;
-  __shared__ uint32_t sh_tile;
-  Ctrl* c = b.ctrl;
-  if (!c->do_resample) return;
-  if (threadIdx.x == 0) sh_tile = atomicAdd(&c->tile_counter, 1u);
-  __syncthreads();
-  const int64_t t = sh_tile;
-  const int64_t n = m.n;
-  const int64_t base = t * kTile;
-  const double lognorm = c->delta;
-  const double u = c->u;
-  const uint64_t A = tile_cdf(ws, c, base, n, lognorm, C, wsum);
-
-  // decoupled look-back (one wave), tile ids handed out in launch order
-  const int lane = threadIdx.x & 63;
-  if (t == 0) {
-    if (threadIdx.x == 0) {
-      __hip_atomic_store(&b.desc[0], kFlagPrefix | A, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      sh_excl = 0;
-    }
-  } else if (threadIdx.x < 64) {
-    if (lane == 0)
-      __hip_atomic_store(&b.desc[t], kFlagAggregate | A, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    uint64_t excl = 0;
-    int64_t j = t - 1;
-    while (true) {
-      const int64_t idx = j - lane;
-      uint64_t d = kFlagPrefix;  // before tile 0: an empty prefix
-      if (idx >= 0) {
-        do {
-          d = __hip_atomic_load(&b.desc[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } while ((d >> 62) == 0);
-      }
-      const uint64_t pmask = __ballot((d >> 62) == 2);
-      const int first = pmask ? (__ffsll((long long)pmask) - 1) : 64;
-      excl += wave_sum_u64(lane <= first ? (d & kValueMask) : 0ull);
-      if (pmask) break;
-      j -= 64;
-    }
-    if (lane == 0) {
-      __hip_atomic_store(&b.desc[t], kFlagPrefix | (excl + A), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      sh_excl = excl;
+  int a = lo, bs = d0 - lo;
+  uint64_t ucur = bs < M ? slot_pos(s_lo + bs, u, inv_n, total) : 0;
+  for (int d = d0; d < d1; ++d) {
+    if (bs < M && (a >= n_it || ucur < sh.C[a])) {
+      sh.stage[bs] = (int32_t)(ib0 + (a < n_it ? a : last_pos));
+      ++bs;
+      if (bs < M) ucur = slot_pos(s_lo + bs, u, inv_n, total);
+    } else {
+      ++a;
     }
   }
   __syncthreads();
-  const uint64_t excl = sh_excl;
-  const double inv_n = m.inv_n;
-  const int64_t o_lo = slot_count(excl, u, inv_n, n);
-  const int64_t o_hi = (t == b.ntiles - 1) ? n : slot_count(excl + A, u, inv_n, n);
-  const int64_t M = o_hi - o_lo;
-  if (M > (int64_t)kHeavyFactor * kTile) {
-    if (threadIdx.x == 0) {
-      const int hq = atomicAdd(&c->heavy_count, 1);
-      b.heavy[2 * hq] = (uint64_t)t;
-      b.heavy[2 * hq + 1] = excl;
-    }
-    return;
-  }
-  const int nvalid = (int)min((int64_t)kTile, n - base);
-  const int64_t per = (M + kScanThreads - 1) / kScanThreads;
-  const int64_t s0 = o_lo + (int64_t)threadIdx.x * per;
-  walk_slots(C, excl, nvalid, base, s0, min(o_hi, s0 + per), u, inv_n, b.anc);
+  for (int q = t; q < M; q += 256) b.anc[s_lo + q] = sh.stage[q];
+  __syncthreads();
 }
 
-// Tiles with many output slots: every workgroup takes chunks of each queued
-// tile round-robin, so one heavy particle's offspring are written by the
-// whole GPU.
-__global__ __launch_bounds__(256) void k_heavy(Model m, Buffers b, WeightSrc ws) {
-  __shared__ uint64_t C[kTile];
-  __shared__ uint64_t wsum[4];
+__global__ __launch_bounds__(256) void k_anc(Model m, Buffers b, WeightSrc ws) {
+  __shared__ SegShared sh;
+  __shared__ int64_t sh_se[2];
+  __shared__ int sh_base;
   Ctrl* c = b.ctrl;
   if (!c->do_resample) return;
-  const int nh = c->heavy_count;
-  const int64_t n = m.n;
-  const double lognorm = c->delta, u = c->u, inv_n = m.inv_n;
-  for (int hq = 0; hq < nh; ++hq) {
-    const int64_t t = (int64_t)b.heavy[2 * hq];
-    const uint64_t excl = b.heavy[2 * hq + 1];
-    const int64_t base = t * kTile;
-    const uint64_t A = tile_cdf(ws, c, base, n, lognorm, C, wsum);
-    const int64_t o_lo = slot_count(excl, u, inv_n, n);
-    const int64_t o_hi = (t == b.ntiles - 1) ? n : slot_count(excl + A, u, inv_n, n);
-    const int64_t nchunks = (o_hi - o_lo + kHeavyChunk - 1) / kHeavyChunk;
-    const int nvalid = (int)min((int64_t)kTile, n - base);
-    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-      const int64_t c0 = o_lo + ch * kHeavyChunk;
-      const int64_t c1 = min(o_hi, c0 + kHeavyChunk);
-      constexpr int per = kHeavyChunk / kScanThreads;
-      const int64_t s0 = c0 + (int64_t)threadIdx.x * per;
-      walk_slots(C, excl, nvalid, base, s0, min(c1, s0 + per), u, inv_n, b.anc);
-    }
+  const int cur = c->cur;
+  const double delta = c->delta, u = c->u;
+  const uint64_t total = c->total;
+  const int64_t seg = blockIdx.x;
+  if (threadIdx.x < 2) sh_se[threadIdx.x] = seg_start(b, seg + threadIdx.x, u, m.inv_n, total, m.n);
+  __syncthreads();
+  const int64_t fs = sh_se[0], fe = sh_se[1];
+  if (fe <= fs) return;
+  if (fe - fs > kSlotChunk) {
+    const int nq = (int)((fe - fs + kSlotChunk - 1) / kSlotChunk) - 1;
+    if (threadIdx.x == 0) sh_base = atomicAdd(&c->heavy_count, nq);
     __syncthreads();
+    // the queue holds at most n / kSlotChunk + 1 entries, which the slot
+    // counts cannot exceed; entries beyond it are never written
+    for (int q = threadIdx.x; q < nq; q += 256)
+      if (sh_base >= 0 && (int64_t)sh_base + q < b.hq_cap)
+        b.hq[sh_base + q] = ((uint64_t)seg << 32) | (uint64_t)(q + 1);
+  }
+  seg_process(m, b, ws, cur, delta, u, total, seg, fs, min(fe, fs + (int64_t)kSlotChunk), sh);
+}
+
+// Slot chunks queued by k_anc (segments owning more than kSlotChunk slots).
+__global__ __launch_bounds__(256) void k_anc_heavy(Model m, Buffers b, WeightSrc ws) {
+  __shared__ SegShared sh;
+  __shared__ int64_t sh_se[2];
+  const Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int64_t nh = min((int64_t)c->heavy_count, b.hq_cap);
+  const int cur = c->cur;
+  const double delta = c->delta, u = c->u;
+  const uint64_t total = c->total;
+  for (int64_t q = blockIdx.x; q < nh; q += gridDim.x) {
+    const uint64_t e = b.hq[q];
+    const int64_t seg = (int64_t)(e >> 32), kq = (int64_t)(e & 0xffffffffu);
+    if (seg >= b.nseg) continue;  // uniform: every thread read the same entry
+    if (threadIdx.x < 2)
+      sh_se[threadIdx.x] = seg_start(b, seg + threadIdx.x, u, m.inv_n, total, m.n);
+    __syncthreads();
+    const int64_t fs = sh_se[0], fe = sh_se[1];
+    __syncthreads();
+    const int64_t lo = fs + kq * kSlotChunk, hi = min(fe, lo + (int64_t)kSlotChunk);
+    if (lo < hi) seg_process(m, b, ws, cur, delta, u, total, seg, lo, hi, sh);
   }
 }
 
 // ------------------------------------------------------------------- RNA
+__device__ __forceinline__ double wave_sum_d(double v, int lane) {
+  return wave_reduce(v, lane, OpAdd());
+}
+
 // One workgroup per group g (Section 3): local systematic resampling of the
 // group's normalised weights, slot weight W_g / n, and the last `moved` slots
 // taken from group g-1's local resampling (recomputed here, so no workgroup
@@ -738,16 +1049,16 @@ __global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
   __shared__ uint64_t wsum[4];
   Ctrl* c = b.ctrl;
   if (!c->do_resample) return;
-  const float* val;
-  const double* off;
-  weight_src(ws, c, val, off);
+  const bool second = ws.use_cur && c->cur;
+  const float* val = second ? ws.val1 : ws.val0;
+  const double* rec = second ? ws.rec1 : ws.rec0;
   const int64_t g = blockIdx.x;
   const int ng = m.group;
   const int64_t G = m.G;
   const int64_t prev = (g + G - 1) % G;
   const double lognorm = c->delta;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int ipt = (ng + kScanThreads - 1) / kScanThreads;
+  const int ipt = (ng + 255) / 256;
   double Wg[2];
   double ug[2];
   for (int side = 0; side < 2; ++side) {
@@ -760,11 +1071,12 @@ __global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
       wl[j] = 0.0;
       if (li < ng) {
         const int64_t idx = base + li;
-        wl[j] = exp((double)val[idx] + off[(idx / kBlock) * ws.stride] - lognorm);
+        const double off = ws.relative ? rec[(idx / kBlock) * kRec] : 0.0;
+        wl[j] = exp((double)val[idx] + off - lognorm);
         part += wl[j];
       }
     }
-    part = wave_sum(part);
+    part = wave_sum_d(part, lane);
     if (lane == 0) dsum[w] = part;
     __syncthreads();
     const double W = (dsum[0] + dsum[1]) + (dsum[2] + dsum[3]);
@@ -775,7 +1087,7 @@ __global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
       run += wf;
       v[j] = run;
     }
-    const uint64_t incl = wave_incl_scan_u64(run, lane);
+    const uint64_t incl = wave_scan(run, lane, OpAdd());
     if (lane == 63) wsum[w] = incl;
     __syncthreads();
     uint64_t before = 0;
@@ -794,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
     }
   }
   // slots of group g: own local resampling, then the received tail
-  for (int l = t; l < ng; l += kScanThreads) {
+  for (int l = t; l < ng; l += 256) {
     const int side = (l >= ng - m.moved) ? 1 : 0;
     const int64_t gg = side ? prev : g;
     int j = l;
@@ -845,37 +1157,6 @@ __global__ __launch_bounds__(256) void k_logw(Model m, Buffers b) {
 
 __global__ void k_set_mode(Ctrl* c, int32_t mode) { c->mode = mode; }
 
-// Records of caller-supplied fp32 log weights (standalone resampling).
-__global__ __launch_bounds__(256) void k_records(Model m, Buffers b,
-                                                 const float* __restrict__ logw) {
-  __shared__ double red[8 + 4 * 7];
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool active = i < m.n;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const double l = active ? (double)logw[i] : -INFINITY;
-  const double mv = wave_max(l);
-  if (lane == 0) red[w] = mv;
-  __syncthreads();
-  const double mb = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-  double e = 0.0;
-  if (active) e = isnan(l) ? NAN : (mb == -INFINITY ? 0.0 : exp(l - mb));
-  const double s1 = wave_sum(e), s2 = wave_sum(e * e);
-  __syncthreads();
-  if (lane == 0) {
-    red[8 + w] = s1;
-    red[12 + w] = s2;
-  }
-  __syncthreads();
-  if (t == 0) {
-    double* R = b.R0 + (int64_t)blockIdx.x * kRec;
-    R[0] = mb;
-    R[1] = (red[8] + red[9]) + (red[10] + red[11]);
-    R[2] = (red[12] + red[13]) + (red[14] + red[15]);
-    for (int d = 0; d < 5; ++d) R[3 + d] = 0.0;
-    b.zeros[blockIdx.x] = 0.0;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_philox(uint32_t k0, uint32_t k1,
                                                 const uint4* __restrict__ ctr,
                                                 uint4* __restrict__ out, int64_t n) {
@@ -921,30 +1202,28 @@ hipError_t launch_step(const Model& m, const Buffers& b, const float* obs, hipSt
   }
 }
 
-hipError_t launch_reduce(const Model&, const Buffers& b, int standalone, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3((unsigned)b.nr2), dim3(256), 0, s, b, standalone);
+hipError_t launch_merge(const Model& m, const Buffers& b, int standalone, double u_given,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_merge, dim3((unsigned)b.nch), dim3(256), 0, s, m, b, standalone, u_given);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Model& m, const Buffers& b, int standalone, double u_given,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, m, b, standalone, u_given);
+hipError_t launch_anc(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_anc, dim3((unsigned)b.nseg), dim3(256), 0, s, m, b, w);
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3((unsigned)b.ntiles), dim3(kScanThreads), 0, s, m, b, w);
-  return hipGetLastError();
-}
-
-hipError_t launch_heavy(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_heavy, dim3(kHeavyBlocks), dim3(kScanThreads), 0, s, m, b, w);
+hipError_t launch_anc_heavy(const Model& m, const Buffers& b, const WeightSrc& w,
+                            hipStream_t s) {
+  const int64_t most = (m.n + kSlotChunk - 1) / kSlotChunk;
+  const unsigned grid = (unsigned)(most < kHeavyGrid ? (most > 0 ? most : 1) : kHeavyGrid);
+  hipLaunchKernelGGL(k_anc_heavy, dim3(grid), dim3(256), 0, s, m, b, w);
   return hipGetLastError();
 }
 
 hipError_t launch_rna(const Model& m, const Buffers& b, const WeightSrc& w, const double* u_dev,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_rna, dim3((unsigned)m.G), dim3(kScanThreads), 0, s, m, b, w, u_dev);
+  hipLaunchKernelGGL(k_rna, dim3((unsigned)m.G), dim3(256), 0, s, m, b, w, u_dev);
   return hipGetLastError();
 }
 
