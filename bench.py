@@ -124,7 +124,7 @@ def main():
     achieved_tf = flops_per_particle * n / step_avg_s / 1e12
     # resampling: read 4 B log weight, write 4 B ancestor per particle; the
     # ancestor pass and its overflow pass together, per step
-    res_ms = kt.get("k_anc", (0, 0.0))[1] + kt.get("k_anc_heavy", (0, 0.0))[1]
+    res_ms = kt.get("k_anc", (0, 0.0))[1] + kt.get("k_fill", (0, 0.0))[1]
     res_avg_s = res_ms / max(kt.get("k_anc", (0, 0.0))[0], 1) / 1e3
     res_gbs = 8.0 * n / res_avg_s / 1e9 if res_avg_s > 0 else 0.0
     step_gbs = 48.0 * n / step_avg_s / 1e9
@@ -151,7 +151,7 @@ def main():
                      "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "avg_launch_ms": step_avg_s * 1e3, "flops_per_particle": flops_per_particle,
                      "hbm_gbs_at_48B_per_particle": step_gbs},
-        "roofline_resample": {"bound": "hbm", "kernel": "k_anc+k_anc_heavy", "achieved": res_gbs,
+        "roofline_resample": {"bound": "hbm", "kernel": "k_anc+k_fill", "achieved": res_gbs,
                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": res_gbs / HBM_PEAK_GBS,
                               "avg_launch_ms": res_avg_s * 1e3, "bytes_per_particle": 8},
         "kernel_ms_total": {k: v[1] for k, v in kt.items()},

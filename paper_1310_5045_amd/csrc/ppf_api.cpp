@@ -20,8 +20,8 @@ using ppf::Model;
 
 namespace {
 
-enum KernelId { kKStep, kKMerge, kKAnc, kKAncHeavy, kKRna, kKInit, kKGather, kKLogw, kNumKernels };
-const char* const kKernelNames[kNumKernels] = {"k_step", "k_merge",  "k_anc",    "k_anc_heavy",
+enum KernelId { kKStep, kKMerge, kKAnc, kKFill, kKRna, kKInit, kKGather, kKLogw, kNumKernels };
+const char* const kKernelNames[kNumKernels] = {"k_step", "k_merge",  "k_anc",    "k_fill",
                                                "k_rna",  "k_init",   "k_gather", "k_logw"};
 
 constexpr size_t kAlign = 256;
@@ -128,15 +128,21 @@ Model make_model(const ppf_params* p) {
 
 int64_t record_blocks(int64_t n) { return (n + ppf::kBlock - 1) / ppf::kBlock; }
 // Records per merge chunk: a multiple of 256, at most 2048 (so a chunk's sum
-// of 2^52-bounded integer weights stays below 2^63), aiming at <= 1024 chunks.
+// of 2^52-bounded integer weights stays below 2^63), aiming at <= 256 chunks
+// so that the final merge is one pass of one workgroup.
 int64_t merge_chunk(int64_t nb) {
-  int64_t per = (nb + 256 * 1024 - 1) / (256 * 1024);
+  int64_t per = (nb + 256 * 256 - 1) / (256 * 256);
   if (per < 1) per = 1;
   if (per > 8) per = 8;
   return 256 * per;
 }
 int64_t seg_count(int64_t n) { return (n + ppf::kSegItems - 1) / ppf::kSegItems; }
-int64_t queue_cap(int64_t n) { return (n + ppf::kSlotChunk - 1) / ppf::kSlotChunk + 1; }
+// Runs spill only from segments with more than kCoopSlots slots, each adding
+// at most one entry per particle (kSegItems) plus one per kFillChunk slots.
+int64_t queue_cap(int64_t n) {
+  const int64_t spilling = n / ppf::kCoopSlots + 1;
+  return spilling * ppf::kSegItems + n / ppf::kFillChunk + 16;
+}
 
 void shape(int64_t n, Buffers* bb) {
   bb->nb = record_blocks(n);
@@ -160,8 +166,8 @@ size_t carve(const ppf_params* p, char* base, Buffers* b) {
   bb.ctrl = reinterpret_cast<Ctrl*>(take(sizeof(Ctrl)));
   bb.X0 = reinterpret_cast<float*>(take(sizeof(float) * 5 * n));
   bb.X1 = reinterpret_cast<float*>(take(sizeof(float) * 5 * n));
-  bb.L0 = reinterpret_cast<float*>(take(sizeof(float) * n));
-  bb.L1 = reinterpret_cast<float*>(take(sizeof(float) * n));
+  bb.E0 = reinterpret_cast<float*>(take(sizeof(float) * n));
+  bb.E1 = reinterpret_cast<float*>(take(sizeof(float) * n));
   bb.R0 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nb));
   bb.R1 = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nb));
   bb.pfx = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * bb.nb));
@@ -170,7 +176,7 @@ size_t carve(const ppf_params* p, char* base, Buffers* b) {
   bb.anc = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
   bb.lw64 = reinterpret_cast<double*>(take(sizeof(double) * n));
   bb.lwg = reinterpret_cast<double*>(take(sizeof(double) * G));
-  bb.hq = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * queue_cap(n)));
+  bb.hq = reinterpret_cast<ppf::FillRun*>(take(sizeof(ppf::FillRun) * queue_cap(n)));
   bb.hq_cap = queue_cap(n);
   if (b) *b = bb;
   return off;
@@ -191,7 +197,7 @@ size_t carve_scratch(int64_t n, char* base, Buffers* b) {
   bb.pfx = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * bb.nb));
   bb.CR = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nch));
   bb.cpre = reinterpret_cast<ppf::ChunkPre*>(take(sizeof(ppf::ChunkPre) * bb.nch));
-  bb.hq = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * queue_cap(n)));
+  bb.hq = reinterpret_cast<ppf::FillRun*>(take(sizeof(ppf::FillRun) * queue_cap(n)));
   bb.hq_cap = queue_cap(n);
   if (b) *b = bb;
   return off;
@@ -262,12 +268,11 @@ struct ppf_ctx {
   }
   ppf::WeightSrc filter_weights() const {
     ppf::WeightSrc w{};
-    w.val0 = b.L0;
-    w.val1 = b.L1;
+    w.E0 = b.E0;
+    w.E1 = b.E1;
     w.rec0 = b.R0;
     w.rec1 = b.R1;
     w.use_cur = 1;
-    w.relative = 1;
     return w;
   }
 };
@@ -354,7 +359,7 @@ int ppf_step(ppf_handle h, const float* obs_dev) {
     return h->run(kKRna, [&] { return ppf::launch_rna(h->m, h->b, w, nullptr, h->stream); });
   rc = h->run(kKAnc, [&] { return ppf::launch_anc(h->m, h->b, w, h->stream); });
   if (rc) return rc;
-  return h->run(kKAncHeavy, [&] { return ppf::launch_anc_heavy(h->m, h->b, w, h->stream); });
+  return h->run(kKFill, [&] { return ppf::launch_fill(h->m, h->b, h->stream); });
 }
 
 int ppf_sync(ppf_handle h) {
@@ -567,11 +572,11 @@ int ppf_resample_systematic(const float* logw_dev, int64_t n, double u, int32_t*
   if (rc) return rc;
   b.anc = anc_dev;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const ppf::WeightSrc w{logw_dev, logw_dev, b.R0, b.R0, 0, 0};
+  const ppf::WeightSrc w{logw_dev, logw_dev, b.R0, b.R0, 0, 1};
   hipError_t e = ppf::launch_records(m, b, logw_dev, s);
   if (e == hipSuccess) e = ppf::launch_merge(m, b, 1, u, s);
   if (e == hipSuccess) e = ppf::launch_anc(m, b, w, s);
-  if (e == hipSuccess) e = ppf::launch_anc_heavy(m, b, w, s);
+  if (e == hipSuccess) e = ppf::launch_fill(m, b, s);
   return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
 }
 
@@ -592,7 +597,7 @@ int ppf_resample_rna(const float* logw_dev, int64_t n, int32_t group, int32_t mo
   b.anc = anc_dev;
   b.lwg = lwg_dev;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const ppf::WeightSrc w{logw_dev, logw_dev, b.R0, b.R0, 0, 0};
+  const ppf::WeightSrc w{logw_dev, logw_dev, b.R0, b.R0, 0, 1};
   hipError_t e = ppf::launch_records(m, b, logw_dev, s);
   if (e == hipSuccess) e = ppf::launch_merge(m, b, 1, 0.0, s);
   if (e == hipSuccess) e = ppf::launch_rna(m, b, w, u_dev, s);

@@ -18,24 +18,37 @@ constexpr int kSqCap = 1536;
 constexpr int kMaxPatch = 25;
 constexpr int kMaxGroup = 1024;
 
-// Normalisation record of one block of kBlock particles (doubles):
+// Normalisation record of one block of kBlock particles (doubles), with
+// E = exp(l - m) rounded to fp32 the stored weight of a particle:
 //   [0] m   maximum log weight of the block
-//   [1] B   sum of the fixed-point weights round(exp(l - m) 2^44) (an exact
-//           integer below 2^52, held in a double)
-//   [2] S2  sum exp(2 (l - m)); NaN marks a non-finite log weight
-//   [3..7]  sum exp(l - m) x_d for the five state components
+//   [1] B   sum of the fixed-point weights round(E 2^44) (an exact integer
+//           below 2^52, held in a double)
+//   [2] S2  sum E^2; NaN marks a non-finite log weight
+//   [3..7]  sum E x_d for the five state components
 constexpr int kRec = 8;
 constexpr double kItemScale = 0x1p44;   // fixed-point weight of one particle
 constexpr double kCdfScale = 0x1p62;    // fixed-point scale of the global CDF
 // Chunk prefixes map 2^44-scaled weights to the 2^62-scaled CDF.
 constexpr double kItemToCdf = 0x1p18;
 
-// Systematic resampling: segments of kSegBlocks blocks; at most kSlotChunk
-// output slots per work item (larger slot ranges are split and queued).
+// Systematic resampling: one workgroup per segment of kSegBlocks blocks
+// writes the segment's output slots itself when they are at most kCoopSlots;
+// beyond that its particles' runs of slots go to a global fill queue in
+// pieces of at most kFillChunk slots.
 constexpr int kSegBlocks = 8;
 constexpr int kSegItems = kSegBlocks * kBlock;
-constexpr int kSlotChunk = 4096;
-constexpr int kHeavyGrid = 2048;
+constexpr int kCoopSlots = 1 << 16;
+constexpr int kSlotTile = 4096;  // slots per LDS tile of the segment's writes
+constexpr int kFillChunk = 1 << 16;
+constexpr int kFillGrid = 2048;
+
+// One entry of the fill queue: slots [lo, lo + len) take particle `item`.
+struct FillRun {
+  int32_t item;
+  int32_t lo;
+  int32_t len;
+  int32_t pad;
+};
 
 enum Purpose : uint32_t { kInit = 1, kPropagate = 2, kResample = 3, kRna = 4 };
 
@@ -57,7 +70,7 @@ struct Ctrl {
   int32_t resampled;    // last committed step resampled
   int32_t rolled_back;  // steps rolled back since the host last read this
   int32_t do_resample;  // set by the merge for the resampling kernels
-  int32_t heavy_count;  // slot chunks queued for k_anc_heavy
+  int32_t heavy_count;  // runs queued for k_fill
   uint32_t ticket;      // arrival counter of the merge kernel's chunks
   uint32_t pad0;
   double m, log_sum, ess, delta, cum;
@@ -105,8 +118,8 @@ struct Buffers {
   Ctrl* ctrl;
   float* X0;     // states, 5*n SoA, double-buffered
   float* X1;
-  float* L0;     // stored log weights minus the block maximum, double-buffered
-  float* L1;
+  float* E0;     // stored weights exp(l - m_block) in fp32, double-buffered
+  float* E1;
   double* R0;    // per-block records, double-buffered
   double* R1;
   uint64_t* pfx;    // per block: exclusive prefix of its chunk's relative weights
@@ -115,7 +128,7 @@ struct Buffers {
   int32_t* anc;  // ancestors of the last resampling
   double* lw64;  // fp64 per-particle log weights (caller-set, or output staging)
   double* lwg;   // RNA per-group log(W_g / n)
-  uint64_t* hq;  // queued slot chunks: (segment << 32) | chunk index
+  FillRun* hq;   // queued long runs of output slots
   int64_t hq_cap;   // entries of hq
   int64_t nb;       // block records = ceil(n / kBlock)
   int64_t chunk;    // records per merge chunk (multiple of 256, at most 2048)
@@ -123,17 +136,18 @@ struct Buffers {
   int64_t nseg;     // resampling segments = ceil(n / kSegItems)
 };
 
-// Where the resampling kernels read log weights. Filter: the stored value L
-// selected by ctrl->cur, relative to its block maximum; standalone: the
-// caller's absolute fp32 log weights (relative = 0). The particle's fixed-point
-// weight is round(exp(relative ? L : L - m_block) 2^44).
+// Where the resampling kernels read weights, with the block records: the
+// filter's stored E (the pair selected by ctrl->cur), or a caller's absolute
+// fp32 log weights (log_src = 1, standalone resampling). A particle's weight
+// relative to its block maximum is e = E, or exp(x - m_block) in fp64 for
+// log weights; its fixed-point weight inside its block is round(e 2^44).
 struct WeightSrc {
-  const float* val0;
-  const float* val1;
+  const float* E0;
+  const float* E1;
   const double* rec0;
   const double* rec1;
   int32_t use_cur;
-  int32_t relative;
+  int32_t log_src;
 };
 
 // Kernel launchers (ppf_kernels.hip). Each returns the launch status.
@@ -142,8 +156,7 @@ hipError_t launch_step(const Model& m, const Buffers& b, const float* obs, hipSt
 hipError_t launch_merge(const Model& m, const Buffers& b, int standalone, double u_given,
                         hipStream_t s);
 hipError_t launch_anc(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s);
-hipError_t launch_anc_heavy(const Model& m, const Buffers& b, const WeightSrc& w,
-                            hipStream_t s);
+hipError_t launch_fill(const Model& m, const Buffers& b, hipStream_t s);
 hipError_t launch_rna(const Model& m, const Buffers& b, const WeightSrc& w, const double* u_dev,
                       hipStream_t s);
 hipError_t launch_gather(const Model& m, const Buffers& b, float* out, hipStream_t s);

@@ -8,10 +8,9 @@
 //                the normaliser, ESS, MMSE estimate, resampling decision and
 //                uniform, commits or rolls back the step, and writes the
 //                fixed-point CDF prefixes of the record chunks
-//   k_anc        systematic resampling: per segment of 2048 particles, the
-//                ancestors of the output slots whose uniforms fall in it,
-//                by a merge of slot positions and the segment's CDF
-//   k_anc_heavy  the remaining slot chunks of segments that own many slots
+//   k_anc        systematic resampling: per segment of 2048 particles, each
+//                particle's run of output slots from the segment's CDF
+//   k_fill       long runs of slots queued by k_anc (concentrated weights)
 //   (or k_rna    RNA of Section 3: one workgroup per group of particles)
 #include "ppf_internal.hpp"
 
@@ -168,6 +167,23 @@ __device__ __forceinline__ T block_reduce(T v, T* sh, Op op) {
   return r;
 }
 
+// Sums of K values over a 256-thread workgroup with one LDS exchange
+// (sh: 4 * K doubles), each in a fixed order.
+template <int K>
+__device__ __forceinline__ void block_sum_n(double (&v)[K], double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_reduce(v[k], lane, OpAdd());
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[w * K + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = (sh[k] + sh[K + k]) + (sh[2 * K + k] + sh[3 * K + k]);
+  __syncthreads();
+}
+
 // Exclusive prefix sum of exact unsigned integers over a 256-thread
 // workgroup; *total receives the sum of all.
 __device__ __forceinline__ uint64_t block_excl_sum(uint64_t v, uint64_t* sh, uint64_t* total) {
@@ -260,9 +276,9 @@ __device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int 
   double lw;
   if (mode == kModeSys || mode == kModeRna) p = b.anc[i];
   if (mode == kModeNone) {
-    const float* Lin = cur ? b.L1 : b.L0;
+    const float* Ein = cur ? b.E1 : b.E0;
     const double* Rin = cur ? b.R1 : b.R0;
-    lw = (double)Lin[i] + Rin[(i / kBlock) * kRec] - delta;
+    lw = log((double)Ein[i]) + Rin[(i / kBlock) * kRec] - delta;
   } else if (mode == kModeRna) {
     const int64_t g = i / m.group;
     const int64_t l = i - g * m.group;
@@ -311,27 +327,28 @@ __device__ __forceinline__ double item_weight(double e) {
   return fma(e, kItemScale, 0x1p52) - 0x1p52;
 }
 
-// The block's normalisation record (see kRec) and the stored log weights
-// l - m_b. red: 7 x 256 doubles of LDS, free for reuse by the caller.
+// The block's normalisation record (see kRec) and the stored weights
+// E = exp(l - m_b) in fp32. red: 7 x 256 doubles of LDS, free for reuse by
+// the caller.
 __device__ __forceinline__ void finish_block(const Buffers& b, int cur, int64_t i, bool active,
                                              double l, const Prop& o, double* red,
                                              double* dsh) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const bool bad = active && (isnan(l) || l == INFINITY);
   const double mb = block_reduce((active && !bad) ? l : -INFINITY, dsh, OpMax());
-  double e = 0.0, wi = 0.0;
+  double e = 0.0;
   if (active) {
-    float Lf = -INFINITY;
+    float Ef = 0.0f;
     if (bad) {
-      Lf = NAN;
+      Ef = NAN;
     } else if (mb != -INFINITY && l != -INFINITY) {
-      Lf = (float)(l - mb);
-      e = exp((double)Lf);
-      wi = item_weight(e);
+      Ef = (float)exp(l - mb);
+      e = (double)Ef;
     }
-    float* Lout = cur ? b.L0 : b.L1;
-    Lout[i] = Lf;
+    float* Eout = cur ? b.E0 : b.E1;
+    Eout[i] = Ef;
   }
+  const double wi = item_weight(e);
   // block_reduce ended with a barrier: every thread is past its reads of
   // the LDS that red aliases
   red[t] = wi;
@@ -585,7 +602,8 @@ __global__ __launch_bounds__(256) void k_step_lg(Model m, Buffers b,
 }
 
 // Records of caller-supplied absolute fp32 log weights (standalone
-// resampling): the same record layout, with zero state sums.
+// resampling): the same layout, with weights e = exp(x - m) in fp64 and zero
+// state sums.
 __global__ __launch_bounds__(256) void k_records(Model m, Buffers b,
                                                  const float* __restrict__ logw) {
   __shared__ double red[2 * 256];
@@ -641,6 +659,7 @@ __global__ __launch_bounds__(256) void k_records(Model m, Buffers b,
 __global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalone,
                                                double u_given) {
   __shared__ double dsh[4];
+  __shared__ double nsh[4 * 7];
   __shared__ uint64_t ush[4];
   __shared__ int sh_last;
   __shared__ int sh_pre;
@@ -684,17 +703,14 @@ __global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalon
       run += (uint64_t)rint(r[1] * f);
     }
   }
-  const double S2c = block_reduce(s2, dsh, OpAdd());
-  double exc[5];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) exc[d] = block_reduce(ex[d], dsh, OpAdd());
+  double sums[6] = {s2, ex[0], ex[1], ex[2], ex[3], ex[4]};
+  block_sum_n(sums, nsh);
   if (t == 0) {
     double* cr = b.CR + ch * kRec;
     cr[0] = Mc;
     cr[1] = __longlong_as_double((long long)qtot);
-    cr[2] = S2c;
 #pragma unroll
-    for (int d = 0; d < 5; ++d) cr[3 + d] = exc[d];
+    for (int d = 0; d < 6; ++d) cr[2 + d] = sums[d];
   }
   // arrival: the last workgroup finishes the step
   __threadfence();
@@ -707,11 +723,10 @@ __global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalon
   const int64_t nch = b.nch;
   const int per2 = (int)((nch + 255) / 256);
   const int64_t c0 = (int64_t)t * per2;
-  auto ld = [&](int64_t idx) {
-    return __longlong_as_double((long long)__hip_atomic_load(
-        reinterpret_cast<unsigned long long*>(b.CR) + idx, __ATOMIC_RELAXED,
-        __HIP_MEMORY_SCOPE_AGENT));
-  };
+  // the device-scope fence above orders these plain loads after every
+  // chunk's record (each chunk fenced before taking its ticket)
+  const double* CRd = b.CR;
+  auto ld = [&](int64_t idx) { return CRd[idx]; };
   double mx2 = -INFINITY;
   for (int q = 0; q < per2; ++q) {
     const int64_t cc = c0 + q;
@@ -731,10 +746,14 @@ __global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalon
       for (int d = 0; d < 5; ++d) E[d] += ld(cc * kRec + 3 + d) * f;
     }
   }
-  S = block_reduce(S, dsh, OpAdd()) * (1.0 / kItemScale);
-  S2 = block_reduce(S2, dsh, OpAdd());
+  {
+    double tot7[7] = {S, S2, E[0], E[1], E[2], E[3], E[4]};
+    block_sum_n(tot7, nsh);
+    S = tot7[0] * (1.0 / kItemScale);
+    S2 = tot7[1];
 #pragma unroll
-  for (int d = 0; d < 5; ++d) E[d] = block_reduce(E[d], dsh, OpAdd());
+    for (int d = 0; d < 5; ++d) E[d] = tot7[2 + d];
+  }
   if (t == 0) {
     bool ok = isfinite(M) && isfinite(S) && S > 0.0 && isfinite(S2);
 #pragma unroll
@@ -807,106 +826,99 @@ __global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalon
 }
 
 // --------------------------------------------------- systematic resampling
-// Slot s of N takes the particle j whose CDF interval holds (s + u) / N
-// (Algorithm 1's resampling step with one uniform u). Positions and CDF are
-// 2^62 fixed point; positions at or beyond the total are clamped below it,
-// so every slot lands on a particle of positive weight.
-__device__ __forceinline__ uint64_t slot_pos(int64_t s, double u, double inv_n, uint64_t total) {
-  const uint64_t p = (uint64_t)((((double)s + u) * inv_n) * kCdfScale);
-  return p < total ? p : total - 1;
-}
+// Slot s of N takes the particle j whose CDF interval [C_{j-1}, C_j) holds
+// (s + u) / N (Algorithm 1's resampling step with one uniform u), so
+// particle j owns the slots [bound(C_{j-1}), bound(C_j)) with bound(C) the
+// number of slots below C. Block starts of the CDF are exact 2^62 fixed-point
+// integers (so the partition of the slots over segments does not depend on
+// summation order); inside a segment the CDF is a running maximum in fp64,
+// so particles of zero weight own no slots, and the segment's last particle
+// of positive weight takes the segment's remaining slots.
 
-// Number of slots whose position is below P.
-__device__ int64_t first_slot(uint64_t P, double u, double inv_n, uint64_t total, int64_t n) {
-  if (P >= total) return n;
-  const double est = (double)P * (1.0 / kCdfScale) * (double)n - u;
-  int64_t s = est <= 0.0 ? 0 : (est >= (double)n ? n : (int64_t)ceil(est));
-  while (s > 0 && slot_pos(s - 1, u, inv_n, total) >= P) --s;
-  while (s < n && slot_pos(s, u, inv_n, total) < P) ++s;
-  return s;
-}
-
-// CDF position of the start of block blk.
-__device__ __forceinline__ uint64_t block_P(const Buffers& b, int64_t blk) {
+// CDF position of the start of block blk, as a fraction of the total.
+__device__ __forceinline__ double block_P(const Buffers& b, int64_t blk) {
   const ChunkPre cp = b.cpre[blk / b.chunk];
-  return cp.P + (uint64_t)rint((double)b.pfx[blk] * cp.phi);
+  const uint64_t P = cp.P + (uint64_t)rint((double)b.pfx[blk] * cp.phi);
+  return (double)P * (1.0 / kCdfScale);
 }
 
-// First output slot of segment seg (seg == nseg: n).
-__device__ __forceinline__ int64_t seg_start(const Buffers& b, int64_t seg, double u,
-                                             double inv_n, uint64_t total, int64_t n) {
-  if (seg <= 0) return 0;
-  if (seg >= b.nseg) return n;
-  return first_slot(block_P(b, seg * kSegBlocks), u, inv_n, total, n);
+// Number of slots s in [0, n) with (s + u) / n < C: ceil(C n - u), clamped.
+// Monotone in C (the fma rounds once), so bounds taken at non-decreasing CDF
+// values never overlap.
+__device__ __forceinline__ int slot_bound(double C, double u, double nd, int n) {
+  const double x = ceil(fma(C, nd, -u));
+  return x <= 0.0 ? 0 : (x >= nd ? n : (int)x);
 }
 
-struct SegShared {
-  uint64_t C[kSegItems];      // CDF (upper end) of each loaded particle
-  int32_t stage[kSlotChunk];  // ancestors of the slots, for coalesced stores
-  uint64_t Pb[kSegBlocks + 1];
-  uint64_t u4[4];
+struct AncShared {
+  int A[kSlotTile];  // owner marks of one tile of slots, then their running maximum
+  double Pb[kSegBlocks + 1];
+  double d4[4];
   int i4[4];
+  int i8[4];
 };
 
-// Ancestors of the slots [s_lo, s_hi) (at most kSlotChunk), all of which lie
-// in segment seg. Loads the blocks of the segment that hold these slots,
-// builds their CDF (a running maximum, so particles of zero weight never own
-// an interval), and merges it with the slot positions: each thread takes an
-// equal share of the merged sequence (merge path).
-__device__ void seg_process(const Model& m, const Buffers& b, const WeightSrc& ws, int cur,
-                            double delta, double u, uint64_t total, int64_t seg, int64_t s_lo,
-                            int64_t s_hi, SegShared& sh) {
+// One workgroup per segment of kSegItems particles (eight consecutive per
+// thread): the segment's slot range from its block starts, the particles'
+// CDF from their fixed-point weights, every particle's run of slots, and
+// the slots' particles, written tile by tile.
+__global__ __launch_bounds__(256) void k_anc(Model m, Buffers b, WeightSrc ws) {
+  __shared__ AncShared sh;
+  Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int64_t n = m.n;
-  const int M = (int)(s_hi - s_lo);
+  const int cur = c->cur;
+  const double delta = c->delta, u = c->u;
+  const int n = (int)m.n;
+  const double nd = (double)m.n;
+  const int64_t seg = blockIdx.x;
   const int64_t b0 = seg * kSegBlocks;
   const int nbs = (int)min((int64_t)kSegBlocks, b.nb - b0);
-  if (t <= nbs)
-    sh.Pb[t] = (t < nbs) ? block_P(b, b0 + t) : (b0 + nbs < b.nb ? block_P(b, b0 + nbs) : total);
+  if (t <= nbs) sh.Pb[t] = (b0 + t < b.nb) ? block_P(b, b0 + t) : 1.0;
   __syncthreads();
-  const double inv_n = m.inv_n;
-  const uint64_t U_lo = slot_pos(s_lo, u, inv_n, total);
-  const uint64_t U_hi = slot_pos(s_hi - 1, u, inv_n, total);
-  int ba = 0, bb = 0;
-  for (int q = 1; q < nbs; ++q) {
-    if (sh.Pb[q] <= U_lo) ba = q;
-    if (sh.Pb[q] <= U_hi) bb = q;
-  }
-  const int64_t ib0 = (b0 + ba) * kBlock;
-  const int64_t ib1 = min(n, (b0 + bb + 1) * kBlock);
-  const int n_it = (int)(ib1 - ib0);
+  const int fs = seg == 0 ? 0 : slot_bound(sh.Pb[0], u, nd, n);
+  const int fe = seg + 1 >= b.nseg ? n : slot_bound(sh.Pb[nbs], u, nd, n);
+  if (fe <= fs) return;  // uniform: no slot falls in this segment
 
   const bool second = ws.use_cur && cur;
-  const float* val = second ? ws.val1 : ws.val0;
+  const float* E = second ? ws.E1 : ws.E0;
   const double* rec = second ? ws.rec1 : ws.rec0;
+  const int64_t ib0 = b0 * kBlock;
+  const int64_t ib1 = min(m.n, (b0 + nbs) * kBlock);
   const int64_t j0 = ib0 + 8 * (int64_t)t;
   const bool mine = j0 < ib1;
   double wi[8], kl[8];
   double tsum = 0.0;
-  uint64_t Pblk = 0;
-  double f = 0.0;
+  double Pblk = 0.0, f = 0.0;
   if (mine) {
     const int64_t blk = j0 / kBlock;
     const double mblk = rec[blk * kRec];
-    const double sub = ws.relative ? 0.0 : mblk;
     float x[8];
-    // vector loads only from 16-byte aligned bases (callers' views may not be)
-    if (j0 + 8 <= ib1 && (reinterpret_cast<uintptr_t>(val) & 15) == 0) {
-      const float4 v0 = *reinterpret_cast<const float4*>(val + j0);
-      const float4 v1 = *reinterpret_cast<const float4*>(val + j0 + 4);
+    // vector loads only from 16-byte aligned bases
+    if (j0 + 8 <= ib1 && (reinterpret_cast<uintptr_t>(E) & 15) == 0) {
+      const float4 v0 = *reinterpret_cast<const float4*>(E + j0);
+      const float4 v1 = *reinterpret_cast<const float4*>(E + j0 + 4);
       x[0] = v0.x; x[1] = v0.y; x[2] = v0.z; x[3] = v0.w;
       x[4] = v1.x; x[5] = v1.y; x[6] = v1.z; x[7] = v1.w;
     } else {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) x[q] = (j0 + q < ib1) ? val[j0 + q] : -INFINITY;
+      for (int q = 0; q < 8; ++q)
+        x[q] = (j0 + q < ib1) ? E[j0 + q] : (ws.log_src ? -INFINITY : 0.0f);
+    }
+    if (ws.log_src) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        wi[q] = item_weight(x[q] == -INFINITY ? 0.0 : exp((double)x[q] - mblk));
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) wi[q] = item_weight((double)x[q]);
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      wi[q] = x[q] == -INFINITY ? 0.0 : item_weight(exp((double)x[q] - sub));
       tsum += wi[q];
       kl[q] = tsum;
     }
-    f = (mblk == -INFINITY) ? 0.0 : exp(mblk - delta) * kItemToCdf;
+    f = (mblk == -INFINITY) ? 0.0 : exp(mblk - delta) * (1.0 / kItemScale);
     Pblk = sh.Pb[blk - b0];
   } else {
 #pragma unroll
@@ -919,117 +931,134 @@ __device__ void seg_process(const Model& m, const Buffers& b, const WeightSrc& w
   if ((lane >> 4) == 1) inc += r0;
   else if ((lane >> 4) == 3) inc += r2;
   const double texcl = inc - tsum;  // exact: integers below 2^53
-  uint64_t cq[8];
-  uint64_t tmax = 0;
+  double cq[8];
+  double tmax = 0.0;
   int lp = -1;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    uint64_t v = 0;
+    double v = 0.0;
     if (wi[q] > 0.0) {
-      v = Pblk + (uint64_t)rint((texcl + kl[q]) * f);
+      v = fma(texcl + kl[q], f, Pblk);
       lp = 8 * t + q;
     }
-    tmax = v > tmax ? v : tmax;
+    tmax = fmax(tmax, v);
     cq[q] = v;
   }
-  // running maximum across the threads, starting at the first block's start
-  const uint64_t winc = wave_scan(tmax, lane, OpMax());
-  uint64_t wex = __shfl_up(winc, 1, 64);
-  if (lane == 0) wex = 0;
-  if (lane == 63) sh.u4[w] = winc;
+  // running maximum of the CDF across the threads, from the segment's start
+  const double winc = wave_scan(tmax, lane, OpMax());
+  double wex = __shfl_up(winc, 1, 64);
+  if (lane == 0) wex = 0.0;
+  if (lane == 63) sh.d4[w] = winc;
   const int lpw = wave_reduce(lp, lane, OpMax());
   if (lane == 0) sh.i4[w] = lpw;
   __syncthreads();
-  uint64_t carry = sh.Pb[ba];
-  for (int q = 0; q < w; ++q) carry = sh.u4[q] > carry ? sh.u4[q] : carry;
-  carry = wex > carry ? wex : carry;
-  // the block holding the first slot has positive weight, so last_pos >= 0;
-  // the clamp keeps every written ancestor a valid index regardless
-  const int last_pos = max(max(max(sh.i4[0], sh.i4[1]), max(sh.i4[2], sh.i4[3])), 0);
+  double carry = sh.Pb[0];
+  for (int q = 0; q < w; ++q) carry = fmax(carry, sh.d4[q]);
+  carry = fmax(carry, wex);
+  const int last_pos = max(max(sh.i4[0], sh.i4[1]), max(sh.i4[2], sh.i4[3]));
+  // runs: particle 8t+q owns the slots [st[q], hq[q]) with hq the bound of
+  // the running CDF; the last particle of positive weight (and every
+  // particle after it) ends at the segment's end
+  int st[8], hq[8];
+  {
+    int hprev = min(max(slot_bound(carry, u, nd, n), fs), fe);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    carry = cq[q] > carry ? cq[q] : carry;
-    if (8 * t + q < n_it) sh.C[8 * t + q] = carry;
-  }
-  __syncthreads();
-
-  // merge path over n_it particles and M slots; a slot precedes particle a
-  // iff its position is below C[a]
-  const int tot_el = n_it + M;
-  const int per = (tot_el + 255) / 256;
-  const int d0 = min(t * per, tot_el), d1 = min(d0 + per, tot_el);
-  int lo = max(0, d0 - M), hi = min(d0, n_it);
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (sh.C[mid] <= slot_pos(s_lo + (d0 - mid - 1), u, inv_n, total))
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  int a = lo, bs = d0 - lo;
-  uint64_t ucur = bs < M ? slot_pos(s_lo + bs, u, inv_n, total) : 0;
-  for (int d = d0; d < d1; ++d) {
-    if (bs < M && (a >= n_it || ucur < sh.C[a])) {
-      sh.stage[bs] = (int32_t)(ib0 + (a < n_it ? a : last_pos));
-      ++bs;
-      if (bs < M) ucur = slot_pos(s_lo + bs, u, inv_n, total);
-    } else {
-      ++a;
+    for (int q = 0; q < 8; ++q) {
+      carry = fmax(carry, cq[q]);
+      const int idx = 8 * t + q;
+      int lo = hprev, hv = hprev;
+      if (idx > last_pos) {
+        lo = hv = fe;  // after the last particle of positive weight: no slots
+      } else if (idx == last_pos) {
+        hv = fe;
+      } else if (wi[q] > 0.0) {
+        hv = min(max(slot_bound(carry, u, nd, n), fs), fe);
+      }
+      st[q] = lo;
+      hq[q] = hv;
+      hprev = hv;
     }
   }
-  __syncthreads();
-  for (int q = t; q < M; q += 256) b.anc[s_lo + q] = sh.stage[q];
-  __syncthreads();
-}
-
-__global__ __launch_bounds__(256) void k_anc(Model m, Buffers b, WeightSrc ws) {
-  __shared__ SegShared sh;
-  __shared__ int64_t sh_se[2];
-  __shared__ int sh_base;
-  Ctrl* c = b.ctrl;
-  if (!c->do_resample) return;
-  const int cur = c->cur;
-  const double delta = c->delta, u = c->u;
-  const uint64_t total = c->total;
-  const int64_t seg = blockIdx.x;
-  if (threadIdx.x < 2) sh_se[threadIdx.x] = seg_start(b, seg + threadIdx.x, u, m.inv_n, total, m.n);
-  __syncthreads();
-  const int64_t fs = sh_se[0], fe = sh_se[1];
-  if (fe <= fs) return;
-  if (fe - fs > kSlotChunk) {
-    const int nq = (int)((fe - fs + kSlotChunk - 1) / kSlotChunk) - 1;
-    if (threadIdx.x == 0) sh_base = atomicAdd(&c->heavy_count, nq);
-    __syncthreads();
-    // the queue holds at most n / kSlotChunk + 1 entries, which the slot
-    // counts cannot exceed; entries beyond it are never written
-    for (int q = threadIdx.x; q < nq; q += 256)
-      if (sh_base >= 0 && (int64_t)sh_base + q < b.hq_cap)
-        b.hq[sh_base + q] = ((uint64_t)seg << 32) | (uint64_t)(q + 1);
+  const int M = fe - fs;
+  int32_t* anc = b.anc;
+  if (M <= kCoopSlots) {
+    // tiles of slots: each run marks its first slot with its particle; the
+    // running maximum of the marks (particles increase with slots) is then
+    // every slot's particle
+    int carry_item = -1;
+    constexpr int kk = kSlotTile / 256;
+    for (int c0 = fs; c0 < fe; c0 += kSlotTile) {
+      const int cn = min(kSlotTile, fe - c0);
+#pragma unroll
+      for (int k = 0; k < kk; ++k) sh.A[k * 256 + t] = -1;
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (hq[q] > st[q] && st[q] >= c0 && st[q] < c0 + cn) sh.A[st[q] - c0] = 8 * t + q;
+      __syncthreads();
+      int v[kk];
+      int run = -1;
+#pragma unroll
+      for (int k = 0; k < kk; ++k) {
+        run = max(run, sh.A[t * kk + k]);
+        v[k] = run;
+      }
+      const int winc2 = wave_scan(run, lane, OpMax());
+      int wex2 = __shfl_up(winc2, 1, 64);
+      if (lane == 0) wex2 = -1;
+      if (lane == 63) sh.i8[w] = winc2;
+      __syncthreads();
+      int before = carry_item;
+      for (int q = 0; q < w; ++q) before = max(before, sh.i8[q]);
+      before = max(before, wex2);
+      // the particles back into the tile, then stored with consecutive
+      // threads on consecutive slots
+#pragma unroll
+      for (int k = 0; k < kk; ++k) sh.A[t * kk + k] = max(max(before, v[k]), 0);
+      carry_item = max(max(carry_item, max(sh.i8[0], sh.i8[1])), max(sh.i8[2], sh.i8[3]));
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kk; ++k) {
+        const int e = k * 256 + t;
+        if (e < cn) anc[c0 + e] = (int32_t)(ib0 + sh.A[e]);
+      }
+      __syncthreads();  // sh.A and sh.i8 are rewritten by the next tile
+    }
+  } else if (mine) {
+    // too many slots for one workgroup: queue this thread's runs for k_fill
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int lo = st[q], len = hq[q] - st[q];
+      if (len > 0) {
+        const int32_t item = (int32_t)(j0 + q);
+        const int pieces = (len + kFillChunk - 1) / kFillChunk;
+        const int base = atomicAdd(&c->heavy_count, pieces);
+        for (int pc = 0; pc < pieces; ++pc) {
+          const int plo = lo + pc * kFillChunk;
+          const int plen = min(kFillChunk, len - pc * kFillChunk);
+          if (base >= 0 && (int64_t)base + pc < b.hq_cap) {
+            b.hq[base + pc] = FillRun{item, plo, plen, 0};
+          } else {
+            for (int r = 0; r < plen; ++r) anc[plo + r] = item;  // ruled out by the queue's size
+          }
+        }
+      }
+    }
   }
-  seg_process(m, b, ws, cur, delta, u, total, seg, fs, min(fe, fs + (int64_t)kSlotChunk), sh);
 }
 
-// Slot chunks queued by k_anc (segments owning more than kSlotChunk slots).
-__global__ __launch_bounds__(256) void k_anc_heavy(Model m, Buffers b, WeightSrc ws) {
-  __shared__ SegShared sh;
-  __shared__ int64_t sh_se[2];
+// Long runs queued by k_anc: each workgroup fills whole runs, coalesced.
+__global__ __launch_bounds__(256) void k_fill(Model m, Buffers b) {
   const Ctrl* c = b.ctrl;
   if (!c->do_resample) return;
   const int64_t nh = min((int64_t)c->heavy_count, b.hq_cap);
-  const int cur = c->cur;
-  const double delta = c->delta, u = c->u;
-  const uint64_t total = c->total;
   for (int64_t q = blockIdx.x; q < nh; q += gridDim.x) {
-    const uint64_t e = b.hq[q];
-    const int64_t seg = (int64_t)(e >> 32), kq = (int64_t)(e & 0xffffffffu);
-    if (seg >= b.nseg) continue;  // uniform: every thread read the same entry
-    if (threadIdx.x < 2)
-      sh_se[threadIdx.x] = seg_start(b, seg + threadIdx.x, u, m.inv_n, total, m.n);
-    __syncthreads();
-    const int64_t fs = sh_se[0], fe = sh_se[1];
-    __syncthreads();
-    const int64_t lo = fs + kq * kSlotChunk, hi = min(fe, lo + (int64_t)kSlotChunk);
-    if (lo < hi) seg_process(m, b, ws, cur, delta, u, total, seg, lo, hi, sh);
+    const FillRun r = b.hq[q];
+    if (r.lo < 0 || r.len <= 0 || (int64_t)r.lo + r.len > m.n || r.item < 0 ||
+        (int64_t)r.item >= m.n)
+      continue;
+    int32_t* out = b.anc + r.lo;
+    for (int k = threadIdx.x; k < r.len; k += 256) out[k] = r.item;
   }
 }
 
@@ -1050,7 +1079,7 @@ __global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
   Ctrl* c = b.ctrl;
   if (!c->do_resample) return;
   const bool second = ws.use_cur && c->cur;
-  const float* val = second ? ws.val1 : ws.val0;
+  const float* E = second ? ws.E1 : ws.E0;
   const double* rec = second ? ws.rec1 : ws.rec0;
   const int64_t g = blockIdx.x;
   const int ng = m.group;
@@ -1071,8 +1100,12 @@ __global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
       wl[j] = 0.0;
       if (li < ng) {
         const int64_t idx = base + li;
-        const double off = ws.relative ? rec[(idx / kBlock) * kRec] : 0.0;
-        wl[j] = exp((double)val[idx] + off - lognorm);
+        if (ws.log_src) {
+          wl[j] = exp((double)E[idx] - lognorm);
+        } else {
+          const double mb = rec[(idx / kBlock) * kRec];
+          wl[j] = mb == -INFINITY ? 0.0 : (double)E[idx] * exp(mb - lognorm);
+        }
         part += wl[j];
       }
     }
@@ -1150,9 +1183,9 @@ __global__ __launch_bounds__(256) void k_logw(Model m, Buffers b) {
     b.lw64[i] = -m.log_n;
     return;
   }
-  const float* L = c->cur ? b.L1 : b.L0;
+  const float* E = c->cur ? b.E1 : b.E0;
   const double* R = c->cur ? b.R1 : b.R0;
-  b.lw64[i] = (double)L[i] + R[(i / kBlock) * kRec] - c->delta;
+  b.lw64[i] = log((double)E[i]) + R[(i / kBlock) * kRec] - c->delta;
 }
 
 __global__ void k_set_mode(Ctrl* c, int32_t mode) { c->mode = mode; }
@@ -1213,11 +1246,9 @@ hipError_t launch_anc(const Model& m, const Buffers& b, const WeightSrc& w, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_anc_heavy(const Model& m, const Buffers& b, const WeightSrc& w,
-                            hipStream_t s) {
-  const int64_t most = (m.n + kSlotChunk - 1) / kSlotChunk;
-  const unsigned grid = (unsigned)(most < kHeavyGrid ? (most > 0 ? most : 1) : kHeavyGrid);
-  hipLaunchKernelGGL(k_anc_heavy, dim3(grid), dim3(256), 0, s, m, b, w);
+hipError_t launch_fill(const Model& m, const Buffers& b, hipStream_t s) {
+  const unsigned grid = (unsigned)(b.hq_cap < kFillGrid ? b.hq_cap : kFillGrid);
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, s, m, b);
   return hipGetLastError();
 }
 
