@@ -32,9 +32,11 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    // one 32 x 32 -> 64-bit product gives both halves
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                   (uint32_t)p0);
   }
   return c;
 }
@@ -68,6 +70,29 @@ __device__ __forceinline__ void box_muller64(uint32_t a, uint32_t b, double& z0,
   sincospi(2.0 * (double)u24_open_hi(b), &s, &c);
   z0 = rad * c;
   z1 = rad * s;
+}
+
+// e^x for finite x: Cody-Waite reduction x = k ln2 + r with ln 2 split into
+// a 32-bit head (k * head exact) and a tail, |r| <= ln2 / 2, and the Taylor
+// polynomial of degree 11 (truncation below 7e-15 relative); the result is
+// scaled by 2^k (0 below the subnormal range, inf above the finite one).
+__device__ __forceinline__ double exp_fast(double x) {
+  const double k = rint(x * 0x1.71547652b82fep+0);  // x / ln 2
+  double r = fma(-k, 0x1.62e42fee00000p-1, x);
+  r = fma(-k, 0x1.a39ef35793c76p-33, r);
+  double p = 0x1.ae64567f544e4p-26;     // 1/11!
+  p = fma(p, r, 0x1.27e4fb7789f5cp-22);  // 1/10!
+  p = fma(p, r, 0x1.71de3a556c734p-19);  // 1/9!
+  p = fma(p, r, 0x1.a01a01a01a01ap-16);  // 1/8!
+  p = fma(p, r, 0x1.a01a01a01a01ap-13);  // 1/7!
+  p = fma(p, r, 0x1.6c16c16c16c17p-10);  // 1/6!
+  p = fma(p, r, 0x1.1111111111111p-7);   // 1/5!
+  p = fma(p, r, 0x1.5555555555555p-5);   // 1/4!
+  p = fma(p, r, 0x1.5555555555555p-3);   // 1/3!
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)fmax(fmin(k, 2100.0), -2100.0));
 }
 
 // ------------------------------------------------------ wave64 primitives
@@ -328,29 +353,32 @@ __device__ __forceinline__ double item_weight(double e) {
 }
 
 // The block's normalisation record (see kRec) and the stored weights
-// E = exp(l - m_b) in fp32. red: 7 x 256 doubles of LDS, free for reuse by
-// the caller.
+// E = exp(l - m_b) in fp32. red: 7 x 256 doubles of LDS that no thread reads
+// once it has reached this call (it may alias the caller's image tile).
 __device__ __forceinline__ void finish_block(const Buffers& b, int cur, int64_t i, bool active,
                                              double l, const Prop& o, double* red,
                                              double* dsh) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const bool bad = active && (isnan(l) || l == INFINITY);
-  const double mb = block_reduce((active && !bad) ? l : -INFINITY, dsh, OpMax());
+  const double wm = wave_reduce((active && !bad) ? l : -INFINITY, lane, OpMax());
+  if (lane == 0) dsh[w] = wm;
+  __syncthreads();
+  const double mb = fmax(fmax(dsh[0], dsh[1]), fmax(dsh[2], dsh[3]));
   double e = 0.0;
   if (active) {
     float Ef = 0.0f;
     if (bad) {
       Ef = NAN;
     } else if (mb != -INFINITY && l != -INFINITY) {
-      Ef = (float)exp(l - mb);
+      Ef = (float)exp_fast(l - mb);
       e = (double)Ef;
     }
     float* Eout = cur ? b.E0 : b.E1;
     Eout[i] = Ef;
   }
   const double wi = item_weight(e);
-  // block_reduce ended with a barrier: every thread is past its reads of
-  // the LDS that red aliases
+  // after the barrier above every thread is past its reads of the LDS that
+  // red may alias
   red[t] = wi;
   red[256 + t] = bad ? NAN : e * e;
   red[512 + t] = e * (double)o.x;
@@ -378,10 +406,12 @@ __device__ __forceinline__ void finish_block(const Buffers& b, int cur, int64_t 
 // Patch sums of one particle over P rows of an LDS tile with row stride tw:
 //   X   += sum_dy g_y(dy) sum_dx Z g_x(dx)    (Gaussian-weighted pixel sum)
 //   Gy, G2y: sum of g_y and of g_y^2
-//   sd2 += sum (Z - b)^2 when the per-centre table is not used (!TAB).
+//   sd2 += sum (Z - b)^2, from the table of row sums hrow (stride hs) when
+//          TAB, else pixel by pixel.
 // g_y is advanced by the exact recurrence g(d+1) = g(d) gstep(d) exp(f/s^2).
 template <int P, bool TAB>
 __device__ __forceinline__ void patch_lds(const float* __restrict__ p0, int tw,
+                                          const double* __restrict__ hrow, int hs,
                                           const double (&gx)[P], double gy, double by,
                                           const double* gstep, double bsub, double& X,
                                           double& Gy, double& G2y, double& sd2) {
@@ -398,6 +428,7 @@ __device__ __forceinline__ void patch_lds(const float* __restrict__ p0, int tw,
         sd2 = fma(d, d, sd2);
       }
     }
+    if (TAB) sd2 += hrow[dy * hs];
     X = fma(gy, rd, X);
     Gy += gy;
     G2y = fma(gy, gy, G2y);
@@ -440,10 +471,13 @@ __device__ __forceinline__ void patch_global(const float* __restrict__ obs, int 
 // with sum D g = sum Z g - b sum g (pixels outside the frame hold Z = b, so
 // D = 0 there) and sum g^2 = (sum g_x^2)(sum g_y^2); everything in fp64. The
 // workgroup stages the bounding box of its patches in LDS and, when small
-// enough, a table of sum D^2 for every patch centre in the box.
+// enough, a table of the P-pixel row sums of D^2 at every patch-centre
+// column, so a particle adds P table entries instead of squaring P^2 pixels.
+// Four barriers per workgroup: the box, the tile and table, the block
+// maximum, and the record exchange.
 template <int P>
-__global__ __launch_bounds__(256) void k_step_spot(Model m, Buffers b,
-                                                   const float* __restrict__ obs) {
+__device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
+                                          const float* __restrict__ obs) {
   constexpr int h = (P - 1) / 2;
   __shared__ __align__(16) float tile[kTileCap];
   __shared__ double sq[kSqCap];
@@ -473,6 +507,25 @@ __global__ __launch_bounds__(256) void k_step_spot(Model m, Buffers b,
     cx = (rx >= lox && rx <= hix) ? (int)rx : (rx > hix ? (int)hix : (int)lox);
     cy = (ry >= loy && ry <= hiy) ? (int)ry : (ry > hiy ? (int)hiy : (int)loy);
   }
+  // the 1-D Gaussian factors of Eq. 3 at the patch's pixel offsets
+  double gx[P];
+  double Gx = 0.0, G2x = 0.0, gy0 = 0.0, by = 0.0;
+  if (active) {
+    gx[0] = exp_fast(-((double)h + fx) * ((double)h + fx) * m.inv2s2);
+    const double bx = exp_fast(2.0 * fx * m.inv2s2);
+#pragma unroll
+    for (int d = 0; d + 1 < P; ++d) gx[d + 1] = gx[d] * (m.gstep[d] * bx);
+#pragma unroll
+    for (int d = 0; d < P; ++d) {
+      Gx += gx[d];
+      G2x = fma(gx[d], gx[d], G2x);
+    }
+    gy0 = exp_fast(-((double)h + fy) * ((double)h + fy) * m.inv2s2);
+    by = exp_fast(2.0 * fy * m.inv2s2);
+  } else {
+#pragma unroll
+    for (int d = 0; d < P; ++d) gx[d] = 0.0;
+  }
   // bounding box of the workgroup's patch centres
   {
     const int a0 = wave_reduce(active ? cx : INT_MAX, lane, OpMin());
@@ -495,9 +548,9 @@ __global__ __launch_bounds__(256) void k_step_spot(Model m, Buffers b,
   const bool use_lds = tw64 * th64 <= kTileCap;  // uniform across the workgroup
   const int tw = (int)tw64, th = (int)th64;
   const int tx0 = mnx - h, ty0 = mny - h;
-  const int64_t acx = (int64_t)mxx - mnx + 1, acy = (int64_t)mxy - mny + 1;
-  const int64_t nH = th64 * acx, nV = acx * acy;
-  const bool use_tab = use_lds && nH + nV <= kSqCap;
+  const int64_t acx = (int64_t)mxx - mnx + 1;
+  const int64_t nH = th64 * acx;
+  const bool use_tab = use_lds && nH <= kSqCap;
   if (use_lds) {
     for (int r = w; r < th; r += 4) {
       const int v = ty0 + r;
@@ -509,62 +562,40 @@ __global__ __launch_bounds__(256) void k_step_spot(Model m, Buffers b,
       }
     }
   }
-  __syncthreads();
   if (use_tab) {
-    // row pass: sq[r][c] = sum_dx (Z[r][c + dx] - b)^2 for c < acx
-    const int ax = (int)acx, nh = (int)nH, nv = (int)nV;
+    // sq[r * acx + c] = sum_dx (Z[r][c + dx] - b)^2 over the tile's rows r and
+    // the centres' columns c, read from the frame (so it needs no barrier
+    // after the tile)
+    const int ax = (int)acx, nh = (int)nH;
     const float rcp = 1.0f / (float)ax;
     for (int e = t; e < nh; e += 256) {
       int r = (int)((float)e * rcp);
       if (r * ax > e) --r;
       else if ((r + 1) * ax <= e) ++r;
-      const float* row = tile + r * tw + (e - r * ax);
-      double s = 0.0;
+      const int v = ty0 + r, u0 = tx0 + (e - r * ax);
+      const bool rin = (unsigned)v < (unsigned)m.H;
+      const float* src = obs + (int64_t)(rin ? v : 0) * m.W;
+      double sacc = 0.0;
 #pragma unroll
       for (int dx = 0; dx < P; ++dx) {
-        const double d = (double)row[dx] - m.b;
-        s = fma(d, d, s);
+        const int u = u0 + dx;
+        const double d = (double)((rin && (unsigned)u < (unsigned)m.W) ? src[u] : m.bf) - m.b;
+        sacc = fma(d, d, sacc);
       }
-      sq[e] = s;
+      sq[e] = sacc;
     }
-    __syncthreads();
-    // centre pass: sq[nH + rr * acx + c] = sum_dy sq[(rr + dy) * acx + c]
-    for (int e = t; e < nv; e += 256) {
-      int r = (int)((float)e * rcp);
-      if (r * ax > e) --r;
-      else if ((r + 1) * ax <= e) ++r;
-      const double* col = sq + r * ax + (e - r * ax);
-      double s = 0.0;
-#pragma unroll
-      for (int dy = 0; dy < P; ++dy) s += col[dy * ax];
-      sq[nh + e] = s;
-    }
-    __syncthreads();
   }
+  __syncthreads();
 
   double l = -INFINITY;
   if (active) {
-    double gx[P];
-    gx[0] = exp(-((double)h + fx) * ((double)h + fx) * m.inv2s2);
-    const double bx = exp(2.0 * fx * m.inv2s2);
-#pragma unroll
-    for (int d = 0; d + 1 < P; ++d) gx[d + 1] = gx[d] * (m.gstep[d] * bx);
-    double Gx = 0.0, G2x = 0.0;
-#pragma unroll
-    for (int d = 0; d < P; ++d) {
-      Gx += gx[d];
-      G2x = fma(gx[d], gx[d], G2x);
-    }
-    const double gy0 = exp(-((double)h + fy) * ((double)h + fy) * m.inv2s2);
-    const double by = exp(2.0 * fy * m.inv2s2);
     double X = 0.0, Gy = 0.0, G2y = 0.0, sd2 = 0.0;
+    const float* p0 = tile + (cy - h - ty0) * tw + (cx - h - tx0);
     if (use_tab) {
-      patch_lds<P, true>(tile + (cy - h - ty0) * tw + (cx - h - tx0), tw, gx, gy0, by, m.gstep,
-                         m.b, X, Gy, G2y, sd2);
-      sd2 = sq[nH + (int64_t)(cy - mny) * acx + (cx - mnx)];
+      patch_lds<P, true>(p0, tw, sq + (int64_t)(cy - mny) * acx + (cx - mnx), (int)acx, gx, gy0,
+                         by, m.gstep, m.b, X, Gy, G2y, sd2);
     } else if (use_lds) {
-      patch_lds<P, false>(tile + (cy - h - ty0) * tw + (cx - h - tx0), tw, gx, gy0, by, m.gstep,
-                          m.b, X, Gy, G2y, sd2);
+      patch_lds<P, false>(p0, tw, sq, 0, gx, gy0, by, m.gstep, m.b, X, Gy, G2y, sd2);
     } else {
       patch_global<P>(obs, cx - h, cy - h, m.W, m.H, m.bf, gx, gy0, by, m.gstep, m.b, X, Gy, G2y,
                       sd2);
@@ -575,6 +606,20 @@ __global__ __launch_bounds__(256) void k_step_spot(Model m, Buffers b,
     l = o.lw - ssq * m.inv2sig2 - m.lognorm_obs;
   }
   finish_block(b, cur, i, active, l, o, reinterpret_cast<double*>(tile), dsh);
+}
+
+// Patches up to 15 x 15 fit five waves per SIMD in registers without
+// spilling; wider ones keep the compiler's default budget.
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+void k_step_spot(Model m, Buffers b, const float* __restrict__ obs) {
+  step_spot<P>(m, b, obs);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_step_spot_wide(Model m, Buffers b,
+                                                        const float* __restrict__ obs) {
+  step_spot<P>(m, b, obs);
 }
 
 // Linear-Gaussian observation of (x, y, I0): three fp32 values on the device.
@@ -1199,7 +1244,10 @@ __global__ __launch_bounds__(256) void k_philox(uint32_t k0, uint32_t k1,
 
 template <int P>
 hipError_t launch_spot(const Model& m, const Buffers& b, const float* obs, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_spot<P>, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);
+  if (P <= 15)
+    hipLaunchKernelGGL(k_step_spot<P>, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);
+  else
+    hipLaunchKernelGGL(k_step_spot_wide<P>, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);
   return hipGetLastError();
 }
 
