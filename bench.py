@@ -14,10 +14,21 @@ Prints one JSON line. `value` is N * steps / wall time of the timed steps.
 use algorithmic work per launch / average launch time measured with HIP
 events on the filter's stream. `cpu_baseline` times the FP64 oracle on a
 bounded sample of the same workload on the host.
+
+`roofline.traffic` is the HBM traffic of one k_step launch in bytes, taken
+from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE) of this script
+with `--copy-probe-mib`, each counter scaled by what it reads for a plain
+device copy of known size. `--traffic-from FETCH_DB WRITE_DB` turns the two
+databases into profiles/traffic_<kernel>_<workload>.json, stamped with a hash
+of the kernel sources; a run reports the figure only while the hash still
+matches (null otherwise).
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
+import sqlite3
 import sys
 import time
 
@@ -27,6 +38,74 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+KERNEL_SOURCES = ("paper_1310_5045_amd/csrc/ppf_kernels.hip",
+                  "paper_1310_5045_amd/csrc/ppf_internal.hpp")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_path(kernel, workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+
+
+def _counter_per_dispatch(db, counter):
+    """{dispatch_id: (kernel name, counter summed over the dispatch's instances)}."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select dispatch_id, kernel_name, counter_name, sum(value) "
+                       "from counters_collection group by dispatch_id, counter_name").fetchall()
+    con.close()
+    return {d: (k, v) for d, k, c, v in rows if c == counter}
+
+
+def traffic_from(fetch_db, write_db, workload, copy_mib, warmup, steps, kernel="k_step",
+                 match="k_step_spot"):
+    """Writes the traffic record of `kernel` from a FETCH_SIZE and a WRITE_SIZE
+    counter database of `bench.py --copy-probe-mib copy_mib` runs with the
+    given warm-up and timed steps; the average covers the timed launches."""
+    copy_bytes = copy_mib * (1 << 20)
+    per = {}
+    for name, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
+        d = _counter_per_dispatch(db, name)
+        ker = [d[i][1] for i in sorted(d) if match in d[i][0]][warmup:]
+        if len(ker) != steps:
+            raise SystemExit(f"{db}: {len(ker)} timed {match} dispatches, expected {steps}")
+        # the probe copies copy_bytes: the largest reading among the kernels
+        # named like a copy
+        cp = ([v for k, v in d.values() if "copy" in k.lower()] or
+              [v for k, v in d.values() if "elementwise" in k.lower()])
+        if not ker or not cp:
+            raise SystemExit(f"{db}: no {match} or copy dispatches with {name}")
+        kib_copy = max(cp)
+        per[name] = dict(kernel_kib_avg=sum(ker) / len(ker), launches=len(ker), copy_kib=kib_copy,
+                         scale=copy_bytes / (kib_copy * 1024.0))
+    traffic = sum(per[c]["kernel_kib_avg"] * 1024.0 * per[c]["scale"] for c in per)
+    rec = {"kernel": kernel, "workload": workload, "source_sha256": kernel_source_hash(),
+           "traffic_bytes_per_launch": traffic, "copy_probe_bytes": copy_bytes,
+           "counters": per,
+           "command": [f"rocprofv3 --kernel-trace --pmc {c} -d <dir> -o run -- python3 bench.py "
+                       f"--steps {steps} --warmup {warmup} --no-cpu-baseline "
+                       f"--copy-probe-mib {copy_mib}" for c in per]}
+    with open(traffic_path(kernel, workload), "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    return rec
+
+
+def load_traffic(kernel, workload):
+    try:
+        with open(traffic_path(kernel, workload)) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 WORKLOADS = {
     # frame size, frames, particles, spot width, patch, resampling threshold
@@ -71,7 +150,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write the k_step traffic record from two counter databases and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        dbs = []
+        for p in args.traffic_from:
+            dbs.append(p if p.endswith(".db") else sorted(glob.glob(os.path.join(p, "*.db")))[0])
+        rec = traffic_from(dbs[0], dbs[1], args.workload, args.copy_probe_mib or 1024,
+                           args.warmup, args.steps)
+        print(json.dumps(rec))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -91,6 +182,13 @@ def main():
                             noise_sd=3.0, seed=1)
     torch.cuda.set_device(0)
     frames = torch.from_numpy(mv.frames).cuda()
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     f = ppf.Filter(make_params(ppf, w, init_kind))
     stream = f.stream
     # warm-up: a few steps, then a fresh initial cloud for the timed steps
@@ -148,7 +246,8 @@ def main():
                    "init": args.init, "frames_timed": K},
         "roofline": {"bound": "alu", "kernel": "k_step", "achieved": achieved_tf,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": load_traffic("k_step", args.workload),
                      "avg_launch_ms": step_avg_s * 1e3, "flops_per_particle": flops_per_particle,
                      "hbm_gbs_at_48B_per_particle": step_gbs},
         "roofline_resample": {"bound": "hbm", "kernel": "k_anc+k_fill", "achieved": res_gbs,

@@ -96,7 +96,6 @@ Model make_model(const ppf_params* p) {
     m.init_a[d] = p->init_a[d];
     m.init_b[d] = p->init_b[d];
   }
-  m.bf = p->background;
   m.b = (double)p->background;
   const double s = p->psf_sigma, sg = p->noise_sigma;
   m.inv2s2 = 1.0 / (2.0 * s * s);

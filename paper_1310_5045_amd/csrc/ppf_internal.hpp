@@ -11,9 +11,9 @@ namespace ppf {
 // Particles per k_step workgroup; also the granularity of the per-block
 // normalisation records and of the stored log-weight offsets.
 constexpr int kBlock = 256;
-// LDS image tile of one k_step workgroup (floats) and its per-centre table of
-// patch sums of squares (doubles: row pass + centre pass).
-constexpr int kTileCap = 4096;
+// LDS image tile of one k_step workgroup (D = Z - b as doubles) and its
+// table of P-pixel row sums of D^2 at the patch-centre columns (doubles).
+constexpr int kTileCap = 2048;
 constexpr int kSqCap = 1536;
 constexpr int kMaxPatch = 25;
 constexpr int kMaxGroup = 1024;
@@ -99,7 +99,6 @@ struct Model {
   float q[5];
   float init_a[5];
   float init_b[5];
-  float bf;              // background as the fp32 value used for tile padding
   double b;              // background
   double inv2s2;         // 1 / (2 s^2)
   double inv2sig2;       // 1 / (2 sigma_xi^2)

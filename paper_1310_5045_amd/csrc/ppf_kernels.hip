@@ -403,34 +403,31 @@ __device__ __forceinline__ void finish_block(const Buffers& b, int cur, int64_t 
   }
 }
 
-// Patch sums of one particle over P rows of an LDS tile with row stride tw:
-//   X   += sum_dy g_y(dy) sum_dx Z g_x(dx)    (Gaussian-weighted pixel sum)
-//   Gy, G2y: sum of g_y and of g_y^2
-//   sd2 += sum (Z - b)^2, from the table of row sums hrow (stride hs) when
-//          TAB, else pixel by pixel.
+// Patch sums of one particle over P rows of an LDS tile of D = Z - b (0
+// outside the frame) with row stride tw:
+//   X   += sum_dy g_y(dy) sum_dx D g_x(dx)    (Gaussian-weighted residual sum)
+//   G2y += g_y^2
+//   sd2 += sum D^2, from the table of row sums hrow (stride hs) when TAB,
+//          else pixel by pixel.
 // g_y is advanced by the exact recurrence g(d+1) = g(d) gstep(d) exp(f/s^2).
 template <int P, bool TAB>
-__device__ __forceinline__ void patch_lds(const float* __restrict__ p0, int tw,
+__device__ __forceinline__ void patch_lds(const double* __restrict__ p0, int tw,
                                           const double* __restrict__ hrow, int hs,
                                           const double (&gx)[P], double gy, double by,
-                                          const double* gstep, double bsub, double& X,
-                                          double& Gy, double& G2y, double& sd2) {
+                                          const double* gstep, double& X, double& G2y,
+                                          double& sd2) {
 #pragma unroll 1
   for (int dy = 0; dy < P; ++dy) {
-    const float* row = p0 + dy * tw;
+    const double* row = p0 + dy * tw;
     double rd = 0.0;
 #pragma unroll
     for (int dx = 0; dx < P; ++dx) {
-      const double z = (double)row[dx];
-      rd = fma(z, gx[dx], rd);
-      if (!TAB) {
-        const double d = z - bsub;
-        sd2 = fma(d, d, sd2);
-      }
+      const double d = row[dx];
+      rd = fma(d, gx[dx], rd);
+      if (!TAB) sd2 = fma(d, d, sd2);
     }
     if (TAB) sd2 += hrow[dy * hs];
     X = fma(gy, rd, X);
-    Gy += gy;
     G2y = fma(gy, gy, G2y);
     gy *= gstep[dy] * by;
   }
@@ -440,10 +437,9 @@ __device__ __forceinline__ void patch_lds(const float* __restrict__ p0, int tw,
 // not fit one LDS tile); pixels outside the frame read as the background.
 template <int P>
 __device__ __forceinline__ void patch_global(const float* __restrict__ obs, int u0, int v0,
-                                             int W, int H, float bf, const double (&gx)[P],
+                                             int W, int H, double bsub, const double (&gx)[P],
                                              double gy, double by, const double* gstep,
-                                             double bsub, double& X, double& Gy, double& G2y,
-                                             double& sd2) {
+                                             double& X, double& G2y, double& sd2) {
 #pragma unroll 1
   for (int dy = 0; dy < P; ++dy) {
     const int v = v0 + dy;
@@ -453,13 +449,11 @@ __device__ __forceinline__ void patch_global(const float* __restrict__ obs, int 
 #pragma unroll
     for (int dx = 0; dx < P; ++dx) {
       const int u = u0 + dx;
-      const double z = (double)((row_in && (unsigned)u < (unsigned)W) ? row[u] : bf);
-      rd = fma(z, gx[dx], rd);
-      const double d = z - bsub;
+      const double d = (row_in && (unsigned)u < (unsigned)W) ? (double)row[u] - bsub : 0.0;
+      rd = fma(d, gx[dx], rd);
       sd2 = fma(d, d, sd2);
     }
     X = fma(gy, rd, X);
-    Gy += gy;
     G2y = fma(gy, gy, G2y);
     gy *= gstep[dy] * by;
   }
@@ -468,18 +462,20 @@ __device__ __forceinline__ void patch_global(const float* __restrict__ obs, int 
 // Propagation and log weight of one particle per thread (Eq. 4 with the spot
 // of Eq. 3 on the P x P patch). The residual sum is expanded as
 //   sum (D - I g)^2 = sum D^2 - 2 I sum D g + I^2 sum g^2,   D = Z - b,
-// with sum D g = sum Z g - b sum g (pixels outside the frame hold Z = b, so
-// D = 0 there) and sum g^2 = (sum g_x^2)(sum g_y^2); everything in fp64. The
-// workgroup stages the bounding box of its patches in LDS and, when small
-// enough, a table of the P-pixel row sums of D^2 at every patch-centre
-// column, so a particle adds P table entries instead of squaring P^2 pixels.
-// Four barriers per workgroup: the box, the tile and table, the block
+// (D = 0 for pixels outside the frame) with sum g^2 = (sum g_x^2)(sum g_y^2);
+// everything in fp64. The workgroup stages D over the bounding box of its
+// patches in LDS as fp64 (the conversion is paid once per pixel, not once per
+// particle and pixel) and, when small enough, a table of the P-pixel row sums
+// of D^2 at every patch-centre column, so a particle adds P table entries
+// instead of squaring P^2 pixels.
+// Five barriers per workgroup: the box, the tile, the table, the block
 // maximum, and the record exchange.
 template <int P>
 __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
                                           const float* __restrict__ obs) {
   constexpr int h = (P - 1) / 2;
-  __shared__ __align__(16) float tile[kTileCap];
+  __shared__ __align__(16) double tile[kTileCap];
+  static_assert(kTileCap >= 7 * kBlock, "the tile doubles as the record exchange buffer");
   __shared__ double sq[kSqCap];
   __shared__ double dsh[4];
   __shared__ int ish[16];
@@ -509,17 +505,14 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   }
   // the 1-D Gaussian factors of Eq. 3 at the patch's pixel offsets
   double gx[P];
-  double Gx = 0.0, G2x = 0.0, gy0 = 0.0, by = 0.0;
+  double G2x = 0.0, gy0 = 0.0, by = 0.0;
   if (active) {
     gx[0] = exp_fast(-((double)h + fx) * ((double)h + fx) * m.inv2s2);
     const double bx = exp_fast(2.0 * fx * m.inv2s2);
 #pragma unroll
     for (int d = 0; d + 1 < P; ++d) gx[d + 1] = gx[d] * (m.gstep[d] * bx);
 #pragma unroll
-    for (int d = 0; d < P; ++d) {
-      Gx += gx[d];
-      G2x = fma(gx[d], gx[d], G2x);
-    }
+    for (int d = 0; d < P; ++d) G2x = fma(gx[d], gx[d], G2x);
     gy0 = exp_fast(-((double)h + fy) * ((double)h + fy) * m.inv2s2);
     by = exp_fast(2.0 * fy * m.inv2s2);
   } else {
@@ -551,37 +544,44 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   const int64_t acx = (int64_t)mxx - mnx + 1;
   const int64_t nH = th64 * acx;
   const bool use_tab = use_lds && nH <= kSqCap;
+  // Row stride ts = tw padded to ts = acx (mod 16): a patch row of the centre
+  // (cx, cy) then starts at the double (cy - mny) acx + (cx - mnx) (mod 16),
+  // so lanes at up to 16 distinct centres of an acx-wide box read distinct
+  // pairs of the 32 four-byte LDS banks.
+  int ts = tw;
+  {
+    const int padw = ((int)(acx & 15) - (tw & 15)) & 15;
+    if ((int64_t)(tw + padw) * th <= kTileCap) ts = tw + padw;
+  }
   if (use_lds) {
-    for (int r = w; r < th; r += 4) {
-      const int v = ty0 + r;
-      const bool rin = (unsigned)v < (unsigned)m.H;
-      const float* src = obs + (int64_t)(rin ? v : 0) * m.W;
-      for (int col = lane; col < tw; col += 64) {
-        const int u = tx0 + col;
-        tile[r * tw + col] = (rin && (unsigned)u < (unsigned)m.W) ? src[u] : m.bf;
-      }
+    // one pass over the tile's pixels (row r = e / tw from a float reciprocal,
+    // corrected by one step: e < 2^11, so the estimate is off by at most 1)
+    const int nt = tw * th;
+    const float rcpw = 1.0f / (float)tw;
+    for (int e = t; e < nt; e += 256) {
+      int r = (int)((float)e * rcpw);
+      if (r * tw > e) --r;
+      else if ((r + 1) * tw <= e) ++r;
+      const int c = e - r * tw, v = ty0 + r, u = tx0 + c;
+      tile[r * ts + c] = ((unsigned)v < (unsigned)m.H && (unsigned)u < (unsigned)m.W)
+                             ? (double)obs[(int64_t)v * m.W + u] - m.b
+                             : 0.0;
     }
   }
+  __syncthreads();
   if (use_tab) {
     // sq[r * acx + c] = sum_dx (Z[r][c + dx] - b)^2 over the tile's rows r and
-    // the centres' columns c, read from the frame (so it needs no barrier
-    // after the tile)
+    // the centres' columns c
     const int ax = (int)acx, nh = (int)nH;
     const float rcp = 1.0f / (float)ax;
     for (int e = t; e < nh; e += 256) {
       int r = (int)((float)e * rcp);
       if (r * ax > e) --r;
       else if ((r + 1) * ax <= e) ++r;
-      const int v = ty0 + r, u0 = tx0 + (e - r * ax);
-      const bool rin = (unsigned)v < (unsigned)m.H;
-      const float* src = obs + (int64_t)(rin ? v : 0) * m.W;
+      const double* src = tile + r * ts + (e - r * ax);
       double sacc = 0.0;
 #pragma unroll
-      for (int dx = 0; dx < P; ++dx) {
-        const int u = u0 + dx;
-        const double d = (double)((rin && (unsigned)u < (unsigned)m.W) ? src[u] : m.bf) - m.b;
-        sacc = fma(d, d, sacc);
-      }
+      for (int dx = 0; dx < P; ++dx) sacc = fma(src[dx], src[dx], sacc);
       sq[e] = sacc;
     }
   }
@@ -589,26 +589,24 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
 
   double l = -INFINITY;
   if (active) {
-    double X = 0.0, Gy = 0.0, G2y = 0.0, sd2 = 0.0;
-    const float* p0 = tile + (cy - h - ty0) * tw + (cx - h - tx0);
+    double X = 0.0, G2y = 0.0, sd2 = 0.0;
+    const double* p0 = tile + (cy - h - ty0) * ts + (cx - h - tx0);
     if (use_tab) {
-      patch_lds<P, true>(p0, tw, sq + (int64_t)(cy - mny) * acx + (cx - mnx), (int)acx, gx, gy0,
-                         by, m.gstep, m.b, X, Gy, G2y, sd2);
+      patch_lds<P, true>(p0, ts, sq + (int64_t)(cy - mny) * acx + (cx - mnx), (int)acx, gx, gy0,
+                         by, m.gstep, X, G2y, sd2);
     } else if (use_lds) {
-      patch_lds<P, false>(p0, tw, sq, 0, gx, gy0, by, m.gstep, m.b, X, Gy, G2y, sd2);
+      patch_lds<P, false>(p0, ts, sq, 0, gx, gy0, by, m.gstep, X, G2y, sd2);
     } else {
-      patch_global<P>(obs, cx - h, cy - h, m.W, m.H, m.bf, gx, gy0, by, m.gstep, m.b, X, Gy, G2y,
-                      sd2);
+      patch_global<P>(obs, cx - h, cy - h, m.W, m.H, m.b, gx, gy0, by, m.gstep, X, G2y, sd2);
     }
-    X -= m.b * (Gx * Gy);
     const double I = (double)o.I;
     const double ssq = sd2 - 2.0 * I * X + I * I * (G2x * G2y);
     l = o.lw - ssq * m.inv2sig2 - m.lognorm_obs;
   }
-  finish_block(b, cur, i, active, l, o, reinterpret_cast<double*>(tile), dsh);
+  finish_block(b, cur, i, active, l, o, tile, dsh);
 }
 
-// Patches up to 15 x 15 fit five waves per SIMD in registers without
+// Patches up to 13 x 13 fit five waves per SIMD in registers without
 // spilling; wider ones keep the compiler's default budget.
 template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
@@ -1244,7 +1242,7 @@ __global__ __launch_bounds__(256) void k_philox(uint32_t k0, uint32_t k1,
 
 template <int P>
 hipError_t launch_spot(const Model& m, const Buffers& b, const float* obs, hipStream_t s) {
-  if (P <= 15)
+  if constexpr (P <= 13)
     hipLaunchKernelGGL(k_step_spot<P>, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);
   else
     hipLaunchKernelGGL(k_step_spot_wide<P>, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);
