@@ -32,11 +32,12 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    // one 32 x 32 -> 64-bit product gives both halves
+    // one 32 x 32 -> 64-bit product gives both halves; each three-way xor
+    // is one v_bitop3 (truth table 0x96 = a ^ b ^ c)
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
-                   (uint32_t)p0);
+    c = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96), (uint32_t)p1,
+                   __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96), (uint32_t)p0);
   }
   return c;
 }
@@ -96,30 +97,45 @@ __device__ __forceinline__ double exp_fast(double x) {
 }
 
 // ------------------------------------------------------ wave64 primitives
-// Cross-lane moves use DPP row shifts (row_shr:k, within rows of 16 lanes;
+// Cross-lane moves use DPP within rows of 16 lanes: row shifts (row_shr:k;
 // lanes whose source falls outside the row read 0 and are masked off by the
-// callers) and v_readlane for the four row results. Every helper must be
-// called with all 64 lanes active.
+// callers) for scans, row rotations (row_ror:k) for reductions, and
+// v_readlane for the four row results. Every helper must be called with all
+// 64 lanes active.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, true);
 }
 
-template <int K>
-__device__ __forceinline__ int shr(int v) {
-  return (int)dpp32<0x110 + K>((uint32_t)v);
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v) {
+  return (int)dpp32<CTRL>((uint32_t)v);
 }
-template <int K>
-__device__ __forceinline__ uint64_t shr(uint64_t v) {
-  return (uint64_t)dpp32<0x110 + K>((uint32_t)v) |
-         ((uint64_t)dpp32<0x110 + K>((uint32_t)(v >> 32)) << 32);
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return dpp32<CTRL>(v);
 }
-template <int K>
-__device__ __forceinline__ double shr(double v) {
-  return __longlong_as_double((long long)shr<K>((uint64_t)__double_as_longlong(v)));
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp(uint64_t v) {
+  return (uint64_t)dpp32<CTRL>((uint32_t)v) | ((uint64_t)dpp32<CTRL>((uint32_t)(v >> 32)) << 32);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  return __longlong_as_double((long long)dpp<CTRL>((uint64_t)__double_as_longlong(v)));
+}
+template <int K, class T>
+__device__ __forceinline__ T shr(T v) {
+  return dpp<0x110 + K>(v);
+}
+template <int K, class T>
+__device__ __forceinline__ T ror(T v) {
+  return dpp<0x120 + K>(v);
 }
 
 __device__ __forceinline__ int readlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
 __device__ __forceinline__ uint64_t readlane(uint64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
@@ -143,6 +159,14 @@ struct OpMax {
 struct OpMin {
   __device__ __forceinline__ int operator()(int a, int b) const { return a < b ? a : b; }
 };
+// Elementwise minimum of two int16 pairs packed in 32 bits (v_pk_min_i16).
+struct OpMin16x2 {
+  __device__ __forceinline__ uint32_t operator()(uint32_t a, uint32_t b) const {
+    typedef short s2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(s2, a),
+                                                                  __builtin_bit_cast(s2, b)));
+  }
+};
 
 // Inclusive scan within each row of 16 lanes (r = lane & 15).
 template <class T, class Op>
@@ -158,11 +182,23 @@ __device__ __forceinline__ T row_scan(T v, int r, Op op) {
   return v;
 }
 
+// Reduction within each row of 16 lanes; every lane receives its row's
+// result, combined in an order fixed for each lane.
+template <class T, class Op>
+__device__ __forceinline__ T row_allreduce(T v, Op op) {
+  v = op(v, ror<1>(v));
+  v = op(v, ror<2>(v));
+  v = op(v, ror<4>(v));
+  v = op(v, ror<8>(v));
+  return v;
+}
+
 // Reduction over the wave, in a fixed order (result uniform).
 template <class T, class Op>
 __device__ __forceinline__ T wave_reduce(T v, int lane, Op op) {
-  v = row_scan(v, lane & 15, op);
-  return op(op(readlane(v, 15), readlane(v, 31)), op(readlane(v, 47), readlane(v, 63)));
+  (void)lane;
+  v = row_allreduce(v, op);
+  return op(op(readlane(v, 0), readlane(v, 16)), op(readlane(v, 32), readlane(v, 48)));
 }
 
 // Inclusive scan over the wave, in a fixed order.
@@ -392,9 +428,9 @@ __device__ __forceinline__ void finish_block(const Buffers& b, int cur, int64_t 
     const double* p = red + (t >> 5) * 256 + (t & 31) * 8;
     s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
   }
-  s = row_scan(s, lane & 15, OpAdd());
-  const double h0 = readlane(s, 15) + readlane(s, 31);  // value 2w
-  const double h1 = readlane(s, 47) + readlane(s, 63);  // value 2w + 1
+  s = row_allreduce(s, OpAdd());
+  const double h0 = readlane(s, 0) + readlane(s, 16);   // value 2w
+  const double h1 = readlane(s, 32) + readlane(s, 48);  // value 2w + 1
   if (lane == 0) {
     double* R = (cur ? b.R0 : b.R1) + (int64_t)blockIdx.x * kRec;
     R[1 + 2 * w] = h0;
@@ -519,17 +555,27 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
 #pragma unroll
     for (int d = 0; d < P; ++d) gx[d] = 0.0;
   }
-  // bounding box of the workgroup's patch centres
+  // Bounding box of the workgroup's patch centres. Each lane packs the
+  // offsets (ox, oy) of its centre from lane 0's, saturated to +-32767, as
+  // two int16 (for the minima) and their negations (for the maxima); an
+  // offset at the saturation bound already makes the box wider than any
+  // tile, so the saturated box still selects the global path. A wave with no
+  // particle reports an empty box.
   {
-    const int a0 = wave_reduce(active ? cx : INT_MAX, lane, OpMin());
-    const int a1 = wave_reduce(active ? cx : INT_MIN, lane, OpMax());
-    const int a2 = wave_reduce(active ? cy : INT_MAX, lane, OpMin());
-    const int a3 = wave_reduce(active ? cy : INT_MIN, lane, OpMax());
+    const int bx0 = readlane(cx, 0), by0 = readlane(cy, 0);
+    const int ox = min(max(cx - bx0, -32767), 32767), oy = min(max(cy - by0, -32767), 32767);
+    const uint32_t pmin = active ? ((uint32_t)(uint16_t)ox | ((uint32_t)(uint16_t)oy << 16))
+                                 : 0x7fff7fffu;
+    const uint32_t pneg = active ? ((uint32_t)(uint16_t)-ox | ((uint32_t)(uint16_t)-oy << 16))
+                                 : 0x7fff7fffu;
+    const uint32_t rmin = wave_reduce(pmin, lane, OpMin16x2());
+    const uint32_t rneg = wave_reduce(pneg, lane, OpMin16x2());
+    const bool any = (int64_t)blockIdx.x * kBlock + w * 64 < m.n;
     if (lane == 0) {
-      ish[w] = a0;
-      ish[4 + w] = a1;
-      ish[8 + w] = a2;
-      ish[12 + w] = a3;
+      ish[w] = any ? bx0 + (int16_t)(rmin & 0xffffu) : INT_MAX;
+      ish[4 + w] = any ? bx0 - (int16_t)(rneg & 0xffffu) : INT_MIN;
+      ish[8 + w] = any ? by0 + (int16_t)(rmin >> 16) : INT_MAX;
+      ish[12 + w] = any ? by0 - (int16_t)(rneg >> 16) : INT_MIN;
     }
   }
   __syncthreads();
@@ -678,9 +724,9 @@ __global__ __launch_bounds__(256) void k_records(Model m, Buffers b,
     const double* p = red + (t >> 5) * 256 + (t & 31) * 8;
     s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
   }
-  s = row_scan(s, lane & 15, OpAdd());
-  const double h0 = readlane(s, 15) + readlane(s, 31);
-  const double h1 = readlane(s, 47) + readlane(s, 63);
+  s = row_allreduce(s, OpAdd());
+  const double h0 = readlane(s, 0) + readlane(s, 16);
+  const double h1 = readlane(s, 32) + readlane(s, 48);
   if (t == 0) {
     double* R = b.R0 + (int64_t)blockIdx.x * kRec;
     R[0] = mb;
