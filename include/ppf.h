@@ -303,6 +303,62 @@ int ppf_resample_rna(const float* logw_dev, int64_t n, int32_t group, int32_t mo
                      const double* u_dev, int32_t* anc_dev, double* lwg_dev, void* scratch,
                      size_t scratch_bytes, void* hip_stream);
 
+/* ------------------------------------------ batched independent filters */
+
+/*
+ * A batch runs `count` independent SIR filters (tracks) over one shared
+ * frame stream: each track is exactly the filter ppf_create would build from
+ * its own ppf_params (its own N, patch, spot model, noise, resampling scheme
+ * and threshold, seed and track_id), and after every step its particles,
+ * weights, ancestors and statistics are bit-identical to that single filter's.
+ * Tracking many spots in one movie (Section 6) this way costs one launch per
+ * kernel kind per frame for the whole batch instead of one set per spot.
+ * Every track must use the spot observation model (Eq. 3-4) and the same
+ * frame width and height. Distinct track_ids give distinct random streams.
+ */
+typedef struct ppf_batch_ctx* ppf_batch;
+
+/* Workspace bytes for a batch of `count` tracks with parameters p[0..count-1].
+ * EINVAL: count < 1, a track's parameters invalid, a track not on the spot
+ * model, or frame sizes that differ between tracks. */
+int ppf_batch_workspace_bytes(const ppf_params* p, int32_t count, size_t* bytes);
+
+/*
+ * Create a batch in a caller-owned device workspace (256-byte aligned, at
+ * least ppf_batch_workspace_bytes) and initialise every track (k = 0). The
+ * batch's tables are uploaded here, so this call syncs hip_stream. Errors as
+ * ppf_batch_workspace_bytes, ENOMEM for a short workspace, EDEVICE.
+ */
+int ppf_batch_create(const ppf_params* p, int32_t count, void* workspace, size_t bytes,
+                     void* hip_stream, ppf_batch* out);
+
+/* Re-initialise every track (k = 0) on the batch's stream; async. */
+int ppf_batch_reset(ppf_batch h);
+
+/* One step of every track on the frame obs_dev (H*W fp32, device, row-major,
+ * shared by all tracks); async, as ppf_step. A track whose normaliser is not
+ * finite rolls back alone and reports it in ppf_batch_stats. */
+int ppf_step_batched(ppf_batch h, const float* obs_dev);
+
+/* Statistics of every track's last committed step (out: count entries, in
+ * track order), as ppf_stats; syncs and clears the roll-back reports. */
+int ppf_batch_stats(ppf_batch h, ppf_stats_t* out, int32_t count);
+
+/* Particles of one track (0 <= track < count), as ppf_get_particles with
+ * that track's N; syncs. EINVAL for a track out of range. */
+int ppf_batch_get_particles(ppf_batch h, int32_t track, float* state_host, double* logw_host,
+                            int32_t* anc_host);
+
+/* Per-kernel HIP-event timing of the batch's launches, as ppf_profile_*. */
+int ppf_batch_profile_enable(ppf_batch h, int on);
+int ppf_batch_profile_read(ppf_batch h, ppf_kernel_time* out, int max_entries, int* n_entries);
+
+/* Release the batch (host memory only); waits for its work. NULL accepted. */
+int ppf_batch_destroy(ppf_batch h);
+
+/* Text of the last error recorded on the batch ("" if none). */
+const char* ppf_batch_last_error(ppf_batch h);
+
 #ifdef __cplusplus
 }
 #endif

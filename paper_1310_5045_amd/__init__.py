@@ -126,6 +126,21 @@ _SIGS = {
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p]),
+    "ppf_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "ppf_batch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "ppf_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "ppf_step_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ppf_batch_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats), ctypes.c_int32]),
+    "ppf_batch_get_particles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
+    "ppf_batch_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "ppf_batch_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelTime),
+                                              ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "ppf_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ppf_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
 
 
@@ -152,11 +167,11 @@ def error_string(code: int) -> str:
     return lib().ppf_error_string(code).decode()
 
 
-def _check(rc: int, handle=None):
+def _check(rc: int, handle=None, last_error=None):
     if rc != PPF_OK:
         msg = error_string(rc)
         if handle is not None:
-            detail = lib().ppf_last_error(handle)
+            detail = (last_error or lib().ppf_last_error)(handle)
             if detail:
                 msg += f" ({detail.decode()})"
         raise PPFError(rc, msg)
@@ -276,9 +291,7 @@ class Filter:
     def stats(self) -> dict:
         s = Stats()
         _check(lib().ppf_stats(self.handle, ctypes.byref(s)), self.handle)
-        return dict(k=s.k, resampled=bool(s.resampled), rolled_back=s.rolled_back, ess=s.ess,
-                    max_logw=s.max_logw, log_sum=s.log_sum, delta=s.delta, cum=s.cum,
-                    mean=np.array(s.mean[:]))
+        return _stats_dict(s)
 
     def particles(self):
         """(state (5, N) float32, normalised log weights (N,) float64,
@@ -317,6 +330,106 @@ class Filter:
         n = ctypes.c_int()
         _check(lib().ppf_profile_read(self.handle, buf, 16, ctypes.byref(n)), self.handle)
         return {buf[j].name.decode(): (buf[j].launches, buf[j].total_ms) for j in range(n.value)}
+
+
+def _stats_dict(s: Stats) -> dict:
+    return dict(k=s.k, resampled=bool(s.resampled), rolled_back=s.rolled_back, ess=s.ess,
+                max_logw=s.max_logw, log_sum=s.log_sum, delta=s.delta, cum=s.cum,
+                mean=np.array(s.mean[:]))
+
+
+def batch_workspace_bytes(ps) -> int:
+    arr = (Params * len(ps))(*ps)
+    n = ctypes.c_size_t()
+    _check(lib().ppf_batch_workspace_bytes(arr, len(ps), ctypes.byref(n)))
+    return n.value
+
+
+class Batch:
+    """Independent filters (tracks), one per Params, stepped together on one
+    shared frame stream by the library's batched launches. Track t behaves
+    exactly as Filter(ps[t]) would."""
+
+    def __init__(self, ps, device=None, stream=None):
+        import torch
+        self.torch = torch
+        self.ps = list(ps)
+        self.count = len(self.ps)
+        self.n = [int(p.n_particles) for p in self.ps]
+        self.device = torch.device(device if device is not None else "cuda")
+        arr = (Params * self.count)(*self.ps)
+        nbytes = batch_workspace_bytes(self.ps)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib().ppf_batch_create(arr, self.count, ctypes.c_void_p(self.workspace.data_ptr()),
+                                      nbytes, ctypes.c_void_p(_stream_ptr(self.stream)),
+                                      ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ppf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise PPFError(PPF_ESTATE, "batch closed")
+        return self._h
+
+    def _chk(self, rc):
+        _check(rc, self.handle, lib().ppf_batch_last_error)
+
+    def step(self, obs):
+        """One step of every track on a device frame; async."""
+        t = self.torch
+        if not isinstance(obs, t.Tensor) or obs.device.type != "cuda":
+            raise TypeError("observation must be a CUDA tensor")
+        if obs.dtype != t.float32 or not obs.is_contiguous():
+            raise TypeError("observation must be contiguous float32")
+        if obs.numel() != self.ps[0].width * self.ps[0].height:
+            raise ValueError("observation must be one H x W frame")
+        self._chk(lib().ppf_step_batched(self.handle, ctypes.c_void_p(obs.data_ptr())))
+
+    def reset(self):
+        self._chk(lib().ppf_batch_reset(self.handle))
+
+    def stats(self):
+        buf = (Stats * self.count)()
+        self._chk(lib().ppf_batch_stats(self.handle, buf, self.count))
+        return [_stats_dict(buf[j]) for j in range(self.count)]
+
+    def particles(self, track: int):
+        n = self.n[track]
+        x = np.empty((5, n), dtype=np.float32)
+        lw = np.empty(n, dtype=np.float64)
+        anc = np.empty(n, dtype=np.int32)
+        self._chk(lib().ppf_batch_get_particles(self.handle, track,
+                                                x.ctypes.data_as(ctypes.c_void_p),
+                                                lw.ctypes.data_as(ctypes.c_void_p),
+                                                anc.ctypes.data_as(ctypes.c_void_p)))
+        return x, lw, anc
+
+    def profile(self, on: bool = True):
+        self._chk(lib().ppf_batch_profile_enable(self.handle, 1 if on else 0))
+
+    def kernel_times(self) -> dict:
+        buf = (KernelTime * 16)()
+        n = ctypes.c_int()
+        self._chk(lib().ppf_batch_profile_read(self.handle, buf, 16, ctypes.byref(n)))
+        return {buf[j].name.decode(): (buf[j].launches, buf[j].total_ms) for j in range(n.value)}
+
+    def sync(self):
+        self.stream.synchronize()
 
 
 # ------------------------------------------------------ standalone primitives

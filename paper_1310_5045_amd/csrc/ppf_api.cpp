@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -151,7 +152,9 @@ void shape(int64_t n, Buffers* bb) {
 }
 
 // Carve the filter workspace; base may be null to only compute the size.
-size_t carve(const ppf_params* p, char* base, Buffers* b) {
+// With own_ctrl false the control block is not carved (a batch keeps the
+// control blocks of its tracks together) and b->ctrl is left null.
+size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) {
   const int64_t n = p->n_particles;
   Buffers bb{};
   shape(n, &bb);
@@ -162,7 +165,7 @@ size_t carve(const ppf_params* p, char* base, Buffers* b) {
     off += align_up(bytes);
     return ptr;
   };
-  bb.ctrl = reinterpret_cast<Ctrl*>(take(sizeof(Ctrl)));
+  if (own_ctrl) bb.ctrl = reinterpret_cast<Ctrl*>(take(sizeof(Ctrl)));
   bb.X0 = reinterpret_cast<float*>(take(sizeof(float) * 5 * n));
   bb.X1 = reinterpret_cast<float*>(take(sizeof(float) * 5 * n));
   bb.E0 = reinterpret_cast<float*>(take(sizeof(float) * n));
@@ -202,12 +205,9 @@ size_t carve_scratch(int64_t n, char* base, Buffers* b) {
   return off;
 }
 
-}  // namespace
-
-struct ppf_ctx {
-  ppf_params p{};
-  Model m{};
-  Buffers b{};
+// Launch bookkeeping shared by filters and batches: the stream, the last
+// error text, and optional per-kernel HIP-event timing.
+struct Runner {
   hipStream_t stream = nullptr;
   std::string err;
   bool prof = false;
@@ -259,6 +259,78 @@ struct ppf_ctx {
     events.clear();
     return PPF_OK;
   }
+  int profile_enable(int on) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return fail(PPF_EDEVICE, "sync");
+    collect();
+    prof = on != 0;
+    if (prof)
+      for (int k = 0; k < kNumKernels; ++k) {
+        total_ms[k] = 0.0;
+        launches[k] = 0;
+      }
+    return PPF_OK;
+  }
+  int profile_read(ppf_kernel_time* out, int max_entries, int* n_entries) {
+    if (!n_entries || (max_entries > 0 && !out)) return PPF_EINVAL;
+    const int rc = collect();
+    if (rc) return rc;
+    int cnt = 0;
+    for (int k = 0; k < kNumKernels && cnt < max_entries; ++k) {
+      if (!launches[k]) continue;
+      std::snprintf(out[cnt].name, sizeof out[cnt].name, "%s", kKernelNames[k]);
+      out[cnt].launches = launches[k];
+      out[cnt].total_ms = total_ms[k];
+      ++cnt;
+    }
+    *n_entries = cnt;
+    return PPF_OK;
+  }
+  // Copy one filter's particles to the host (state, normalised fp64 log
+  // weights, ancestors); syncs.
+  int particles(const Model& m, const Buffers& b, float* state_host, double* logw_host,
+                int32_t* anc_host) {
+    Ctrl c;
+    hipError_t e = hipMemcpyAsync(&c, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "reading control block");
+    const int64_t n = m.n;
+    if (state_host)
+      e = hipMemcpyAsync(state_host, c.cur ? b.X1 : b.X0, sizeof(float) * 5 * n,
+                         hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess && logw_host) {
+      const int rc = run(kKLogw, [&] { return ppf::launch_logw(m, b, stream); });
+      if (rc) return rc;
+      e = hipMemcpyAsync(logw_host, b.lw64, sizeof(double) * n, hipMemcpyDeviceToHost, stream);
+    }
+    const bool resampled = c.mode == ppf::kModeSys || c.mode == ppf::kModeRna;
+    if (e == hipSuccess && anc_host && resampled)
+      e = hipMemcpyAsync(anc_host, b.anc, sizeof(int32_t) * n, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "copying particles");
+    if (anc_host && !resampled)
+      for (int64_t i = 0; i < n; ++i) anc_host[i] = (int32_t)i;
+    return PPF_OK;
+  }
+};
+
+void fill_stats(const Ctrl& c, ppf_stats_t* out) {
+  out->k = c.k;
+  out->resampled = c.resampled;
+  out->rolled_back = c.rolled_back;
+  out->ess = c.ess;
+  out->max_logw = c.m;
+  out->log_sum = c.log_sum;
+  out->delta = c.delta;
+  out->cum = c.cum;
+  for (int d = 0; d < 5; ++d) out->mean[d] = c.mean[d];
+}
+
+}  // namespace
+
+struct ppf_ctx : Runner {
+  ppf_params p{};
+  Model m{};
+  Buffers b{};
   int read_ctrl(Ctrl* c) {
     hipError_t e = hipMemcpyAsync(c, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -408,15 +480,7 @@ int ppf_stats(ppf_handle h, ppf_stats_t* out) {
   Ctrl c;
   int rc = h->read_ctrl(&c);
   if (rc) return rc;
-  out->k = c.k;
-  out->resampled = c.resampled;
-  out->rolled_back = c.rolled_back;
-  out->ess = c.ess;
-  out->max_logw = c.m;
-  out->log_sum = c.log_sum;
-  out->delta = c.delta;
-  out->cum = c.cum;
-  for (int d = 0; d < 5; ++d) out->mean[d] = c.mean[d];
+  fill_stats(c, out);
   if (c.rolled_back) {
     const int32_t zero = 0;
     hipError_t e = hipMemcpyAsync(&h->b.ctrl->rolled_back, &zero, sizeof zero,
@@ -429,29 +493,7 @@ int ppf_stats(ppf_handle h, ppf_stats_t* out) {
 
 int ppf_get_particles(ppf_handle h, float* state_host, double* logw_host, int32_t* anc_host) {
   if (!h) return PPF_ESTATE;
-  Ctrl c;
-  int rc = h->read_ctrl(&c);
-  if (rc) return rc;
-  const int64_t n = h->m.n;
-  hipError_t e = hipSuccess;
-  if (state_host)
-    e = hipMemcpyAsync(state_host, c.cur ? h->b.X1 : h->b.X0, sizeof(float) * 5 * n,
-                       hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess && logw_host) {
-    rc = h->run(kKLogw, [&] { return ppf::launch_logw(h->m, h->b, h->stream); });
-    if (rc) return rc;
-    e = hipMemcpyAsync(logw_host, h->b.lw64, sizeof(double) * n, hipMemcpyDeviceToHost,
-                       h->stream);
-  }
-  const bool resampled = c.mode == ppf::kModeSys || c.mode == ppf::kModeRna;
-  if (e == hipSuccess && anc_host && resampled)
-    e = hipMemcpyAsync(anc_host, h->b.anc, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
-                       h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return h->hip_fail(e, "copying particles");
-  if (anc_host && !resampled)
-    for (int64_t i = 0; i < n; ++i) anc_host[i] = (int32_t)i;
-  return PPF_OK;
+  return h->particles(h->m, h->b, state_host, logw_host, anc_host);
 }
 
 int ppf_set_particles(ppf_handle h, const float* state_host, const double* logw_host) {
@@ -480,32 +522,12 @@ int ppf_gather(ppf_handle h, float* out_dev) {
 
 int ppf_profile_enable(ppf_handle h, int on) {
   if (!h) return PPF_ESTATE;
-  if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(PPF_EDEVICE, "sync");
-  h->collect();
-  h->prof = on != 0;
-  if (h->prof)
-    for (int k = 0; k < kNumKernels; ++k) {
-      h->total_ms[k] = 0.0;
-      h->launches[k] = 0;
-    }
-  return PPF_OK;
+  return h->profile_enable(on);
 }
 
 int ppf_profile_read(ppf_handle h, ppf_kernel_time* out, int max_entries, int* n_entries) {
   if (!h) return PPF_ESTATE;
-  if (!n_entries || (max_entries > 0 && !out)) return PPF_EINVAL;
-  const int rc = h->collect();
-  if (rc) return rc;
-  int cnt = 0;
-  for (int k = 0; k < kNumKernels && cnt < max_entries; ++k) {
-    if (!h->launches[k]) continue;
-    std::snprintf(out[cnt].name, sizeof out[cnt].name, "%s", kKernelNames[k]);
-    out[cnt].launches = h->launches[k];
-    out[cnt].total_ms = h->total_ms[k];
-    ++cnt;
-  }
-  *n_entries = cnt;
-  return PPF_OK;
+  return h->profile_read(out, max_entries, n_entries);
 }
 
 int ppf_destroy(ppf_handle h) {
@@ -602,5 +624,268 @@ int ppf_resample_rna(const float* logw_dev, int64_t n, int32_t group, int32_t mo
   if (e == hipSuccess) e = ppf::launch_rna(m, b, w, u_dev, s);
   return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+// A batch keeps its tables at the start of its workspace, then every track's
+// filter workspace (carved as for a single filter, minus the control block):
+//   Ctrl[count] | Model[count] | Buffers[count] | block items (grouped by
+//   patch size) | merge-chunk items | segment items | RNA-group items |
+//   systematic track list | track workspaces.
+namespace {
+
+struct BatchPlan {
+  std::vector<Model> models;
+  std::vector<Buffers> bufs;
+  std::vector<ppf::BatchItem> blocks, chunks, segs, groups;
+  std::vector<int32_t> sys_tracks;
+  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> step_ranges;  // P -> [first, count)
+  size_t off_models = 0, off_bufs = 0, off_blocks = 0, off_chunks = 0, off_segs = 0,
+         off_groups = 0, off_sys = 0, off_tracks = 0, total = 0;
+  std::vector<size_t> track_off;
+};
+
+std::string validate_batch(const ppf_params* p, int32_t count) {
+  if (!p) return "null parameters";
+  if (count < 1) return "count must be >= 1";
+  for (int32_t t = 0; t < count; ++t) {
+    const std::string e = validate(&p[t]);
+    if (!e.empty()) return "track " + std::to_string(t) + ": " + e;
+    if (p[t].obs_model != PPF_OBS_SPOT)
+      return "track " + std::to_string(t) + ": batches take the spot model only";
+    if (p[t].width != p[0].width || p[t].height != p[0].height)
+      return "track " + std::to_string(t) + ": frame size differs from track 0";
+  }
+  return "";
+}
+
+// Sizes, offsets and work lists of a batch (p already validated).
+void plan_batch(const ppf_params* p, int32_t count, BatchPlan* bp) {
+  bp->models.resize(count);
+  bp->bufs.resize(count);
+  bp->track_off.resize(count);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  take(sizeof(Ctrl) * count);
+  bp->off_models = take(sizeof(Model) * count);
+  bp->off_bufs = take(sizeof(Buffers) * count);
+  for (int32_t t = 0; t < count; ++t) {
+    bp->models[t] = make_model(&p[t]);
+    carve(&p[t], nullptr, &bp->bufs[t], false);
+  }
+  // step items grouped by patch size, one launch per distinct size
+  std::vector<int> sizes;
+  for (int32_t t = 0; t < count; ++t) sizes.push_back(bp->models[t].P);
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  for (int P : sizes) {
+    const int64_t first = (int64_t)bp->blocks.size();
+    for (int32_t t = 0; t < count; ++t)
+      if (bp->models[t].P == P)
+        for (int64_t j = 0; j < bp->bufs[t].nb; ++j) bp->blocks.push_back({t, (int32_t)j});
+    bp->step_ranges.push_back({P, {first, (int64_t)bp->blocks.size() - first}});
+  }
+  for (int32_t t = 0; t < count; ++t) {
+    for (int64_t j = 0; j < bp->bufs[t].nch; ++j) bp->chunks.push_back({t, (int32_t)j});
+    if (p[t].resample == PPF_RESAMPLE_RNA) {
+      for (int64_t g = 0; g < bp->models[t].G; ++g) bp->groups.push_back({t, (int32_t)g});
+    } else {
+      for (int64_t j = 0; j < bp->bufs[t].nseg; ++j) bp->segs.push_back({t, (int32_t)j});
+      bp->sys_tracks.push_back(t);
+    }
+  }
+  bp->off_blocks = take(sizeof(ppf::BatchItem) * bp->blocks.size());
+  bp->off_chunks = take(sizeof(ppf::BatchItem) * bp->chunks.size());
+  bp->off_segs = take(sizeof(ppf::BatchItem) * bp->segs.size());
+  bp->off_groups = take(sizeof(ppf::BatchItem) * bp->groups.size());
+  bp->off_sys = take(sizeof(int32_t) * bp->sys_tracks.size());
+  for (int32_t t = 0; t < count; ++t) bp->track_off[t] = take(carve(&p[t], nullptr, nullptr, false));
+  bp->total = off;
+}
+
+}  // namespace
+
+struct ppf_batch_ctx : Runner {
+  int32_t count = 0;
+  BatchPlan plan;
+  char* base = nullptr;
+  Ctrl* ctrl = nullptr;
+  const Model* d_models = nullptr;
+  const Buffers* d_bufs = nullptr;
+  const ppf::BatchItem *d_blocks = nullptr, *d_chunks = nullptr, *d_segs = nullptr,
+                       *d_groups = nullptr;
+  const int32_t* d_sys = nullptr;
+
+  int init() {
+    return run(kKInit, [&] {
+      return ppf::launch_init_batch(d_models, d_bufs, d_blocks, (int64_t)plan.blocks.size(),
+                                    stream);
+    });
+  }
+};
+
+extern "C" {
+
+int ppf_batch_workspace_bytes(const ppf_params* p, int32_t count, size_t* bytes) {
+  if (!bytes || !validate_batch(p, count).empty()) return PPF_EINVAL;
+  BatchPlan bp;
+  plan_batch(p, count, &bp);
+  *bytes = bp.total;
+  return PPF_OK;
+}
+
+int ppf_batch_create(const ppf_params* p, int32_t count, void* workspace, size_t bytes,
+                     void* hip_stream, ppf_batch* out) {
+  if (!out) return PPF_EINVAL;
+  *out = nullptr;
+  if (!validate_batch(p, count).empty() || !workspace) return PPF_EINVAL;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return PPF_EINVAL;
+  ppf_batch_ctx* h = new (std::nothrow) ppf_batch_ctx();
+  if (!h) return PPF_ENOMEM;
+  plan_batch(p, count, &h->plan);
+  if (bytes < h->plan.total) {
+    delete h;
+    return PPF_ENOMEM;
+  }
+  BatchPlan& bp = h->plan;
+  h->count = count;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->base = static_cast<char*>(workspace);
+  h->ctrl = reinterpret_cast<Ctrl*>(h->base);
+  for (int32_t t = 0; t < count; ++t) {
+    carve(&p[t], h->base + bp.track_off[t], &bp.bufs[t], false);
+    bp.bufs[t].ctrl = h->ctrl + t;
+  }
+  h->d_models = reinterpret_cast<const Model*>(h->base + bp.off_models);
+  h->d_bufs = reinterpret_cast<const Buffers*>(h->base + bp.off_bufs);
+  h->d_blocks = reinterpret_cast<const ppf::BatchItem*>(h->base + bp.off_blocks);
+  h->d_chunks = reinterpret_cast<const ppf::BatchItem*>(h->base + bp.off_chunks);
+  h->d_segs = reinterpret_cast<const ppf::BatchItem*>(h->base + bp.off_segs);
+  h->d_groups = reinterpret_cast<const ppf::BatchItem*>(h->base + bp.off_groups);
+  h->d_sys = reinterpret_cast<const int32_t*>(h->base + bp.off_sys);
+  struct Up {
+    size_t off;
+    const void* src;
+    size_t n;
+  };
+  const Up ups[] = {
+      {bp.off_models, bp.models.data(), sizeof(Model) * bp.models.size()},
+      {bp.off_bufs, bp.bufs.data(), sizeof(Buffers) * bp.bufs.size()},
+      {bp.off_blocks, bp.blocks.data(), sizeof(ppf::BatchItem) * bp.blocks.size()},
+      {bp.off_chunks, bp.chunks.data(), sizeof(ppf::BatchItem) * bp.chunks.size()},
+      {bp.off_segs, bp.segs.data(), sizeof(ppf::BatchItem) * bp.segs.size()},
+      {bp.off_groups, bp.groups.data(), sizeof(ppf::BatchItem) * bp.groups.size()},
+      {bp.off_sys, bp.sys_tracks.data(), sizeof(int32_t) * bp.sys_tracks.size()},
+  };
+  hipError_t e = hipSuccess;
+  for (const Up& u : ups)
+    if (e == hipSuccess && u.n)
+      e = hipMemcpyAsync(h->base + u.off, u.src, u.n, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return PPF_EDEVICE;
+  }
+  const int rc = h->init();
+  if (rc != PPF_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return PPF_OK;
+}
+
+int ppf_batch_reset(ppf_batch h) {
+  if (!h) return PPF_ESTATE;
+  return h->init();
+}
+
+int ppf_step_batched(ppf_batch h, const float* obs_dev) {
+  if (!h) return PPF_ESTATE;
+  if (!obs_dev) return h->fail(PPF_EINVAL, "null observation");
+  const BatchPlan& bp = h->plan;
+  for (const auto& r : bp.step_ranges) {
+    const int rc = h->run(kKStep, [&] {
+      return ppf::launch_step_batch(r.first, h->d_models, h->d_bufs, h->d_blocks + r.second.first,
+                                    r.second.second, obs_dev, h->stream);
+    });
+    if (rc) return rc;
+  }
+  int rc = h->run(kKMerge, [&] {
+    return ppf::launch_merge_batch(h->d_models, h->d_bufs, h->d_chunks,
+                                   (int64_t)bp.chunks.size(), h->stream);
+  });
+  if (rc) return rc;
+  if (!bp.segs.empty()) {
+    rc = h->run(kKAnc, [&] {
+      return ppf::launch_anc_batch(h->d_models, h->d_bufs, h->d_segs, (int64_t)bp.segs.size(),
+                                   h->stream);
+    });
+    if (rc) return rc;
+    rc = h->run(kKFill, [&] {
+      return ppf::launch_fill_batch(h->d_models, h->d_bufs, h->d_sys,
+                                    (int32_t)bp.sys_tracks.size(), h->stream);
+    });
+    if (rc) return rc;
+  }
+  if (!bp.groups.empty())
+    return h->run(kKRna, [&] {
+      return ppf::launch_rna_batch(h->d_models, h->d_bufs, h->d_groups,
+                                   (int64_t)bp.groups.size(), h->stream);
+    });
+  return PPF_OK;
+}
+
+int ppf_batch_stats(ppf_batch h, ppf_stats_t* out, int32_t count) {
+  if (!h) return PPF_ESTATE;
+  if (!out || count != h->count) return h->fail(PPF_EINVAL, "stats buffer must hold count entries");
+  std::vector<Ctrl> c(h->count);
+  hipError_t e = hipMemcpyAsync(c.data(), h->ctrl, sizeof(Ctrl) * h->count, hipMemcpyDeviceToHost,
+                                h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "reading control blocks");
+  const int32_t zero = 0;
+  for (int32_t t = 0; t < h->count; ++t) {
+    fill_stats(c[t], &out[t]);
+    if (c[t].rolled_back && e == hipSuccess)
+      e = hipMemcpyAsync(&h->ctrl[t].rolled_back, &zero, sizeof zero, hipMemcpyHostToDevice,
+                         h->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "clearing roll-back reports");
+  return PPF_OK;
+}
+
+int ppf_batch_get_particles(ppf_batch h, int32_t track, float* state_host, double* logw_host,
+                            int32_t* anc_host) {
+  if (!h) return PPF_ESTATE;
+  if (track < 0 || track >= h->count) return h->fail(PPF_EINVAL, "track out of range");
+  return h->particles(h->plan.models[track], h->plan.bufs[track], state_host, logw_host, anc_host);
+}
+
+int ppf_batch_profile_enable(ppf_batch h, int on) {
+  if (!h) return PPF_ESTATE;
+  return h->profile_enable(on);
+}
+
+int ppf_batch_profile_read(ppf_batch h, ppf_kernel_time* out, int max_entries, int* n_entries) {
+  if (!h) return PPF_ESTATE;
+  return h->profile_read(out, max_entries, n_entries);
+}
+
+int ppf_batch_destroy(ppf_batch h) {
+  if (!h) return PPF_OK;
+  (void)hipStreamSynchronize(h->stream);
+  h->collect();
+  delete h;
+  return PPF_OK;
+}
+
+const char* ppf_batch_last_error(ppf_batch h) { return h ? h->err.c_str() : "null handle"; }
 
 }  // extern "C"

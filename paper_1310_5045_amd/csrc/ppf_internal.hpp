@@ -41,6 +41,14 @@ constexpr int kCoopSlots = 1 << 16;
 constexpr int kSlotTile = 4096;  // slots per LDS tile of the segment's writes
 constexpr int kFillChunk = 1 << 16;
 constexpr int kFillGrid = 2048;
+constexpr int kFillGridBatch = 64;  // workgroups per track of a batched fill
+
+// One work item of a batched launch: the track, and the index of the track's
+// block, merge chunk, resampling segment or RNA group.
+struct BatchItem {
+  int32_t track;
+  int32_t idx;
+};
 
 // One entry of the fill queue: slots [lo, lo + len) take particle `item`.
 struct FillRun {
@@ -164,5 +172,20 @@ hipError_t launch_set_mode(const Buffers& b, int32_t mode, hipStream_t s);
 hipError_t launch_records(const Model& m, const Buffers& b, const float* logw, hipStream_t s);
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
                          hipStream_t s);
+
+// Batched launches over independent filters: ms and bs are device arrays of
+// the tracks' models and buffers, items the device list of work items.
+hipError_t launch_init_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
+                             int64_t n_items, hipStream_t s);
+hipError_t launch_step_batch(int P, const Model* ms, const Buffers* bs, const BatchItem* items,
+                             int64_t n_items, const float* obs, hipStream_t s);
+hipError_t launch_merge_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
+                              int64_t n_items, hipStream_t s);
+hipError_t launch_anc_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
+                            int64_t n_items, hipStream_t s);
+hipError_t launch_fill_batch(const Model* ms, const Buffers* bs, const int32_t* tracks,
+                             int32_t n_tracks, hipStream_t s);
+hipError_t launch_rna_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
+                            int64_t n_items, hipStream_t s);
 
 }  // namespace ppf

@@ -262,8 +262,8 @@ __device__ __forceinline__ uint64_t block_excl_sum(uint64_t v, uint64_t* sh, uin
 // ------------------------------------------------------------ k_init
 // Algorithm 1 initialisation, k = 0. The state is computed in fp64 and
 // rounded once to fp32.
-__global__ __launch_bounds__(256) void k_init(Model m, Buffers b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void init_body(const Model& m, const Buffers& b, int64_t blk) {
+  const int64_t i = blk * kBlock + threadIdx.x;
   if (i == 0) {
     Ctrl* c = b.ctrl;
     c->k = 0;
@@ -322,6 +322,8 @@ __global__ __launch_bounds__(256) void k_init(Model m, Buffers b) {
 #pragma unroll
   for (int d = 0; d < 5; ++d) b.X0[(int64_t)d * m.n + i] = (float)x[d];
 }
+
+__global__ __launch_bounds__(256) void k_init(Model m, Buffers b) { init_body(m, b, blockIdx.x); }
 
 // ------------------------------------------------------------ k_step
 // Parent, carried log weight and propagated state of particle i.
@@ -432,7 +434,7 @@ __device__ __forceinline__ void finish_block(const Buffers& b, int cur, int64_t 
   const double h0 = readlane(s, 0) + readlane(s, 16);   // value 2w
   const double h1 = readlane(s, 32) + readlane(s, 48);  // value 2w + 1
   if (lane == 0) {
-    double* R = (cur ? b.R0 : b.R1) + (int64_t)blockIdx.x * kRec;
+    double* R = (cur ? b.R0 : b.R1) + (i / kBlock) * kRec;
     R[1 + 2 * w] = h0;
     if (2 * w + 1 < 7) R[2 + 2 * w] = h1;
     if (w == 0) R[0] = mb;
@@ -508,7 +510,7 @@ __device__ __forceinline__ void patch_global(const float* __restrict__ obs, int 
 // maximum, and the record exchange.
 template <int P>
 __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
-                                          const float* __restrict__ obs) {
+                                          const float* __restrict__ obs, int64_t blk) {
   constexpr int h = (P - 1) / 2;
   __shared__ __align__(16) double tile[kTileCap];
   static_assert(kTileCap >= 7 * kBlock, "the tile doubles as the record exchange buffer");
@@ -520,7 +522,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   const double cdelta = cp->delta;
   const uint32_t k = (uint32_t)(cp->k + 1);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+  const int64_t i = blk * kBlock + t;
   const bool active = i < m.n;
 
   Prop o{};
@@ -570,7 +572,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
                                  : 0x7fff7fffu;
     const uint32_t rmin = wave_reduce(pmin, lane, OpMin16x2());
     const uint32_t rneg = wave_reduce(pneg, lane, OpMin16x2());
-    const bool any = (int64_t)blockIdx.x * kBlock + w * 64 < m.n;
+    const bool any = blk * kBlock + w * 64 < m.n;
     if (lane == 0) {
       ish[w] = any ? bx0 + (int16_t)(rmin & 0xffffu) : INT_MAX;
       ish[4 + w] = any ? bx0 - (int16_t)(rneg & 0xffffu) : INT_MIN;
@@ -657,13 +659,13 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
 template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 void k_step_spot(Model m, Buffers b, const float* __restrict__ obs) {
-  step_spot<P>(m, b, obs);
+  step_spot<P>(m, b, obs, blockIdx.x);
 }
 
 template <int P>
 __global__ __launch_bounds__(256) void k_step_spot_wide(Model m, Buffers b,
                                                         const float* __restrict__ obs) {
-  step_spot<P>(m, b, obs);
+  step_spot<P>(m, b, obs, blockIdx.x);
 }
 
 // Linear-Gaussian observation of (x, y, I0): three fp32 values on the device.
@@ -745,8 +747,8 @@ __global__ __launch_bounds__(256) void k_records(Model m, Buffers b,
 // of Algorithm 1 (normaliser, ESS, MMSE estimate), decides on resampling,
 // commits or rolls back the step, and for systematic resampling writes each
 // chunk's fixed-point CDF prefix.
-__global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalone,
-                                               double u_given) {
+__device__ __forceinline__ void merge_body(const Model& m, const Buffers& b, int standalone,
+                                           double u_given, int64_t ch) {
   __shared__ double dsh[4];
   __shared__ double nsh[4 * 7];
   __shared__ uint64_t ush[4];
@@ -757,7 +759,6 @@ __global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalon
   const int t = threadIdx.x;
   const int which = standalone ? 0 : (c->cur ^ 1);  // the records this step wrote
   const double* R = which ? b.R1 : b.R0;
-  const int64_t ch = blockIdx.x;
   const int64_t lo = ch * b.chunk, hi = min(b.nb, lo + b.chunk);
   const int per = (int)(b.chunk / 256);
   const int64_t j0 = lo + (int64_t)t * per;
@@ -914,6 +915,11 @@ __global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalon
   if (t == 0) c->total = tot;
 }
 
+__global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalone,
+                                               double u_given) {
+  merge_body(m, b, standalone, u_given, blockIdx.x);
+}
+
 // --------------------------------------------------- systematic resampling
 // Slot s of N takes the particle j whose CDF interval [C_{j-1}, C_j) holds
 // (s + u) / N (Algorithm 1's resampling step with one uniform u), so
@@ -951,7 +957,8 @@ struct AncShared {
 // thread): the segment's slot range from its block starts, the particles'
 // CDF from their fixed-point weights, every particle's run of slots, and
 // the slots' particles, written tile by tile.
-__global__ __launch_bounds__(256) void k_anc(Model m, Buffers b, WeightSrc ws) {
+__device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const WeightSrc& ws,
+                                         int64_t seg) {
   __shared__ AncShared sh;
   Ctrl* c = b.ctrl;
   if (!c->do_resample) return;
@@ -960,7 +967,6 @@ __global__ __launch_bounds__(256) void k_anc(Model m, Buffers b, WeightSrc ws) {
   const double delta = c->delta, u = c->u;
   const int n = (int)m.n;
   const double nd = (double)m.n;
-  const int64_t seg = blockIdx.x;
   const int64_t b0 = seg * kSegBlocks;
   const int nbs = (int)min((int64_t)kSegBlocks, b.nb - b0);
   if (t <= nbs) sh.Pb[t] = (b0 + t < b.nb) ? block_P(b, b0 + t) : 1.0;
@@ -1136,12 +1142,17 @@ __global__ __launch_bounds__(256) void k_anc(Model m, Buffers b, WeightSrc ws) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_anc(Model m, Buffers b, WeightSrc ws) {
+  anc_body(m, b, ws, blockIdx.x);
+}
+
 // Long runs queued by k_anc: each workgroup fills whole runs, coalesced.
-__global__ __launch_bounds__(256) void k_fill(Model m, Buffers b) {
+__device__ __forceinline__ void fill_body(const Model& m, const Buffers& b, int64_t q0,
+                                          int64_t qstep) {
   const Ctrl* c = b.ctrl;
   if (!c->do_resample) return;
   const int64_t nh = min((int64_t)c->heavy_count, b.hq_cap);
-  for (int64_t q = blockIdx.x; q < nh; q += gridDim.x) {
+  for (int64_t q = q0; q < nh; q += qstep) {
     const FillRun r = b.hq[q];
     if (r.lo < 0 || r.len <= 0 || (int64_t)r.lo + r.len > m.n || r.item < 0 ||
         (int64_t)r.item >= m.n)
@@ -1149,6 +1160,10 @@ __global__ __launch_bounds__(256) void k_fill(Model m, Buffers b) {
     int32_t* out = b.anc + r.lo;
     for (int k = threadIdx.x; k < r.len; k += 256) out[k] = r.item;
   }
+}
+
+__global__ __launch_bounds__(256) void k_fill(Model m, Buffers b) {
+  fill_body(m, b, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------- RNA
@@ -1160,8 +1175,8 @@ __device__ __forceinline__ double wave_sum_d(double v, int lane) {
 // group's normalised weights, slot weight W_g / n, and the last `moved` slots
 // taken from group g-1's local resampling (recomputed here, so no workgroup
 // waits for another).
-__global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
-                                             const double* __restrict__ u_dev) {
+__device__ __forceinline__ void rna_body(const Model& m, const Buffers& b, const WeightSrc& ws,
+                                         const double* __restrict__ u_dev, int64_t g) {
   __shared__ uint64_t C[2][kMaxGroup];
   __shared__ double dsum[4];
   __shared__ uint64_t wsum[4];
@@ -1170,7 +1185,6 @@ __global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
   const bool second = ws.use_cur && c->cur;
   const float* E = second ? ws.E1 : ws.E0;
   const double* rec = second ? ws.rec1 : ws.rec0;
-  const int64_t g = blockIdx.x;
   const int ng = m.group;
   const int64_t G = m.G;
   const int64_t prev = (g + G - 1) % G;
@@ -1249,6 +1263,82 @@ __global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
   if (t == 0) b.lwg[g] = log(Wg[0] / (double)ng);
 }
 
+__global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
+                                             const double* __restrict__ u_dev) {
+  rna_body(m, b, ws, u_dev, blockIdx.x);
+}
+
+// --------------------------------------------------------------- batches
+// Independent filters (tracks) advance together: each launch covers every
+// track, one workgroup per work item (track, index of the track's block,
+// chunk, segment or group) from a list built on the host, with the track's
+// model and buffers read from device arrays.
+__device__ __forceinline__ WeightSrc own_weights(const Buffers& b) {
+  WeightSrc w{};
+  w.E0 = b.E0;
+  w.E1 = b.E1;
+  w.rec0 = b.R0;
+  w.rec1 = b.R1;
+  w.use_cur = 1;
+  w.log_src = 0;
+  return w;
+}
+
+__global__ __launch_bounds__(256) void k_init_batch(const Model* __restrict__ ms,
+                                                    const Buffers* __restrict__ bs,
+                                                    const BatchItem* __restrict__ items) {
+  const BatchItem it = items[blockIdx.x];
+  init_body(ms[it.track], bs[it.track], it.idx);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+void k_step_batch(const Model* __restrict__ ms, const Buffers* __restrict__ bs,
+                  const BatchItem* __restrict__ items, const float* __restrict__ obs) {
+  const BatchItem it = items[blockIdx.x];
+  step_spot<P>(ms[it.track], bs[it.track], obs, it.idx);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_step_batch_wide(const Model* __restrict__ ms,
+                                                         const Buffers* __restrict__ bs,
+                                                         const BatchItem* __restrict__ items,
+                                                         const float* __restrict__ obs) {
+  const BatchItem it = items[blockIdx.x];
+  step_spot<P>(ms[it.track], bs[it.track], obs, it.idx);
+}
+
+__global__ __launch_bounds__(256) void k_merge_batch(const Model* __restrict__ ms,
+                                                     const Buffers* __restrict__ bs,
+                                                     const BatchItem* __restrict__ items) {
+  const BatchItem it = items[blockIdx.x];
+  merge_body(ms[it.track], bs[it.track], 0, 0.0, it.idx);
+}
+
+__global__ __launch_bounds__(256) void k_anc_batch(const Model* __restrict__ ms,
+                                                   const Buffers* __restrict__ bs,
+                                                   const BatchItem* __restrict__ items) {
+  const BatchItem it = items[blockIdx.x];
+  const Buffers& b = bs[it.track];
+  anc_body(ms[it.track], b, own_weights(b), it.idx);
+}
+
+// blockIdx.y selects the track (from `tracks`); blockIdx.x strides its queue.
+__global__ __launch_bounds__(256) void k_fill_batch(const Model* __restrict__ ms,
+                                                    const Buffers* __restrict__ bs,
+                                                    const int32_t* __restrict__ tracks) {
+  const int32_t tr = tracks[blockIdx.y];
+  fill_body(ms[tr], bs[tr], blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_rna_batch(const Model* __restrict__ ms,
+                                                   const Buffers* __restrict__ bs,
+                                                   const BatchItem* __restrict__ items) {
+  const BatchItem it = items[blockIdx.x];
+  const Buffers& b = bs[it.track];
+  rna_body(ms[it.track], b, own_weights(b), nullptr, it.idx);
+}
+
 // ------------------------------------------------------------- utilities
 __global__ __launch_bounds__(256) void k_gather(Model m, Buffers b, float* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1297,6 +1387,18 @@ hipError_t launch_spot(const Model& m, const Buffers& b, const float* obs, hipSt
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+template <int P>
+hipError_t launch_spot_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
+                             int64_t n_items, const float* obs, hipStream_t s) {
+  if constexpr (P <= 13)
+    hipLaunchKernelGGL(k_step_batch<P>, dim3((unsigned)n_items), dim3(kBlock), 0, s, ms, bs,
+                       items, obs);
+  else
+    hipLaunchKernelGGL(k_step_batch_wide<P>, dim3((unsigned)n_items), dim3(kBlock), 0, s, ms,
+                       bs, items, obs);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_init(const Model& m, const Buffers& b, hipStream_t s) {
@@ -1325,6 +1427,63 @@ hipError_t launch_step(const Model& m, const Buffers& b, const float* obs, hipSt
     case 25: return launch_spot<25>(m, b, obs, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_init_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
+                             int64_t n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_batch, dim3((unsigned)n_items), dim3(kBlock), 0, s, ms, bs, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_batch(int P, const Model* ms, const Buffers* bs, const BatchItem* items,
+                             int64_t n_items, const float* obs, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  switch (P) {
+    case 1: return launch_spot_batch<1>(ms, bs, items, n_items, obs, s);
+    case 3: return launch_spot_batch<3>(ms, bs, items, n_items, obs, s);
+    case 5: return launch_spot_batch<5>(ms, bs, items, n_items, obs, s);
+    case 7: return launch_spot_batch<7>(ms, bs, items, n_items, obs, s);
+    case 9: return launch_spot_batch<9>(ms, bs, items, n_items, obs, s);
+    case 11: return launch_spot_batch<11>(ms, bs, items, n_items, obs, s);
+    case 13: return launch_spot_batch<13>(ms, bs, items, n_items, obs, s);
+    case 15: return launch_spot_batch<15>(ms, bs, items, n_items, obs, s);
+    case 17: return launch_spot_batch<17>(ms, bs, items, n_items, obs, s);
+    case 19: return launch_spot_batch<19>(ms, bs, items, n_items, obs, s);
+    case 21: return launch_spot_batch<21>(ms, bs, items, n_items, obs, s);
+    case 23: return launch_spot_batch<23>(ms, bs, items, n_items, obs, s);
+    case 25: return launch_spot_batch<25>(ms, bs, items, n_items, obs, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_merge_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
+                              int64_t n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_merge_batch, dim3((unsigned)n_items), dim3(256), 0, s, ms, bs, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_anc_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
+                            int64_t n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_anc_batch, dim3((unsigned)n_items), dim3(256), 0, s, ms, bs, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_batch(const Model* ms, const Buffers* bs, const int32_t* tracks,
+                             int32_t n_tracks, hipStream_t s) {
+  if (n_tracks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_batch, dim3(kFillGridBatch, (unsigned)n_tracks), dim3(256), 0, s, ms,
+                     bs, tracks);
+  return hipGetLastError();
+}
+
+hipError_t launch_rna_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
+                            int64_t n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rna_batch, dim3((unsigned)n_items), dim3(256), 0, s, ms, bs, items);
+  return hipGetLastError();
 }
 
 hipError_t launch_merge(const Model& m, const Buffers& b, int standalone, double u_given,

@@ -25,6 +25,17 @@ MEAN_ATOL = 1e-3
 DELTA_ATOL = 1e-4
 
 
+def pair(ppf, **kw):
+    """Matching library parameters and oracle model."""
+    okw = dict(kw)
+    pkw = {}
+    ren = dict(n="n_particles", s="psf_sigma", b="background", sigma="noise_sigma", track="track_id",
+               rna_exchange="rna_exchange")
+    for k, v in kw.items():
+        pkw[ren.get(k, k)] = v
+    return ppf.params(**pkw), oracle.Model(**okw)
+
+
 @dataclass
 class GpuState:
     x: np.ndarray       # (5, N) float32
@@ -112,3 +123,25 @@ def check_rna(w_gpu, group, moved, u_g, anc_gpu, band=1e-9):
         outside = mism & (d > band)
         assert not outside.any(), f"RNA ancestors: {outside.sum()} mismatches outside band"
     return int(mism.sum()), lws
+
+
+def check_step(m, k, prev: GpuState, cur: GpuState, st, obs, rna=False):
+    """All checks of step k (propagate, weights, then the resampling or the
+    carried weights); sets cur.lw_next and returns a report tuple."""
+    n = m.n
+    assert st["k"] == k
+    check_propagate(m, k, prev, cur.x)
+    rel, _ = check_weights(m, obs, prev.lw_next, cur.x, cur.lw, st)
+    w_gpu = np.exp(cur.lw)
+    if cur.resampled:
+        if rna:
+            ug = oracle.rna_uniforms(m, k)
+            nm, lws = check_rna(w_gpu, m.rna_group, m.rna_moved, ug, cur.anc)
+            cur.lw_next = lws
+            return (k, rel, nm)
+        nm, nm10 = check_systematic(w_gpu, oracle.resample_uniform(m, k), cur.anc)
+        cur.lw_next = np.full(n, -math.log(n))
+        return (k, rel, nm, nm10)
+    assert np.array_equal(cur.anc, np.arange(n))
+    cur.lw_next = cur.lw.copy()
+    return (k, rel, 0)

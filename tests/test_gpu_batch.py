@@ -1,0 +1,180 @@
+"""GPU parity of batched independent filters (tracks). Every track of a batch
+must equal the single filter built from its own parameters bit for bit after
+every step, and, teacher-forced step by step, the FP64 oracle run with that
+track's parameters (its own N, patch, seed stream and resampling scheme)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1310_5045_amd import synth
+
+from parity import GpuState, check_step, pair
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+W, H = 160, 128
+
+
+@pytest.fixture(scope="module")
+def ppf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1310_5045_amd as p
+    p.lib()
+    return p
+
+
+@pytest.fixture(scope="module")
+def movie():
+    return synth.render_movie(W, H, 6, n_spots=6, intensity=(20.0, 40.0), sigma=(1.2, 2.4),
+                              start_box=(24, 136, 24, 104), seed=11)
+
+
+# (particles, psf sigma -> patch, extra parameters); patches 7, 13, 9, 11, 15, 9
+SPEC = [
+    (1000, 1.2, {}),
+    (4096, 2.0, dict(ess_threshold=2048.0)),
+    (257, 1.5, {}),
+    (2048, 1.7, dict(resample=1, rna_group=256, rna_exchange=0.1)),
+    (3000, 2.4, {}),
+    (1, 1.5, {}),
+]
+
+
+def track_kw(mv, j, n, s, **extra):
+    """Track j follows spot j: an init box of +-5 px around its first
+    position, velocities in [-1, 1], intensity within a factor 2."""
+    x0, y0 = mv.truth[0, j]
+    I = float(mv.intensity[j])
+    kw = dict(n=n, width=W, height=H, s=s, b=10.0, sigma=3.0,
+              init_a=(x0 - 5, y0 - 5, -1, -1, I / 2), init_b=(x0 + 5, y0 + 5, 1, 1, 1.5 * I),
+              track=j, seed=7)
+    kw.update(extra)
+    return kw
+
+
+def make_pairs(ppf, mv, spec):
+    return [pair(ppf, **track_kw(mv, j, n, s, **extra)) for j, (n, s, extra) in enumerate(spec)]
+
+
+def assert_same_as_single(b, singles, bst=None, sst=None):
+    bst = b.stats() if bst is None else bst
+    sst = [f.stats() for f in singles] if sst is None else sst
+    for t, f in enumerate(singles):
+        xb, lwb, ab = b.particles(t)
+        xs, lws, as_ = f.particles()
+        assert np.array_equal(xb, xs), f"track {t}: states differ"
+        assert np.array_equal(ab, as_), f"track {t}: ancestors differ"
+        assert np.array_equal(lwb, lws), f"track {t}: log weights differ"
+        st = sst[t]
+        for key in ("k", "resampled", "rolled_back", "ess", "max_logw", "log_sum", "delta", "cum"):
+            assert bst[t][key] == st[key] or (math.isnan(bst[t][key]) and math.isnan(st[key])), \
+                (t, key, bst[t][key], st[key])
+        assert np.array_equal(bst[t]["mean"], st["mean"]), t
+
+
+def test_batch_patch_sizes(ppf, movie):
+    ps = [p for p, _ in make_pairs(ppf, movie, SPEC)]
+    assert [ppf.patch_size(p) for p in ps] == [7, 13, 9, 11, 15, 9]
+
+
+def test_batch_equals_single_filters(ppf, movie):
+    ps = [p for p, _ in make_pairs(ppf, movie, SPEC)]
+    b = ppf.Batch(ps)
+    singles = [ppf.Filter(p) for p in ps]
+    frames = torch.from_numpy(movie.frames).cuda()
+    assert_same_as_single(b, singles)
+    for k in range(movie.frames.shape[0]):
+        b.step(frames[k])
+        for f in singles:
+            f.step(frames[k])
+        assert_same_as_single(b, singles)
+    # a reset starts every track again from its k = 0 cloud
+    b.reset()
+    for f in singles:
+        f.reset()
+    b.step(frames[0])
+    for f in singles:
+        f.step(frames[0])
+    assert_same_as_single(b, singles)
+    b.close()
+    for f in singles:
+        f.close()
+
+
+def test_batch_track_rolls_back_alone(ppf, movie):
+    """A frame with NaN pixels under one spot: the track whose patches touch
+    them rolls back, the others commit, each as its single filter does."""
+    ps = [p for p, _ in make_pairs(ppf, movie, SPEC[:3])]
+    b = ppf.Batch(ps)
+    singles = [ppf.Filter(p) for p in ps]
+    frames = movie.frames.copy()
+    x0, y0 = movie.truth[1, 0]
+    frames[1, int(y0) - 3:int(y0) + 4, int(x0) - 3:int(x0) + 4] = np.nan
+    ft = torch.from_numpy(frames).cuda()
+    for k in range(3):
+        b.step(ft[k])
+        for f in singles:
+            f.step(ft[k])
+        bst = b.stats()
+        if k == 1:
+            assert bst[0]["rolled_back"] >= 1 and bst[0]["k"] == 1
+            assert any(st["rolled_back"] == 0 and st["k"] == 2 for st in bst[1:])
+        assert_same_as_single(b, singles, bst)
+    b.close()
+    for f in singles:
+        f.close()
+
+
+def test_batch_teacher_forced_vs_oracle(ppf, movie):
+    pairs = make_pairs(ppf, movie, SPEC)
+    b = ppf.Batch([p for p, _ in pairs])
+    frames = torch.from_numpy(movie.frames).cuda()
+    prev = []
+    for t, (_, m) in enumerate(pairs):
+        x, lw, anc = b.particles(t)
+        xo, _ = oracle.init(m)
+        assert np.all(np.abs(x - xo) <= np.spacing(np.abs(xo).astype(np.float32)) + 1e-12)
+        prev.append(GpuState(x, lw, anc, False, np.full(m.n, -math.log(m.n))))
+    for k in range(1, 5):
+        b.step(frames[k - 1])
+        sts = b.stats()
+        for t, (_, m) in enumerate(pairs):
+            x, lw, anc = b.particles(t)
+            cur = GpuState(x, lw, anc, bool(sts[t]["resampled"]), None)
+            rep = check_step(m, k, prev[t], cur, sts[t], movie.frames[k - 1], rna=m.resample == 1)
+            if len(rep) == 4:
+                assert rep[3] == 0, (t, rep)  # no ancestor mismatch beyond the 1e-10 band
+            prev[t] = cur
+    b.close()
+
+
+def test_batch_many_small_tracks(ppf, movie):
+    """256 tracks of ragged sizes in one batch: each equals its single filter."""
+    rng = np.random.default_rng(3)
+    spec = [(int(n), float(s), {}) for n, s in zip(rng.integers(1, 700, 256),
+                                                   rng.uniform(1.2, 2.5, 256))]
+    ps = [ppf.params(n_particles=n, width=W, height=H, psf_sigma=s, seed=5, track_id=t,
+                     init_a=(40, 40, -1, -1, 15), init_b=(120, 90, 1, 1, 45))
+          for t, (n, s, _) in enumerate(spec)]
+    b = ppf.Batch(ps)
+    frames = torch.from_numpy(movie.frames).cuda()
+    for k in range(2):
+        b.step(frames[k])
+    check = [0, 1, 17, 128, 255]
+    singles = [ppf.Filter(ps[t]) for t in check]
+    for k in range(2):
+        for f in singles:
+            f.step(frames[k])
+    bst = b.stats()
+    for f, t in zip(singles, check):
+        xb, lwb, ab = b.particles(t)
+        xs, lws, as_ = f.particles()
+        assert np.array_equal(xb, xs) and np.array_equal(ab, as_) and np.array_equal(lwb, lws), t
+        assert bst[t]["delta"] == f.stats()["delta"]
+        f.close()
+    b.close()

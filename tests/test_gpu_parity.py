@@ -8,8 +8,8 @@ import pytest
 import oracle
 from paper_1310_5045_amd import synth
 
-from parity import (GpuState, check_propagate, check_rna, check_systematic, check_weights,
-                    snapshot)
+from parity import (GpuState, check_propagate, check_rna, check_step, check_systematic,
+                    check_weights, pair, snapshot)
 
 pytestmark = pytest.mark.gpu
 
@@ -25,17 +25,6 @@ def ppf():
     return p
 
 
-def pair(ppf, **kw):
-    """Matching library parameters and oracle model."""
-    okw = dict(kw)
-    pkw = {}
-    ren = dict(n="n_particles", s="psf_sigma", b="background", sigma="noise_sigma", track="track_id",
-               rna_exchange="rna_exchange")
-    for k, v in kw.items():
-        pkw[ren.get(k, k)] = v
-    return ppf.params(**pkw), oracle.Model(**okw)
-
-
 def run_teacher_forced(ppf, p, m, obs_np, T, rna=False):
     f = ppf.Filter(p)
     n = m.n
@@ -48,24 +37,7 @@ def run_teacher_forced(ppf, p, m, obs_np, T, rna=False):
     for k in range(1, T + 1):
         f.step(obs_t[k - 1])
         cur, st = snapshot(f, n, None)
-        assert st["k"] == k
-        check_propagate(m, k, prev, cur.x)
-        rel, s = check_weights(m, obs_np[k - 1], prev.lw_next, cur.x, cur.lw, st)
-        w_gpu = np.exp(cur.lw)
-        if cur.resampled:
-            if rna:
-                ug = oracle.rna_uniforms(m, k)
-                nm, lws = check_rna(w_gpu, m.rna_group, m.rna_moved, ug, cur.anc)
-                cur.lw_next = lws
-                report.append((k, rel, nm))
-            else:
-                nm, nm10 = check_systematic(w_gpu, oracle.resample_uniform(m, k), cur.anc)
-                cur.lw_next = np.full(n, -math.log(n))
-                report.append((k, rel, nm, nm10))
-        else:
-            assert np.array_equal(cur.anc, np.arange(n))
-            cur.lw_next = cur.lw.copy()
-            report.append((k, rel, 0))
+        report.append(check_step(m, k, prev, cur, st, obs_np[k - 1], rna))
         prev = cur
     f.close()
     return report
