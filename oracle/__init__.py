@@ -84,6 +84,11 @@ def lib():
         L.orc_resample_rna.argtypes = [i64, i32, i32, vp, vp, vp, vp, vp]
         L.orc_run.argtypes = [P(_Model), i32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_run.restype = ctypes.c_int
+        L.orc_propagate_tangent.argtypes = [P(_Model), i64, vp, vp, vp]
+        L.orc_loglik_spot_grad.argtypes = [P(_Model), vp, vp, vp]
+        L.orc_step_grad.argtypes = [i64, vp, vp, vp, vp]
+        L.orc_run_grad.argtypes = [P(_Model), i32, vp, vp, vp, vp, P(d), vp]
+        L.orc_run_grad.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -194,8 +199,8 @@ def init(m: Model):
     return x.reshape(5, m.n), lw
 
 
-def propagate(m: Model, k: int, x_prev: np.ndarray, parent: Optional[np.ndarray] = None):
-    c = m.c()
+def propagate(m: Model, k: int, x_prev: np.ndarray, parent: Optional[np.ndarray] = None, c=None):
+    c = m.c() if c is None else c
     xp = np.ascontiguousarray(x_prev, dtype=np.float64).reshape(5, m.n)
     par = None if parent is None else np.ascontiguousarray(parent, dtype=np.int32)
     xn = np.empty((5, m.n))
@@ -225,8 +230,8 @@ def propagate_indexed(m: Model, k: int, index: np.ndarray, parents: np.ndarray) 
     return xn
 
 
-def loglik(m: Model, obs: np.ndarray, x: np.ndarray) -> np.ndarray:
-    c = m.c()
+def loglik(m: Model, obs: np.ndarray, x: np.ndarray, c=None) -> np.ndarray:
+    c = m.c() if c is None else c
     z = np.ascontiguousarray(obs, dtype=np.float32)
     xx = np.ascontiguousarray(x, dtype=np.float64).reshape(5, m.n)
     ll = np.empty(m.n)
@@ -301,3 +306,59 @@ def run(m: Model, obs: np.ndarray, T: Optional[int] = None) -> RunResult:
     st = lib().orc_run(ctypes.byref(c), T, _ptr(z), _ptr(mean), _ptr(ess), _ptr(delta), _ptr(res),
                        _ptr(x), _ptr(lw), _ptr(anc))
     return RunResult(mean, ess, delta, res, x, lw, anc, st)
+
+
+# ------------------------------------------------------------ derivatives
+GRAD_NAMES = ("s", "b", "sigma", "q_x", "q_y", "q_vx", "q_vy", "q_I", "I0")
+
+
+def propagate_tangent(m: Model, k: int, t_prev: np.ndarray, parent: Optional[np.ndarray] = None):
+    """Tangents (7, n) of frame k's states in q from the parents' (see
+    orc_propagate_tangent)."""
+    c = m.c()
+    tp = np.ascontiguousarray(t_prev, dtype=np.float64).reshape(7, m.n)
+    par = None if parent is None else np.ascontiguousarray(parent, dtype=np.int32)
+    out = np.empty((7, m.n))
+    lib().orc_propagate_tangent(ctypes.byref(c), k, _ptr(tp), _ptr(par), _ptr(out))
+    return out
+
+
+def loglik_grad(m: Model, obs: np.ndarray, x: np.ndarray, c=None) -> np.ndarray:
+    """dl/d(x, y, I0, s, b, sigma) per particle, (6, n). `c` may give the
+    C model directly (fp64 fields, e.g. perturbed off the fp32 grid)."""
+    c = m.c() if c is None else c
+    fr = np.ascontiguousarray(obs, dtype=np.float32)
+    xx = np.ascontiguousarray(x, dtype=np.float64).reshape(5, m.n)
+    out = np.empty((6, m.n))
+    lib().orc_loglik_spot_grad(ctypes.byref(c), _ptr(fr), _ptr(xx), _ptr(out))
+    return out
+
+
+def step_grad(w: np.ndarray, dll: np.ndarray, tang: np.ndarray) -> np.ndarray:
+    """sum_i w_i dl_i/dtheta, theta as GRAD_NAMES."""
+    n = w.size
+    ww = np.ascontiguousarray(w, dtype=np.float64)
+    dd = np.ascontiguousarray(dll, dtype=np.float64).reshape(6, n)
+    tt = np.ascontiguousarray(tang, dtype=np.float64).reshape(7, n)
+    g = np.empty(9)
+    lib().orc_step_grad(n, _ptr(ww), _ptr(dd), _ptr(tt), _ptr(g))
+    return g
+
+
+def run_grad(m: Model, frames: np.ndarray, T: int, anc_replay: Optional[np.ndarray] = None,
+             trace: bool = False, c=None):
+    """(cum, grad (9,), ancestors (T, n)[, states (T, 5, n)]) of a whole run
+    with systematic resampling at every step; anc_replay fixes the ancestors.
+    `c` may give the C model directly."""
+    c = m.c() if c is None else c
+    fr = np.ascontiguousarray(frames[:T], dtype=np.float32)
+    rep_ = None if anc_replay is None else np.ascontiguousarray(anc_replay, dtype=np.int32)
+    anc = np.empty((T, m.n), dtype=np.int32)
+    xt = np.empty((T, 5, m.n)) if trace else None
+    cum = ctypes.c_double()
+    g = np.empty(9)
+    st = lib().orc_run_grad(ctypes.byref(c), T, _ptr(fr), _ptr(rep_), _ptr(anc), _ptr(xt),
+                            ctypes.byref(cum), _ptr(g))
+    if st != 0:
+        raise FloatingPointError(f"orc_run_grad returned {st}")
+    return (cum.value, g, anc, xt) if trace else (cum.value, g, anc)

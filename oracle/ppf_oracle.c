@@ -416,3 +416,170 @@ int orc_run(const orc_model* m, int32_t T, const float* obs, double* mean, doubl
   free(ug);
   return status;
 }
+
+/* ------------------------------------------------ derivatives of log p^ */
+
+/*
+ * Derivatives of the log-likelihood estimate log p^(z_1:T) = sum_k delta_k
+ * (Eq. 1 with the normaliser delta_k of Algorithm 1) with respect to
+ *   theta = (s, b, sigma_xi, q_x, q_y, q_vx, q_vy, q_I, I0),
+ * I0 being a common offset of every particle's initial intensity, with the
+ * Philox noise and the resampling ancestors held fixed (the draws are
+ * reparameterised, the discrete ancestor choice is not differentiated). The
+ * patch centre c = floor(x + 1/2) is piecewise constant, so it carries no
+ * derivative. Under resampling at every step the carried weights are 1/N,
+ * and d delta_k / d theta = sum_i w_k^i d l_k^i / d theta with w_k the
+ * normalised weights and l_k^i = log p(z_k | x~_k^i).
+ */
+
+/* Tangents of the propagated state along each particle's ancestral line
+ * (fixed noise z): the near-constant-velocity update x' = x + vx + q_x z_x,
+ * vx' = vx + q_vx z_vx (and y, I alike) differentiated in q:
+ *   0 dx/dq_x   1 dy/dq_y   2 dvx/dq_vx   3 dx/dq_vx
+ *   4 dvy/dq_vy 5 dy/dq_vy  6 dI/dq_I
+ * t_prev, t_new: 7 * n SoA; parent NULL = identity. dI/dI0 = 1 throughout. */
+void orc_propagate_tangent(const orc_model* m, int64_t k, const double* t_prev,
+                           const int32_t* parent, double* t_new) {
+  const int64_t n = m->n;
+  for (int64_t i = 0; i < n; ++i) {
+    double z[5];
+    five_normals(m, (uint32_t)i, (uint32_t)k, PURPOSE_PROPAGATE, z);
+    const int64_t p = parent ? (int64_t)parent[i] : i;
+    double t[7];
+    for (int d = 0; d < 7; ++d) t[d] = t_prev[d * n + p];
+    t_new[0 * n + i] = t[0] + z[0];        /* x' = x + vx + q_x z_x            */
+    t_new[1 * n + i] = t[1] + z[1];
+    t_new[2 * n + i] = t[2] + z[2];        /* vx' = vx + q_vx z_vx             */
+    t_new[3 * n + i] = t[3] + t[2];        /* x' depends on q_vx through vx    */
+    t_new[4 * n + i] = t[4] + z[3];
+    t_new[5 * n + i] = t[5] + t[4];
+    t_new[6 * n + i] = t[6] + z[4];        /* I' = I + q_I z_I                 */
+  }
+}
+
+/* Partial derivatives of l = log p(z | x) of Eq. 4 (with its normaliser) per
+ * particle, by the chain rule pixel by pixel on the same P x P block as
+ * orc_loglik_spot: with r = (u - x)^2 + (v - y)^2, g = exp(-r / (2 s^2)) and
+ * the residual R = D - I0 g (D = Z - b inside the frame, 0 outside),
+ *   dl/dx     = I0 / (sigma^2 s^2) sum R g (u - x)
+ *   dl/dy     = I0 / (sigma^2 s^2) sum R g (v - y)
+ *   dl/dI0    = 1 / sigma^2 sum R g
+ *   dl/ds     = I0 / (sigma^2 s^3) sum R g r
+ *   dl/db     = 1 / sigma^2 sum_{pixels inside the frame} R
+ *   dl/dsigma = sum R^2 / sigma^3 - P^2 / sigma
+ * dll: 6 * n SoA in that order. */
+void orc_loglik_spot_grad(const orc_model* m, const float* frame, const double* x,
+                          double* dll) {
+  const int64_t n = m->n;
+  const int h = (m->patch - 1) / 2;
+  const double s = m->s, sg = m->sigma;
+  for (int64_t i = 0; i < n; ++i) {
+    const double xt = x[0 * n + i], yt = x[1 * n + i], It = x[4 * n + i];
+    const double cx = floor(xt + 0.5), cy = floor(yt + 0.5);
+    double ss = 0.0, a_g = 0.0, a_x = 0.0, a_y = 0.0, a_r = 0.0, a_in = 0.0;
+    for (int dy = -h; dy <= h; ++dy) {
+      for (int dx = -h; dx <= h; ++dx) {
+        const double u = cx + dx, v = cy + dy;
+        const int in = u >= 0.0 && u < (double)m->width && v >= 0.0 && v < (double)m->height;
+        const double D = in ? (double)frame[(int64_t)v * m->width + (int64_t)u] - m->b : 0.0;
+        const double r = (u - xt) * (u - xt) + (v - yt) * (v - yt);
+        const double g = exp(-r / (2.0 * s * s));
+        const double R = D - It * g;
+        ss += R * R;
+        a_g += R * g;
+        a_x += R * g * (u - xt);
+        a_y += R * g * (v - yt);
+        a_r += R * g * r;
+        if (in) a_in += R;
+      }
+    }
+    dll[0 * n + i] = It * a_x / (sg * sg * s * s);
+    dll[1 * n + i] = It * a_y / (sg * sg * s * s);
+    dll[2 * n + i] = a_g / (sg * sg);
+    dll[3 * n + i] = It * a_r / (sg * sg * s * s * s);
+    dll[4 * n + i] = a_in / (sg * sg);
+    dll[5 * n + i] = ss / (sg * sg * sg) - (double)m->patch * (double)m->patch / sg;
+  }
+}
+
+/* One step's d delta / d theta = sum_i w_i d l_i / d theta (9 values) from
+ * the normalised weights w, the partial derivatives dll and the tangents. */
+void orc_step_grad(int64_t n, const double* w, const double* dll, const double* tang,
+                   double g[9]) {
+  for (int d = 0; d < 9; ++d) g[d] = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double lx = dll[0 * n + i], ly = dll[1 * n + i], lI = dll[2 * n + i];
+    const double v[9] = {dll[3 * n + i], dll[4 * n + i], dll[5 * n + i],
+                         lx * tang[0 * n + i], ly * tang[1 * n + i], lx * tang[3 * n + i],
+                         ly * tang[5 * n + i], lI * tang[6 * n + i], lI};
+    for (int d = 0; d < 9; ++d) g[d] += w[i] * v[d];
+  }
+}
+
+/* A whole run (spot model, systematic resampling at every step) with the
+ * derivatives of cum = sum_k delta_k. anc_replay (T * n, may be NULL)
+ * replaces the resampling's ancestors of each step (ancestor replay, so that
+ * perturbed runs keep the discrete choices of a base run); anc_out (T * n,
+ * may be NULL) records the ancestors used; x_trace (T * 5 * n, may be NULL)
+ * the propagated states. Returns 0, -1 for an unsupported model, or -k when
+ * frame k had no finite normaliser. */
+int orc_run_grad(const orc_model* m, int32_t T, const float* obs, const int32_t* anc_replay,
+                 int32_t* anc_out, double* x_trace, double* cum, double grad[9]) {
+  if (m->obs_model != 0 || m->resample != 0 || !isinf(m->ess_threshold)) return -1;
+  const int64_t n = m->n;
+  double* x = (double*)malloc((size_t)(5 * n) * sizeof(double));
+  double* xn = (double*)malloc((size_t)(5 * n) * sizeof(double));
+  double* t = (double*)calloc((size_t)(7 * n), sizeof(double));
+  double* tn = (double*)malloc((size_t)(7 * n) * sizeof(double));
+  double* lw = (double*)malloc((size_t)n * sizeof(double));
+  double* ll = (double*)malloc((size_t)n * sizeof(double));
+  double* dll = (double*)malloc((size_t)(6 * n) * sizeof(double));
+  double* w = (double*)malloc((size_t)n * sizeof(double));
+  int32_t* parent = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  int have_parent = 0, status = 0;
+  const int64_t frame_len = (int64_t)m->width * m->height;
+  *cum = 0.0;
+  for (int d = 0; d < 9; ++d) grad[d] = 0.0;
+  orc_init(m, x, lw);
+  for (int32_t k = 1; k <= T; ++k) {
+    const float* z = obs + (int64_t)(k - 1) * frame_len;
+    orc_propagate(m, k, x, have_parent ? parent : NULL, xn);
+    orc_propagate_tangent(m, k, t, have_parent ? parent : NULL, tn);
+    if (x_trace) memcpy(x_trace + (int64_t)(k - 1) * 5 * n, xn, (size_t)(5 * n) * sizeof(double));
+    orc_loglik_spot(m, z, xn, ll);
+    for (int64_t i = 0; i < n; ++i) ll[i] += lw[i];
+    double st[4];
+    if (orc_normalize(n, ll, w, st) != 0) {
+      status = -k;
+      break;
+    }
+    *cum += st[3];
+    orc_loglik_spot_grad(m, z, xn, dll);
+    double g[9];
+    orc_step_grad(n, w, dll, tn, g);
+    for (int d = 0; d < 9; ++d) grad[d] += g[d];
+    if (anc_replay)
+      memcpy(parent, anc_replay + (int64_t)(k - 1) * n, (size_t)n * sizeof(int32_t));
+    else
+      orc_resample_systematic(n, w, orc_resample_uniform(m, k), parent);
+    if (anc_out) memcpy(anc_out + (int64_t)(k - 1) * n, parent, (size_t)n * sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) lw[i] = -log((double)n);
+    have_parent = 1;
+    double* sw = x;
+    x = xn;
+    xn = sw;
+    sw = t;
+    t = tn;
+    tn = sw;
+  }
+  free(x);
+  free(xn);
+  free(t);
+  free(tn);
+  free(lw);
+  free(ll);
+  free(dll);
+  free(w);
+  free(parent);
+  return status;
+}

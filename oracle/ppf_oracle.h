@@ -103,6 +103,23 @@ void orc_resample_rna(int64_t n, int32_t group, int32_t moved, const double* w,
 int orc_run(const orc_model* m, int32_t T, const float* obs, double* mean, double* ess,
             double* delta, int32_t* resampled, double* x_out, double* lw_out, int32_t* anc_out);
 
+/* Derivatives of log p^ = sum_k delta_k with respect to theta = (s, b,
+ * sigma_xi, q_x, q_y, q_vx, q_vy, q_I, I0), noise and ancestors fixed. */
+/* Tangents (7 * n SoA: dx/dq_x, dy/dq_y, dvx/dq_vx, dx/dq_vx, dvy/dq_vy,
+ * dy/dq_vy, dI/dq_I) of frame k's states from those of the parents. */
+void orc_propagate_tangent(const orc_model* m, int64_t k, const double* t_prev,
+                           const int32_t* parent, double* t_new);
+/* Per particle dl/d(x, y, I0, s, b, sigma) of Eq. 4 (6 * n SoA). */
+void orc_loglik_spot_grad(const orc_model* m, const float* frame, const double* x,
+                          double* dll);
+/* sum_i w_i dl_i/dtheta (9 values). */
+void orc_step_grad(int64_t n, const double* w, const double* dll, const double* tang,
+                   double g[9]);
+/* Whole run with derivatives; systematic resampling at every step; optional
+ * ancestor replay (T * n), ancestor record (T * n), state trace (T * 5 * n). */
+int orc_run_grad(const orc_model* m, int32_t T, const float* obs, const int32_t* anc_replay,
+                 int32_t* anc_out, double* x_trace, double* cum, double grad[9]);
+
 #ifdef __cplusplus
 }
 #endif
