@@ -113,6 +113,9 @@ WORKLOADS = {
                                    thr=float("inf")),
     "sir_512x512_n1m_p9": dict(W=512, H=512, T=50, n=1 << 20, s=1.5, P=9, thr=float(1 << 19)),
     "sir_128x128_n4096_p9": dict(W=128, H=128, T=10, n=4096, s=1.5, P=9, thr=float("inf")),
+    # forward pass with the derivatives of log p^ in (s, b, sigma, q, I0)
+    "grad_512x512_n262k_p11": dict(W=512, H=512, T=30, n=1 << 18, s=1.7, P=11, thr=float("inf"),
+                                   I=25.0, grad=1),
     # 256 spots, one independent filter each, stepped as one batch
     "multitrack_1024x1024_t256": dict(W=1024, H=1024, T=30, tracks=256, n_lo=1024, n_hi=262144,
                                       s_lo=1.2, s_hi=2.5, I_lo=15.0, I_hi=60.0, vmax=2.0,
@@ -210,11 +213,30 @@ def run_multitrack(args, w):
     print(json.dumps(out), flush=True)
 
 
-def make_params(ppf, w, init_kind):
+def make_params(ppf, w, init_kind, grad=0):
     return ppf.params(n_particles=w["n"], width=w["W"], height=w["H"], psf_sigma=w["s"],
                       background=10.0, noise_sigma=3.0, patch=w["P"], init_kind=init_kind,
                       init_a=(0, 0, -1, -1, 15), init_b=(w["W"], w["H"], 1, 1, 45),
-                      ess_threshold=w["thr"], seed=1)
+                      ess_threshold=w["thr"], seed=1, grad=grad)
+
+
+def time_filter(ppf, torch, p, frames, K, Wm, T):
+    """(ms of K steps after Wm warm-up steps and a reset, kernel times, filter)."""
+    f = ppf.Filter(p)
+    for k in range(Wm):
+        f.step(frames[k % T])
+    f.reset()
+    f.sync()
+    torch.cuda.synchronize()
+    f.profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(f.stream)
+    for k in range(K):
+        f.step(frames[k % T])
+    ev1.record(f.stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1), f.kernel_times(), f
 
 
 def cpu_baseline(w, frames, sample_n, sample_t, init_kind):
@@ -274,8 +296,8 @@ def main():
     init_kind = ppf.INIT_STRATIFIED if args.init == "stratified" else ppf.INIT_UNIFORM
     K, Wm = args.steps, args.warmup
     T = max(K, w["T"], Wm)
-    mv = synth.render_movie(w["W"], w["H"], T, intensity=30.0, sigma=w["s"], background=10.0,
-                            noise_sd=3.0, seed=1)
+    mv = synth.render_movie(w["W"], w["H"], T, intensity=w.get("I", 30.0), sigma=w["s"],
+                            background=10.0, noise_sd=3.0, seed=1)
     torch.cuda.set_device(0)
     frames = torch.from_numpy(mv.frames).cuda()
     if args.copy_probe_mib:
@@ -285,7 +307,14 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    f = ppf.Filter(make_params(ppf, w, init_kind))
+    plain = None
+    if w.get("grad"):
+        # the same configuration without derivatives, for the ratio
+        pms, pkt, pf = time_filter(ppf, torch, make_params(ppf, w, init_kind), frames, K, Wm, T)
+        pf.close()
+        plain = {"value": w["n"] * K / (pms / 1e3), "ms_per_step": pms / K,
+                 "k_step_ms": pkt.get("k_step", (1, 0.0))[1] / K}
+    f = ppf.Filter(make_params(ppf, w, init_kind, grad=w.get("grad", 0)))
     stream = f.stream
     # warm-up: a few steps, then a fresh initial cloud for the timed steps
     for k in range(Wm):
@@ -324,7 +353,8 @@ def main():
     step_gbs = 48.0 * n / step_avg_s / 1e9
 
     out = {
-        "metric": "particle updates/s at N=38M on 1 GPU",
+        "metric": ("particle updates/s at N=38M on 1 GPU" if n == 38_000_000
+                   else f"particle updates/s at N={n} on 1 GPU"),
         "value": value,
         "unit": "particle updates/s",
         "n_gpus": 1,
@@ -355,6 +385,13 @@ def main():
         "tracking_error_px": err,
         "final_ess": st["ess"],
     }
+    if plain is not None:
+        g, _ = f.grad()
+        out["metric"] = "particle updates/s with d log p^ / d theta (9 parameters) on 1 GPU"
+        out["plain_forward"] = plain
+        out["ratio_to_plain"] = out["value"] / plain["value"]
+        out["grad_cum"] = dict(zip(ppf.GRAD_NAMES, [float(v) for v in g]))
+        out["config"]["gradient"] = list(ppf.GRAD_NAMES)
     f.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, mv.frames, min(args.cpu_sample, n), args.cpu_frames,

@@ -103,6 +103,11 @@ typedef struct ppf_ctx* ppf_handle;
  *               slots of group g-1 mod G (Section 3, ring of processes).
  * seed          Philox key.
  * track_id      Philox counter word 3 (distinguishes independent filters).
+ * grad          1: every step also accumulates the derivatives of log p^ in
+ *               theta (see ppf_grad). Needs the spot model, systematic
+ *               resampling and ess_threshold = +INFINITY; the workspace then
+ *               also holds 2 x 7 tangents per particle (fp32) and 9 doubles
+ *               per 256-particle block. 0: none.
  */
 typedef struct ppf_params {
   int32_t state_dim;
@@ -125,7 +130,7 @@ typedef struct ppf_params {
   float rna_exchange;
   uint64_t seed;
   uint32_t track_id;
-  int32_t reserved; /* must be 0 */
+  int32_t grad; /* 0, or 1: also accumulate d log p^ / d theta (ppf_grad) */
 } ppf_params;
 
 /* Scalars of the last committed step (see ppf_stats). */
@@ -211,6 +216,26 @@ int ppf_estimate(ppf_handle h, double mean[5], double* ess);
  * the normalised previous weights times the likelihood); syncs. Either
  * pointer may be NULL. Returns PPF_ENUMERIC like ppf_sync. */
 int ppf_loglik(ppf_handle h, double* cum, double* last);
+
+/*
+ * Derivatives of the log-likelihood estimate (the cum of ppf_loglik) with
+ * respect to
+ *   theta = (psf_sigma, background, noise_sigma, q[0..4], I0),
+ * I0 being a common offset of every particle's initial intensity (init_a[4]
+ * and init_b[4] moved together), with the Philox noise and the resampling
+ * ancestors held fixed: the state draws are reparameterised and the
+ * discrete ancestor choice is not differentiated (a stop-gradient through
+ * resampling). The patch size stays fixed while psf_sigma varies. With
+ * resampling at every step, each step adds sum_i w_i d l_i / d theta, the
+ * normalised weights times the derivative of the particle's log-likelihood
+ * (Eqs. 3-4) through its parameters and its state, whose tangents in q are
+ * carried along the ancestral lines. cum: 9 doubles summed over committed
+ * steps since create/reset; last: the last committed step's term. Either
+ * pointer may be NULL; syncs. EINVAL when the filter was created with
+ * grad = 0.
+ */
+#define PPF_NGRAD 9
+int ppf_grad(ppf_handle h, double cum[PPF_NGRAD], double last[PPF_NGRAD]);
 
 /* All scalars of the last committed step; syncs and clears the roll-back
  * report (returns PPF_OK even if steps were rolled back: see rolled_back). */

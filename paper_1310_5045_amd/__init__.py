@@ -28,6 +28,8 @@ RESAMPLE_SYSTEMATIC, RESAMPLE_RNA = 0, 1
 OBS_SPOT, OBS_LINEAR_GAUSSIAN = 0, 1
 INIT_UNIFORM, INIT_GAUSSIAN, INIT_STRATIFIED = 0, 1, 2
 MAX_PATCH = 25
+# theta of ppf_grad, in order
+GRAD_NAMES = ("psf_sigma", "background", "noise_sigma", "q_x", "q_y", "q_vx", "q_vy", "q_I", "I0")
 
 
 class Params(ctypes.Structure):
@@ -53,7 +55,7 @@ class Params(ctypes.Structure):
         ("rna_exchange", ctypes.c_float),
         ("seed", ctypes.c_uint64),
         ("track_id", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32),
+        ("grad", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -106,6 +108,7 @@ _SIGS = {
     "ppf_loglik": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]),
     "ppf_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ppf_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ppf_get_particles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]),
     "ppf_set_particles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -293,6 +296,15 @@ class Filter:
         _check(lib().ppf_stats(self.handle, ctypes.byref(s)), self.handle)
         return _stats_dict(s)
 
+    def grad(self) -> Tuple[np.ndarray, np.ndarray]:
+        """(d cum / d theta, the last step's term), theta as GRAD_NAMES; the
+        filter must have been created with grad=1. Syncs."""
+        cum = np.empty(len(GRAD_NAMES))
+        last = np.empty(len(GRAD_NAMES))
+        _check(lib().ppf_grad(self.handle, cum.ctypes.data_as(ctypes.c_void_p),
+                              last.ctypes.data_as(ctypes.c_void_p)), self.handle)
+        return cum, last
+
     def particles(self):
         """(state (5, N) float32, normalised log weights (N,) float64,
         ancestors (N,) int32) of the last committed step, on the host."""
@@ -430,6 +442,72 @@ class Batch:
 
     def sync(self):
         self.stream.synchronize()
+
+
+# --------------------------------------------------- differentiable log p^
+def params_at(base: Params, theta) -> Params:
+    """A copy of `base` with theta = (psf_sigma, background, noise_sigma,
+    q[0..4], I0) applied: I0 moves init_a[4] and init_b[4] together, and the
+    patch is pinned to base's so that it does not jump as psf_sigma moves."""
+    p = Params.from_buffer_copy(base)
+    th = [float(v) for v in theta]
+    p.patch = patch_size(base)
+    p.psf_sigma, p.background, p.noise_sigma = th[0], th[1], th[2]
+    for d in range(5):
+        p.q[d] = th[3 + d]
+    p.init_a[4] = base.init_a[4] + th[8]
+    p.init_b[4] = base.init_b[4] + th[8]
+    p.grad = 1
+    return p
+
+
+def theta_of(base: Params):
+    """theta of `base` itself (I0 offset 0)."""
+    return [base.psf_sigma, base.background, base.noise_sigma] + list(base.q) + [0.0]
+
+
+def _make_loglik_function():
+    import torch
+
+    class LogLikelihood(torch.autograd.Function):
+        """log p^(z_1:T) of one filter run over `frames` as a function of
+        theta (see params_at): the forward pass runs the filter in gradient
+        mode, which carries the derivatives alongside the particles, and the
+        backward pass scales them by the incoming gradient."""
+
+        @staticmethod
+        def forward(ctx, theta, frames, base):
+            p = params_at(base, theta.detach().cpu().tolist())
+            f = Filter(p, device=frames.device)
+            for k in range(frames.shape[0]):
+                f.step(frames[k])
+            cum, _ = f.loglik()
+            g, _ = f.grad()
+            f.close()
+            ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype, device=theta.device))
+            return torch.tensor(cum, dtype=theta.dtype, device=theta.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            return grad_out * g, None, None
+
+    return LogLikelihood
+
+
+_LogLikelihood = None
+
+
+def loglik(theta, frames, base: Params):
+    """Differentiable log p^(z_1:T): theta a 9-element float64 tensor (see
+    GRAD_NAMES), frames a (T, H, W) float32 CUDA tensor, base the filter's
+    other parameters (systematic resampling at every step, spot model). The
+    Philox noise and the resampling ancestors are held fixed in the
+    derivative."""
+    global _LogLikelihood
+    if _LogLikelihood is None:
+        _LogLikelihood = _make_loglik_function()
+    return _LogLikelihood.apply(theta, frames, base)
 
 
 # ------------------------------------------------------ standalone primitives

@@ -37,7 +37,13 @@ int derived_patch(const ppf_params* p) {
 std::string validate(const ppf_params* p) {
   if (!p) return "null parameters";
   if (p->state_dim != 5) return "state_dim must be 5";
-  if (p->reserved != 0) return "reserved must be 0";
+  if (p->grad != 0 && p->grad != 1) return "grad must be 0 or 1";
+  if (p->grad) {
+    if (p->obs_model != PPF_OBS_SPOT) return "grad needs the spot model";
+    if (p->resample != PPF_RESAMPLE_SYSTEMATIC) return "grad needs systematic resampling";
+    if (!(std::isinf(p->ess_threshold) && p->ess_threshold > 0))
+      return "grad needs resampling at every step (ess_threshold = +inf)";
+  }
   if (p->n_particles < 1 || p->n_particles > 2147483647LL) return "n_particles out of range";
   if (p->obs_model != PPF_OBS_SPOT && p->obs_model != PPF_OBS_LINEAR_GAUSSIAN)
     return "unknown obs_model";
@@ -123,6 +129,9 @@ Model make_model(const ppf_params* p) {
   m.key1 = (uint32_t)(p->seed >> 32);
   m.track = p->track_id;
   m.strat_t = strat_bits(m.n);
+  m.grad = p->grad;
+  m.s_psf = s;
+  m.sig = sg;
   return m;
 }
 
@@ -180,6 +189,12 @@ size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) 
   bb.lwg = reinterpret_cast<double*>(take(sizeof(double) * G));
   bb.hq = reinterpret_cast<ppf::FillRun*>(take(sizeof(ppf::FillRun) * queue_cap(n)));
   bb.hq_cap = queue_cap(n);
+  if (p->grad) {
+    bb.T0 = reinterpret_cast<float*>(take(sizeof(float) * ppf::kNTan * n));
+    bb.T1 = reinterpret_cast<float*>(take(sizeof(float) * ppf::kNTan * n));
+    bb.RG = reinterpret_cast<double*>(take(sizeof(double) * ppf::kNGrad * bb.nb));
+    bb.CRG = reinterpret_cast<double*>(take(sizeof(double) * ppf::kNGrad * bb.nch));
+  }
   if (b) *b = bb;
   return off;
 }
@@ -474,6 +489,21 @@ int ppf_loglik(ppf_handle h, double* cum, double* last) {
   return rc;
 }
 
+int ppf_grad(ppf_handle h, double cum[PPF_NGRAD], double last[PPF_NGRAD]) {
+  if (!h) return PPF_ESTATE;
+  if (!h->m.grad) return h->fail(PPF_EINVAL, "the filter was created with grad = 0");
+  const int rc = ppf_sync(h);
+  if (rc != PPF_OK && rc != PPF_ENUMERIC) return rc;
+  Ctrl c;
+  const int rc2 = h->read_ctrl(&c);
+  if (rc2) return rc2;
+  for (int d = 0; d < PPF_NGRAD; ++d) {
+    if (cum) cum[d] = c.grad_cum[d];
+    if (last) last[d] = c.grad_last[d];
+  }
+  return rc;
+}
+
 int ppf_stats(ppf_handle h, ppf_stats_t* out) {
   if (!h) return PPF_ESTATE;
   if (!out) return PPF_EINVAL;
@@ -508,6 +538,9 @@ int ppf_set_particles(ppf_handle h, const float* state_host, const double* logw_
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->b.lw64, logw_host, sizeof(double) * n, hipMemcpyHostToDevice,
                        h->stream);
+  // gradient mode: the new states are constants (zero tangents)
+  if (e == hipSuccess && h->m.grad)
+    e = hipMemsetAsync(c.cur ? h->b.T1 : h->b.T0, 0, sizeof(float) * ppf::kNTan * n, h->stream);
   if (e == hipSuccess) e = ppf::launch_set_mode(h->b, ppf::kModeSet, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "setting particles");
@@ -654,6 +687,7 @@ std::string validate_batch(const ppf_params* p, int32_t count) {
     if (!e.empty()) return "track " + std::to_string(t) + ": " + e;
     if (p[t].obs_model != PPF_OBS_SPOT)
       return "track " + std::to_string(t) + ": batches take the spot model only";
+    if (p[t].grad) return "track " + std::to_string(t) + ": batches do not take grad = 1";
     if (p[t].width != p[0].width || p[t].height != p[0].height)
       return "track " + std::to_string(t) + ": frame size differs from track 0";
   }

@@ -69,7 +69,13 @@ enum Mode : int32_t {
   kModeSet = 4    // parents identity, log w = caller-supplied fp64 values
 };
 
-// Device-resident control block (256 bytes). Kernels read and update it, so a
+// Derivatives of log p^ kept in gradient mode, theta = (s, b, sigma_xi,
+// q_x, q_y, q_vx, q_vy, q_I, I0), and the per-particle tangents of the state
+// in q (dx/dq_x, dy/dq_y, dvx/dq_vx, dx/dq_vx, dvy/dq_vy, dy/dq_vy, dI/dq_I).
+constexpr int kNGrad = 9;
+constexpr int kNTan = 7;
+
+// Device-resident control block (384 bytes). Kernels read and update it, so a
 // step needs no host synchronisation.
 struct Ctrl {
   int64_t k;            // committed steps
@@ -85,9 +91,11 @@ struct Ctrl {
   double mean[5];
   double u;             // uniform of the systematic resampling
   uint64_t total;       // fixed-point total weight (2^62 scale) of the CDF
-  double pad1[15];
+  double grad_cum[kNGrad];   // d cum / d theta over committed steps
+  double grad_last[kNGrad];  // the last committed step's term
+  double pad1[13];
 };
-static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
+static_assert(sizeof(Ctrl) == 384, "Ctrl must stay 384 bytes");
 
 // Prefix of one chunk of block records: P = fixed-point CDF before the chunk,
 // phi = factor from the chunk's relative integer weights to the CDF scale.
@@ -118,6 +126,9 @@ struct Model {
   double inv_group;
   uint32_t key0, key1, track;
   int32_t strat_t;       // stratified init: total cell bits
+  int32_t grad;          // accumulate d log p^ / d theta
+  double s_psf;          // s
+  double sig;            // sigma_xi
 };
 
 // Device buffers carved from the caller's workspace (or a scratch area).
@@ -136,6 +147,10 @@ struct Buffers {
   double* lw64;  // fp64 per-particle log weights (caller-set, or output staging)
   double* lwg;   // RNA per-group log(W_g / n)
   FillRun* hq;   // queued long runs of output slots
+  float* T0;     // gradient mode: tangents, kNTan*n SoA, double-buffered with X
+  float* T1;
+  double* RG;    // gradient mode: per block sum E d l / d theta (kNGrad doubles)
+  double* CRG;   // gradient mode: per chunk, the same merged (kNGrad doubles)
   int64_t hq_cap;   // entries of hq
   int64_t nb;       // block records = ceil(n / kBlock)
   int64_t chunk;    // records per merge chunk (multiple of 256, at most 2048)

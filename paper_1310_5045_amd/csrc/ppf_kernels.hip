@@ -278,8 +278,11 @@ __device__ __forceinline__ void init_body(const Model& m, const Buffers& b, int6
     for (int d = 0; d < 5; ++d) c->mean[d] = 0.0;
     c->u = 0.0;
     c->total = 0;
+    for (int d = 0; d < kNGrad; ++d) c->grad_cum[d] = c->grad_last[d] = 0.0;
   }
   if (i >= m.n) return;
+  if (m.grad)
+    for (int d = 0; d < kNTan; ++d) b.T0[(int64_t)d * m.n + i] = 0.0f;
   const uint4 r0 = draw(m, (uint32_t)i, 0u, kInit, 0u);
   const uint4 r1 = draw(m, (uint32_t)i, 0u, kInit, 1u);
   double x[5];
@@ -332,8 +335,10 @@ struct Prop {
   double lw;
 };
 
+// zo (5 normals) and po (the parent) are optional outputs for the tangents.
 __device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int cur, int mode,
-                                          double delta, int64_t i, uint32_t k) {
+                                          double delta, int64_t i, uint32_t k,
+                                          float* zo = nullptr, int64_t* po = nullptr) {
   const float* Xin = cur ? b.X1 : b.X0;
   int64_t p = i;
   double lw;
@@ -361,6 +366,14 @@ __device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int 
   box_muller(r0.x, r0.y, z0, z1);
   box_muller(r0.z, r0.w, z2, z3);
   box_muller(r1.x, r1.y, z4, unused);
+  if (zo) {
+    zo[0] = z0;
+    zo[1] = z1;
+    zo[2] = z2;
+    zo[3] = z3;
+    zo[4] = z4;
+  }
+  if (po) *po = p;
   Prop o;
   // near-constant velocity, unit frame interval; fp64 sum rounded once
   o.x = (float)((double)px + (double)pvx + (double)m.q[0] * (double)z0);
@@ -393,9 +406,10 @@ __device__ __forceinline__ double item_weight(double e) {
 // The block's normalisation record (see kRec) and the stored weights
 // E = exp(l - m_b) in fp32. red: 7 x 256 doubles of LDS that no thread reads
 // once it has reached this call (it may alias the caller's image tile).
-__device__ __forceinline__ void finish_block(const Buffers& b, int cur, int64_t i, bool active,
-                                             double l, const Prop& o, double* red,
-                                             double* dsh) {
+// Returns e = E (0 for an inactive or non-finite particle).
+__device__ __forceinline__ double finish_block(const Buffers& b, int cur, int64_t i, bool active,
+                                               double l, const Prop& o, double* red,
+                                               double* dsh) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const bool bad = active && (isnan(l) || l == INFINITY);
   const double wm = wave_reduce((active && !bad) ? l : -INFINITY, lane, OpMax());
@@ -439,6 +453,7 @@ __device__ __forceinline__ void finish_block(const Buffers& b, int cur, int64_t 
     if (2 * w + 1 < 7) R[2 + 2 * w] = h1;
     if (w == 0) R[0] = mb;
   }
+  return e;
 }
 
 // Patch sums of one particle over P rows of an LDS tile of D = Z - b (0
@@ -497,6 +512,81 @@ __device__ __forceinline__ void patch_global(const float* __restrict__ obs, int 
   }
 }
 
+// Gradient mode: moments of one particle's patch. With D = Z - b (0 outside
+// the frame), the Gaussian factors g = g_x g_y and the integer offsets
+// a = dx - h, c = dy - h of a pixel from the patch centre:
+//   X0 = sum D g,  X1 = sum D g a,  X2 = sum D g a^2,
+//   Y1 = sum D g c,  Y2 = sum D g c^2,
+//   B0, B1, B2 = sum_dy g_y^2 c^{0,1,2},  SD = sum D,
+//   Gin = sum of g_y over the rows inside the frame,
+//   sd2 = sum D^2 (from the row-sum table when TAB).
+// X0, B0 and sd2 are accumulated in the same order as patch_lds, so the log
+// weights equal those of the plain step.
+struct Moments {
+  double X0, X1, X2, Y1, Y2, B0, B1, B2, SD, Gin, sd2;
+};
+
+template <int P>
+__device__ __forceinline__ void moments_row(const double (&d)[P], const double (&gx)[P], int dy,
+                                            double gy, bool row_in, bool sq_pix, Moments& mo) {
+  constexpr int h = (P - 1) / 2;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0, s1 = 0.0;
+#pragma unroll
+  for (int dx = 0; dx < P; ++dx) {
+    r0 = fma(d[dx], gx[dx], r0);
+    const double tt = d[dx] * gx[dx];
+    r1 = fma(tt, (double)(dx - h), r1);
+    r2 = fma(tt, (double)((dx - h) * (dx - h)), r2);
+    s1 += d[dx];
+    if (sq_pix) mo.sd2 = fma(d[dx], d[dx], mo.sd2);
+  }
+  const double c = (double)(dy - h);
+  mo.X0 = fma(gy, r0, mo.X0);
+  mo.X1 = fma(gy, r1, mo.X1);
+  mo.X2 = fma(gy, r2, mo.X2);
+  const double gr = gy * r0;
+  mo.Y1 = fma(gr, c, mo.Y1);
+  mo.Y2 = fma(gr, c * c, mo.Y2);
+  mo.B0 = fma(gy, gy, mo.B0);
+  const double g2 = gy * gy;
+  mo.B1 = fma(g2, c, mo.B1);
+  mo.B2 = fma(g2, c * c, mo.B2);
+  mo.SD += s1;
+  if (row_in) mo.Gin += gy;
+}
+
+// Rows from the LDS tile (TAB: sum D^2 from the row-sum table) or from the
+// frame; v0 is the frame row of the patch's first row.
+template <int P, bool TAB, bool GLOBAL>
+__device__ __forceinline__ void patch_moments(const double* __restrict__ p0, int tw,
+                                              const double* __restrict__ hrow, int hs,
+                                              const float* __restrict__ obs, int u0, double bsub,
+                                              int W, int H, int64_t v0,
+                                              const double (&gx)[P], double gy, double by,
+                                              const double* gstep, Moments& mo) {
+#pragma unroll 1
+  for (int dy = 0; dy < P; ++dy) {
+    const int64_t v = v0 + dy;
+    const bool row_in = v >= 0 && v < H;
+    double d[P];
+    if (GLOBAL) {
+      const float* row = obs + (row_in ? v : 0) * (int64_t)W;
+#pragma unroll
+      for (int dx = 0; dx < P; ++dx) {
+        const int u = u0 + dx;
+        d[dx] = (row_in && (unsigned)u < (unsigned)W) ? (double)row[u] - bsub : 0.0;
+      }
+    } else {
+      const double* row = p0 + dy * tw;
+#pragma unroll
+      for (int dx = 0; dx < P; ++dx) d[dx] = row[dx];
+    }
+    moments_row<P>(d, gx, dy, gy, row_in, !TAB, mo);
+    if (TAB) mo.sd2 += hrow[dy * hs];
+    gy *= gstep[dy] * by;
+  }
+}
+
 // Propagation and log weight of one particle per thread (Eq. 4 with the spot
 // of Eq. 3 on the P x P patch). The residual sum is expanded as
 //   sum (D - I g)^2 = sum D^2 - 2 I sum D g + I^2 sum g^2,   D = Z - b,
@@ -508,7 +598,7 @@ __device__ __forceinline__ void patch_global(const float* __restrict__ obs, int 
 // instead of squaring P^2 pixels.
 // Five barriers per workgroup: the box, the tile, the table, the block
 // maximum, and the record exchange.
-template <int P>
+template <int P, bool GRAD = false>
 __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
                                           const float* __restrict__ obs, int64_t blk) {
   constexpr int h = (P - 1) / 2;
@@ -526,13 +616,37 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   const bool active = i < m.n;
 
   Prop o{};
-  double fx = 0.0, fy = 0.0;
+  double fx = 0.0, fy = 0.0, rx = 0.0, ry = 0.0;
   int cx = 0, cy = 0;
+  float tg[kNTan] = {};  // gradient mode: the particle's new tangents
   if (active) {
-    o = propagate(m, b, cur, mode, cdelta, i, k);
+    if (GRAD) {
+      float z[5];
+      int64_t p;
+      o = propagate(m, b, cur, mode, cdelta, i, k, z, &p);
+      // tangents along the ancestral line (see kNTan): dx'/dq_x = dx/dq_x +
+      // z_x, dx'/dq_vx = dx/dq_vx + dvx/dq_vx (the parent's), and alike
+      const float* Tin = cur ? b.T1 : b.T0;
+      float* Tout = cur ? b.T0 : b.T1;
+      float tp[kNTan];
+#pragma unroll
+      for (int d = 0; d < kNTan; ++d) tp[d] = Tin[(int64_t)d * m.n + p];
+      tg[0] = (float)((double)tp[0] + (double)z[0]);
+      tg[1] = (float)((double)tp[1] + (double)z[1]);
+      tg[2] = (float)((double)tp[2] + (double)z[2]);
+      tg[3] = (float)((double)tp[3] + (double)tp[2]);
+      tg[4] = (float)((double)tp[4] + (double)z[3]);
+      tg[5] = (float)((double)tp[5] + (double)tp[4]);
+      tg[6] = (float)((double)tp[6] + (double)z[4]);
+#pragma unroll
+      for (int d = 0; d < kNTan; ++d) Tout[(int64_t)d * m.n + i] = tg[d];
+    } else {
+      o = propagate(m, b, cur, mode, cdelta, i, k);
+    }
     store_state(m, b, cur, i, o);
     // patch centre: pixel nearest to (x, y); the offset f is exact in fp64
-    const double rx = floor((double)o.x + 0.5), ry = floor((double)o.y + 0.5);
+    rx = floor((double)o.x + 0.5);
+    ry = floor((double)o.y + 0.5);
     fx = (double)o.x - rx;
     fy = (double)o.y - ry;
     // addresses only: far-away centres are clamped where the whole patch
@@ -636,7 +750,61 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   __syncthreads();
 
   double l = -INFINITY;
-  if (active) {
+  double gth[GRAD ? kNGrad : 1] = {};
+  if (GRAD && active) {
+    const double* p0 = tile + (cy - h - ty0) * ts + (cx - h - tx0);
+    Moments mo{};
+    // frame row of the patch's first row; centres far outside are clamped,
+    // as for the addresses (every row of such a patch is outside the frame)
+    const int64_t v0 = (int64_t)fmin(fmax(ry, -(double)P - 1.0), (double)m.H + P + 1.0) - h;
+    if (use_tab)
+      patch_moments<P, true, false>(p0, ts, sq + (int64_t)(cy - mny) * acx + (cx - mnx),
+                                    (int)acx, obs, 0, m.b, m.W, m.H, v0, gx, gy0, by, m.gstep,
+                                    mo);
+    else if (use_lds)
+      patch_moments<P, false, false>(p0, ts, sq, 0, obs, 0, m.b, m.W, m.H, v0, gx, gy0, by,
+                                     m.gstep, mo);
+    else
+      patch_moments<P, false, true>(p0, 0, sq, 0, obs, cx - h, m.b, m.W, m.H, v0, gx, gy0, by,
+                                    m.gstep, mo);
+    const double I = (double)o.I;
+    const double ssq = mo.sd2 - 2.0 * I * mo.X0 + I * I * (G2x * mo.B0);
+    l = o.lw - ssq * m.inv2sig2 - m.lognorm_obs;
+    // 1-D moments of g_x^2 and the in-frame sum of g_x (true centre rx)
+    double A1 = 0.0, A2 = 0.0, Gin_x = 0.0;
+#pragma unroll
+    for (int dx = 0; dx < P; ++dx) {
+      const double g2 = gx[dx] * gx[dx];
+      A1 = fma(g2, (double)(dx - h), A1);
+      A2 = fma(g2, (double)((dx - h) * (dx - h)), A2);
+      const double u = rx + (double)(dx - h);
+      if (u >= 0.0 && u < (double)m.W) Gin_x += gx[dx];
+    }
+    const double A0 = G2x, B0 = mo.B0;
+    // moments in the offsets from the particle, e = a - f
+    const double ex1 = mo.X1 - fx * mo.X0;
+    const double ex2 = mo.X2 - 2.0 * fx * mo.X1 + fx * fx * mo.X0;
+    const double ey1 = mo.Y1 - fy * mo.X0;
+    const double ey2 = mo.Y2 - 2.0 * fy * mo.Y1 + fy * fy * mo.X0;
+    const double gx1 = A1 - fx * A0, gx2 = A2 - 2.0 * fx * A1 + fx * fx * A0;
+    const double gy1 = mo.B1 - fy * B0, gy2 = mo.B2 - 2.0 * fy * mo.B1 + fy * fy * B0;
+    const double isg2 = 2.0 * m.inv2sig2, is2 = 2.0 * m.inv2s2;
+    const double lI = (mo.X0 - I * A0 * B0) * isg2;
+    const double lx = I * isg2 * is2 * (ex1 - I * B0 * gx1);
+    const double ly = I * isg2 * is2 * (ey1 - I * A0 * gy1);
+    const double ls = I * isg2 * is2 / m.s_psf * (ex2 + ey2 - I * (B0 * gx2 + A0 * gy2));
+    const double lb = isg2 * (mo.SD - I * Gin_x * mo.Gin);
+    const double lsig = ssq / (m.sig * m.sig * m.sig) - (double)(P * P) / m.sig;
+    gth[0] = ls;
+    gth[1] = lb;
+    gth[2] = lsig;
+    gth[3] = lx * (double)tg[0];
+    gth[4] = ly * (double)tg[1];
+    gth[5] = lx * (double)tg[3];
+    gth[6] = ly * (double)tg[5];
+    gth[7] = lI * (double)tg[6];
+    gth[8] = lI;
+  } else if (active) {
     double X = 0.0, G2y = 0.0, sd2 = 0.0;
     const double* p0 = tile + (cy - h - ty0) * ts + (cx - h - tx0);
     if (use_tab) {
@@ -651,7 +819,18 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     const double ssq = sd2 - 2.0 * I * X + I * I * (G2x * G2y);
     l = o.lw - ssq * m.inv2sig2 - m.lognorm_obs;
   }
-  finish_block(b, cur, i, active, l, o, tile, dsh);
+  const double e = finish_block(b, cur, i, active, l, o, tile, dsh);
+  if (GRAD) {
+    // the block's sum_i E_i d l_i / d theta, weighted like the MMSE sums
+    __shared__ double gsh[4 * kNGrad];
+    double v[kNGrad];
+#pragma unroll
+    for (int d = 0; d < kNGrad; ++d) v[d] = (e > 0.0) ? e * gth[d] : 0.0;
+    block_sum_n<kNGrad>(v, gsh);
+    if (t == 0)
+#pragma unroll
+      for (int d = 0; d < kNGrad; ++d) b.RG[blk * kNGrad + d] = v[d];
+  }
 }
 
 // Patches up to 13 x 13 fit five waves per SIMD in registers without
@@ -666,6 +845,13 @@ template <int P>
 __global__ __launch_bounds__(256) void k_step_spot_wide(Model m, Buffers b,
                                                         const float* __restrict__ obs) {
   step_spot<P>(m, b, obs, blockIdx.x);
+}
+
+// Gradient mode (derivatives of log p^ alongside the step).
+template <int P>
+__global__ __launch_bounds__(256) void k_step_spot_grad(Model m, Buffers b,
+                                                        const float* __restrict__ obs) {
+  step_spot<P, true>(m, b, obs, blockIdx.x);
 }
 
 // Linear-Gaussian observation of (x, y, I0): three fp32 values on the device.
@@ -751,6 +937,7 @@ __device__ __forceinline__ void merge_body(const Model& m, const Buffers& b, int
                                            double u_given, int64_t ch) {
   __shared__ double dsh[4];
   __shared__ double nsh[4 * 7];
+  __shared__ double gsh[4 * kNGrad];
   __shared__ uint64_t ush[4];
   __shared__ int sh_last;
   __shared__ int sh_pre;
@@ -771,6 +958,7 @@ __device__ __forceinline__ void merge_body(const Model& m, const Buffers& b, int
   const double Mc = block_reduce(mx, dsh, OpMax());
   uint64_t qs = 0;
   double s2 = 0.0, ex[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double gs[kNGrad] = {};
   for (int q = 0; q < per; ++q) {
     const int64_t j = j0 + q;
     if (j < hi) {
@@ -780,6 +968,9 @@ __device__ __forceinline__ void merge_body(const Model& m, const Buffers& b, int
       s2 += r[2] * (f * f);
 #pragma unroll
       for (int d = 0; d < 5; ++d) ex[d] += r[3 + d] * f;
+      if (m.grad && f != 0.0)
+#pragma unroll
+        for (int d = 0; d < kNGrad; ++d) gs[d] += b.RG[j * kNGrad + d] * f;
     }
   }
   uint64_t qtot;
@@ -801,6 +992,12 @@ __device__ __forceinline__ void merge_body(const Model& m, const Buffers& b, int
     cr[1] = __longlong_as_double((long long)qtot);
 #pragma unroll
     for (int d = 0; d < 6; ++d) cr[2 + d] = sums[d];
+  }
+  if (m.grad) {
+    block_sum_n<kNGrad>(gs, gsh);
+    if (t == 0)
+#pragma unroll
+      for (int d = 0; d < kNGrad; ++d) b.CRG[ch * kNGrad + d] = gs[d];
   }
   // arrival: the last workgroup finishes the step
   __threadfence();
@@ -844,10 +1041,27 @@ __device__ __forceinline__ void merge_body(const Model& m, const Buffers& b, int
 #pragma unroll
     for (int d = 0; d < 5; ++d) E[d] = tot7[2 + d];
   }
+  double G[kNGrad] = {};
+  if (m.grad) {
+    for (int q = 0; q < per2; ++q) {
+      const int64_t cc = c0 + q;
+      if (cc < nch) {
+        const double mc = ld(cc * kRec);
+        if (mc != -INFINITY) {
+          const double f = exp(mc - M);
+#pragma unroll
+          for (int d = 0; d < kNGrad; ++d) G[d] += b.CRG[cc * kNGrad + d] * f;
+        }
+      }
+    }
+    block_sum_n<kNGrad>(G, gsh);
+  }
   if (t == 0) {
     bool ok = isfinite(M) && isfinite(S) && S > 0.0 && isfinite(S2);
 #pragma unroll
     for (int d = 0; d < 5; ++d) ok = ok && isfinite(E[d]);
+#pragma unroll
+    for (int d = 0; d < kNGrad; ++d) ok = ok && isfinite(G[d]);
     int pre = 0;
     if (standalone) {
       c->cur = 0;
@@ -870,6 +1084,12 @@ __device__ __forceinline__ void merge_body(const Model& m, const Buffers& b, int
       c->cum += M + logS;
 #pragma unroll
       for (int d = 0; d < 5; ++d) c->mean[d] = E[d] / S;
+      if (m.grad)
+#pragma unroll
+        for (int d = 0; d < kNGrad; ++d) {
+          c->grad_last[d] = G[d] / S;
+          c->grad_cum[d] += G[d] / S;
+        }
       c->resampled = res ? 1 : 0;
       c->do_resample = res ? 1 : 0;
       c->mode = res ? (m.group > 0 ? kModeRna : kModeSys) : kModeNone;
@@ -1378,7 +1598,9 @@ __global__ __launch_bounds__(256) void k_philox(uint32_t k0, uint32_t k1,
 
 template <int P>
 hipError_t launch_spot(const Model& m, const Buffers& b, const float* obs, hipStream_t s) {
-  if constexpr (P <= 13)
+  if (m.grad)
+    hipLaunchKernelGGL(k_step_spot_grad<P>, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);
+  else if constexpr (P <= 13)
     hipLaunchKernelGGL(k_step_spot<P>, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);
   else
     hipLaunchKernelGGL(k_step_spot_wide<P>, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);

@@ -26,8 +26,9 @@ DELTA_ATOL = 1e-4
 
 
 def pair(ppf, **kw):
-    """Matching library parameters and oracle model."""
-    okw = dict(kw)
+    """Matching library parameters and oracle model (library-only keys such
+    as grad are not passed to the oracle)."""
+    okw = {k: v for k, v in kw.items() if k not in ("grad",)}
     pkw = {}
     ren = dict(n="n_particles", s="psf_sigma", b="background", sigma="noise_sigma", track="track_id",
                rna_exchange="rna_exchange")

@@ -46,7 +46,7 @@ def test_params_layout_and_defaults():
     dict(resample=1, rna_group=300), dict(resample=1, rna_group=2048, n_particles=4096),
     dict(resample=1, rna_exchange=1.0), dict(obs_model=7), dict(init_kind=9),
     dict(q=(0.5, 0.5, -0.1, 0.1, 1.0)), dict(ess_threshold=float("nan")),
-    dict(psf_sigma=0.2, patch=25), dict(obs_model=1, lg_r=(1.0, 0.0, 1.0)), dict(reserved=1),
+    dict(psf_sigma=0.2, patch=25), dict(obs_model=1, lg_r=(1.0, 0.0, 1.0)), dict(grad=2), dict(grad=1, resample=1), dict(grad=1, ess_threshold=1e3), dict(grad=1, obs_model=1),
 ])
 def test_invalid_parameters_are_rejected(bad):
     p = ppf.params(**bad)
