@@ -115,7 +115,9 @@ WORKLOADS = {
     "sir_128x128_n4096_p9": dict(W=128, H=128, T=10, n=4096, s=1.5, P=9, thr=float("inf")),
     # forward pass with the derivatives of log p^ in (s, b, sigma, q, I0)
     "grad_512x512_n262k_p11": dict(W=512, H=512, T=30, n=1 << 18, s=1.7, P=11, thr=float("inf"),
-                                   I=25.0, grad=1),
+                                   I=25.0, grad=1, box=(128, 384, 128, 384)),
+    "grad_1024x1024_n38m_p13": dict(W=1024, H=1024, T=20, n=38_000_000, s=2.0, P=13,
+                                    thr=float("inf"), grad=1),
     # 256 spots, one independent filter each, stepped as one batch
     "multitrack_1024x1024_t256": dict(W=1024, H=1024, T=30, tracks=256, n_lo=1024, n_hi=262144,
                                       s_lo=1.2, s_hi=2.5, I_lo=15.0, I_hi=60.0, vmax=2.0,
@@ -214,9 +216,14 @@ def run_multitrack(args, w):
 
 
 def make_params(ppf, w, init_kind, grad=0):
+    """The filter of a single-filter workload: the initial cloud covers the
+    spot's start box (default the whole frame), intensity within a factor
+    of 2 of the spot's."""
+    x0, x1, y0, y1 = w.get("box", (0, w["W"], 0, w["H"]))
+    I = w.get("I", 30.0)
     return ppf.params(n_particles=w["n"], width=w["W"], height=w["H"], psf_sigma=w["s"],
                       background=10.0, noise_sigma=3.0, patch=w["P"], init_kind=init_kind,
-                      init_a=(0, 0, -1, -1, 15), init_b=(w["W"], w["H"], 1, 1, 45),
+                      init_a=(x0, y0, -1, -1, I / 2), init_b=(x1, y1, 1, 1, 1.5 * I),
                       ess_threshold=w["thr"], seed=1, grad=grad)
 
 
@@ -243,9 +250,11 @@ def cpu_baseline(w, frames, sample_n, sample_t, init_kind):
     """The oracle as it stands, single-threaded, on a bounded sample: the
     first `sample_t` frames of the same movie with `sample_n` particles."""
     import oracle
+    x0, x1, y0, y1 = w.get("box", (0, w["W"], 0, w["H"]))
+    I = w.get("I", 30.0)
     m = oracle.Model(n=sample_n, width=w["W"], height=w["H"], s=w["s"], b=10.0, sigma=3.0,
-                     patch=w["P"], init_kind=init_kind, init_a=(0, 0, -1, -1, 15),
-                     init_b=(w["W"], w["H"], 1, 1, 45), ess_threshold=w["thr"], seed=1)
+                     patch=w["P"], init_kind=init_kind, init_a=(x0, y0, -1, -1, I / 2),
+                     init_b=(x1, y1, 1, 1, 1.5 * I), ess_threshold=w["thr"], seed=1)
     t0 = time.perf_counter()
     r = oracle.run(m, frames[:sample_t], sample_t)
     dt = time.perf_counter() - t0
@@ -296,8 +305,10 @@ def main():
     init_kind = ppf.INIT_STRATIFIED if args.init == "stratified" else ppf.INIT_UNIFORM
     K, Wm = args.steps, args.warmup
     T = max(K, w["T"], Wm)
+    box = w.get("box")
     mv = synth.render_movie(w["W"], w["H"], T, intensity=w.get("I", 30.0), sigma=w["s"],
-                            background=10.0, noise_sd=3.0, seed=1)
+                            background=10.0, noise_sd=3.0, seed=1,
+                            start_box=None if box is None else tuple(float(v) for v in box))
     torch.cuda.set_device(0)
     frames = torch.from_numpy(mv.frames).cuda()
     if args.copy_probe_mib:
