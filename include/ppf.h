@@ -81,7 +81,9 @@ typedef struct ppf_ctx* ppf_handle;
  * noise_sigma   sigma_xi of Eq. 4 (> 0).
  * patch         P, the edge of the square pixel set S_x of Eq. 4, odd,
  *               1..PPF_MAX_PATCH; 0 selects 2*floor(3*psf_sigma)+1, the
- *               integer reading of the +-3 sigma_PSF box.
+ *               integer reading of the +-3 sigma_PSF box. EINVAL when
+ *               (h + 1/2)^2 / (2 psf_sigma^2) > 350, h = (P - 1) / 2 (a patch
+ *               so wide that its edge factors would leave the fp64 range).
  * q[5]          process-noise standard deviations of (x, y, vx, vy, I0).
  * init_kind     PPF_INIT_UNIFORM: x0[d] ~ U[init_a[d], init_b[d]) i.i.d. (the
  *               paper initialises uniformly at random, Section 6.3);

@@ -67,8 +67,9 @@ std::string validate(const ppf_params* p) {
     const int P = derived_patch(p);
     if (P < 1 || P > PPF_MAX_PATCH || P % 2 == 0) return "patch must be odd and <= 25";
     const double s = p->psf_sigma, h = (P - 1) / 2;
-    // the Gaussian recurrence starts at the patch edge: keep exp() normal
-    if ((h + 0.5) * (h + 0.5) / (2.0 * s * s) > 700.0) return "patch too wide for psf_sigma";
+    // the Gaussian factors start at the patch corner, the product of the two
+    // axes' edge values: keep it normal (e^-700 > 2^-1022)
+    if ((h + 0.5) * (h + 0.5) / (2.0 * s * s) > 350.0) return "patch too wide for psf_sigma";
   } else {
     for (int d = 0; d < 3; ++d)
       if (!(p->lg_r[d] > 0.0f) || !std::isfinite(p->lg_r[d])) return "lg_r must be > 0";

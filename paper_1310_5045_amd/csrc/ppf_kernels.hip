@@ -655,17 +655,22 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     cx = (rx >= lox && rx <= hix) ? (int)rx : (rx > hix ? (int)hix : (int)lox);
     cy = (ry >= loy && ry <= hiy) ? (int)ry : (ry > hiy ? (int)hiy : (int)loy);
   }
-  // the 1-D Gaussian factors of Eq. 3 at the patch's pixel offsets
+  // The 1-D Gaussian factors of Eq. 3 at the patch's pixel offsets. Only
+  // their products g_x g_y enter the likelihood, so g_x is taken relative to
+  // its first value, which moves into the first g_y: three exps per particle
+  // (the host keeps both first values above e^-350, so the product stays
+  // normal).
   double gx[P];
   double G2x = 0.0, gy0 = 0.0, by = 0.0;
   if (active) {
-    gx[0] = exp_fast(-((double)h + fx) * ((double)h + fx) * m.inv2s2);
+    gx[0] = 1.0;
     const double bx = exp_fast(2.0 * fx * m.inv2s2);
 #pragma unroll
     for (int d = 0; d + 1 < P; ++d) gx[d + 1] = gx[d] * (m.gstep[d] * bx);
 #pragma unroll
     for (int d = 0; d < P; ++d) G2x = fma(gx[d], gx[d], G2x);
-    gy0 = exp_fast(-((double)h + fy) * ((double)h + fy) * m.inv2s2);
+    const double ax = (double)h + fx, ay = (double)h + fy;
+    gy0 = exp_fast(-(ax * ax + ay * ay) * m.inv2s2);
     by = exp_fast(2.0 * fy * m.inv2s2);
   } else {
 #pragma unroll
