@@ -1157,7 +1157,8 @@ __global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalon
 
 // CDF position of the start of block blk, as a fraction of the total.
 __device__ __forceinline__ double block_P(const Buffers& b, int64_t blk) {
-  const ChunkPre cp = b.cpre[blk / b.chunk];
+  // chunk = 256 per with per <= 8 and blk < 2^23: a 32-bit quotient
+  const ChunkPre cp = b.cpre[(uint32_t)(blk >> 8) / (uint32_t)(b.chunk >> 8)];
   const uint64_t P = cp.P + (uint64_t)rint((double)b.pfx[blk] * cp.phi);
   return (double)P * (1.0 / kCdfScale);
 }
@@ -1170,8 +1171,14 @@ __device__ __forceinline__ int slot_bound(double C, double u, double nd, int n) 
   return x <= 0.0 ? 0 : (x >= nd ? n : (int)x);
 }
 
+__device__ __forceinline__ int slot_pad(int e) { return e + (e >> 4); }
+
 struct AncShared {
-  int A[kSlotTile];  // owner marks of one tile of slots, then their running maximum
+  // owner marks of one tile of slots, then their running maximum; slot e
+  // lives at slot_pad(e), one spare word after every 16, so that a thread
+  // walking its own 16 consecutive slots and the threads of a wave walking
+  // consecutive slots both meet distinct banks
+  int A[kSlotTile + kSlotTile / 16];
   double Pb[kSegBlocks + 1];
   double d4[4];
   int i4[4];
@@ -1186,15 +1193,18 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
                                          int64_t seg) {
   __shared__ AncShared sh;
   Ctrl* c = b.ctrl;
-  if (!c->do_resample) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int cur = c->cur;
-  const double delta = c->delta, u = c->u;
-  const int n = (int)m.n;
-  const double nd = (double)m.n;
   const int64_t b0 = seg * kSegBlocks;
   const int nbs = (int)min((int64_t)kSegBlocks, b.nb - b0);
-  if (t <= nbs) sh.Pb[t] = (b0 + t < b.nb) ? block_P(b, b0 + t) : 1.0;
+  // the block starts of the CDF do not depend on the control block: their
+  // loads go out with its (in-bounds reads, discarded when nothing resamples)
+  const int do_res = c->do_resample, cur = c->cur;
+  const double delta = c->delta, u = c->u;
+  const double pbt = (t <= nbs && b0 + t < b.nb) ? block_P(b, b0 + t) : 1.0;
+  if (!do_res) return;
+  const int n = (int)m.n;
+  const double nd = (double)m.n;
+  if (t <= nbs) sh.Pb[t] = pbt;
   __syncthreads();
   const int fs = seg == 0 ? 0 : slot_bound(sh.Pb[0], u, nd, n);
   const int fe = seg + 1 >= b.nseg ? n : slot_bound(sh.Pb[nbs], u, nd, n);
@@ -1310,17 +1320,17 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
     for (int c0 = fs; c0 < fe; c0 += kSlotTile) {
       const int cn = min(kSlotTile, fe - c0);
 #pragma unroll
-      for (int k = 0; k < kk; ++k) sh.A[k * 256 + t] = -1;
+      for (int k = 0; k < kk; ++k) sh.A[slot_pad(k * 256 + t)] = -1;
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (hq[q] > st[q] && st[q] >= c0 && st[q] < c0 + cn) sh.A[st[q] - c0] = 8 * t + q;
+        if (hq[q] > st[q] && st[q] >= c0 && st[q] < c0 + cn) sh.A[slot_pad(st[q] - c0)] = 8 * t + q;
       __syncthreads();
       int v[kk];
       int run = -1;
 #pragma unroll
       for (int k = 0; k < kk; ++k) {
-        run = max(run, sh.A[t * kk + k]);
+        run = max(run, sh.A[slot_pad(t * kk + k)]);
         v[k] = run;
       }
       const int winc2 = wave_scan(run, lane, OpMax());
@@ -1334,13 +1344,13 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
       // the particles back into the tile, then stored with consecutive
       // threads on consecutive slots
 #pragma unroll
-      for (int k = 0; k < kk; ++k) sh.A[t * kk + k] = max(max(before, v[k]), 0);
+      for (int k = 0; k < kk; ++k) sh.A[slot_pad(t * kk + k)] = max(max(before, v[k]), 0);
       carry_item = max(max(carry_item, max(sh.i8[0], sh.i8[1])), max(sh.i8[2], sh.i8[3]));
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < kk; ++k) {
         const int e = k * 256 + t;
-        if (e < cn) anc[c0 + e] = (int32_t)(ib0 + sh.A[e]);
+        if (e < cn) anc[c0 + e] = (int32_t)(ib0 + sh.A[slot_pad(e)]);
       }
       __syncthreads();  // sh.A and sh.i8 are rewritten by the next tile
     }
