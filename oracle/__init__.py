@@ -89,6 +89,11 @@ def lib():
         L.orc_step_grad.argtypes = [i64, vp, vp, vp, vp]
         L.orc_run_grad.argtypes = [P(_Model), i32, vp, vp, vp, vp, P(d), vp]
         L.orc_run_grad.restype = ctypes.c_int
+        L.orc_rpa_counts.argtypes = [i64, i32, vp, vp]
+        L.orc_dlb_schedule.argtypes = [ctypes.c_int, i64, i32, vp, i64, vp]
+        L.orc_dlb_schedule.restype = i64
+        L.orc_resample_rpa.argtypes = [i64, i32, ctypes.c_int, vp, vp]
+        L.orc_resample_rpa.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -362,3 +367,36 @@ def run_grad(m: Model, frames: np.ndarray, T: int, anc_replay: Optional[np.ndarr
     if st != 0:
         raise FloatingPointError(f"orc_run_grad returned {st}")
     return (cum.value, g, anc, xt) if trace else (cum.value, g, anc)
+
+
+# ------------------------------------------------------ RPA and DLB (Section 4)
+DLB_GS, DLB_SGS, DLB_LGS = 0, 1, 2
+
+
+def rpa_counts(anc_sys: np.ndarray, group: int) -> np.ndarray:
+    a = np.ascontiguousarray(anc_sys, dtype=np.int32)
+    out = np.empty(a.size // group, dtype=np.int32)
+    lib().orc_rpa_counts(a.size, group, _ptr(a), _ptr(out))
+    return out
+
+
+def dlb_schedule(kind: int, counts: np.ndarray, n: int) -> np.ndarray:
+    """(m, 3) int32 entries (sender group, receiver group, particles)."""
+    c = np.ascontiguousarray(counts, dtype=np.int32)
+    cap = 2 * c.size + 1
+    out = np.empty((cap, 3), dtype=np.int32)
+    m = lib().orc_dlb_schedule(kind, c.size, n, _ptr(c), cap, _ptr(out))
+    if m < 0:
+        raise RuntimeError("schedule capacity exceeded")
+    return out[:m].copy()
+
+
+def resample_rpa(w: np.ndarray, u: float, group: int, kind: int) -> np.ndarray:
+    """RPA ancestors (kind GS or SGS) for normalised weights w with the
+    systematic uniform u."""
+    a_sys = resample_systematic(w, u)
+    out = np.empty(w.size, dtype=np.int32)
+    st = lib().orc_resample_rpa(w.size, group, kind, _ptr(a_sys), _ptr(out))
+    if st != 0:
+        raise RuntimeError("RPA left a group unbalanced")
+    return out

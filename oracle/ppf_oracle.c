@@ -583,3 +583,156 @@ int orc_run_grad(const orc_model* m, int32_t T, const float* obs, const int32_t*
   free(parent);
   return status;
 }
+
+/* ------------------------------------------- RPA and its DLB schedules */
+
+/*
+ * Resampling with proportional allocation (RPA, Section 3) over G groups of
+ * n consecutive particles standing in for processes: the number of
+ * offspring of group g, N_g, is its share of the global systematic
+ * resampling (slots i whose (i + u)/N falls in the group's CDF range), so
+ * heavy groups produce more than n offspring (senders, surplus N_g - n) and
+ * light ones fewer (receivers, deficit n - N_g). The DLB schedules of
+ * Section 4 route the surplus so that every group ends with n particles.
+ */
+
+/* Offspring counts N_g (G values) from the ancestors of global systematic
+ * resampling. */
+void orc_rpa_counts(int64_t n_total, int32_t group, const int32_t* anc_sys, int32_t* counts) {
+  const int64_t G = n_total / group;
+  for (int64_t g = 0; g < G; ++g) counts[g] = 0;
+  for (int64_t i = 0; i < n_total; ++i) counts[anc_sys[i] / group] += 1;
+}
+
+/* Sort the entries idx[0..m) by key[idx] descending, ties by index
+ * ascending (insertion sort: plain and stable). */
+static void sort_desc(int32_t* idx, int64_t m, const int64_t* key) {
+  for (int64_t a = 1; a < m; ++a) {
+    const int32_t v = idx[a];
+    int64_t b = a;
+    while (b > 0 && key[idx[b - 1]] < key[v]) {
+      idx[b] = idx[b - 1];
+      --b;
+    }
+    idx[b] = v;
+  }
+}
+
+/*
+ * DLB schedule over the groups' counts (kind 0 = Greedy, Alg. 2; 1 = Sorted
+ * Greedy, Alg. 3; 2 = Largest Gradient, Alg. 4). Senders are the groups with
+ * counts[g] > n, receivers those with counts[g] < n, each listed in group
+ * order (GS) or by surplus / deficit descending (SGS, LGS; ties by group).
+ * Writes up to `cap` entries (sender group, receiver group, particles) to
+ * sched (3 per entry) and returns their number (-1 if cap is too small).
+ *   GS/SGS: each sender in turn fills the current receiver; a filled
+ *           receiver is skipped and the next one taken (the printed loop
+ *           resets j to 0 and never ends on a filled receiver; the reading
+ *           keeps j and skips, which gives the balance the text states);
+ *   LGS:    the i-th sender pairs with the i-th receiver for
+ *           min(|S|, |R|) ranks, moving min(surplus, deficit) particles (the
+ *           printed else branch zeroes the surplus before recording it; the
+ *           reading records it, then zeroes it).
+ */
+int64_t orc_dlb_schedule(int kind, int64_t G, int32_t n, const int32_t* counts, int64_t cap,
+                         int32_t* sched) {
+  int64_t* surplus = (int64_t*)malloc((size_t)G * sizeof(int64_t));
+  int64_t* deficit = (int64_t*)malloc((size_t)G * sizeof(int64_t));
+  int32_t* S = (int32_t*)malloc((size_t)G * sizeof(int32_t));
+  int32_t* R = (int32_t*)malloc((size_t)G * sizeof(int32_t));
+  int64_t ns = 0, nr = 0, m = 0;
+  for (int64_t g = 0; g < G; ++g) {
+    surplus[g] = counts[g] > n ? (int64_t)counts[g] - n : 0;
+    deficit[g] = counts[g] < n ? (int64_t)n - counts[g] : 0;
+    if (surplus[g] > 0) S[ns++] = (int32_t)g;
+    if (deficit[g] > 0) R[nr++] = (int32_t)g;
+  }
+  if (kind != 0) {
+    sort_desc(S, ns, surplus);
+    sort_desc(R, nr, deficit);
+  }
+  if (kind == 2) {
+    const int64_t c = ns < nr ? ns : nr;
+    for (int64_t i = 0; i < c; ++i) {
+      int64_t moved;
+      if (surplus[S[i]] >= deficit[R[i]]) {
+        moved = deficit[R[i]];
+        surplus[S[i]] -= moved;
+      } else {
+        moved = surplus[S[i]];
+        surplus[S[i]] = 0;
+      }
+      if (m >= cap) { m = -1; break; }
+      sched[3 * m] = S[i];
+      sched[3 * m + 1] = R[i];
+      sched[3 * m + 2] = (int32_t)moved;
+      ++m;
+    }
+  } else {
+    int64_t j = 0;
+    for (int64_t i = 0; i < ns && m >= 0; ++i) {
+      while (surplus[S[i]] != 0) {
+        while (j < nr && deficit[R[j]] == 0) ++j;  /* skip filled receivers */
+        if (j >= nr) break;                         /* not reached when balanced */
+        const int64_t moved = surplus[S[i]] >= deficit[R[j]] ? deficit[R[j]] : surplus[S[i]];
+        if (m >= cap) { m = -1; break; }
+        sched[3 * m] = S[i];
+        sched[3 * m + 1] = R[j];
+        sched[3 * m + 2] = (int32_t)moved;
+        ++m;
+        surplus[S[i]] -= moved;
+        deficit[R[j]] -= moved;
+      }
+    }
+  }
+  free(surplus);
+  free(deficit);
+  free(S);
+  free(R);
+  return m;
+}
+
+/*
+ * RPA resampling with a balancing schedule (kind 0 = GS, 1 = SGS): the
+ * offspring of each group are its slots of the global systematic resampling
+ * (anc_sys, in slot order); a group keeps its first min(N_g, n) offspring in
+ * its own slots [g n, g n + min(N_g, n)); then the schedule's entries, in
+ * order, move `particles` of the sender's remaining offspring (in order)
+ * into the receiver's next free slots. anc: n_total ancestors out. Returns
+ * 0, or -1 when a group is left unbalanced.
+ */
+int orc_resample_rpa(int64_t n_total, int32_t group, int kind, const int32_t* anc_sys,
+                     int32_t* anc) {
+  const int64_t G = n_total / group;
+  int32_t* counts = (int32_t*)malloc((size_t)G * sizeof(int32_t));
+  int64_t* first = (int64_t*)malloc((size_t)G * sizeof(int64_t));
+  int64_t* next_out = (int64_t*)malloc((size_t)G * sizeof(int64_t)); /* sender: next offspring */
+  int64_t* fill = (int64_t*)malloc((size_t)G * sizeof(int64_t));     /* receiver: slots filled */
+  int32_t* sched = (int32_t*)malloc((size_t)(3 * 2 * G + 3) * sizeof(int32_t));
+  int status = 0;
+  orc_rpa_counts(n_total, group, anc_sys, counts);
+  int64_t acc = 0;
+  for (int64_t g = 0; g < G; ++g) {
+    first[g] = acc; /* slots of group g's offspring in anc_sys */
+    acc += counts[g];
+    const int64_t keep = counts[g] < group ? counts[g] : group;
+    for (int64_t p = 0; p < keep; ++p) anc[g * group + p] = anc_sys[first[g] + p];
+    next_out[g] = keep;
+    fill[g] = keep;
+  }
+  const int64_t m = orc_dlb_schedule(kind, G, group, counts, 2 * G + 1, sched);
+  if (m < 0) status = -1;
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t s = sched[3 * e], r = sched[3 * e + 1], c = sched[3 * e + 2];
+    for (int32_t q = 0; q < c; ++q)
+      anc[(int64_t)r * group + fill[r]++] = anc_sys[first[s] + next_out[s]++];
+  }
+  for (int64_t g = 0; g < G; ++g)
+    if (fill[g] != group || next_out[g] != counts[g]) status = -1;
+  free(counts);
+  free(first);
+  free(next_out);
+  free(fill);
+  free(sched);
+  return status;
+}

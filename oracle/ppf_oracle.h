@@ -120,6 +120,16 @@ void orc_step_grad(int64_t n, const double* w, const double* dll, const double* 
 int orc_run_grad(const orc_model* m, int32_t T, const float* obs, const int32_t* anc_replay,
                  int32_t* anc_out, double* x_trace, double* cum, double grad[9]);
 
+/* RPA (Section 3) with the DLB schedules of Section 4 over G = n_total /
+ * group groups: offspring counts from the global systematic ancestors, the
+ * schedule (kind 0 GS, 1 SGS, 2 LGS; entries (sender, receiver, particles),
+ * returns their number or -1), and the balanced resampling (kind 0 or 1). */
+void orc_rpa_counts(int64_t n_total, int32_t group, const int32_t* anc_sys, int32_t* counts);
+int64_t orc_dlb_schedule(int kind, int64_t G, int32_t n, const int32_t* counts, int64_t cap,
+                         int32_t* sched);
+int orc_resample_rpa(int64_t n_total, int32_t group, int kind, const int32_t* anc_sys,
+                     int32_t* anc);
+
 #ifdef __cplusplus
 }
 #endif
