@@ -55,7 +55,11 @@ enum {
   PPF_ENOTIMPL = -6   /* option recognised but not built                    */
 };
 
-enum { PPF_RESAMPLE_SYSTEMATIC = 0, PPF_RESAMPLE_RNA = 1 };
+enum { PPF_RESAMPLE_SYSTEMATIC = 0, PPF_RESAMPLE_RNA = 1, PPF_RESAMPLE_RPA = 2 };
+/* DLB schedules of Section 4: Greedy (Alg. 2), Sorted Greedy (Alg. 3),
+ * Largest Gradient (Alg. 4). */
+enum { PPF_DLB_GS = 0, PPF_DLB_SGS = 1, PPF_DLB_LGS = 2 };
+#define PPF_DLB_MAX_SORTED 4096 /* groups a sorted schedule accepts */
 enum { PPF_OBS_SPOT = 0, PPF_OBS_LINEAR_GAUSSIAN = 1 };
 enum { PPF_INIT_UNIFORM = 0, PPF_INIT_GAUSSIAN = 1, PPF_INIT_STRATIFIED = 2 };
 
@@ -95,16 +99,29 @@ typedef struct ppf_ctx* ppf_handle;
  *               indices are then neighbours in the image, which keeps the
  *               first frame's image tiles small.
  * lg_r[3]       observation noise sds of the linear-Gaussian model (> 0).
- * resample      PPF_RESAMPLE_SYSTEMATIC or PPF_RESAMPLE_RNA.
+ * resample      PPF_RESAMPLE_SYSTEMATIC, PPF_RESAMPLE_RNA, or PPF_RESAMPLE_RPA:
+ *               resampling with proportional allocation (Section 3) over
+ *               groups of rna_group consecutive particles standing in for
+ *               processes. Group g's offspring are its share N_g of the
+ *               global systematic resampling (so the resampled multiset is
+ *               that of PPF_RESAMPLE_SYSTEMATIC); it keeps its first
+ *               min(N_g, n) offspring in its own slots, and the surplus of
+ *               groups with N_g > n fills the free slots of groups with
+ *               N_g < n following the DLB schedule `dlb` (GS or SGS, which
+ *               balance exactly). Weights afterwards 1/N.
  * ess_threshold resample iff ESS < ess_threshold (Algorithm 1); +INFINITY
  *               resamples every step, 0 never.
  * rna_group     n, particles per RNA group (one workgroup each); N % n == 0,
- *               1 <= n <= 1024. Ignored for systematic resampling.
+ *               1 <= n <= 1024. For RPA the group size: N % n == 0, and at
+ *               most PPF_DLB_MAX_SORTED groups under SGS. Ignored for
+ *               systematic resampling.
  * rna_exchange  rho in [0, 1): after local resampling the last floor(rho * n)
  *               slots of group g take the particles (and weight) of the same
  *               slots of group g-1 mod G (Section 3, ring of processes).
  * seed          Philox key.
  * track_id      Philox counter word 3 (distinguishes independent filters).
+ * dlb           PPF_DLB_GS or PPF_DLB_SGS: the schedule of RPA.
+ * reserved      must be 0.
  * grad          1: every step also accumulates the derivatives of log p^ in
  *               theta (see ppf_grad). Needs the spot model, systematic
  *               resampling and ess_threshold = +INFINITY; the workspace then
@@ -133,6 +150,8 @@ typedef struct ppf_params {
   uint64_t seed;
   uint32_t track_id;
   int32_t grad; /* 0, or 1: also accumulate d log p^ / d theta (ppf_grad) */
+  int32_t dlb;      /* PPF_DLB_* schedule of RPA */
+  int32_t reserved; /* must be 0 */
 } ppf_params;
 
 /* Scalars of the last committed step (see ppf_stats). */
@@ -329,6 +348,29 @@ int ppf_resample_systematic(const float* logw_dev, int64_t n, double u, int32_t*
 int ppf_resample_rna(const float* logw_dev, int64_t n, int32_t group, int32_t moved,
                      const double* u_dev, int32_t* anc_dev, double* lwg_dev, void* scratch,
                      size_t scratch_bytes, void* hip_stream);
+
+/*
+ * DLB schedule of Section 4 on the device; async. For G groups whose
+ * particle counts counts_dev[g] (int32) should become n each, the senders
+ * (counts > n, surplus counts - n) and receivers (counts < n, deficit
+ * n - counts) are matched:
+ *   PPF_DLB_GS   senders and receivers in group order; each sender in turn
+ *                fills the current receiver and moves to the next one when
+ *                it is full (Alg. 2, read so that a filled receiver is
+ *                skipped and the loop ends: the printed loop resets j to 0
+ *                and has no branch for a filled receiver);
+ *   PPF_DLB_SGS  the same after sorting both lists by surplus / deficit,
+ *                descending, ties by group (Alg. 3);
+ *   PPF_DLB_LGS  the i-th largest sender pairs with the i-th largest
+ *                receiver for min(|S|, |R|) ranks, moving the smaller of the
+ *                two (Alg. 4, recording the count before zeroing it).
+ * sched_dev: 3 int32 per entry (sender group, receiver group, particles),
+ * at most cap entries; *n_entries_dev (int32, device) receives their number,
+ * or -1 when cap is too small. EINVAL: G < 1, n < 0, an unknown kind, or G
+ * above PPF_DLB_MAX_SORTED (all kinds run in one workgroup).
+ */
+int ppf_dlb_schedule(int32_t kind, const int32_t* counts_dev, int32_t G, int32_t n,
+                     int32_t* sched_dev, int32_t cap, int32_t* n_entries_dev, void* hip_stream);
 
 /* ------------------------------------------ batched independent filters */
 

@@ -391,12 +391,17 @@ def dlb_schedule(kind: int, counts: np.ndarray, n: int) -> np.ndarray:
     return out[:m].copy()
 
 
-def resample_rpa(w: np.ndarray, u: float, group: int, kind: int) -> np.ndarray:
-    """RPA ancestors (kind GS or SGS) for normalised weights w with the
-    systematic uniform u."""
-    a_sys = resample_systematic(w, u)
-    out = np.empty(w.size, dtype=np.int32)
-    st = lib().orc_resample_rpa(w.size, group, kind, _ptr(a_sys), _ptr(out))
+def route_rpa(anc_sys: np.ndarray, group: int, kind: int) -> np.ndarray:
+    """RPA ancestors (kind GS or SGS) from the global systematic ancestors."""
+    a = np.ascontiguousarray(anc_sys, dtype=np.int32)
+    out = np.empty(a.size, dtype=np.int32)
+    st = lib().orc_resample_rpa(a.size, group, kind, _ptr(a), _ptr(out))
     if st != 0:
         raise RuntimeError("RPA left a group unbalanced")
     return out
+
+
+def resample_rpa(w: np.ndarray, u: float, group: int, kind: int) -> np.ndarray:
+    """RPA ancestors (kind GS or SGS) for normalised weights w with the
+    systematic uniform u."""
+    return route_rpa(resample_systematic(w, u), group, kind)

@@ -24,7 +24,9 @@ LIB_PATH = os.path.join(_HERE, "libppf.so")
 
 PPF_OK, PPF_EINVAL, PPF_ENOMEM, PPF_EDEVICE, PPF_ESTATE, PPF_ENUMERIC, PPF_ENOTIMPL = (
     0, -1, -2, -3, -4, -5, -6)
-RESAMPLE_SYSTEMATIC, RESAMPLE_RNA = 0, 1
+RESAMPLE_SYSTEMATIC, RESAMPLE_RNA, RESAMPLE_RPA = 0, 1, 2
+DLB_GS, DLB_SGS, DLB_LGS = 0, 1, 2
+DLB_MAX_SORTED = 4096
 OBS_SPOT, OBS_LINEAR_GAUSSIAN = 0, 1
 INIT_UNIFORM, INIT_GAUSSIAN, INIT_STRATIFIED = 0, 1, 2
 MAX_PATCH = 25
@@ -56,6 +58,8 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("track_id", ctypes.c_uint32),
         ("grad", ctypes.c_int32),
+        ("dlb", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -129,6 +133,9 @@ _SIGS = {
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p]),
+    "ppf_dlb_schedule": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
     "ppf_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32,
                                                  ctypes.POINTER(ctypes.c_size_t)]),
     "ppf_batch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_void_p,
@@ -547,6 +554,27 @@ def resample_systematic(logw, u: float, stream=None):
                                          ctypes.c_void_p(_stream_ptr(s))))
     anc._ppf_scratch = scr  # keep the scratch alive until the caller syncs
     return anc
+
+
+def dlb_schedule(kind: int, counts, n: int, stream=None):
+    """DLB schedule (DLB_GS, DLB_SGS or DLB_LGS) of int32 group counts (CUDA
+    tensor) towards n each: an (m, 3) int32 tensor of (sender group,
+    receiver group, particles). Syncs to read the entry count."""
+    import torch
+    if counts.dtype != torch.int32 or not counts.is_contiguous() or counts.dim() != 1:
+        raise TypeError("counts must be a contiguous 1-D int32 CUDA tensor")
+    G = counts.numel()
+    cap = 2 * G + 1
+    sched = torch.empty((cap, 3), dtype=torch.int32, device=counts.device)
+    m = torch.empty(1, dtype=torch.int32, device=counts.device)
+    s = stream if stream is not None else torch.cuda.current_stream(counts.device)
+    _check(lib().ppf_dlb_schedule(kind, ctypes.c_void_p(counts.data_ptr()), G, n,
+                                  ctypes.c_void_p(sched.data_ptr()), cap,
+                                  ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(_stream_ptr(s))))
+    k = int(m.cpu())
+    if k < 0:
+        raise PPFError(PPF_EINVAL, "schedule capacity exceeded")
+    return sched[:k]
 
 
 def resample_rna(logw, group: int, moved: int, u, stream=None):

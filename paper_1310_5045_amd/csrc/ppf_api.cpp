@@ -21,9 +21,11 @@ using ppf::Model;
 
 namespace {
 
-enum KernelId { kKStep, kKMerge, kKAnc, kKFill, kKRna, kKInit, kKGather, kKLogw, kNumKernels };
-const char* const kKernelNames[kNumKernels] = {"k_step", "k_merge",  "k_anc",    "k_fill",
-                                               "k_rna",  "k_init",   "k_gather", "k_logw"};
+enum KernelId {
+  kKStep, kKMerge, kKAnc, kKFill, kKRna, kKInit, kKGather, kKLogw, kKRpa, kNumKernels
+};
+const char* const kKernelNames[kNumKernels] = {"k_step", "k_merge",  "k_anc",  "k_fill", "k_rna",
+                                               "k_init", "k_gather", "k_logw", "k_rpa"};
 
 constexpr size_t kAlign = 256;
 
@@ -49,8 +51,17 @@ std::string validate(const ppf_params* p) {
     return "unknown obs_model";
   if (p->init_kind < PPF_INIT_UNIFORM || p->init_kind > PPF_INIT_STRATIFIED)
     return "unknown init_kind";
-  if (p->resample != PPF_RESAMPLE_SYSTEMATIC && p->resample != PPF_RESAMPLE_RNA)
+  if (p->resample != PPF_RESAMPLE_SYSTEMATIC && p->resample != PPF_RESAMPLE_RNA &&
+      p->resample != PPF_RESAMPLE_RPA)
     return "unknown resample scheme";
+  if (p->reserved != 0) return "reserved must be 0";
+  if (p->resample == PPF_RESAMPLE_RPA) {
+    if (p->rna_group < 1 || p->n_particles % p->rna_group != 0)
+      return "RPA: n_particles must be a multiple of rna_group";
+    if (p->dlb != PPF_DLB_GS && p->dlb != PPF_DLB_SGS) return "RPA: dlb must be GS or SGS";
+    if (p->dlb == PPF_DLB_SGS && p->n_particles / p->rna_group > PPF_DLB_MAX_SORTED)
+      return "RPA with SGS: too many groups";
+  }
   for (int d = 0; d < 5; ++d) {
     if (!std::isfinite(p->q[d]) || p->q[d] < 0.0f) return "q must be finite and >= 0";
     if (!std::isfinite(p->init_a[d]) || !std::isfinite(p->init_b[d]))
@@ -131,6 +142,12 @@ Model make_model(const ppf_params* p) {
   m.track = p->track_id;
   m.strat_t = strat_bits(m.n);
   m.grad = p->grad;
+  if (p->resample == PPF_RESAMPLE_RPA) {
+    m.rpa = 1;
+    m.dlb = p->dlb;
+    m.rpa_group = p->rna_group;
+    m.rpa_G = (int32_t)(m.n / p->rna_group);
+  }
   m.s_psf = s;
   m.sig = sg;
   return m;
@@ -190,6 +207,15 @@ size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) 
   bb.lwg = reinterpret_cast<double*>(take(sizeof(double) * G));
   bb.hq = reinterpret_cast<ppf::FillRun*>(take(sizeof(ppf::FillRun) * queue_cap(n)));
   bb.hq_cap = queue_cap(n);
+  if (p->resample == PPF_RESAMPLE_RPA) {
+    const int64_t Gr = n / p->rna_group;
+    bb.asys = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
+    bb.rfirst = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (Gr + 1)));
+    bb.rdbase = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * Gr));
+    bb.rsend = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * Gr));
+    bb.rscum = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (Gr + 1)));
+    bb.rns = reinterpret_cast<int32_t*>(take(sizeof(int32_t)));
+  }
   if (p->grad) {
     bb.T0 = reinterpret_cast<float*>(take(sizeof(float) * ppf::kNTan * n));
     bb.T1 = reinterpret_cast<float*>(take(sizeof(float) * ppf::kNTan * n));
@@ -446,7 +472,9 @@ int ppf_step(ppf_handle h, const float* obs_dev) {
     return h->run(kKRna, [&] { return ppf::launch_rna(h->m, h->b, w, nullptr, h->stream); });
   rc = h->run(kKAnc, [&] { return ppf::launch_anc(h->m, h->b, w, h->stream); });
   if (rc) return rc;
-  return h->run(kKFill, [&] { return ppf::launch_fill(h->m, h->b, h->stream); });
+  rc = h->run(kKFill, [&] { return ppf::launch_fill(h->m, h->b, h->stream); });
+  if (rc || !h->m.rpa) return rc;
+  return h->run(kKRpa, [&] { return ppf::launch_rpa(h->m, h->b, h->stream); });
 }
 
 int ppf_sync(ppf_handle h) {
@@ -595,6 +623,16 @@ int ppf_philox4x32_10(uint64_t seed, const uint32_t* ctr_dev, uint32_t* out_dev,
   return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
 }
 
+int ppf_dlb_schedule(int32_t kind, const int32_t* counts_dev, int32_t G, int32_t n,
+                     int32_t* sched_dev, int32_t cap, int32_t* n_entries_dev, void* hip_stream) {
+  if (kind < PPF_DLB_GS || kind > PPF_DLB_LGS || G < 1 || G > PPF_DLB_MAX_SORTED || n < 0)
+    return PPF_EINVAL;
+  if (!counts_dev || !n_entries_dev || cap < 0 || (cap > 0 && !sched_dev)) return PPF_EINVAL;
+  const hipError_t e = ppf::launch_dlb_schedule(kind, counts_dev, G, n, sched_dev, cap,
+                                                n_entries_dev, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
+}
+
 int ppf_resample_scratch_bytes(int64_t n, size_t* bytes) {
   if (!bytes || n < 1 || n > 2147483647LL) return PPF_EINVAL;
   *bytes = carve_scratch(n, nullptr, nullptr);
@@ -689,6 +727,8 @@ std::string validate_batch(const ppf_params* p, int32_t count) {
     if (p[t].obs_model != PPF_OBS_SPOT)
       return "track " + std::to_string(t) + ": batches take the spot model only";
     if (p[t].grad) return "track " + std::to_string(t) + ": batches do not take grad = 1";
+    if (p[t].resample == PPF_RESAMPLE_RPA)
+      return "track " + std::to_string(t) + ": batches do not take RPA";
     if (p[t].width != p[0].width || p[t].height != p[0].height)
       return "track " + std::to_string(t) + ": frame size differs from track 0";
   }

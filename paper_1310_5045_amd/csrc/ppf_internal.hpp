@@ -42,6 +42,7 @@ constexpr int kSlotTile = 4096;  // slots per LDS tile of the segment's writes
 constexpr int kFillChunk = 1 << 16;
 constexpr int kFillGrid = 2048;
 constexpr int kFillGridBatch = 64;  // workgroups per track of a batched fill
+constexpr int kDlbMaxSorted = 4096;  // groups of a sorted DLB schedule (LDS sort)
 
 // One work item of a batched launch: the track, and the index of the track's
 // block, merge chunk, resampling segment or RNA group.
@@ -127,6 +128,10 @@ struct Model {
   uint32_t key0, key1, track;
   int32_t strat_t;       // stratified init: total cell bits
   int32_t grad;          // accumulate d log p^ / d theta
+  int32_t rpa;           // resampling with proportional allocation
+  int32_t dlb;           // its schedule (0 greedy, 1 sorted greedy)
+  int32_t rpa_group;     // particles per RPA group
+  int32_t rpa_G;         // RPA groups
   double s_psf;          // s
   double sig;            // sigma_xi
 };
@@ -151,6 +156,12 @@ struct Buffers {
   float* T1;
   double* RG;    // gradient mode: per block sum E d l / d theta (kNGrad doubles)
   double* CRG;   // gradient mode: per chunk, the same merged (kNGrad doubles)
+  int32_t* asys;     // RPA: ancestors of the global systematic resampling
+  int64_t* rfirst;   // RPA: first systematic slot of each group's offspring (G + 1)
+  int64_t* rdbase;   // RPA: per receiver group, its first surplus particle
+  int32_t* rsend;    // RPA: sender groups in schedule order
+  int64_t* rscum;    // RPA: exclusive prefix of the senders' surplus (ns + 1)
+  int32_t* rns;      // RPA: number of senders
   int64_t hq_cap;   // entries of hq
   int64_t nb;       // block records = ceil(n / kBlock)
   int64_t chunk;    // records per merge chunk (multiple of 256, at most 2048)
@@ -187,6 +198,12 @@ hipError_t launch_set_mode(const Buffers& b, int32_t mode, hipStream_t s);
 hipError_t launch_records(const Model& m, const Buffers& b, const float* logw, hipStream_t s);
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
                          hipStream_t s);
+
+// RPA: the balancing plan and the routed ancestors of one filter.
+hipError_t launch_rpa(const Model& m, const Buffers& b, hipStream_t s);
+// DLB schedule of G groups' counts (kind 0 GS, 1 SGS, 2 LGS; G <= kDlbMaxSorted).
+hipError_t launch_dlb_schedule(int32_t kind, const int32_t* counts, int32_t G, int32_t n,
+                               int32_t* sched, int32_t cap, int32_t* n_entries, hipStream_t s);
 
 // Batched launches over independent filters: ms and bs are device arrays of
 // the tracks' models and buffers, items the device list of work items.

@@ -1310,7 +1310,7 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
     }
   }
   const int M = fe - fs;
-  int32_t* anc = b.anc;
+  int32_t* anc = m.rpa ? b.asys : b.anc;  // RPA routes the systematic result afterwards
   if (M <= kCoopSlots) {
     // tiles of slots: each run marks its first slot with its particle; the
     // running maximum of the marks (particles increase with slots) is then
@@ -1392,7 +1392,7 @@ __device__ __forceinline__ void fill_body(const Model& m, const Buffers& b, int6
     if (r.lo < 0 || r.len <= 0 || (int64_t)r.lo + r.len > m.n || r.item < 0 ||
         (int64_t)r.item >= m.n)
       continue;
-    int32_t* out = b.anc + r.lo;
+    int32_t* out = (m.rpa ? b.asys : b.anc) + r.lo;
     for (int k = threadIdx.x; k < r.len; k += 256) out[k] = r.item;
   }
 }
@@ -1501,6 +1501,245 @@ __device__ __forceinline__ void rna_body(const Model& m, const Buffers& b, const
 __global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
                                              const double* __restrict__ u_dev) {
   rna_body(m, b, ws, u_dev, blockIdx.x);
+}
+
+// ------------------------------------------------------------------- RPA
+// Resampling with proportional allocation (Section 3) over groups of n
+// particles: group g's offspring are its share of the global systematic
+// resampling (the slots whose ancestor lies in the group; the systematic
+// ancestors are non-decreasing, so they form one range, found by binary
+// search); a group keeps its first min(N_g, n) offspring, and the DLB
+// schedule of Section 4 routes the surplus of the senders (N_g > n) into the
+// free slots of the receivers (N_g < n). Greedy matching is the overlap of
+// the senders' surplus intervals and the receivers' deficit intervals laid
+// end to end in schedule order (group order for GS, by size descending for
+// SGS), so each routed slot finds its sender by binary search.
+
+// First index of the non-decreasing a[0..n) with a[i] >= v.
+__device__ __forceinline__ int64_t lower_bound_i32(const int32_t* a, int64_t n, int64_t v) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)a[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Ascending bitonic sort of key[0..size) in LDS (size a power of two) by the
+// whole workgroup.
+__device__ __forceinline__ void bitonic_sort(uint64_t* key, int size) {
+  for (int k = 2; k <= size; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < size; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const bool up = (i & k) == 0;
+          const uint64_t a = key[i], c = key[ixj];
+          if ((a > c) == up) {
+            key[i] = c;
+            key[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Key of a sort by value descending, ties by group ascending (~0: absent).
+__device__ __forceinline__ uint64_t desc_key(int64_t value, int64_t g) {
+  return value > 0 ? (((uint64_t)(0xffffffffu - (uint32_t)value) << 32) | (uint64_t)g) : ~0ull;
+}
+
+__device__ __forceinline__ int64_t rpa_count(const Buffers& b, int64_t g) {
+  return b.rfirst[g + 1] - b.rfirst[g];
+}
+
+// One workgroup: the groups' offspring ranges, the sender order with the
+// prefix of their surplus, and each receiver's first surplus particle.
+__global__ __launch_bounds__(256) void k_rpa_plan(Model m, Buffers b) {
+  __shared__ uint64_t key[kDlbMaxSorted];
+  __shared__ uint64_t ush[4];
+  const Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int t = threadIdx.x;
+  const int64_t N = m.n, n = m.rpa_group, G = m.rpa_G;
+  for (int64_t g = t; g <= G; g += 256) b.rfirst[g] = g == G ? N : lower_bound_i32(b.asys, N, g * n);
+  __syncthreads();
+  if (m.dlb == 0) {
+    // GS: both lists in group order
+    uint64_t cs = 0, cr = 0, cns = 0;
+    for (int64_t g0 = 0; g0 < G; g0 += 256) {
+      const int64_t g = g0 + t;
+      const int64_t cg = g < G ? rpa_count(b, g) : n;
+      const uint64_t su = cg > n ? (uint64_t)(cg - n) : 0, de = cg < n ? (uint64_t)(n - cg) : 0;
+      uint64_t tsu, tde, tfl;
+      const uint64_t esu = block_excl_sum(su, ush, &tsu);
+      const uint64_t ede = block_excl_sum(de, ush, &tde);
+      const uint64_t efl = block_excl_sum(su > 0 ? 1 : 0, ush, &tfl);
+      if (g < G) {
+        b.rdbase[g] = (int64_t)(cr + ede);
+        if (su > 0) {
+          b.rsend[cns + efl] = (int32_t)g;
+          b.rscum[cns + efl] = (int64_t)(cs + esu);
+        }
+      }
+      cs += tsu;
+      cr += tde;
+      cns += tfl;
+    }
+    if (t == 0) {
+      *b.rns = (int32_t)cns;
+      b.rscum[cns] = (int64_t)cs;
+    }
+    return;
+  }
+  // SGS: both lists by size descending, ties by group (G <= kDlbMaxSorted)
+  int size = 1;
+  while (size < G) size <<= 1;
+  for (int side = 0; side < 2; ++side) {
+    for (int i = t; i < size; i += 256) {
+      int64_t v = 0;
+      if (i < G) {
+        const int64_t cg = rpa_count(b, i);
+        v = side == 0 ? (cg > n ? cg - n : 0) : (cg < n ? n - cg : 0);
+      }
+      key[i] = desc_key(v, i);
+    }
+    __syncthreads();
+    bitonic_sort(key, size);
+    uint64_t carry = 0, cnt = 0;
+    for (int k0 = 0; k0 < size; k0 += 256) {
+      const int k = k0 + t;
+      const uint64_t kv = k < size ? key[k] : ~0ull;
+      const bool here = kv != ~0ull;
+      const int64_t g = (int64_t)(kv & 0xffffffffu);
+      uint64_t v = 0;
+      if (here) {
+        const int64_t cg = rpa_count(b, g);
+        v = (uint64_t)(side == 0 ? cg - n : n - cg);
+      }
+      uint64_t tv, tc;
+      const uint64_t ev = block_excl_sum(v, ush, &tv);
+      const uint64_t ec = block_excl_sum(here ? 1 : 0, ush, &tc);
+      if (here) {
+        if (side == 0) {
+          b.rsend[cnt + ec] = (int32_t)g;
+          b.rscum[cnt + ec] = (int64_t)(carry + ev);
+        } else {
+          b.rdbase[g] = (int64_t)(carry + ev);
+        }
+      }
+      carry += tv;
+      cnt += tc;
+    }
+    if (side == 0 && t == 0) {
+      *b.rns = (int32_t)cnt;
+      b.rscum[cnt] = (int64_t)carry;
+    }
+    __syncthreads();  // key is rewritten by the receivers' pass
+  }
+}
+
+// One thread per output slot.
+__global__ __launch_bounds__(256) void k_rpa_route(Model m, Buffers b) {
+  const Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t N = m.n;
+  if (s >= N) return;
+  const int64_t n = m.rpa_group;
+  const int64_t g = (int64_t)((uint32_t)s / (uint32_t)n);
+  const int64_t p = s - g * n;
+  const int64_t f0 = b.rfirst[g];
+  const int64_t keep = min(b.rfirst[g + 1] - f0, n);
+  int64_t src;
+  if (p < keep) {
+    src = f0 + p;
+  } else {
+    // the q-th surplus particle in schedule order belongs to the last
+    // sender whose prefix is <= q
+    const int64_t q = b.rdbase[g] + (p - keep);
+    int64_t lo = 0, hi = max((int64_t)*b.rns - 1, (int64_t)0);
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (b.rscum[mid] <= q) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t gs = min(max((int64_t)b.rsend[lo], (int64_t)0), m.rpa_G - 1);
+    src = b.rfirst[gs] + n + (q - b.rscum[lo]);
+  }
+  src = min(max(src, (int64_t)0), N - 1);  // a balanced plan never clamps
+  b.anc[s] = b.asys[src];
+}
+
+// The DLB schedules of Section 4 for G <= kDlbMaxSorted groups, one
+// workgroup: the lists (sorted for SGS and LGS by a bitonic sort in LDS),
+// then the matching by one thread in list order.
+__global__ __launch_bounds__(256) void k_dlb_schedule(int32_t kind, const int32_t* counts,
+                                                      int32_t G, int32_t n, int32_t* sched,
+                                                      int32_t cap, int32_t* n_entries) {
+  __shared__ uint64_t key[kDlbMaxSorted];
+  __shared__ int32_t S[kDlbMaxSorted];
+  __shared__ int32_t R[kDlbMaxSorted];
+  __shared__ int32_t nsr[2];
+  const int t = threadIdx.x;
+  int size = 1;
+  while (size < G) size <<= 1;
+  for (int side = 0; side < 2; ++side) {
+    for (int i = t; i < size; i += 256) {
+      int64_t v = 0;
+      if (i < G) v = side == 0 ? (int64_t)counts[i] - n : (int64_t)n - counts[i];
+      // GS keeps group order: the key is the group index alone
+      key[i] = v > 0 ? (kind == 0 ? (uint64_t)i : desc_key(v, i)) : ~0ull;
+    }
+    __syncthreads();
+    bitonic_sort(key, size);
+    for (int i = t; i < size; i += 256) {
+      if (key[i] != ~0ull) (side == 0 ? S : R)[i] = (int32_t)(key[i] & 0xffffffffu);
+      if (key[i] != ~0ull && (i + 1 == size || key[i + 1] == ~0ull)) nsr[side] = i + 1;
+      if (i == 0 && key[0] == ~0ull) nsr[side] = 0;
+    }
+    __syncthreads();
+  }
+  if (t != 0) return;
+  const int ns = nsr[0], nr = nsr[1];
+  int32_t m = 0;
+  if (kind == 2) {
+    for (int i = 0; i < min(ns, nr) && m >= 0; ++i) {
+      const int64_t su = (int64_t)counts[S[i]] - n, de = (int64_t)n - counts[R[i]];
+      if (m >= cap) {
+        m = -1;
+        break;
+      }
+      sched[3 * m] = S[i];
+      sched[3 * m + 1] = R[i];
+      sched[3 * m + 2] = (int32_t)min(su, de);
+      ++m;
+    }
+  } else {
+    int j = 0;
+    int64_t dj = nr > 0 ? (int64_t)n - counts[R[0]] : 0;  // remaining deficit of R[j]
+    for (int i = 0; i < ns && m >= 0; ++i) {
+      int64_t si = (int64_t)counts[S[i]] - n;
+      while (si > 0 && j < nr) {
+        const int64_t mv = min(si, dj);
+        if (m >= cap) {
+          m = -1;
+          break;
+        }
+        sched[3 * m] = S[i];
+        sched[3 * m + 1] = R[j];
+        sched[3 * m + 2] = (int32_t)mv;
+        ++m;
+        si -= mv;
+        dj -= mv;
+        if (dj == 0 && ++j < nr) dj = (int64_t)n - counts[R[j]];  // the next receiver
+      }
+    }
+  }
+  *n_entries = m;
 }
 
 // --------------------------------------------------------------- batches
@@ -1720,6 +1959,19 @@ hipError_t launch_rna_batch(const Model* ms, const Buffers* bs, const BatchItem*
                             int64_t n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rna_batch, dim3((unsigned)n_items), dim3(256), 0, s, ms, bs, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_rpa(const Model& m, const Buffers& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_rpa_plan, dim3(1), dim3(256), 0, s, m, b);
+  hipLaunchKernelGGL(k_rpa_route, dim3(grid_for(m.n, 256)), dim3(256), 0, s, m, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_dlb_schedule(int32_t kind, const int32_t* counts, int32_t G, int32_t n,
+                               int32_t* sched, int32_t cap, int32_t* n_entries, hipStream_t s) {
+  hipLaunchKernelGGL(k_dlb_schedule, dim3(1), dim3(256), 0, s, kind, counts, G, n, sched, cap,
+                     n_entries);
   return hipGetLastError();
 }
 

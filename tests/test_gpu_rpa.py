@@ -1,0 +1,84 @@
+"""GPU parity of resampling with proportional allocation (RPA, Section 3)
+and the DLB schedules of Section 4 against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1310_5045_amd import synth
+
+from parity import GpuState, check_propagate, check_systematic, check_weights, pair
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ppf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1310_5045_amd as p
+    p.lib()
+    return p
+
+
+def test_dlb_hand_example(ppf):
+    counts = torch.tensor([9, 3, 7, 1, 4, 6, 2], dtype=torch.int32).cuda()
+    assert ppf.dlb_schedule(ppf.DLB_GS, counts, 4).cpu().tolist() == [[0, 1, 1], [0, 3, 3],
+                                                                      [0, 6, 1], [2, 6, 1]]
+    assert ppf.dlb_schedule(ppf.DLB_SGS, counts, 4).cpu().tolist() == [[0, 3, 3], [0, 6, 2],
+                                                                       [2, 1, 1]]
+    assert ppf.dlb_schedule(ppf.DLB_LGS, counts, 4).cpu().tolist() == [[0, 3, 3], [2, 6, 2],
+                                                                       [5, 1, 1]]
+
+
+@pytest.mark.parametrize("G,n", [(1, 8), (37, 16), (1000, 64), (4096, 256)])
+def test_dlb_schedules_match_oracle(ppf, G, n):
+    rng = np.random.default_rng(G)
+    for trial in range(3):
+        if trial == 0:  # a real systematic allocation (balanced)
+            w = rng.gamma(0.3, 1.0, G * n)
+            w /= w.sum()
+            counts = oracle.rpa_counts(oracle.resample_systematic(w, float(rng.uniform())), n)
+        else:  # arbitrary counts, balanced or not
+            counts = rng.integers(0, 3 * n, G).astype(np.int32)
+        ct = torch.from_numpy(counts.astype(np.int32)).cuda()
+        for kind in (ppf.DLB_GS, ppf.DLB_SGS, ppf.DLB_LGS):
+            got = ppf.dlb_schedule(kind, ct, n).cpu().numpy()
+            want = oracle.dlb_schedule(kind, counts, n)
+            assert np.array_equal(got, want), (G, n, trial, kind)
+
+
+@pytest.mark.parametrize("dlb", [0, 1])
+@pytest.mark.parametrize("n,group", [(4096, 256), (8192, 64), (3000, 1000)])
+def test_rpa_filter(ppf, dlb, n, group):
+    mv = synth.render_movie(128, 128, 5, intensity=30.0, sigma=1.5, start_box=(40, 88, 40, 88),
+                            seed=21)
+    p, m = pair(ppf, n=n, width=128, height=128, s=1.5, b=10.0, sigma=3.0,
+                init_a=(32, 32, -1, -1, 15), init_b=(96, 96, 1, 1, 45), resample=0, seed=4)
+    p.resample = ppf.RESAMPLE_RPA
+    p.rna_group = group
+    p.dlb = dlb
+    f = ppf.Filter(p)
+    frames = torch.from_numpy(mv.frames).cuda()
+    x, lw, anc = f.particles()
+    prev = GpuState(x, lw, anc, False, np.full(n, -math.log(n)))
+    for k in range(1, 5):
+        f.step(frames[k - 1])
+        x, lw, anc = f.particles()
+        st = f.stats()
+        cur = GpuState(x, lw, anc, bool(st["resampled"]), None)
+        # the oracle's systematic filter step: propagation and weights
+        check_propagate(m, k, prev, cur.x)
+        check_weights(m, mv.frames[k - 1], prev.lw_next, cur.x, cur.lw, st)
+        w_gpu = np.exp(cur.lw)
+        # the resampled multiset is that of global systematic resampling
+        sys_anc = np.sort(cur.anc)
+        check_systematic(w_gpu, oracle.resample_uniform(m, k), sys_anc)
+        # and the placement is the oracle's routing of that multiset
+        assert np.array_equal(cur.anc, oracle.route_rpa(sys_anc, group, dlb)), k
+        cur.lw_next = np.full(n, -math.log(n))
+        prev = cur
+    f.close()
