@@ -112,6 +112,13 @@ WORKLOADS = {
     "sir_1024x1024_n38m_p13": dict(W=1024, H=1024, T=20, n=38_000_000, s=2.0, P=13,
                                    thr=float("inf")),
     "sir_512x512_n1m_p9": dict(W=512, H=512, T=50, n=1 << 20, s=1.5, P=9, thr=float(1 << 19)),
+    # the same with the distributed schemes over groups of 256 (4096 groups)
+    "rna_512x512_n1m_p9": dict(W=512, H=512, T=50, n=1 << 20, s=1.5, P=9, thr=float(1 << 19),
+                               scheme=(1, 256, 0)),
+    "rpa_gs_512x512_n1m_p9": dict(W=512, H=512, T=50, n=1 << 20, s=1.5, P=9,
+                                  thr=float(1 << 19), scheme=(2, 256, 0)),
+    "rpa_sgs_512x512_n1m_p9": dict(W=512, H=512, T=50, n=1 << 20, s=1.5, P=9,
+                                   thr=float(1 << 19), scheme=(2, 256, 1)),
     "sir_128x128_n4096_p9": dict(W=128, H=128, T=10, n=4096, s=1.5, P=9, thr=float("inf")),
     # forward pass with the derivatives of log p^ in (s, b, sigma, q, I0)
     "grad_512x512_n262k_p11": dict(W=512, H=512, T=30, n=1 << 18, s=1.7, P=11, thr=float("inf"),
@@ -221,10 +228,12 @@ def make_params(ppf, w, init_kind, grad=0):
     of 2 of the spot's."""
     x0, x1, y0, y1 = w.get("box", (0, w["W"], 0, w["H"]))
     I = w.get("I", 30.0)
+    resample, group, dlb = w.get("scheme", (0, 256, 0))
     return ppf.params(n_particles=w["n"], width=w["W"], height=w["H"], psf_sigma=w["s"],
                       background=10.0, noise_sigma=3.0, patch=w["P"], init_kind=init_kind,
                       init_a=(x0, y0, -1, -1, I / 2), init_b=(x1, y1, 1, 1, 1.5 * I),
-                      ess_threshold=w["thr"], seed=1, grad=grad)
+                      ess_threshold=w["thr"], seed=1, grad=grad, resample=resample,
+                      rna_group=group, dlb=dlb)
 
 
 def time_filter(ppf, torch, p, frames, K, Wm, T):
@@ -378,8 +387,10 @@ def main():
         "dtype": "f32 state, f64 likelihood/normalisation",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_particles": n, "frame": [w["W"], w["H"]],
-                   "patch": P, "psf_sigma": w["s"], "resampling": "systematic"
-                   if w["thr"] == float("inf") else f"systematic when ESS < {w['thr']:.0f}",
+                   "patch": P, "psf_sigma": w["s"],
+                   "resampling": ({0: "systematic", 1: "RNA", 2: "RPA"}[w.get("scheme", (0,))[0]]
+                                  + ("" if w["thr"] == float("inf")
+                                     else f" when ESS < {w['thr']:.0f}")),
                    "init": args.init, "frames_timed": K},
         "roofline": {"bound": "alu", "kernel": "k_step", "achieved": achieved_tf,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -214,7 +214,9 @@ size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) 
     bb.rdbase = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * Gr));
     bb.rsend = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * Gr));
     bb.rscum = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (Gr + 1)));
-    bb.rns = reinterpret_cast<int32_t*>(take(sizeof(int32_t)));
+    bb.rns = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2));
+    bb.rrank = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2 * Gr));
+    bb.rsorted = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2 * Gr));
   }
   if (p->grad) {
     bb.T0 = reinterpret_cast<float*>(take(sizeof(float) * ppf::kNTan * n));

@@ -162,6 +162,8 @@ struct Buffers {
   int32_t* rsend;    // RPA: sender groups in schedule order
   int64_t* rscum;    // RPA: exclusive prefix of the senders' surplus (ns + 1)
   int32_t* rns;      // RPA: number of senders
+  int32_t* rrank;    // RPA with SGS: rank of each group among senders, then receivers (2G)
+  int32_t* rsorted;  // RPA with SGS: groups in sender order, then receiver order (2G)
   int64_t hq_cap;   // entries of hq
   int64_t nb;       // block records = ceil(n / kBlock)
   int64_t chunk;    // records per merge chunk (multiple of 256, at most 2048)

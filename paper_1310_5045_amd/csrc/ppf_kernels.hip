@@ -1556,17 +1556,58 @@ __device__ __forceinline__ int64_t rpa_count(const Buffers& b, int64_t g) {
   return b.rfirst[g + 1] - b.rfirst[g];
 }
 
-// One workgroup: the groups' offspring ranges, the sender order with the
-// prefix of their surplus, and each receiver's first surplus particle.
+// The groups' offspring ranges: one binary search per group boundary.
+__global__ __launch_bounds__(256) void k_rpa_first(Model m, Buffers b) {
+  const Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t N = m.n, G = m.rpa_G;
+  if (g <= G) b.rfirst[g] = g == G ? N : lower_bound_i32(b.asys, N, g * (int64_t)m.rpa_group);
+  if (m.dlb == 1 && g < G) {  // SGS: the ranks are summed by k_rpa_rank
+    b.rrank[g] = 0;
+    b.rrank[G + g] = 0;
+  }
+  if (m.dlb == 1 && g < 2) b.rns[g] = 0;
+}
+
+// Sort key of group g for the senders (side 0: surplus) or the receivers
+// (side 1: deficit): descending size, ties by group; ~0 when absent.
+__device__ __forceinline__ uint64_t rpa_key(const Buffers& b, int64_t n, int64_t g, int side) {
+  const int64_t cg = b.rfirst[g + 1] - b.rfirst[g];
+  return desc_key(side == 0 ? cg - n : n - cg, g);
+}
+
+// SGS order by counting: the rank of a present key is the number of keys
+// below it (keys are distinct); workgroup (x, y, side) adds the count over
+// the y-th slice of 1024 keys for 256 groups.
+__global__ __launch_bounds__(256) void k_rpa_rank(Model m, Buffers b) {
+  __shared__ uint64_t ks[1024];
+  const Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int side = blockIdx.z;
+  const int64_t n = m.rpa_group, G = m.rpa_G;
+  const int64_t h0 = (int64_t)blockIdx.y * 1024;
+  for (int i = threadIdx.x; i < 1024; i += 256)
+    ks[i] = h0 + i < G ? rpa_key(b, n, h0 + i, side) : ~0ull;
+  __syncthreads();
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= G) return;
+  const uint64_t kg = rpa_key(b, n, g, side);
+  if (kg == ~0ull) return;
+  int cnt = 0;
+  for (int i = 0; i < 1024; ++i) cnt += ks[i] < kg ? 1 : 0;
+  if (cnt) atomicAdd(&b.rrank[side * G + g], cnt);
+  if (blockIdx.y == 0) atomicAdd(&b.rns[side], 1);  // present keys of this side
+}
+
+// One workgroup: the sender order with the prefix of their surplus, and each
+// receiver's first surplus particle.
 __global__ __launch_bounds__(256) void k_rpa_plan(Model m, Buffers b) {
-  __shared__ uint64_t key[kDlbMaxSorted];
   __shared__ uint64_t ush[4];
   const Ctrl* c = b.ctrl;
   if (!c->do_resample) return;
   const int t = threadIdx.x;
-  const int64_t N = m.n, n = m.rpa_group, G = m.rpa_G;
-  for (int64_t g = t; g <= G; g += 256) b.rfirst[g] = g == G ? N : lower_bound_i32(b.asys, N, g * n);
-  __syncthreads();
+  const int64_t n = m.rpa_group, G = m.rpa_G;
   if (m.dlb == 0) {
     // GS: both lists in group order
     uint64_t cs = 0, cr = 0, cns = 0;
@@ -1595,26 +1636,19 @@ __global__ __launch_bounds__(256) void k_rpa_plan(Model m, Buffers b) {
     }
     return;
   }
-  // SGS: both lists by size descending, ties by group (G <= kDlbMaxSorted)
-  int size = 1;
-  while (size < G) size <<= 1;
+  // SGS: both lists by size descending, ties by group, placed by the ranks
+  // of k_rpa_rank
+  const int64_t nside[2] = {b.rns[0], b.rns[1]};
+  __syncthreads();
   for (int side = 0; side < 2; ++side) {
-    for (int i = t; i < size; i += 256) {
-      int64_t v = 0;
-      if (i < G) {
-        const int64_t cg = rpa_count(b, i);
-        v = side == 0 ? (cg > n ? cg - n : 0) : (cg < n ? n - cg : 0);
-      }
-      key[i] = desc_key(v, i);
-    }
+    for (int64_t g = t; g < G; g += 256)
+      if (rpa_key(b, n, g, side) != ~0ull) b.rsorted[side * G + b.rrank[side * G + g]] = (int32_t)g;
     __syncthreads();
-    bitonic_sort(key, size);
     uint64_t carry = 0, cnt = 0;
-    for (int k0 = 0; k0 < size; k0 += 256) {
-      const int k = k0 + t;
-      const uint64_t kv = k < size ? key[k] : ~0ull;
-      const bool here = kv != ~0ull;
-      const int64_t g = (int64_t)(kv & 0xffffffffu);
+    for (int64_t k0 = 0; k0 < G; k0 += 256) {
+      const int64_t k = k0 + t;
+      const bool here = k < nside[side];
+      const int64_t g = here ? (int64_t)b.rsorted[side * G + k] : 0;
       uint64_t v = 0;
       if (here) {
         const int64_t cg = rpa_count(b, g);
@@ -1638,7 +1672,7 @@ __global__ __launch_bounds__(256) void k_rpa_plan(Model m, Buffers b) {
       *b.rns = (int32_t)cnt;
       b.rscum[cnt] = (int64_t)carry;
     }
-    __syncthreads();  // key is rewritten by the receivers' pass
+    __syncthreads();
   }
 }
 
@@ -1963,6 +1997,12 @@ hipError_t launch_rna_batch(const Model* ms, const Buffers* bs, const BatchItem*
 }
 
 hipError_t launch_rpa(const Model& m, const Buffers& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_rpa_first, dim3(grid_for((int64_t)m.rpa_G + 1, 256)), dim3(256), 0, s, m,
+                     b);
+  if (m.dlb == 1)
+    hipLaunchKernelGGL(k_rpa_rank,
+                       dim3(grid_for(m.rpa_G, 256), grid_for(m.rpa_G, 1024), 2), dim3(256), 0, s,
+                       m, b);
   hipLaunchKernelGGL(k_rpa_plan, dim3(1), dim3(256), 0, s, m, b);
   hipLaunchKernelGGL(k_rpa_route, dim3(grid_for(m.n, 256)), dim3(256), 0, s, m, b);
   return hipGetLastError();

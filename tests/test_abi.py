@@ -99,6 +99,36 @@ def test_standalone_argument_checks():
     assert L.ppf_resample_rna(ctypes.c_void_p(256), 10, 3, 0, ctypes.c_void_p(256),
                               ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
                               1 << 20, None) == ppf.PPF_EINVAL
+    v = ctypes.c_void_p(256)
+    dlb = L.ppf_dlb_schedule
+    assert dlb(3, v, 10, 4, v, 10, v, None) == ppf.PPF_EINVAL      # unknown kind
+    assert dlb(0, v, 0, 4, v, 10, v, None) == ppf.PPF_EINVAL       # no groups
+    assert dlb(1, v, 4097, 4, v, 10, v, None) == ppf.PPF_EINVAL    # above the sorted limit
+    assert dlb(0, None, 10, 4, v, 10, v, None) == ppf.PPF_EINVAL   # null counts
+    assert dlb(0, v, 10, -1, v, 10, v, None) == ppf.PPF_EINVAL     # negative n
+    assert dlb(0, v, 10, 4, None, 10, v, None) == ppf.PPF_EINVAL   # null schedule
+
+
+def test_batch_and_grad_argument_checks():
+    good = ppf.params(n_particles=1000, width=64, height=64)
+    assert ppf.batch_workspace_bytes([good, good]) > 2 * 1000 * 24
+    for bad in (dict(grad=1), dict(resample=2, rna_group=100), dict(obs_model=1)):
+        with pytest.raises(ppf.PPFError):
+            ppf.batch_workspace_bytes([good, ppf.params(n_particles=1000, width=64, height=64,
+                                                        **bad)])
+    with pytest.raises(ppf.PPFError):
+        ppf.batch_workspace_bytes([good, ppf.params(n_particles=1000, width=65, height=64)])
+    with pytest.raises(ppf.PPFError):
+        ppf.batch_workspace_bytes([])
+    # gradient mode needs more workspace (tangents and derivative records)
+    g = ppf.params(n_particles=1000, width=64, height=64, grad=1)
+    assert ppf.workspace_bytes(g) >= ppf.workspace_bytes(good) + 2 * 7 * 4 * 1000
+    # RPA adds the systematic ancestors and the plan
+    r = ppf.params(n_particles=1024, width=64, height=64, resample=2, rna_group=256)
+    assert ppf.workspace_bytes(r) > ppf.workspace_bytes(ppf.params(n_particles=1024, width=64,
+                                                                   height=64))
+    assert ppf.lib().ppf_grad(None, None, None) == ppf.PPF_ESTATE
+    assert ppf.lib().ppf_step_batched(None, None) == ppf.PPF_ESTATE
 
 
 def test_product_package_never_imports_the_oracle():
