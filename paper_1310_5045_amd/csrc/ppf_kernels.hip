@@ -375,12 +375,15 @@ __device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int 
   }
   if (po) *po = p;
   Prop o;
-  // near-constant velocity, unit frame interval; fp64 sum rounded once
-  o.x = (float)((double)px + (double)pvx + (double)m.q[0] * (double)z0);
-  o.y = (float)((double)py + (double)pvy + (double)m.q[1] * (double)z1);
-  o.vx = (float)((double)pvx + (double)m.q[2] * (double)z2);
-  o.vy = (float)((double)pvy + (double)m.q[3] * (double)z3);
-  o.I = (float)((double)pI + (double)m.q[4] * (double)z4);
+  // near-constant velocity, unit frame interval; in fp32 with one fused
+  // multiply-add per component, the small velocity and noise terms first,
+  // so a position is within half an ulp (plus the rounding of that small
+  // sum) of the exact value
+  o.x = px + fmaf(m.q[0], z0, pvx);
+  o.y = py + fmaf(m.q[1], z1, pvy);
+  o.vx = fmaf(m.q[2], z2, pvx);
+  o.vy = fmaf(m.q[3], z3, pvy);
+  o.I = fmaf(m.q[4], z4, pI);
   o.lw = lw;
   return o;
 }
@@ -469,7 +472,7 @@ __device__ __forceinline__ void patch_lds(const double* __restrict__ p0, int tw,
                                           const double (&gx)[P], double gy, double by,
                                           const double* gstep, double& X, double& G2y,
                                           double& sd2) {
-#pragma unroll 1
+#pragma unroll
   for (int dy = 0; dy < P; ++dy) {
     const double* row = p0 + dy * tw;
     double rd = 0.0;
