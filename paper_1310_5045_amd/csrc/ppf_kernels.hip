@@ -56,13 +56,57 @@ __device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
   return ((double)a * 2097152.0 + (double)(b >> 11)) * 0x1p-53;
 }
 
-// Box-Muller in fp32: radius from (0, 1], angle 2 pi u from [0, 1).
+// Box-Muller in fp32. The radius sqrt(-2 ln u), u in (0, 1], uses the
+// hardware log2 and square root (measured over all 2^24 uniforms: at most
+// 1.9 ulp for ln u, 0.9 ulp for the root). The angle 2 pi t, t in [0, 1),
+// is reduced exactly: x = 4 t, q = rint(x), r = x - q in [-1/2, 1/2], and
+// sin, cos(2 pi t) are sin, cos(pi/2 r) rotated by the quadrant q, from the
+// Taylor series in r to degree 9 and 10 (truncation below 2e-9; measured at
+// most 8.8e-8 absolute with fp32 rounding).
+__device__ __forceinline__ float bm_radius(uint32_t a) {
+  // -2 ln u = -(2 ln 2) log2 u
+  return __builtin_amdgcn_sqrtf(-0x1.62e430p+0f * __builtin_amdgcn_logf(u24_open_lo(a)));
+}
+
+__device__ __forceinline__ float sin_halfpi(float r, float r2) {
+  float p = 0x1.507834p-13f;   //  (pi/2)^9 / 9!
+  p = fmaf(p, r2, -0x1.32d2ccp-8f);  // -(pi/2)^7 / 7!
+  p = fmaf(p, r2, 0x1.466bc6p-4f);   //  (pi/2)^5 / 5!
+  p = fmaf(p, r2, -0x1.4abbcep-1f);  // -(pi/2)^3 / 3!
+  p = fmaf(p, r2, 0x1.921fb6p+0f);   //   pi/2
+  return p * r;
+}
+
+__device__ __forceinline__ float cos_halfpi(float r2) {
+  float p = -0x1.a6d1f2p-16f;        // -(pi/2)^10 / 10!
+  p = fmaf(p, r2, 0x1.e1f506p-11f);  //  (pi/2)^8 / 8!
+  p = fmaf(p, r2, -0x1.55d3c8p-6f);  // -(pi/2)^6 / 6!
+  p = fmaf(p, r2, 0x1.03c1f0p-2f);   //  (pi/2)^4 / 4!
+  p = fmaf(p, r2, -0x1.3bd3ccp+0f);  // -(pi/2)^2 / 2!
+  return fmaf(p, r2, 1.0f);
+}
+
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
-  const float rad = sqrtf(-2.0f * logf(u24_open_lo(a)));
-  float s, c;
-  sincospif(2.0f * u24_open_hi(b), &s, &c);
-  z0 = rad * c;
-  z1 = rad * s;
+  const float rad = bm_radius(a);
+  const float x = (float)(b >> 8) * 0x1p-22f;  // 4 t, exact
+  const float q = rintf(x);
+  const float r = x - q, r2 = r * r;
+  const float sn = sin_halfpi(r, r2), cs = cos_halfpi(r2);
+  const int qi = (int)q & 3;
+  const float ss = (qi & 1) ? cs : sn, cc = (qi & 1) ? sn : cs;
+  z0 = rad * (((qi + 1) & 2) ? -cc : cc);
+  z1 = rad * ((qi & 2) ? -ss : ss);
+}
+
+// The cosine branch alone.
+__device__ __forceinline__ float box_muller_cos(uint32_t a, uint32_t b) {
+  const float rad = bm_radius(a);
+  const float x = (float)(b >> 8) * 0x1p-22f;
+  const float q = rintf(x);
+  const float r = x - q, r2 = r * r;
+  const int qi = (int)q & 3;
+  const float cc = (qi & 1) ? sin_halfpi(r, r2) : cos_halfpi(r2);
+  return rad * (((qi + 1) & 2) ? -cc : cc);
 }
 
 __device__ __forceinline__ void box_muller64(uint32_t a, uint32_t b, double& z0, double& z1) {
@@ -362,10 +406,10 @@ __device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int 
               pI = Xin[4 * n + p];
   const uint4 r0 = draw(m, (uint32_t)i, k, kPropagate, 0u);
   const uint4 r1 = draw(m, (uint32_t)i, k, kPropagate, 1u);
-  float z0, z1, z2, z3, z4, unused;
+  float z0, z1, z2, z3;
   box_muller(r0.x, r0.y, z0, z1);
   box_muller(r0.z, r0.w, z2, z3);
-  box_muller(r1.x, r1.y, z4, unused);
+  const float z4 = box_muller_cos(r1.x, r1.y);
   if (zo) {
     zo[0] = z0;
     zo[1] = z1;

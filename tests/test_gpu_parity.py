@@ -240,6 +240,25 @@ def test_set_particles_and_gather(ppf, movie128):
     f.close()
 
 
+def test_normals_accuracy(ppf, movie128):
+    """From zero states with unit process noise the propagated state is the
+    five normals themselves: compare 5 x 2^20 of them with the oracle's fp64
+    Box-Muller. Bound: the fp32 radius is within about 2 ulp (hardware log2
+    and root), sin/cos(2 pi t) within 9e-8 absolute, so |dz| <= 2.5e-7 |z|
+    + 5.2e-7 (the absolute part scaled by the radius, at most 5.8)."""
+    n = 1 << 20
+    p, m = pair(ppf, n=n, q=(1, 1, 1, 1, 1), **SPOT)
+    f = ppf.Filter(p)
+    f.set_particles(np.zeros((5, n), np.float32), np.full(n, -math.log(n)))
+    f.step(torch.from_numpy(movie128.frames[0]).cuda())
+    z_gpu = f.particles()[0].astype(np.float64)
+    z = oracle.propagate(m, 1, np.zeros((5, n)))
+    err = np.abs(z_gpu - z)
+    assert np.all(err <= 3e-7 * np.abs(z) + 6e-7), err.max()
+    print("normals: max error", err.max(), "relative", (err / np.maximum(np.abs(z), 1)).max())
+    f.close()
+
+
 def test_free_running_matches_until_first_flip(ppf, movie128):
     p, m = pair(ppf, n=4096, **SPOT)
     f = ppf.Filter(p)
