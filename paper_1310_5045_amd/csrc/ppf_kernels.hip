@@ -143,9 +143,9 @@ __device__ __forceinline__ double exp_fast(double x) {
 // ------------------------------------------------------ wave64 primitives
 // Cross-lane moves use DPP within rows of 16 lanes: row shifts (row_shr:k;
 // lanes whose source falls outside the row read 0 and are masked off by the
-// callers) for scans, row rotations (row_ror:k) for reductions, and
-// v_readlane for the four row results. Every helper must be called with all
-// 64 lanes active.
+// callers) for scans, row rotations (row_ror:k) for reductions, and either
+// v_readlane for the four row results or row broadcasts that carry them into
+// the last row. Every helper must be called with all 64 lanes active.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, true);
@@ -177,9 +177,6 @@ __device__ __forceinline__ T ror(T v) {
 }
 
 __device__ __forceinline__ int readlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
-}
 __device__ __forceinline__ uint64_t readlane(uint64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
@@ -245,6 +242,62 @@ __device__ __forceinline__ T wave_reduce(T v, int lane, Op op) {
   return op(op(readlane(v, 0), readlane(v, 16)), op(readlane(v, 32), readlane(v, 48)));
 }
 
+// Row broadcasts: CTRL 0x142 (row_bcast:15) hands lane 15 of each row to the
+// whole next row, CTRL 0x143 (row_bcast:31) hands lane 31 to rows 2 and 3.
+// Only the rows in the mask ROWS receive; the others read `id`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t bcast32(uint32_t v, uint32_t id) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int bcast(int v, int id) {
+  return (int)bcast32<CTRL, ROWS>((uint32_t)v, (uint32_t)id);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t bcast(uint32_t v, uint32_t id) {
+  return bcast32<CTRL, ROWS>(v, id);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double bcast(double v, double id) {
+  const uint64_t x = (uint64_t)__double_as_longlong(v), z = (uint64_t)__double_as_longlong(id);
+  const uint64_t r = (uint64_t)bcast32<CTRL, ROWS>((uint32_t)x, (uint32_t)z) |
+                     ((uint64_t)bcast32<CTRL, ROWS>((uint32_t)(x >> 32), (uint32_t)(z >> 32))
+                      << 32);
+  return __longlong_as_double((long long)r);
+}
+
+// Combines each odd row's result with the even row before it: after a
+// row_allreduce, rows 1 and 3 hold op(row 0, row 1) and op(row 2, row 3).
+template <class T, class Op>
+__device__ __forceinline__ T pair_rows(T v, Op op, T id) {
+  return op(v, bcast<0x142, 0xa>(v, id));
+}
+
+// Reduction over the wave whose result is exact in lane 63 only (no
+// v_readlane): rows paired by row_bcast:15, then the pairs by row_bcast:31.
+// id is the identity of op.
+template <class T, class Op>
+__device__ __forceinline__ T wave_reduce_last(T v, Op op, T id) {
+  v = pair_rows(row_allreduce(v, op), op, id);
+  return op(v, bcast<0x143, 0xc>(v, id));
+}
+
+// Order-preserving integer key of a float that is not NaN: a < b exactly
+// when key(a) < key(b) (-0 sorts just below +0), and key + 1 is the key of
+// the next float up.
+__device__ __forceinline__ int ord_key(float f) {
+  const int x = __float_as_int(f);
+  return x ^ ((x >> 31) & 0x7fffffff);
+}
+__device__ __forceinline__ float ord_val(int k) {
+  return __int_as_float(k ^ ((k >> 31) & 0x7fffffff));
+}
+// Key of the smallest float >= x (x not NaN).
+__device__ __forceinline__ int ord_key_up(double x) {
+  const float f = (float)x;
+  return ord_key(f) + ((double)f < x ? 1 : 0);
+}
+
 // Inclusive scan over the wave, in a fixed order.
 template <class T, class Op>
 __device__ __forceinline__ T wave_scan(T v, int lane, Op op) {
@@ -278,8 +331,8 @@ template <int K>
 __device__ __forceinline__ void block_sum_n(double (&v)[K], double* sh) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = wave_reduce(v[k], lane, OpAdd());
-  if (lane == 0) {
+  for (int k = 0; k < K; ++k) v[k] = wave_reduce_last(v[k], OpAdd(), 0.0);
+  if (lane == 63) {
 #pragma unroll
     for (int k = 0; k < K; ++k) sh[w * K + k] = v[k];
   }
@@ -450,26 +503,64 @@ __device__ __forceinline__ double item_weight(double e) {
   return fma(e, kItemScale, 0x1p52) - 0x1p52;
 }
 
+// e^x for x <= 0 rounded to fp32 (0 below -104, where e^x is under half the
+// least fp32 subnormal). Cody-Waite reduction x = k ln 2 + r with one fp64
+// constant (|k| <= 150 keeps its error below 2^-47) and the Taylor polynomial
+// of degree 9 on |r| <= ln 2 / 2 (truncation below 2^-36 relative): the fp64
+// value is far closer to e^x than the fp32 rounding step.
+__device__ __forceinline__ float exp_neg_f32(double x) {
+  const double k = rint(x * 0x1.71547652b82fep+0);
+  const double r = fma(-k, 0x1.62e42fefa39efp-1, x);
+  double p = 0x1.71de3a556c734p-19;     // 1/9!
+  p = fma(p, r, 0x1.a01a01a01a01ap-16);  // 1/8!
+  p = fma(p, r, 0x1.a01a01a01a01ap-13);  // 1/7!
+  p = fma(p, r, 0x1.6c16c16c16c17p-10);  // 1/6!
+  p = fma(p, r, 0x1.1111111111111p-7);   // 1/5!
+  p = fma(p, r, 0x1.5555555555555p-5);   // 1/4!
+  p = fma(p, r, 0x1.5555555555555p-3);   // 1/3!
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  const float v = (float)ldexp(p, (int)k);
+  return x < -104.0 ? 0.0f : v;
+}
+
 // The block's normalisation record (see kRec) and the stored weights
 // E = exp(l - m_b) in fp32. red: 7 x 256 doubles of LDS that no thread reads
 // once it has reached this call (it may alias the caller's image tile).
 // Returns e = E (0 for an inactive or non-finite particle).
+//
+// The shift m_b is any value at or above every finite l of the block and
+// close to their maximum (the record carries it, so the normalisation does
+// not depend on which): the maximum of the l rounded up to fp32, taken as
+// order-preserving integer keys so that each DPP step is one v_max_i32, and
+// within one fp32 ulp of the largest l. Where that ulp exceeds 1/8 (block
+// maxima of magnitude 2^20 and above) the exact fp64 maximum is taken instead.
 __device__ __forceinline__ double finish_block(const Buffers& b, int cur, int64_t i, bool active,
                                                double l, const Prop& o, double* red,
                                                double* dsh) {
+  __shared__ int ksh[4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const bool bad = active && (isnan(l) || l == INFINITY);
-  const double wm = wave_reduce((active && !bad) ? l : -INFINITY, lane, OpMax());
-  if (lane == 0) dsh[w] = wm;
+  const bool ok = active && !bad;
+  const int wk = wave_reduce_last(ok ? ord_key_up(l) : ord_key(-INFINITY), OpMax(), INT_MIN);
+  if (lane == 63) ksh[w] = wk;
   __syncthreads();
-  const double mb = fmax(fmax(dsh[0], dsh[1]), fmax(dsh[2], dsh[3]));
+  const float mf = ord_val(max(max(ksh[0], ksh[1]), max(ksh[2], ksh[3])));
+  double mb = (double)mf;
+  if (mf != -INFINITY && !(fabsf(mf) < 0x1p20f)) {  // uniform across the workgroup
+    const double wm = wave_reduce_last(ok ? l : -INFINITY, OpMax(), (double)-INFINITY);
+    if (lane == 63) dsh[w] = wm;
+    __syncthreads();
+    mb = fmax(fmax(dsh[0], dsh[1]), fmax(dsh[2], dsh[3]));
+  }
   double e = 0.0;
   if (active) {
     float Ef = 0.0f;
     if (bad) {
       Ef = NAN;
-    } else if (mb != -INFINITY && l != -INFINITY) {
-      Ef = (float)exp_fast(l - mb);
+    } else if (l != -INFINITY) {  // then m_b >= l > -inf
+      Ef = exp_neg_f32(l - mb);
       e = (double)Ef;
     }
     float* Eout = cur ? b.E0 : b.E1;
@@ -491,15 +582,12 @@ __device__ __forceinline__ double finish_block(const Buffers& b, int cur, int64_
     const double* p = red + (t >> 5) * 256 + (t & 31) * 8;
     s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
   }
-  s = row_allreduce(s, OpAdd());
-  const double h0 = readlane(s, 0) + readlane(s, 16);   // value 2w
-  const double h1 = readlane(s, 32) + readlane(s, 48);  // value 2w + 1
-  if (lane == 0) {
-    double* R = (cur ? b.R0 : b.R1) + (i / kBlock) * kRec;
-    R[1 + 2 * w] = h0;
-    if (2 * w + 1 < 7) R[2 + 2 * w] = h1;
-    if (w == 0) R[0] = mb;
-  }
+  // value 2w in row 1 of wave w, value 2w + 1 in row 3
+  s = pair_rows(row_allreduce(s, OpAdd()), OpAdd(), 0.0);
+  double* R = (cur ? b.R0 : b.R1) + (i / kBlock) * kRec;
+  if (lane == 16) R[1 + 2 * w] = s;
+  if (lane == 48 && 2 * w + 1 < 7) R[2 + 2 * w] = s;
+  if (t == 0) R[0] = mb;
   return e;
 }
 
@@ -661,89 +749,82 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t i = blk * kBlock + t;
   const bool active = i < m.n;
+  // Lanes past the last particle (the tail of the last workgroup) repeat the
+  // work of particle n - 1, which lies in the same workgroup, and store
+  // nothing: every lane runs the same instructions on valid data.
+  const int64_t ia = active ? i : m.n - 1;
 
-  Prop o{};
-  double fx = 0.0, fy = 0.0, rx = 0.0, ry = 0.0;
-  int cx = 0, cy = 0;
-  float tg[kNTan] = {};  // gradient mode: the particle's new tangents
-  if (active) {
-    if (GRAD) {
-      float z[5];
-      int64_t p;
-      o = propagate(m, b, cur, mode, cdelta, i, k, z, &p);
-      // tangents along the ancestral line (see kNTan): dx'/dq_x = dx/dq_x +
-      // z_x, dx'/dq_vx = dx/dq_vx + dvx/dq_vx (the parent's), and alike
-      const float* Tin = cur ? b.T1 : b.T0;
-      float* Tout = cur ? b.T0 : b.T1;
-      float tp[kNTan];
+  Prop o;
+  float tg[kNTan];  // gradient mode: the particle's new tangents
+  if (GRAD) {
+    float z[5];
+    int64_t p;
+    o = propagate(m, b, cur, mode, cdelta, ia, k, z, &p);
+    // tangents along the ancestral line (see kNTan): dx'/dq_x = dx/dq_x +
+    // z_x, dx'/dq_vx = dx/dq_vx + dvx/dq_vx (the parent's), and alike
+    const float* Tin = cur ? b.T1 : b.T0;
+    float* Tout = cur ? b.T0 : b.T1;
+    float tp[kNTan];
 #pragma unroll
-      for (int d = 0; d < kNTan; ++d) tp[d] = Tin[(int64_t)d * m.n + p];
-      tg[0] = (float)((double)tp[0] + (double)z[0]);
-      tg[1] = (float)((double)tp[1] + (double)z[1]);
-      tg[2] = (float)((double)tp[2] + (double)z[2]);
-      tg[3] = (float)((double)tp[3] + (double)tp[2]);
-      tg[4] = (float)((double)tp[4] + (double)z[3]);
-      tg[5] = (float)((double)tp[5] + (double)tp[4]);
-      tg[6] = (float)((double)tp[6] + (double)z[4]);
+    for (int d = 0; d < kNTan; ++d) tp[d] = Tin[(int64_t)d * m.n + p];
+    tg[0] = (float)((double)tp[0] + (double)z[0]);
+    tg[1] = (float)((double)tp[1] + (double)z[1]);
+    tg[2] = (float)((double)tp[2] + (double)z[2]);
+    tg[3] = (float)((double)tp[3] + (double)tp[2]);
+    tg[4] = (float)((double)tp[4] + (double)z[3]);
+    tg[5] = (float)((double)tp[5] + (double)tp[4]);
+    tg[6] = (float)((double)tp[6] + (double)z[4]);
+    if (active)
 #pragma unroll
       for (int d = 0; d < kNTan; ++d) Tout[(int64_t)d * m.n + i] = tg[d];
-    } else {
-      o = propagate(m, b, cur, mode, cdelta, i, k);
-    }
-    store_state(m, b, cur, i, o);
-    // patch centre: pixel nearest to (x, y); the offset f is exact in fp64
-    rx = floor((double)o.x + 0.5);
-    ry = floor((double)o.y + 0.5);
-    fx = (double)o.x - rx;
-    fy = (double)o.y - ry;
-    // addresses only: far-away centres are clamped where the whole patch
-    // already lies outside the frame (their pixels read as background)
-    const double lox = -(double)P, hix = (double)m.W + P, loy = -(double)P, hiy = (double)m.H + P;
-    cx = (rx >= lox && rx <= hix) ? (int)rx : (rx > hix ? (int)hix : (int)lox);
-    cy = (ry >= loy && ry <= hiy) ? (int)ry : (ry > hiy ? (int)hiy : (int)loy);
+  } else {
+    o = propagate(m, b, cur, mode, cdelta, ia, k);
   }
+  if (active) store_state(m, b, cur, i, o);
+  // patch centre: pixel nearest to (x, y); the offset f is exact in fp64
+  const double rx = floor((double)o.x + 0.5);
+  const double ry = floor((double)o.y + 0.5);
+  const double fx = (double)o.x - rx;
+  const double fy = (double)o.y - ry;
+  // addresses only: far-away centres are clamped where the whole patch
+  // already lies outside the frame (their pixels read as background)
+  const double lox = -(double)P, hix = (double)m.W + P, loy = -(double)P, hiy = (double)m.H + P;
+  const int cx = (rx >= lox && rx <= hix) ? (int)rx : (rx > hix ? (int)hix : (int)lox);
+  const int cy = (ry >= loy && ry <= hiy) ? (int)ry : (ry > hiy ? (int)hiy : (int)loy);
   // The 1-D Gaussian factors of Eq. 3 at the patch's pixel offsets. Only
   // their products g_x g_y enter the likelihood, so g_x is taken relative to
   // its first value, which moves into the first g_y: three exps per particle
   // (the host keeps both first values above e^-350, so the product stays
   // normal).
   double gx[P];
-  double G2x = 0.0, gy0 = 0.0, by = 0.0;
-  if (active) {
-    gx[0] = 1.0;
-    const double bx = exp_fast(2.0 * fx * m.inv2s2);
+  gx[0] = 1.0;
+  const double bx = exp_fast(2.0 * fx * m.inv2s2);
 #pragma unroll
-    for (int d = 0; d + 1 < P; ++d) gx[d + 1] = gx[d] * (m.gstep[d] * bx);
+  for (int d = 0; d + 1 < P; ++d) gx[d + 1] = gx[d] * (m.gstep[d] * bx);
+  double G2x = 0.0;
 #pragma unroll
-    for (int d = 0; d < P; ++d) G2x = fma(gx[d], gx[d], G2x);
-    const double ax = (double)h + fx, ay = (double)h + fy;
-    gy0 = exp_fast(-(ax * ax + ay * ay) * m.inv2s2);
-    by = exp_fast(2.0 * fy * m.inv2s2);
-  } else {
-#pragma unroll
-    for (int d = 0; d < P; ++d) gx[d] = 0.0;
-  }
-  // Bounding box of the workgroup's patch centres. Each lane packs the
+  for (int d = 0; d < P; ++d) G2x = fma(gx[d], gx[d], G2x);
+  const double ax = (double)h + fx, ay = (double)h + fy;
+  const double gy0 = exp_fast(-(ax * ax + ay * ay) * m.inv2s2);
+  const double by = exp_fast(2.0 * fy * m.inv2s2);
+  // Bounding box of the workgroup's patch centres (the tail lanes repeat
+  // particle n - 1, whose centre is in the box anyway). Each lane packs the
   // offsets (ox, oy) of its centre from lane 0's, saturated to +-32767, as
   // two int16 (for the minima) and their negations (for the maxima); an
   // offset at the saturation bound already makes the box wider than any
-  // tile, so the saturated box still selects the global path. A wave with no
-  // particle reports an empty box.
+  // tile, so the saturated box still selects the global path.
   {
     const int bx0 = readlane(cx, 0), by0 = readlane(cy, 0);
     const int ox = min(max(cx - bx0, -32767), 32767), oy = min(max(cy - by0, -32767), 32767);
-    const uint32_t pmin = active ? ((uint32_t)(uint16_t)ox | ((uint32_t)(uint16_t)oy << 16))
-                                 : 0x7fff7fffu;
-    const uint32_t pneg = active ? ((uint32_t)(uint16_t)-ox | ((uint32_t)(uint16_t)-oy << 16))
-                                 : 0x7fff7fffu;
-    const uint32_t rmin = wave_reduce(pmin, lane, OpMin16x2());
-    const uint32_t rneg = wave_reduce(pneg, lane, OpMin16x2());
-    const bool any = blk * kBlock + w * 64 < m.n;
-    if (lane == 0) {
-      ish[w] = any ? bx0 + (int16_t)(rmin & 0xffffu) : INT_MAX;
-      ish[4 + w] = any ? bx0 - (int16_t)(rneg & 0xffffu) : INT_MIN;
-      ish[8 + w] = any ? by0 + (int16_t)(rmin >> 16) : INT_MAX;
-      ish[12 + w] = any ? by0 - (int16_t)(rneg >> 16) : INT_MIN;
+    const uint32_t pmin = (uint32_t)(uint16_t)ox | ((uint32_t)(uint16_t)oy << 16);
+    const uint32_t pneg = (uint32_t)(uint16_t)-ox | ((uint32_t)(uint16_t)-oy << 16);
+    const uint32_t rmin = wave_reduce_last(pmin, OpMin16x2(), 0x7fff7fffu);
+    const uint32_t rneg = wave_reduce_last(pneg, OpMin16x2(), 0x7fff7fffu);
+    if (lane == 63) {
+      ish[w] = bx0 + (int16_t)(rmin & 0xffffu);
+      ish[4 + w] = bx0 - (int16_t)(rneg & 0xffffu);
+      ish[8 + w] = by0 + (int16_t)(rmin >> 16);
+      ish[12 + w] = by0 - (int16_t)(rneg >> 16);
     }
   }
   __syncthreads();
@@ -801,9 +882,11 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   }
   __syncthreads();
 
-  double l = -INFINITY;
+  // every lane's patch lies in the tile (the tail lanes' is particle
+  // n - 1's); finish_block ignores the tail lanes' l
+  double l;
   double gth[GRAD ? kNGrad : 1] = {};
-  if (GRAD && active) {
+  if (GRAD) {
     const double* p0 = tile + (cy - h - ty0) * ts + (cx - h - tx0);
     Moments mo{};
     // frame row of the patch's first row; centres far outside are clamped,
@@ -856,7 +939,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     gth[6] = ly * (double)tg[5];
     gth[7] = lI * (double)tg[6];
     gth[8] = lI;
-  } else if (active) {
+  } else {
     double X = 0.0, G2y = 0.0, sd2 = 0.0;
     const double* p0 = tile + (cy - h - ty0) * ts + (cx - h - tx0);
     if (use_tab) {
@@ -937,7 +1020,7 @@ __global__ __launch_bounds__(256) void k_records(Model m, Buffers b,
                                                  const float* __restrict__ logw) {
   __shared__ double red[2 * 256];
   __shared__ double dsh[4];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int t = threadIdx.x;
   const int64_t i = (int64_t)blockIdx.x * kBlock + t;
   if (i == 0) {
     // the standalone scratch starts uninitialised: clear the counters and
@@ -974,7 +1057,6 @@ __global__ __launch_bounds__(256) void k_records(Model m, Buffers b,
     R[2] = h1;
     for (int d = 0; d < 5; ++d) R[3 + d] = 0.0;
   }
-  (void)w;
 }
 
 // ------------------------------------------------------------- k_merge

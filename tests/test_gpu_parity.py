@@ -102,6 +102,14 @@ def test_spot_patch_extremes(ppf, movie128, P):
     run_teacher_forced(ppf, p, m, movie128.frames, 3)
 
 
+def test_spot_log_weights_beyond_2_20(ppf, movie128):
+    """A tiny noise sigma (0.02) puts every block maximum of l below -2^20,
+    where the block shift is the exact fp64 maximum instead of the fp32 one."""
+    p, m = pair(ppf, n=3001, **dict(SPOT, sigma=0.02))
+    assert oracle.loglik(m, movie128.frames[0], oracle.init(m)[0]).max() < -2.0**20
+    run_teacher_forced(ppf, p, m, movie128.frames, 3)
+
+
 def test_spot_particles_leaving_frame(ppf):
     # a wide init box: many patches cross the border or lie fully outside
     mv = synth.render_movie(48, 40, 3, seed=2, start_box=(10, 38, 10, 30))
