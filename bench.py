@@ -168,22 +168,8 @@ def run_multitrack(args, w):
     torch.cuda.set_device(0)
     frames = torch.from_numpy(mv.frames).cuda()
     b = ppf.Batch(ps)
-    for k in range(Wm):
-        b.step(frames[k % T])
-    b.reset()
-    torch.cuda.synchronize()
-    b.profile(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(b.stream)
-    for k in range(K):
-        b.step(frames[k % T])
-    ev1.record(b.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    kt = b.kernel_times()
+    graph = args.launch == "graph"
+    gpu_ms, wall, kt = timed_steps(torch, b, frames, K, Wm, T, graph)
     sts = b.stats()
     ntot = sum(int(p.n_particles) for p in ps)
     flops = sum(4 * ppf.patch_size(p) ** 2 * int(p.n_particles) for p in ps)
@@ -208,7 +194,8 @@ def run_multitrack(args, w):
                    "n_min": min(int(p.n_particles) for p in ps),
                    "n_max": max(int(p.n_particles) for p in ps),
                    "patches": sorted({ppf.patch_size(p) for p in ps}),
-                   "frame": [w["W"], w["H"]], "resampling": "systematic", "frames_timed": K},
+                   "frame": [w["W"], w["H"]], "resampling": "systematic", "frames_timed": K,
+                   "launch": args.launch},
         "roofline": {"bound": "alu", "kernel": "k_step (all patch sizes)",
                      "achieved": achieved_tf, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
@@ -234,6 +221,42 @@ def make_params(ppf, w, init_kind, grad=0):
                       init_a=(x0, y0, -1, -1, I / 2), init_b=(x1, y1, 1, 1, 1.5 * I),
                       ess_threshold=w["thr"], seed=1, grad=grad, resample=resample,
                       rna_group=group, dlb=dlb)
+
+
+def timed_steps(torch, f, frames, K, Wm, T, graph):
+    """K steps of filter or batch f from a fresh initial cloud, after Wm
+    warm-up steps: (GPU ms of the K steps between two events on f's stream,
+    wall s, per-kernel times). With graph=True the timed steps replay the
+    step's HIP graph (recorded in the warm-up), and the per-kernel times come
+    from a second pass over the same K steps with plain launches and kernel
+    timing on (the two exclude each other)."""
+    f.graph(graph)
+    for k in range(Wm):
+        f.step(frames[k % T])
+    f.reset()
+    torch.cuda.synchronize()
+    if not graph:
+        f.profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(f.stream)
+    for k in range(K):
+        f.step(frames[k % T])
+    ev1.record(f.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    if graph:
+        # the same K steps again from the same initial cloud: they end in the
+        # same state, bit for bit, which the caller then reads
+        f.graph(False)
+        f.reset()
+        f.profile(True)
+        for k in range(K):
+            f.step(frames[k % T])
+    kt = f.kernel_times()
+    return gpu_ms, wall, kt
 
 
 def time_filter(ppf, torch, p, frames, K, Wm, T):
@@ -278,10 +301,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    # the card reaches its steady clocks after about 50 ms of load (measured:
+    # 1.29 ms per step after 2 warm-up steps, 1.19 ms after 40, and 1.19 ms
+    # averaged over 100 steps after 2)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="sir_1024x1024_n38m_p13", choices=sorted(WORKLOADS))
     ap.add_argument("--init", default="stratified", choices=["stratified", "uniform"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch", default="stream", choices=["stream", "graph"],
+                    help="timed steps as plain launches or as replays of one HIP graph")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -313,7 +341,7 @@ def main():
         return run_multitrack(args, w)
     init_kind = ppf.INIT_STRATIFIED if args.init == "stratified" else ppf.INIT_UNIFORM
     K, Wm = args.steps, args.warmup
-    T = max(K, w["T"], Wm)
+    T = max(K, w["T"])  # the warm-up steps cycle through these frames
     box = w.get("box")
     mv = synth.render_movie(w["W"], w["H"], T, intensity=w.get("I", 30.0), sigma=w["s"],
                             background=10.0, noise_sd=3.0, seed=1,
@@ -335,25 +363,8 @@ def main():
         plain = {"value": w["n"] * K / (pms / 1e3), "ms_per_step": pms / K,
                  "k_step_ms": pkt.get("k_step", (1, 0.0))[1] / K}
     f = ppf.Filter(make_params(ppf, w, init_kind, grad=w.get("grad", 0)))
-    stream = f.stream
-    # warm-up: a few steps, then a fresh initial cloud for the timed steps
-    for k in range(Wm):
-        f.step(frames[k])
-    f.reset()
-    f.sync()
-    torch.cuda.synchronize()
-    f.profile(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for k in range(K):
-        f.step(frames[k % T])
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    kt = f.kernel_times()
+    graph = args.launch == "graph"
+    gpu_ms, wall, kt = timed_steps(torch, f, frames, K, Wm, T, graph)
     st = f.stats()
     err = float(np.linalg.norm(st["mean"][:2] - mv.truth[(K - 1) % T, 0]))
     n = w["n"]
@@ -391,7 +402,7 @@ def main():
                    "resampling": ({0: "systematic", 1: "RNA", 2: "RPA"}[w.get("scheme", (0,))[0]]
                                   + ("" if w["thr"] == float("inf")
                                      else f" when ESS < {w['thr']:.0f}")),
-                   "init": args.init, "frames_timed": K},
+                   "init": args.init, "frames_timed": K, "launch": args.launch},
         "roofline": {"bound": "alu", "kernel": "k_step", "achieved": achieved_tf,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,

@@ -223,6 +223,19 @@ int ppf_reset(ppf_handle h);
  */
 int ppf_step(ppf_handle h, const float* obs_dev);
 
+/*
+ * Graph mode (1 on, 0 off; off after create). When on, the next ppf_step
+ * records the step's kernel launches into a HIP graph instead of launching
+ * them, and that step and every later one launch the graph (hipGraphLaunch)
+ * with its frame argument pointed at the call's obs_dev; results are the
+ * same as without the graph. The launch sequence of a step does not depend
+ * on the filter's state (every decision is taken on the device), so one
+ * recording serves all steps. Switching syncs the handle's stream and drops
+ * the recorded graph. ESTATE while kernel timing (ppf_profile_enable) is on:
+ * the two exclude each other.
+ */
+int ppf_set_graph(ppf_handle h, int enable);
+
 /* Wait for the handle's stream. Returns PPF_ENUMERIC if any step enqueued
  * since the last report was rolled back (and clears the report), else OK. */
 int ppf_sync(ppf_handle h);
@@ -288,7 +301,7 @@ int ppf_set_particles(ppf_handle h, const float* state_host, const double* logw_
 int ppf_gather(ppf_handle h, float* out_dev);
 
 /* Enable (1) / disable (0) per-kernel HIP-event timing of the handle's
- * launches; enabling clears the accumulated times. */
+ * launches; enabling clears the accumulated times. ESTATE in graph mode. */
 int ppf_profile_enable(ppf_handle h, int on);
 
 /* Read accumulated kernel times; syncs. Writes at most max_entries entries
@@ -408,6 +421,11 @@ int ppf_batch_reset(ppf_batch h);
  * shared by all tracks); async, as ppf_step. A track whose normaliser is not
  * finite rolls back alone and reports it in ppf_batch_stats. */
 int ppf_step_batched(ppf_batch h, const float* obs_dev);
+
+/* Graph mode of a batch, as ppf_set_graph: one HIP graph holds every launch
+ * of a batched step (one step launch for all patch sizes up to 13, one per
+ * wider size, then the merge and resampling launches). */
+int ppf_batch_set_graph(ppf_batch h, int enable);
 
 /* Statistics of every track's last committed step (out: count entries, in
  * track order), as ppf_stats; syncs and clears the roll-back reports. */

@@ -107,6 +107,7 @@ _SIGS = {
                                   ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "ppf_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "ppf_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ppf_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "ppf_sync": (ctypes.c_int, [ctypes.c_void_p]),
     "ppf_estimate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "ppf_loglik": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -143,6 +144,7 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "ppf_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "ppf_step_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ppf_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "ppf_batch_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats), ctypes.c_int32]),
     "ppf_batch_get_particles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p]),
@@ -340,6 +342,10 @@ class Filter:
         _check(lib().ppf_gather(self.handle, ctypes.c_void_p(out.data_ptr())), self.handle)
         return out
 
+    def graph(self, on: bool = True):
+        """Graph mode: steps replay one recorded HIP graph of their launches."""
+        _check(lib().ppf_set_graph(self.handle, 1 if on else 0), self.handle)
+
     # -- timing
     def profile(self, on: bool = True):
         _check(lib().ppf_profile_enable(self.handle, 1 if on else 0), self.handle)
@@ -437,6 +443,10 @@ class Batch:
                                                 lw.ctypes.data_as(ctypes.c_void_p),
                                                 anc.ctypes.data_as(ctypes.c_void_p)))
         return x, lw, anc
+
+    def graph(self, on: bool = True):
+        """Graph mode: batched steps replay one recorded HIP graph."""
+        self._chk(lib().ppf_batch_set_graph(self.handle, 1 if on else 0))
 
     def profile(self, on: bool = True):
         self._chk(lib().ppf_batch_profile_enable(self.handle, 1 if on else 0))

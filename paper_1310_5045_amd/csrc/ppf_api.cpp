@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -303,7 +304,39 @@ struct Runner {
     events.clear();
     return PPF_OK;
   }
+  // Graph mode: a step is recorded once into a HIP graph (the first step
+  // after enabling) and replayed, pointed at each call's frame.
+  bool graph_on = false;
+  std::unique_ptr<ppf::StepGraph> graph;
+  int graph_enable(int on) {
+    if (on && prof) return fail(PPF_ESTATE, "graph mode and kernel timing exclude each other");
+    if (hipStreamSynchronize(stream) != hipSuccess) return fail(PPF_EDEVICE, "sync");
+    graph_on = on != 0;
+    graph.reset();
+    return PPF_OK;
+  }
+  // Enqueues one step: enqueue() itself, or the graph of its launches.
+  template <class F>
+  int step(const float* frame, F&& enqueue) {
+    if (!graph_on) return enqueue();
+    if (!graph) {
+      auto g = std::make_unique<ppf::StepGraph>();
+      hipError_t e = g->begin(frame);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+      const int rc = enqueue();
+      e = g->end();
+      if (rc) return rc;
+      if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+      graph = std::move(g);
+    }
+    hipError_t e = graph->set_frame(frame);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphExecKernelNodeSetParams");
+    e = graph->launch(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return PPF_OK;
+  }
   int profile_enable(int on) {
+    if (on && graph_on) return fail(PPF_ESTATE, "graph mode and kernel timing exclude each other");
     if (hipStreamSynchronize(stream) != hipSuccess) return fail(PPF_EDEVICE, "sync");
     collect();
     prof = on != 0;
@@ -462,9 +495,10 @@ int ppf_reset(ppf_handle h) {
   return h->run(kKInit, [&] { return ppf::launch_init(h->m, h->b, h->stream); });
 }
 
-int ppf_step(ppf_handle h, const float* obs_dev) {
-  if (!h) return PPF_ESTATE;
-  if (!obs_dev) return h->fail(PPF_EINVAL, "null observation");
+namespace {
+// The launches of one step; every decision between them is taken on the
+// device, so the same sequence serves every step (and a graph of it).
+int enqueue_step(ppf_handle h, const float* obs_dev) {
   int rc = h->run(kKStep, [&] { return ppf::launch_step(h->m, h->b, obs_dev, h->stream); });
   if (rc) return rc;
   rc = h->run(kKMerge, [&] { return ppf::launch_merge(h->m, h->b, 0, 0.0, h->stream); });
@@ -477,6 +511,18 @@ int ppf_step(ppf_handle h, const float* obs_dev) {
   rc = h->run(kKFill, [&] { return ppf::launch_fill(h->m, h->b, h->stream); });
   if (rc || !h->m.rpa) return rc;
   return h->run(kKRpa, [&] { return ppf::launch_rpa(h->m, h->b, h->stream); });
+}
+}  // namespace
+
+int ppf_step(ppf_handle h, const float* obs_dev) {
+  if (!h) return PPF_ESTATE;
+  if (!obs_dev) return h->fail(PPF_EINVAL, "null observation");
+  return h->step(obs_dev, [&] { return enqueue_step(h, obs_dev); });
+}
+
+int ppf_set_graph(ppf_handle h, int enable) {
+  if (!h) return PPF_ESTATE;
+  return h->graph_enable(enable);
 }
 
 int ppf_sync(ppf_handle h) {
@@ -714,7 +760,8 @@ struct BatchPlan {
   std::vector<Buffers> bufs;
   std::vector<ppf::BatchItem> blocks, chunks, segs, groups;
   std::vector<int32_t> sys_tracks;
-  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> step_ranges;  // P -> [first, count)
+  // patch size (0: every size up to kFusedMaxP) -> [first, count) of blocks
+  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> step_ranges;
   size_t off_models = 0, off_bufs = 0, off_blocks = 0, off_chunks = 0, off_segs = 0,
          off_groups = 0, off_sys = 0, off_tracks = 0, total = 0;
   std::vector<size_t> track_off;
@@ -755,17 +802,25 @@ void plan_batch(const ppf_params* p, int32_t count, BatchPlan* bp) {
     bp->models[t] = make_model(&p[t]);
     carve(&p[t], nullptr, &bp->bufs[t], false);
   }
-  // step items grouped by patch size, one launch per distinct size
+  // step items grouped by patch size: the sizes up to kFusedMaxP in one
+  // launch (range key 0), each wider size in a launch of its own
   std::vector<int> sizes;
   for (int32_t t = 0; t < count; ++t) sizes.push_back(bp->models[t].P);
   std::sort(sizes.begin(), sizes.end());
   sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  int64_t first = 0;
   for (int P : sizes) {
-    const int64_t first = (int64_t)bp->blocks.size();
+    if (P > ppf::kFusedMaxP) first = (int64_t)bp->blocks.size();
     for (int32_t t = 0; t < count; ++t)
       if (bp->models[t].P == P)
         for (int64_t j = 0; j < bp->bufs[t].nb; ++j) bp->blocks.push_back({t, (int32_t)j});
-    bp->step_ranges.push_back({P, {first, (int64_t)bp->blocks.size() - first}});
+    const int64_t cnt = (int64_t)bp->blocks.size() - first;
+    if (P <= ppf::kFusedMaxP) {
+      if (bp->step_ranges.empty()) bp->step_ranges.push_back({0, {first, cnt}});
+      else bp->step_ranges.back().second.second = cnt;
+    } else {
+      bp->step_ranges.push_back({P, {first, cnt}});
+    }
   }
   for (int32_t t = 0; t < count; ++t) {
     for (int64_t j = 0; j < bp->bufs[t].nch; ++j) bp->chunks.push_back({t, (int32_t)j});
@@ -882,14 +937,17 @@ int ppf_batch_reset(ppf_batch h) {
   return h->init();
 }
 
-int ppf_step_batched(ppf_batch h, const float* obs_dev) {
-  if (!h) return PPF_ESTATE;
-  if (!obs_dev) return h->fail(PPF_EINVAL, "null observation");
+namespace {
+int enqueue_batch_step(ppf_batch h, const float* obs_dev) {
   const BatchPlan& bp = h->plan;
   for (const auto& r : bp.step_ranges) {
     const int rc = h->run(kKStep, [&] {
-      return ppf::launch_step_batch(r.first, h->d_models, h->d_bufs, h->d_blocks + r.second.first,
-                                    r.second.second, obs_dev, h->stream);
+      const ppf::BatchItem* it = h->d_blocks + r.second.first;
+      return r.first == 0
+                 ? ppf::launch_step_batch_fused(h->d_models, h->d_bufs, it, r.second.second,
+                                                obs_dev, h->stream)
+                 : ppf::launch_step_batch(r.first, h->d_models, h->d_bufs, it, r.second.second,
+                                          obs_dev, h->stream);
     });
     if (rc) return rc;
   }
@@ -916,6 +974,18 @@ int ppf_step_batched(ppf_batch h, const float* obs_dev) {
                                    (int64_t)bp.groups.size(), h->stream);
     });
   return PPF_OK;
+}
+}  // namespace
+
+int ppf_step_batched(ppf_batch h, const float* obs_dev) {
+  if (!h) return PPF_ESTATE;
+  if (!obs_dev) return h->fail(PPF_EINVAL, "null observation");
+  return h->step(obs_dev, [&] { return enqueue_batch_step(h, obs_dev); });
+}
+
+int ppf_batch_set_graph(ppf_batch h, int enable) {
+  if (!h) return PPF_ESTATE;
+  return h->graph_enable(enable);
 }
 
 int ppf_batch_stats(ppf_batch h, ppf_stats_t* out, int32_t count) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
+#include <vector>
 
 namespace ppf {
 
@@ -42,6 +44,9 @@ constexpr int kSlotTile = 4096;  // slots per LDS tile of the segment's writes
 constexpr int kFillChunk = 1 << 16;
 constexpr int kFillGrid = 2048;
 constexpr int kFillGridBatch = 64;  // workgroups per track of a batched fill
+// Batched steps run every patch size up to this one in a single launch (the
+// sizes that fit five waves per SIMD); wider patches launch per size.
+constexpr int kFusedMaxP = 13;
 constexpr int kDlbMaxSorted = 4096;  // groups of a sorted DLB schedule (LDS sort)
 
 // One work item of a batched launch: the track, and the index of the track's
@@ -213,6 +218,9 @@ hipError_t launch_init_batch(const Model* ms, const Buffers* bs, const BatchItem
                              int64_t n_items, hipStream_t s);
 hipError_t launch_step_batch(int P, const Model* ms, const Buffers* bs, const BatchItem* items,
                              int64_t n_items, const float* obs, hipStream_t s);
+// All items with patch sizes up to kFusedMaxP, whatever their size, in one launch.
+hipError_t launch_step_batch_fused(const Model* ms, const Buffers* bs, const BatchItem* items,
+                                   int64_t n_items, const float* obs, hipStream_t s);
 hipError_t launch_merge_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                               int64_t n_items, hipStream_t s);
 hipError_t launch_anc_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
@@ -221,5 +229,45 @@ hipError_t launch_fill_batch(const Model* ms, const Buffers* bs, const int32_t* 
                              int32_t n_tracks, hipStream_t s);
 hipError_t launch_rna_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                             int64_t n_items, hipStream_t s);
+
+// A HIP graph of one step's launches, replayed with another frame. While a
+// StepGraph records (begin() to end(), on the calling thread), the launch_*
+// functions above add kernel nodes to it, each depending on the one before,
+// instead of launching; the graph keeps every node's argument values, and
+// notes the arguments equal to the frame pointer given to begin() so that
+// set_frame() can point them at another frame before a replay.
+class StepGraph {
+ public:
+  StepGraph() = default;
+  StepGraph(const StepGraph&) = delete;
+  StepGraph& operator=(const StepGraph&) = delete;
+  ~StepGraph();
+  hipError_t begin(const float* frame);
+  hipError_t end();  // stops recording and instantiates the graph
+  bool ready() const { return exec_ != nullptr; }
+  hipError_t set_frame(const float* frame);
+  hipError_t launch(hipStream_t s) const { return hipGraphLaunch(exec_, s); }
+
+  // used by the launch functions while recording
+  struct Args {
+    virtual ~Args() = default;
+  };
+  hipError_t add(const void* fn, dim3 grid, dim3 block, std::unique_ptr<Args> args,
+                 std::vector<void*> argv, std::vector<const float**> frame_slots);
+  const float* frame() const { return frame_; }
+
+ private:
+  struct Node {
+    hipGraphNode_t node = nullptr;
+    hipKernelNodeParams params{};
+    std::unique_ptr<Args> args;
+    std::vector<void*> argv;
+    std::vector<const float**> frame_slots;
+  };
+  hipGraph_t graph_ = nullptr;
+  hipGraphExec_t exec_ = nullptr;
+  std::vector<Node> nodes_;
+  const float* frame_ = nullptr;
+};
 
 }  // namespace ppf

@@ -14,9 +14,12 @@
 //   (or k_rna    RNA of Section 3: one workgroup per group of particles)
 #include "ppf_internal.hpp"
 
+#include <array>
 #include <cfloat>
 #include <climits>
 #include <cmath>
+#include <tuple>
+#include <utility>
 
 namespace ppf {
 namespace {
@@ -527,7 +530,8 @@ __device__ __forceinline__ float exp_neg_f32(double x) {
 
 // The block's normalisation record (see kRec) and the stored weights
 // E = exp(l - m_b) in fp32. red: 7 x 256 doubles of LDS that no thread reads
-// once it has reached this call (it may alias the caller's image tile).
+// once it has reached this call (it may alias the caller's image tile); dsh
+// and ksh: 4 doubles and 4 ints of LDS scratch.
 // Returns e = E (0 for an inactive or non-finite particle).
 //
 // The shift m_b is any value at or above every finite l of the block and
@@ -538,8 +542,7 @@ __device__ __forceinline__ float exp_neg_f32(double x) {
 // maxima of magnitude 2^20 and above) the exact fp64 maximum is taken instead.
 __device__ __forceinline__ double finish_block(const Buffers& b, int cur, int64_t i, bool active,
                                                double l, const Prop& o, double* red,
-                                               double* dsh) {
-  __shared__ int ksh[4];
+                                               double* dsh, int* ksh) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const bool bad = active && (isnan(l) || l == INFINITY);
   const bool ok = active && !bad;
@@ -590,6 +593,18 @@ __device__ __forceinline__ double finish_block(const Buffers& b, int cur, int64_
   if (t == 0) R[0] = mb;
   return e;
 }
+
+// LDS of one step workgroup: the tile of D = Z - b (its first 7 x 256
+// doubles double as the record exchange), the table of row sums of D^2, and
+// the reduction scratch. Kernels that run several patch sizes declare it once.
+struct StepLds {
+  __align__(16) double tile[kTileCap];
+  double sq[kSqCap];
+  double dsh[4];
+  int ish[16];
+  int ksh[4];
+};
+static_assert(kTileCap >= 7 * kBlock, "the tile doubles as the record exchange buffer");
 
 // Patch sums of one particle over P rows of an LDS tile of D = Z - b (0
 // outside the frame) with row stride tw:
@@ -735,13 +750,13 @@ __device__ __forceinline__ void patch_moments(const double* __restrict__ p0, int
 // maximum, and the record exchange.
 template <int P, bool GRAD = false>
 __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
-                                          const float* __restrict__ obs, int64_t blk) {
+                                          const float* __restrict__ obs, int64_t blk,
+                                          StepLds& L) {
   constexpr int h = (P - 1) / 2;
-  __shared__ __align__(16) double tile[kTileCap];
-  static_assert(kTileCap >= 7 * kBlock, "the tile doubles as the record exchange buffer");
-  __shared__ double sq[kSqCap];
-  __shared__ double dsh[4];
-  __shared__ int ish[16];
+  double* const tile = L.tile;
+  double* const sq = L.sq;
+  double* const dsh = L.dsh;
+  int* const ish = L.ish;
   const Ctrl* cp = b.ctrl;
   const int cur = cp->cur, mode = cp->mode;
   const double cdelta = cp->delta;
@@ -954,7 +969,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     const double ssq = sd2 - 2.0 * I * X + I * I * (G2x * G2y);
     l = o.lw - ssq * m.inv2sig2 - m.lognorm_obs;
   }
-  const double e = finish_block(b, cur, i, active, l, o, tile, dsh);
+  const double e = finish_block(b, cur, i, active, l, o, tile, dsh, L.ksh);
   if (GRAD) {
     // the block's sum_i E_i d l_i / d theta, weighted like the MMSE sums
     __shared__ double gsh[4 * kNGrad];
@@ -973,20 +988,23 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
 template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 void k_step_spot(Model m, Buffers b, const float* __restrict__ obs) {
-  step_spot<P>(m, b, obs, blockIdx.x);
+  __shared__ StepLds L;
+  step_spot<P>(m, b, obs, blockIdx.x, L);
 }
 
 template <int P>
 __global__ __launch_bounds__(256) void k_step_spot_wide(Model m, Buffers b,
                                                         const float* __restrict__ obs) {
-  step_spot<P>(m, b, obs, blockIdx.x);
+  __shared__ StepLds L;
+  step_spot<P>(m, b, obs, blockIdx.x, L);
 }
 
 // Gradient mode (derivatives of log p^ alongside the step).
 template <int P>
 __global__ __launch_bounds__(256) void k_step_spot_grad(Model m, Buffers b,
                                                         const float* __restrict__ obs) {
-  step_spot<P, true>(m, b, obs, blockIdx.x);
+  __shared__ StepLds L;
+  step_spot<P, true>(m, b, obs, blockIdx.x, L);
 }
 
 // Linear-Gaussian observation of (x, y, I0): three fp32 values on the device.
@@ -994,6 +1012,7 @@ __global__ __launch_bounds__(256) void k_step_lg(Model m, Buffers b,
                                                  const float* __restrict__ obs) {
   __shared__ double red[7 * 256];
   __shared__ double dsh[4];
+  __shared__ int ksh[4];
   const Ctrl* cp = b.ctrl;
   const int cur = cp->cur, mode = cp->mode;
   const double cdelta = cp->delta;
@@ -1010,7 +1029,7 @@ __global__ __launch_bounds__(256) void k_step_lg(Model m, Buffers b,
     l = o.lw - ex * ex * m.lg_inv2r2[0] - ey * ey * m.lg_inv2r2[1] - eI * eI * m.lg_inv2r2[2] -
         m.lg_norm;
   }
-  finish_block(b, cur, i, active, l, o, red, dsh);
+  finish_block(b, cur, i, active, l, o, red, dsh, ksh);
 }
 
 // Records of caller-supplied absolute fp32 log weights (standalone
@@ -1932,8 +1951,9 @@ template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 void k_step_batch(const Model* __restrict__ ms, const Buffers* __restrict__ bs,
                   const BatchItem* __restrict__ items, const float* __restrict__ obs) {
+  __shared__ StepLds L;
   const BatchItem it = items[blockIdx.x];
-  step_spot<P>(ms[it.track], bs[it.track], obs, it.idx);
+  step_spot<P>(ms[it.track], bs[it.track], obs, it.idx, L);
 }
 
 template <int P>
@@ -1941,9 +1961,32 @@ __global__ __launch_bounds__(256) void k_step_batch_wide(const Model* __restrict
                                                          const Buffers* __restrict__ bs,
                                                          const BatchItem* __restrict__ items,
                                                          const float* __restrict__ obs) {
+  __shared__ StepLds L;
   const BatchItem it = items[blockIdx.x];
-  step_spot<P>(ms[it.track], bs[it.track], obs, it.idx);
+  step_spot<P>(ms[it.track], bs[it.track], obs, it.idx, L);
 }
+
+// Every patch size up to kFusedMaxP in one launch: each workgroup takes its
+// item's patch size (uniform across the workgroup) and shares one LDS block.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+void k_step_batch_fused(const Model* __restrict__ ms, const Buffers* __restrict__ bs,
+                        const BatchItem* __restrict__ items, const float* __restrict__ obs) {
+  __shared__ StepLds L;
+  const BatchItem it = items[blockIdx.x];
+  const Model& m = ms[it.track];
+  const Buffers& b = bs[it.track];
+  switch (m.P) {
+    case 1: step_spot<1>(m, b, obs, it.idx, L); break;
+    case 3: step_spot<3>(m, b, obs, it.idx, L); break;
+    case 5: step_spot<5>(m, b, obs, it.idx, L); break;
+    case 7: step_spot<7>(m, b, obs, it.idx, L); break;
+    case 9: step_spot<9>(m, b, obs, it.idx, L); break;
+    case 11: step_spot<11>(m, b, obs, it.idx, L); break;
+    case 13: step_spot<13>(m, b, obs, it.idx, L); break;
+    default: break;  // the host puts only these sizes in a fused launch
+  }
+}
+static_assert(kFusedMaxP == 13, "k_step_batch_fused handles the odd patch sizes up to 13");
 
 __global__ __launch_bounds__(256) void k_merge_batch(const Model* __restrict__ ms,
                                                      const Buffers* __restrict__ bs,
@@ -2013,15 +2056,52 @@ __global__ __launch_bounds__(256) void k_philox(uint32_t k0, uint32_t k1,
   if (i < n) out[i] = philox(ctr[i], k0, k1);
 }
 
+// ---------------------------------------------------------------- launches
+// Every kernel goes out through launch_k: onto the stream, or, while a
+// StepGraph records on the calling thread, into its graph.
+thread_local StepGraph* t_rec = nullptr;
+
+template <class... T>
+struct ArgTuple final : StepGraph::Args {
+  std::tuple<T...> v;
+  template <class... A>
+  explicit ArgTuple(A&&... a) : v(std::forward<A>(a)...) {}
+};
+
+template <class Tup, size_t... I>
+std::array<void*, sizeof...(I)> arg_ptrs(Tup& t, std::index_sequence<I...>) {
+  return {{static_cast<void*>(&std::get<I>(t))...}};
+}
+
+template <class T>
+void note_frame(T&, const float*, std::vector<const float**>*) {}
+void note_frame(const float*& p, const float* frame, std::vector<const float**>* out) {
+  if (p == frame) out->push_back(&p);
+}
+
+template <class... P, class... A>
+hipError_t launch_k(void (*k)(P...), dim3 grid, dim3 block, hipStream_t s, A&&... a) {
+  static_assert(sizeof...(P) == sizeof...(A), "kernel argument count");
+  constexpr auto idx = std::index_sequence_for<P...>{};
+  if (!t_rec) {
+    std::tuple<P...> v(std::forward<A>(a)...);
+    std::array<void*, sizeof...(P)> argv = arg_ptrs(v, idx);
+    return hipLaunchKernel(reinterpret_cast<const void*>(k), grid, block, argv.data(), 0, s);
+  }
+  auto pack = std::make_unique<ArgTuple<P...>>(std::forward<A>(a)...);
+  const std::array<void*, sizeof...(P)> argv = arg_ptrs(pack->v, idx);
+  std::vector<const float**> slots;
+  std::apply([&](auto&... x) { (note_frame(x, t_rec->frame(), &slots), ...); }, pack->v);
+  return t_rec->add(reinterpret_cast<const void*>(k), grid, block, std::move(pack),
+                    std::vector<void*>(argv.begin(), argv.end()), std::move(slots));
+}
+
 template <int P>
 hipError_t launch_spot(const Model& m, const Buffers& b, const float* obs, hipStream_t s) {
-  if (m.grad)
-    hipLaunchKernelGGL(k_step_spot_grad<P>, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);
-  else if constexpr (P <= 13)
-    hipLaunchKernelGGL(k_step_spot<P>, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);
-  else
-    hipLaunchKernelGGL(k_step_spot_wide<P>, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);
-  return hipGetLastError();
+  const dim3 grid((unsigned)b.nb), block(kBlock);
+  if (m.grad) return launch_k(k_step_spot_grad<P>, grid, block, s, m, b, obs);
+  if constexpr (P <= 13) return launch_k(k_step_spot<P>, grid, block, s, m, b, obs);
+  return launch_k(k_step_spot_wide<P>, grid, block, s, m, b, obs);
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -2029,26 +2109,75 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 template <int P>
 hipError_t launch_spot_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                              int64_t n_items, const float* obs, hipStream_t s) {
-  if constexpr (P <= 13)
-    hipLaunchKernelGGL(k_step_batch<P>, dim3((unsigned)n_items), dim3(kBlock), 0, s, ms, bs,
-                       items, obs);
-  else
-    hipLaunchKernelGGL(k_step_batch_wide<P>, dim3((unsigned)n_items), dim3(kBlock), 0, s, ms,
-                       bs, items, obs);
-  return hipGetLastError();
+  const dim3 grid((unsigned)n_items), block(kBlock);
+  if constexpr (P <= 13) return launch_k(k_step_batch<P>, grid, block, s, ms, bs, items, obs);
+  return launch_k(k_step_batch_wide<P>, grid, block, s, ms, bs, items, obs);
 }
 
 }  // namespace
 
+StepGraph::~StepGraph() {
+  if (t_rec == this) t_rec = nullptr;
+  if (exec_) (void)hipGraphExecDestroy(exec_);
+  if (graph_) (void)hipGraphDestroy(graph_);
+}
+
+hipError_t StepGraph::begin(const float* frame) {
+  if (t_rec || graph_) return hipErrorInvalidValue;  // one recording per graph and thread
+  const hipError_t e = hipGraphCreate(&graph_, 0);
+  if (e != hipSuccess) return e;
+  frame_ = frame;
+  t_rec = this;
+  return hipSuccess;
+}
+
+hipError_t StepGraph::end() {
+  if (t_rec != this) return hipErrorInvalidValue;
+  t_rec = nullptr;
+  if (nodes_.empty()) return hipErrorInvalidValue;
+  return hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0);
+}
+
+hipError_t StepGraph::add(const void* fn, dim3 grid, dim3 block, std::unique_ptr<Args> args,
+                          std::vector<void*> argv, std::vector<const float**> frame_slots) {
+  Node n;
+  n.args = std::move(args);
+  n.argv = std::move(argv);
+  n.frame_slots = std::move(frame_slots);
+  n.params.func = const_cast<void*>(fn);
+  n.params.gridDim = grid;
+  n.params.blockDim = block;
+  n.params.sharedMemBytes = 0;
+  n.params.kernelParams = n.argv.data();  // moving the vector keeps its storage
+  n.params.extra = nullptr;
+  hipGraphNode_t dep = nodes_.empty() ? nullptr : nodes_.back().node;
+  const hipError_t e =
+      hipGraphAddKernelNode(&n.node, graph_, dep ? &dep : nullptr, dep ? 1 : 0, &n.params);
+  if (e != hipSuccess) return e;
+  nodes_.push_back(std::move(n));
+  return hipSuccess;
+}
+
+hipError_t StepGraph::set_frame(const float* frame) {
+  if (!exec_) return hipErrorInvalidValue;
+  if (frame == frame_) return hipSuccess;
+  for (Node& n : nodes_) {
+    if (n.frame_slots.empty()) continue;
+    for (const float** slot : n.frame_slots) *slot = frame;
+    const hipError_t e = hipGraphExecKernelNodeSetParams(exec_, n.node, &n.params);
+    if (e != hipSuccess) return e;
+  }
+  frame_ = frame;
+  return hipSuccess;
+}
+
 hipError_t launch_init(const Model& m, const Buffers& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_init, dim3(grid_for(m.n, 256)), dim3(256), 0, s, m, b);
-  return hipGetLastError();
+  return launch_k(k_init, dim3(grid_for(m.n, 256)), dim3(256), s, m, b);
 }
 
 hipError_t launch_step(const Model& m, const Buffers& b, const float* obs, hipStream_t s) {
   if (m.obs == 1) {
-    hipLaunchKernelGGL(k_step_lg, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, obs);
-    return hipGetLastError();
+    return launch_k(k_step_lg, dim3((unsigned)b.nb), dim3(kBlock), s, m, b, obs);
   }
   switch (m.P) {
     case 1: return launch_spot<1>(m, b, obs, s);
@@ -2071,8 +2200,14 @@ hipError_t launch_step(const Model& m, const Buffers& b, const float* obs, hipSt
 hipError_t launch_init_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                              int64_t n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_init_batch, dim3((unsigned)n_items), dim3(kBlock), 0, s, ms, bs, items);
-  return hipGetLastError();
+  return launch_k(k_init_batch, dim3((unsigned)n_items), dim3(kBlock), s, ms, bs, items);
+}
+
+hipError_t launch_step_batch_fused(const Model* ms, const Buffers* bs, const BatchItem* items,
+                                   int64_t n_items, const float* obs, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  return launch_k(k_step_batch_fused, dim3((unsigned)n_items), dim3(kBlock), s, ms, bs, items,
+                  obs);
 }
 
 hipError_t launch_step_batch(int P, const Model* ms, const Buffers* bs, const BatchItem* items,
@@ -2099,101 +2234,86 @@ hipError_t launch_step_batch(int P, const Model* ms, const Buffers* bs, const Ba
 hipError_t launch_merge_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                               int64_t n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_merge_batch, dim3((unsigned)n_items), dim3(256), 0, s, ms, bs, items);
-  return hipGetLastError();
+  return launch_k(k_merge_batch, dim3((unsigned)n_items), dim3(256), s, ms, bs, items);
 }
 
 hipError_t launch_anc_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                             int64_t n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_anc_batch, dim3((unsigned)n_items), dim3(256), 0, s, ms, bs, items);
-  return hipGetLastError();
+  return launch_k(k_anc_batch, dim3((unsigned)n_items), dim3(256), s, ms, bs, items);
 }
 
 hipError_t launch_fill_batch(const Model* ms, const Buffers* bs, const int32_t* tracks,
                              int32_t n_tracks, hipStream_t s) {
   if (n_tracks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_batch, dim3(kFillGridBatch, (unsigned)n_tracks), dim3(256), 0, s, ms,
-                     bs, tracks);
-  return hipGetLastError();
+  return launch_k(k_fill_batch, dim3(kFillGridBatch, (unsigned)n_tracks), dim3(256), s, ms, bs,
+                  tracks);
 }
 
 hipError_t launch_rna_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                             int64_t n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rna_batch, dim3((unsigned)n_items), dim3(256), 0, s, ms, bs, items);
-  return hipGetLastError();
+  return launch_k(k_rna_batch, dim3((unsigned)n_items), dim3(256), s, ms, bs, items);
 }
 
 hipError_t launch_rpa(const Model& m, const Buffers& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_rpa_first, dim3(grid_for((int64_t)m.rpa_G + 1, 256)), dim3(256), 0, s, m,
-                     b);
-  if (m.dlb == 1)
-    hipLaunchKernelGGL(k_rpa_rank,
-                       dim3(grid_for(m.rpa_G, 256), grid_for(m.rpa_G, 1024), 2), dim3(256), 0, s,
-                       m, b);
-  hipLaunchKernelGGL(k_rpa_plan, dim3(1), dim3(256), 0, s, m, b);
-  hipLaunchKernelGGL(k_rpa_route, dim3(grid_for(m.n, 256)), dim3(256), 0, s, m, b);
-  return hipGetLastError();
+  hipError_t e =
+      launch_k(k_rpa_first, dim3(grid_for((int64_t)m.rpa_G + 1, 256)), dim3(256), s, m, b);
+  if (e == hipSuccess && m.dlb == 1)
+    e = launch_k(k_rpa_rank, dim3(grid_for(m.rpa_G, 256), grid_for(m.rpa_G, 1024), 2), dim3(256),
+                 s, m, b);
+  if (e == hipSuccess) e = launch_k(k_rpa_plan, dim3(1), dim3(256), s, m, b);
+  if (e == hipSuccess) e = launch_k(k_rpa_route, dim3(grid_for(m.n, 256)), dim3(256), s, m, b);
+  return e;
 }
 
 hipError_t launch_dlb_schedule(int32_t kind, const int32_t* counts, int32_t G, int32_t n,
                                int32_t* sched, int32_t cap, int32_t* n_entries, hipStream_t s) {
-  hipLaunchKernelGGL(k_dlb_schedule, dim3(1), dim3(256), 0, s, kind, counts, G, n, sched, cap,
-                     n_entries);
-  return hipGetLastError();
+  return launch_k(k_dlb_schedule, dim3(1), dim3(256), s, kind, counts, G, n, sched, cap,
+                  n_entries);
 }
 
 hipError_t launch_merge(const Model& m, const Buffers& b, int standalone, double u_given,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_merge, dim3((unsigned)b.nch), dim3(256), 0, s, m, b, standalone, u_given);
-  return hipGetLastError();
+  return launch_k(k_merge, dim3((unsigned)b.nch), dim3(256), s, m, b, standalone, u_given);
 }
 
 hipError_t launch_anc(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_anc, dim3((unsigned)b.nseg), dim3(256), 0, s, m, b, w);
-  return hipGetLastError();
+  return launch_k(k_anc, dim3((unsigned)b.nseg), dim3(256), s, m, b, w);
 }
 
 hipError_t launch_fill(const Model& m, const Buffers& b, hipStream_t s) {
   const unsigned grid = (unsigned)(b.hq_cap < kFillGrid ? b.hq_cap : kFillGrid);
-  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, s, m, b);
-  return hipGetLastError();
+  return launch_k(k_fill, dim3(grid), dim3(256), s, m, b);
 }
 
 hipError_t launch_rna(const Model& m, const Buffers& b, const WeightSrc& w, const double* u_dev,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_rna, dim3((unsigned)m.G), dim3(256), 0, s, m, b, w, u_dev);
-  return hipGetLastError();
+  return launch_k(k_rna, dim3((unsigned)m.G), dim3(256), s, m, b, w, u_dev);
 }
 
 hipError_t launch_gather(const Model& m, const Buffers& b, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather, dim3(grid_for(m.n, 256)), dim3(256), 0, s, m, b, out);
-  return hipGetLastError();
+  return launch_k(k_gather, dim3(grid_for(m.n, 256)), dim3(256), s, m, b, out);
 }
 
 hipError_t launch_logw(const Model& m, const Buffers& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_logw, dim3(grid_for(m.n, 256)), dim3(256), 0, s, m, b);
-  return hipGetLastError();
+  return launch_k(k_logw, dim3(grid_for(m.n, 256)), dim3(256), s, m, b);
 }
 
 hipError_t launch_set_mode(const Buffers& b, int32_t mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_mode, dim3(1), dim3(1), 0, s, b.ctrl, mode);
-  return hipGetLastError();
+  return launch_k(k_set_mode, dim3(1), dim3(1), s, b.ctrl, mode);
 }
 
 hipError_t launch_records(const Model& m, const Buffers& b, const float* logw, hipStream_t s) {
-  hipLaunchKernelGGL(k_records, dim3((unsigned)b.nb), dim3(kBlock), 0, s, m, b, logw);
-  return hipGetLastError();
+  return launch_k(k_records, dim3((unsigned)b.nb), dim3(kBlock), s, m, b, logw);
 }
 
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
                          hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_philox, dim3(grid_for(n, 256)), dim3(256), 0, s, (uint32_t)seed,
-                     (uint32_t)(seed >> 32), reinterpret_cast<const uint4*>(ctr),
-                     reinterpret_cast<uint4*>(out), n);
-  return hipGetLastError();
+  return launch_k(k_philox, dim3(grid_for(n, 256)), dim3(256), s, (uint32_t)seed,
+                  (uint32_t)(seed >> 32), reinterpret_cast<const uint4*>(ctr),
+                  reinterpret_cast<uint4*>(out), n);
 }
 
 }  // namespace ppf

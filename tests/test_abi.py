@@ -129,6 +129,8 @@ def test_batch_and_grad_argument_checks():
                                                                    height=64))
     assert ppf.lib().ppf_grad(None, None, None) == ppf.PPF_ESTATE
     assert ppf.lib().ppf_step_batched(None, None) == ppf.PPF_ESTATE
+    assert ppf.lib().ppf_set_graph(None, 1) == ppf.PPF_ESTATE
+    assert ppf.lib().ppf_batch_set_graph(None, 1) == ppf.PPF_ESTATE
 
 
 def test_product_package_never_imports_the_oracle():
