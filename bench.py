@@ -169,7 +169,7 @@ def run_multitrack(args, w):
     frames = torch.from_numpy(mv.frames).cuda()
     b = ppf.Batch(ps)
     graph = args.launch == "graph"
-    gpu_ms, wall, kt = timed_steps(torch, b, frames, K, Wm, T, graph)
+    gpu_ms, wall, kt, tuned = timed_steps(torch, b, frames, K, Wm, T, graph, not args.no_autotune)
     sts = b.stats()
     ntot = sum(int(p.n_particles) for p in ps)
     flops = sum(4 * ppf.patch_size(p) ** 2 * int(p.n_particles) for p in ps)
@@ -195,7 +195,7 @@ def run_multitrack(args, w):
                    "n_max": max(int(p.n_particles) for p in ps),
                    "patches": sorted({ppf.patch_size(p) for p in ps}),
                    "frame": [w["W"], w["H"]], "resampling": "systematic", "frames_timed": K,
-                   "launch": args.launch},
+                   "launch": args.launch, "autotune": tuned},
         "roofline": {"bound": "alu", "kernel": "k_step (all patch sizes)",
                      "achieved": achieved_tf, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
@@ -223,16 +223,27 @@ def make_params(ppf, w, init_kind, grad=0):
                       rna_group=group, dlb=dlb)
 
 
-def timed_steps(torch, f, frames, K, Wm, T, graph):
+def timed_steps(torch, f, frames, K, Wm, T, graph, tune):
     """K steps of filter or batch f from a fresh initial cloud, after Wm
     warm-up steps: (GPU ms of the K steps between two events on f's stream,
-    wall s, per-kernel times). With graph=True the timed steps replay the
-    step's HIP graph (recorded in the warm-up), and the per-kernel times come
-    from a second pass over the same K steps with plain launches and kernel
-    timing on (the two exclude each other)."""
+    wall s, per-kernel times, autotuner result or None). With tune=True the
+    autotuner picks the step kernel's workgroup shape on the warm filter two
+    steps before the end of the warm-up (so that a graph is recorded again
+    before the timed steps). With graph=True the timed steps replay the
+    step's HIP graph, and the per-kernel times come from a second pass over
+    the same K steps with plain launches and kernel timing on (the two
+    exclude each other)."""
     f.graph(graph)
+    tuned = None
+    tune_at = max(Wm - 2, 0)
     for k in range(Wm):
         f.step(frames[k % T])
+        if tune and k == tune_at:
+            ms, chosen = f.autotune(frames[(k + 1) % T], reps=5)
+            tuned = {"ms_per_launch": ms, "chosen": chosen}
+    if tune and tuned is None:
+        ms, chosen = f.autotune(frames[0], reps=5)
+        tuned = {"ms_per_launch": ms, "chosen": chosen}
     f.reset()
     torch.cuda.synchronize()
     if not graph:
@@ -256,26 +267,7 @@ def timed_steps(torch, f, frames, K, Wm, T, graph):
         for k in range(K):
             f.step(frames[k % T])
     kt = f.kernel_times()
-    return gpu_ms, wall, kt
-
-
-def time_filter(ppf, torch, p, frames, K, Wm, T):
-    """(ms of K steps after Wm warm-up steps and a reset, kernel times, filter)."""
-    f = ppf.Filter(p)
-    for k in range(Wm):
-        f.step(frames[k % T])
-    f.reset()
-    f.sync()
-    torch.cuda.synchronize()
-    f.profile(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(f.stream)
-    for k in range(K):
-        f.step(frames[k % T])
-    ev1.record(f.stream)
-    torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1), f.kernel_times(), f
+    return gpu_ms, wall, kt, tuned
 
 
 def cpu_baseline(w, frames, sample_n, sample_t, init_kind):
@@ -310,6 +302,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="stream", choices=["stream", "graph"],
                     help="timed steps as plain launches or as replays of one HIP graph")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default step-kernel workgroup shape")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -358,13 +352,14 @@ def main():
     plain = None
     if w.get("grad"):
         # the same configuration without derivatives, for the ratio
-        pms, pkt, pf = time_filter(ppf, torch, make_params(ppf, w, init_kind), frames, K, Wm, T)
+        pf = ppf.Filter(make_params(ppf, w, init_kind))
+        pms, _, pkt, _ = timed_steps(torch, pf, frames, K, Wm, T, False, not args.no_autotune)
         pf.close()
         plain = {"value": w["n"] * K / (pms / 1e3), "ms_per_step": pms / K,
                  "k_step_ms": pkt.get("k_step", (1, 0.0))[1] / K}
     f = ppf.Filter(make_params(ppf, w, init_kind, grad=w.get("grad", 0)))
     graph = args.launch == "graph"
-    gpu_ms, wall, kt = timed_steps(torch, f, frames, K, Wm, T, graph)
+    gpu_ms, wall, kt, tuned = timed_steps(torch, f, frames, K, Wm, T, graph, not args.no_autotune)
     st = f.stats()
     err = float(np.linalg.norm(st["mean"][:2] - mv.truth[(K - 1) % T, 0]))
     n = w["n"]
@@ -402,7 +397,8 @@ def main():
                    "resampling": ({0: "systematic", 1: "RNA", 2: "RPA"}[w.get("scheme", (0,))[0]]
                                   + ("" if w["thr"] == float("inf")
                                      else f" when ESS < {w['thr']:.0f}")),
-                   "init": args.init, "frames_timed": K, "launch": args.launch},
+                   "init": args.init, "frames_timed": K, "launch": args.launch,
+                   "autotune": tuned},
         "roofline": {"bound": "alu", "kernel": "k_step", "achieved": achieved_tf,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,

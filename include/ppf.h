@@ -236,6 +236,45 @@ int ppf_step(ppf_handle h, const float* obs_dev);
  */
 int ppf_set_graph(ppf_handle h, int enable);
 
+/*
+ * Workgroup shapes of the spot-model step kernel for patches up to 13 x 13
+ * (larger patches and derivative mode have one kernel each):
+ *   0  LDS image tile of up to 2048 doubles, compiled for 5 waves per SIMD
+ *   1  tile of up to 1792 doubles, 6 waves per SIMD (six workgroups share a
+ *      CU, fewer registers per lane)
+ * Both compute the same likelihood; a workgroup whose patches span between
+ * 1792 and 2048 tile pixels reads them from the frame under shape 1 instead
+ * of from LDS, which sums the same terms in another order. Create selects
+ * shape 0.
+ */
+#define PPF_NUM_SHAPES 2
+/* Most tuning candidates any autotune call times (size of its ms_out). */
+#define PPF_TUNE_MAX 3
+
+/* Select the step kernel's workgroup shape (0 or 1, EINVAL otherwise);
+ * syncs the stream and drops a recorded graph. Has no effect where only one
+ * kernel exists (see above). */
+int ppf_set_shape(ppf_handle h, int32_t shape);
+
+/*
+ * Autotuner: time every workgroup shape of the step kernel on this filter's
+ * current particles and the frame obs_dev, and keep the fastest for the
+ * following steps. Each candidate runs the step kernel once untimed, then
+ * reps times between two HIP events on the handle's stream. The step kernel
+ * alone writes only the next state buffer, weights and records, so the
+ * committed step, its counter and statistics, and the next ppf_step are
+ * unchanged (the timed launches are not part of any step). Candidates:
+ * shapes 0 and 1 for a spot model with P <= 13 without derivatives, else
+ * the single kernel (one candidate, nothing changes).
+ *   reps     launches timed per candidate, 1..10000 (EINVAL otherwise)
+ *   ms_out   NULL or PPF_TUNE_MAX doubles: average ms per launch, by candidate
+ *   n_out    NULL or the number of candidates timed
+ *   chosen   NULL or the candidate kept
+ * Syncs; drops a recorded graph. EINVAL for a null frame.
+ */
+int ppf_autotune(ppf_handle h, const float* obs_dev, int32_t reps, double* ms_out,
+                 int32_t* n_out, int32_t* chosen);
+
 /* Wait for the handle's stream. Returns PPF_ENUMERIC if any step enqueued
  * since the last report was rolled back (and clears the report), else OK. */
 int ppf_sync(ppf_handle h);
@@ -426,6 +465,25 @@ int ppf_step_batched(ppf_batch h, const float* obs_dev);
  * of a batched step (one step launch for all patch sizes up to 13, one per
  * wider size, then the merge and resampling launches). */
 int ppf_batch_set_graph(ppf_batch h, int enable);
+
+/*
+ * Workgroup shapes of a batch's fused step launches, by candidate:
+ *   0  every track with P <= 13 in one launch of shape 0
+ *   1  every track with P <= 13 in one launch of shape 1
+ *   2  tracks with P <= 11 in a launch of shape 1, tracks with P = 13 in a
+ *      launch of shape 0
+ * (tracks with P > 13 keep a launch per size). EINVAL for another value.
+ * Re-orders the batch's step items on the device; syncs; drops a recorded
+ * graph. Create selects candidate 0.
+ */
+int ppf_batch_set_shapes(ppf_batch h, int32_t candidate);
+
+/* Autotuner of a batch, as ppf_autotune: times candidates 0 and 1 above,
+ * and 2 when the batch has tracks with P = 13 and with P < 13, on the
+ * batch's current particles and obs_dev (the step launches of every track,
+ * once untimed, then reps times), and keeps the fastest. */
+int ppf_batch_autotune(ppf_batch h, const float* obs_dev, int32_t reps, double* ms_out,
+                       int32_t* n_out, int32_t* chosen);
 
 /* Statistics of every track's last committed step (out: count entries, in
  * track order), as ppf_stats; syncs and clears the roll-back reports. */

@@ -30,6 +30,7 @@ DLB_MAX_SORTED = 4096
 OBS_SPOT, OBS_LINEAR_GAUSSIAN = 0, 1
 INIT_UNIFORM, INIT_GAUSSIAN, INIT_STRATIFIED = 0, 1, 2
 MAX_PATCH = 25
+NUM_SHAPES, TUNE_MAX = 2, 3  # step-kernel workgroup shapes; tuning candidates at most
 # theta of ppf_grad, in order
 GRAD_NAMES = ("psf_sigma", "background", "noise_sigma", "q_x", "q_y", "q_vx", "q_vy", "q_I", "I0")
 
@@ -108,6 +109,11 @@ _SIGS = {
     "ppf_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "ppf_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "ppf_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "ppf_set_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "ppf_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]),
     "ppf_sync": (ctypes.c_int, [ctypes.c_void_p]),
     "ppf_estimate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "ppf_loglik": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -145,6 +151,11 @@ _SIGS = {
     "ppf_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "ppf_step_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "ppf_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "ppf_batch_set_shapes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "ppf_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32)]),
     "ppf_batch_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats), ctypes.c_int32]),
     "ppf_batch_get_particles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p]),
@@ -346,6 +357,19 @@ class Filter:
         """Graph mode: steps replay one recorded HIP graph of their launches."""
         _check(lib().ppf_set_graph(self.handle, 1 if on else 0), self.handle)
 
+    def set_shape(self, shape: int):
+        """Workgroup shape of the step kernel (see PPF_NUM_SHAPES)."""
+        _check(lib().ppf_set_shape(self.handle, int(shape)), self.handle)
+
+    def autotune(self, obs, reps: int = 5):
+        """Times each step-kernel shape on the current particles and frame
+        `obs`, keeps the fastest; returns (ms per launch by candidate, chosen)."""
+        ms = (ctypes.c_double * TUNE_MAX)()
+        n, ch = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().ppf_autotune(self.handle, self._obs_ptr(obs), int(reps), ms,
+                                  ctypes.byref(n), ctypes.byref(ch)), self.handle)
+        return list(ms[:n.value]), ch.value
+
     # -- timing
     def profile(self, on: bool = True):
         _check(lib().ppf_profile_enable(self.handle, 1 if on else 0), self.handle)
@@ -414,8 +438,7 @@ class Batch:
     def _chk(self, rc):
         _check(rc, self.handle, lib().ppf_batch_last_error)
 
-    def step(self, obs):
-        """One step of every track on a device frame; async."""
+    def _obs_ptr(self, obs):
         t = self.torch
         if not isinstance(obs, t.Tensor) or obs.device.type != "cuda":
             raise TypeError("observation must be a CUDA tensor")
@@ -423,7 +446,11 @@ class Batch:
             raise TypeError("observation must be contiguous float32")
         if obs.numel() != self.ps[0].width * self.ps[0].height:
             raise ValueError("observation must be one H x W frame")
-        self._chk(lib().ppf_step_batched(self.handle, ctypes.c_void_p(obs.data_ptr())))
+        return ctypes.c_void_p(obs.data_ptr())
+
+    def step(self, obs):
+        """One step of every track on a device frame; async."""
+        self._chk(lib().ppf_step_batched(self.handle, self._obs_ptr(obs)))
 
     def reset(self):
         self._chk(lib().ppf_batch_reset(self.handle))
@@ -447,6 +474,19 @@ class Batch:
     def graph(self, on: bool = True):
         """Graph mode: batched steps replay one recorded HIP graph."""
         self._chk(lib().ppf_batch_set_graph(self.handle, 1 if on else 0))
+
+    def set_shapes(self, candidate: int):
+        """Workgroup shapes of the fused step launches (candidates 0-2)."""
+        self._chk(lib().ppf_batch_set_shapes(self.handle, int(candidate)))
+
+    def autotune(self, obs, reps: int = 5):
+        """Times the shape candidates on the current particles and frame
+        `obs`, keeps the fastest; returns (ms per step launches, chosen)."""
+        ms = (ctypes.c_double * TUNE_MAX)()
+        n, ch = ctypes.c_int32(), ctypes.c_int32()
+        self._chk(lib().ppf_batch_autotune(self.handle, self._obs_ptr(obs), int(reps), ms,
+                                           ctypes.byref(n), ctypes.byref(ch)))
+        return list(ms[:n.value]), ch.value
 
     def profile(self, on: bool = True):
         self._chk(lib().ppf_batch_profile_enable(self.handle, 1 if on else 0))

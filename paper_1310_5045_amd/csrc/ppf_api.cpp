@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -335,6 +336,26 @@ struct Runner {
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return PPF_OK;
   }
+  // Average ms of one call of launch() over reps calls, after one untimed
+  // call; syncs.
+  template <class F>
+  int time_launches(int reps, F&& launch, double* ms) {
+    hipEvent_t a = nullptr, z = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&z);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(a, stream);
+    for (int r = 0; e == hipSuccess && r < reps; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(z, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(z);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, z);
+    if (a) (void)hipEventDestroy(a);
+    if (z) (void)hipEventDestroy(z);
+    if (e != hipSuccess) return hip_fail(e, "timing a tuning candidate");
+    *ms = (double)t / reps;
+    return PPF_OK;
+  }
   int profile_enable(int on) {
     if (on && graph_on) return fail(PPF_ESTATE, "graph mode and kernel timing exclude each other");
     if (hipStreamSynchronize(stream) != hipSuccess) return fail(PPF_EDEVICE, "sync");
@@ -523,6 +544,55 @@ int ppf_step(ppf_handle h, const float* obs_dev) {
 int ppf_set_graph(ppf_handle h, int enable) {
   if (!h) return PPF_ESTATE;
   return h->graph_enable(enable);
+}
+
+int ppf_set_shape(ppf_handle h, int32_t shape) {
+  if (!h) return PPF_ESTATE;
+  if (shape < 0 || shape >= ppf::kNumShapes) return h->fail(PPF_EINVAL, "shape must be 0 or 1");
+  const hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "sync");
+  h->m.shape = shape;
+  h->graph.reset();
+  return PPF_OK;
+}
+
+namespace {
+void tune_report(const double* ms, int n, int best, double* ms_out, int32_t* n_out,
+                 int32_t* chosen) {
+  if (ms_out)
+    for (int c = 0; c < n; ++c) ms_out[c] = ms[c];
+  if (n_out) *n_out = n;
+  if (chosen) *chosen = best;
+}
+}  // namespace
+
+int ppf_autotune(ppf_handle h, const float* obs_dev, int32_t reps, double* ms_out,
+                 int32_t* n_out, int32_t* chosen) {
+  if (!h) return PPF_ESTATE;
+  if (!obs_dev) return h->fail(PPF_EINVAL, "null observation");
+  if (reps < 1 || reps > 10000) return h->fail(PPF_EINVAL, "reps must be in [1, 10000]");
+  // the step kernel alone writes only the next state, weights and records:
+  // the committed step, counter and statistics stay as they are
+  const bool shapes = h->m.obs == 0 && !h->m.grad && h->m.P <= ppf::kFusedMaxP;
+  const int n = shapes ? ppf::kNumShapes : 1;
+  const int keep = h->m.shape;
+  double ms[ppf::kNumShapes] = {};
+  for (int c = 0; c < n; ++c) {
+    if (shapes) h->m.shape = c;
+    const int rc = h->time_launches(
+        reps, [&] { return ppf::launch_step(h->m, h->b, obs_dev, h->stream); }, &ms[c]);
+    if (rc) {
+      h->m.shape = keep;
+      return rc;
+    }
+  }
+  int best = 0;
+  for (int c = 1; c < n; ++c)
+    if (ms[c] < ms[best]) best = c;
+  h->m.shape = shapes ? best : keep;
+  h->graph.reset();
+  tune_report(ms, n, best, ms_out, n_out, chosen);
+  return PPF_OK;
 }
 
 int ppf_sync(ppf_handle h) {
@@ -760,8 +830,13 @@ struct BatchPlan {
   std::vector<Buffers> bufs;
   std::vector<ppf::BatchItem> blocks, chunks, segs, groups;
   std::vector<int32_t> sys_tracks;
-  // patch size (0: every size up to kFusedMaxP) -> [first, count) of blocks
-  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> step_ranges;
+  struct StepRange {
+    int P;      // patch size; 0: sizes up to kFusedMaxP in one fused launch
+    int shape;  // workgroup shape of a fused launch
+    int64_t first, count;  // of blocks
+  };
+  std::vector<StepRange> step_ranges;
+  std::array<int, ppf::kFusedMaxP + 1> shape_of{};  // fused sizes' shapes
   size_t off_models = 0, off_bufs = 0, off_blocks = 0, off_chunks = 0, off_segs = 0,
          off_groups = 0, off_sys = 0, off_tracks = 0, total = 0;
   std::vector<size_t> track_off;
@@ -785,6 +860,38 @@ std::string validate_batch(const ppf_params* p, int32_t count) {
 }
 
 // Sizes, offsets and work lists of a batch (p already validated).
+// Step items: the sizes up to kFusedMaxP in one fused launch per workgroup
+// shape (shape_of[P]), then each wider size in a launch of its own; the
+// items of one size in track order.
+void order_steps(BatchPlan* bp, const std::array<int, ppf::kFusedMaxP + 1>& shape_of) {
+  const int32_t count = (int32_t)bp->models.size();
+  std::vector<int> sizes;
+  for (int32_t t = 0; t < count; ++t) sizes.push_back(bp->models[t].P);
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  bp->blocks.clear();
+  bp->step_ranges.clear();
+  bp->shape_of = shape_of;
+  auto add_size = [&](int P) {
+    for (int32_t t = 0; t < count; ++t)
+      if (bp->models[t].P == P)
+        for (int64_t j = 0; j < bp->bufs[t].nb; ++j) bp->blocks.push_back({t, (int32_t)j});
+  };
+  for (int sh = 0; sh < ppf::kNumShapes; ++sh) {
+    const int64_t first = (int64_t)bp->blocks.size();
+    for (int P : sizes)
+      if (P <= ppf::kFusedMaxP && shape_of[P] == sh) add_size(P);
+    const int64_t cnt = (int64_t)bp->blocks.size() - first;
+    if (cnt) bp->step_ranges.push_back({0, sh, first, cnt});
+  }
+  for (int P : sizes) {
+    if (P <= ppf::kFusedMaxP) continue;
+    const int64_t first = (int64_t)bp->blocks.size();
+    add_size(P);
+    bp->step_ranges.push_back({P, 0, first, (int64_t)bp->blocks.size() - first});
+  }
+}
+
 void plan_batch(const ppf_params* p, int32_t count, BatchPlan* bp) {
   bp->models.resize(count);
   bp->bufs.resize(count);
@@ -802,26 +909,7 @@ void plan_batch(const ppf_params* p, int32_t count, BatchPlan* bp) {
     bp->models[t] = make_model(&p[t]);
     carve(&p[t], nullptr, &bp->bufs[t], false);
   }
-  // step items grouped by patch size: the sizes up to kFusedMaxP in one
-  // launch (range key 0), each wider size in a launch of its own
-  std::vector<int> sizes;
-  for (int32_t t = 0; t < count; ++t) sizes.push_back(bp->models[t].P);
-  std::sort(sizes.begin(), sizes.end());
-  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
-  int64_t first = 0;
-  for (int P : sizes) {
-    if (P > ppf::kFusedMaxP) first = (int64_t)bp->blocks.size();
-    for (int32_t t = 0; t < count; ++t)
-      if (bp->models[t].P == P)
-        for (int64_t j = 0; j < bp->bufs[t].nb; ++j) bp->blocks.push_back({t, (int32_t)j});
-    const int64_t cnt = (int64_t)bp->blocks.size() - first;
-    if (P <= ppf::kFusedMaxP) {
-      if (bp->step_ranges.empty()) bp->step_ranges.push_back({0, {first, cnt}});
-      else bp->step_ranges.back().second.second = cnt;
-    } else {
-      bp->step_ranges.push_back({P, {first, cnt}});
-    }
-  }
+  order_steps(bp, bp->shape_of);
   for (int32_t t = 0; t < count; ++t) {
     for (int64_t j = 0; j < bp->bufs[t].nch; ++j) bp->chunks.push_back({t, (int32_t)j});
     if (p[t].resample == PPF_RESAMPLE_RNA) {
@@ -858,6 +946,35 @@ struct ppf_batch_ctx : Runner {
       return ppf::launch_init_batch(d_models, d_bufs, d_blocks, (int64_t)plan.blocks.size(),
                                     stream);
     });
+  }
+  // The step launches of every track (one range after another).
+  hipError_t launch_steps(const float* obs) {
+    hipError_t e = hipSuccess;
+    for (const auto& r : plan.step_ranges) {
+      const ppf::BatchItem* it = d_blocks + r.first;
+      e = r.P == 0 ? ppf::launch_step_batch_fused(r.shape, d_models, d_bufs, it, r.count, obs,
+                                                  stream)
+                   : ppf::launch_step_batch(r.P, d_models, d_bufs, it, r.count, obs, stream);
+      if (e != hipSuccess) break;
+    }
+    return e;
+  }
+  // Fused step launches per tuning candidate: 0 every fused size in shape 0,
+  // 1 all in shape 1, 2 sizes below kFusedMaxP in shape 1 and kFusedMaxP
+  // itself in shape 0. Re-orders the step items on the device; syncs.
+  int set_shapes(int cand) {
+    if (cand < 0 || cand > 2) return fail(PPF_EINVAL, "shape candidate must be 0, 1 or 2");
+    std::array<int, ppf::kFusedMaxP + 1> sh{};
+    for (int P = 0; P <= ppf::kFusedMaxP; ++P)
+      sh[P] = cand == 0 ? 0 : (cand == 1 ? 1 : (P < ppf::kFusedMaxP ? 1 : 0));
+    order_steps(&plan, sh);
+    hipError_t e = hipMemcpyAsync(base + plan.off_blocks, plan.blocks.data(),
+                                  sizeof(ppf::BatchItem) * plan.blocks.size(),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "uploading the step items");
+    graph.reset();
+    return PPF_OK;
   }
 };
 
@@ -940,17 +1057,8 @@ int ppf_batch_reset(ppf_batch h) {
 namespace {
 int enqueue_batch_step(ppf_batch h, const float* obs_dev) {
   const BatchPlan& bp = h->plan;
-  for (const auto& r : bp.step_ranges) {
-    const int rc = h->run(kKStep, [&] {
-      const ppf::BatchItem* it = h->d_blocks + r.second.first;
-      return r.first == 0
-                 ? ppf::launch_step_batch_fused(h->d_models, h->d_bufs, it, r.second.second,
-                                                obs_dev, h->stream)
-                 : ppf::launch_step_batch(r.first, h->d_models, h->d_bufs, it, r.second.second,
-                                          obs_dev, h->stream);
-    });
-    if (rc) return rc;
-  }
+  const int rc0 = h->run(kKStep, [&] { return h->launch_steps(obs_dev); });
+  if (rc0) return rc0;
   int rc = h->run(kKMerge, [&] {
     return ppf::launch_merge_batch(h->d_models, h->d_bufs, h->d_chunks,
                                    (int64_t)bp.chunks.size(), h->stream);
@@ -986,6 +1094,37 @@ int ppf_step_batched(ppf_batch h, const float* obs_dev) {
 int ppf_batch_set_graph(ppf_batch h, int enable) {
   if (!h) return PPF_ESTATE;
   return h->graph_enable(enable);
+}
+
+int ppf_batch_set_shapes(ppf_batch h, int32_t candidate) {
+  if (!h) return PPF_ESTATE;
+  return h->set_shapes(candidate);
+}
+
+int ppf_batch_autotune(ppf_batch h, const float* obs_dev, int32_t reps, double* ms_out,
+                       int32_t* n_out, int32_t* chosen) {
+  if (!h) return PPF_ESTATE;
+  if (!obs_dev) return h->fail(PPF_EINVAL, "null observation");
+  if (reps < 1 || reps > 10000) return h->fail(PPF_EINVAL, "reps must be in [1, 10000]");
+  bool top = false, below = false;
+  for (const Model& m : h->plan.models) {
+    top = top || m.P == ppf::kFusedMaxP;
+    below = below || m.P < ppf::kFusedMaxP;
+  }
+  const int n = (top && below) ? 3 : 2;
+  double ms[3] = {};
+  for (int c = 0; c < n; ++c) {
+    int rc = h->set_shapes(c);
+    if (!rc) rc = h->time_launches(reps, [&] { return h->launch_steps(obs_dev); }, &ms[c]);
+    if (rc) return rc;
+  }
+  int best = 0;
+  for (int c = 1; c < n; ++c)
+    if (ms[c] < ms[best]) best = c;
+  const int rc = h->set_shapes(best);
+  if (rc) return rc;
+  tune_report(ms, n, best, ms_out, n_out, chosen);
+  return PPF_OK;
 }
 
 int ppf_batch_stats(ppf_batch h, ppf_stats_t* out, int32_t count) {

@@ -13,10 +13,19 @@ namespace ppf {
 // Particles per k_step workgroup; also the granularity of the per-block
 // normalisation records and of the stored log-weight offsets.
 constexpr int kBlock = 256;
-// LDS image tile of one k_step workgroup (D = Z - b as doubles) and its
-// table of P-pixel row sums of D^2 at the patch-centre columns (doubles).
+// LDS image tile of one k_step workgroup (D = Z - b as doubles; this is the
+// widest) and its table of P-pixel row sums of D^2 at the patch-centre
+// columns (doubles).
 constexpr int kTileCap = 2048;
 constexpr int kSqCap = 1536;
+// Workgroup shapes of the step kernel for patches up to kFusedMaxP: shape s
+// stages a tile of up to kShapeTile[s] doubles and is compiled for
+// kShapeWaves[s] waves per SIMD, which its LDS lets as many workgroups share
+// a CU with. Which is faster depends on the patch size (register demand
+// grows with it); the autotuner measures them on the live workload.
+constexpr int kNumShapes = 2;
+constexpr int kShapeTile[kNumShapes] = {2048, 1792};
+constexpr int kShapeWaves[kNumShapes] = {5, 6};
 constexpr int kMaxPatch = 25;
 constexpr int kMaxGroup = 1024;
 
@@ -137,6 +146,7 @@ struct Model {
   int32_t dlb;           // its schedule (0 greedy, 1 sorted greedy)
   int32_t rpa_group;     // particles per RPA group
   int32_t rpa_G;         // RPA groups
+  int32_t shape;         // step workgroup shape (patches up to kFusedMaxP)
   double s_psf;          // s
   double sig;            // sigma_xi
 };
@@ -216,11 +226,14 @@ hipError_t launch_dlb_schedule(int32_t kind, const int32_t* counts, int32_t G, i
 // the tracks' models and buffers, items the device list of work items.
 hipError_t launch_init_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                              int64_t n_items, hipStream_t s);
+// Items of one patch size above kFusedMaxP.
 hipError_t launch_step_batch(int P, const Model* ms, const Buffers* bs, const BatchItem* items,
                              int64_t n_items, const float* obs, hipStream_t s);
-// All items with patch sizes up to kFusedMaxP, whatever their size, in one launch.
-hipError_t launch_step_batch_fused(const Model* ms, const Buffers* bs, const BatchItem* items,
-                                   int64_t n_items, const float* obs, hipStream_t s);
+// Items with patch sizes up to kFusedMaxP, whatever their size, in one
+// launch of the given workgroup shape.
+hipError_t launch_step_batch_fused(int shape, const Model* ms, const Buffers* bs,
+                                   const BatchItem* items, int64_t n_items, const float* obs,
+                                   hipStream_t s);
 hipError_t launch_merge_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                               int64_t n_items, hipStream_t s);
 hipError_t launch_anc_batch(const Model* ms, const Buffers* bs, const BatchItem* items,

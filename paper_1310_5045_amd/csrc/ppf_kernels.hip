@@ -597,14 +597,15 @@ __device__ __forceinline__ double finish_block(const Buffers& b, int cur, int64_
 // LDS of one step workgroup: the tile of D = Z - b (its first 7 x 256
 // doubles double as the record exchange), the table of row sums of D^2, and
 // the reduction scratch. Kernels that run several patch sizes declare it once.
+template <int TILE>
 struct StepLds {
-  __align__(16) double tile[kTileCap];
+  static_assert(TILE >= 7 * kBlock, "the tile doubles as the record exchange buffer");
+  __align__(16) double tile[TILE];
   double sq[kSqCap];
   double dsh[4];
   int ish[16];
   int ksh[4];
 };
-static_assert(kTileCap >= 7 * kBlock, "the tile doubles as the record exchange buffer");
 
 // Patch sums of one particle over P rows of an LDS tile of D = Z - b (0
 // outside the frame) with row stride tw:
@@ -748,10 +749,10 @@ __device__ __forceinline__ void patch_moments(const double* __restrict__ p0, int
 // instead of squaring P^2 pixels.
 // Five barriers per workgroup: the box, the tile, the table, the block
 // maximum, and the record exchange.
-template <int P, bool GRAD = false>
+template <int P, bool GRAD = false, int TILE = kTileCap>
 __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
                                           const float* __restrict__ obs, int64_t blk,
-                                          StepLds& L) {
+                                          StepLds<TILE>& L) {
   constexpr int h = (P - 1) / 2;
   double* const tile = L.tile;
   double* const sq = L.sq;
@@ -848,7 +849,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   const int mny = min(min(ish[8], ish[9]), min(ish[10], ish[11]));
   const int mxy = max(max(ish[12], ish[13]), max(ish[14], ish[15]));
   const int64_t tw64 = (int64_t)mxx - mnx + P, th64 = (int64_t)mxy - mny + P;
-  const bool use_lds = tw64 * th64 <= kTileCap;  // uniform across the workgroup
+  const bool use_lds = tw64 * th64 <= TILE;  // uniform across the workgroup
   const int tw = (int)tw64, th = (int)th64;
   const int tx0 = mnx - h, ty0 = mny - h;
   const int64_t acx = (int64_t)mxx - mnx + 1;
@@ -861,7 +862,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   int ts = tw;
   {
     const int padw = ((int)(acx & 15) - (tw & 15)) & 15;
-    if ((int64_t)(tw + padw) * th <= kTileCap) ts = tw + padw;
+    if ((int64_t)(tw + padw) * th <= TILE) ts = tw + padw;
   }
   if (use_lds) {
     // one pass over the tile's pixels (row r = e / tw from a float reciprocal,
@@ -985,17 +986,17 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
 
 // Patches up to 13 x 13 fit five waves per SIMD in registers without
 // spilling; wider ones keep the compiler's default budget.
-template <int P>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+template <int P, int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kShapeWaves[S])))
 void k_step_spot(Model m, Buffers b, const float* __restrict__ obs) {
-  __shared__ StepLds L;
-  step_spot<P>(m, b, obs, blockIdx.x, L);
+  __shared__ StepLds<kShapeTile[S]> L;
+  step_spot<P, false, kShapeTile[S]>(m, b, obs, blockIdx.x, L);
 }
 
 template <int P>
 __global__ __launch_bounds__(256) void k_step_spot_wide(Model m, Buffers b,
                                                         const float* __restrict__ obs) {
-  __shared__ StepLds L;
+  __shared__ StepLds<kTileCap> L;
   step_spot<P>(m, b, obs, blockIdx.x, L);
 }
 
@@ -1003,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_step_spot_wide(Model m, Buffers b,
 template <int P>
 __global__ __launch_bounds__(256) void k_step_spot_grad(Model m, Buffers b,
                                                         const float* __restrict__ obs) {
-  __shared__ StepLds L;
+  __shared__ StepLds<kTileCap> L;
   step_spot<P, true>(m, b, obs, blockIdx.x, L);
 }
 
@@ -1948,41 +1949,35 @@ __global__ __launch_bounds__(256) void k_init_batch(const Model* __restrict__ ms
 }
 
 template <int P>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
-void k_step_batch(const Model* __restrict__ ms, const Buffers* __restrict__ bs,
-                  const BatchItem* __restrict__ items, const float* __restrict__ obs) {
-  __shared__ StepLds L;
-  const BatchItem it = items[blockIdx.x];
-  step_spot<P>(ms[it.track], bs[it.track], obs, it.idx, L);
-}
-
-template <int P>
 __global__ __launch_bounds__(256) void k_step_batch_wide(const Model* __restrict__ ms,
                                                          const Buffers* __restrict__ bs,
                                                          const BatchItem* __restrict__ items,
                                                          const float* __restrict__ obs) {
-  __shared__ StepLds L;
+  __shared__ StepLds<kTileCap> L;
   const BatchItem it = items[blockIdx.x];
   step_spot<P>(ms[it.track], bs[it.track], obs, it.idx, L);
 }
 
-// Every patch size up to kFusedMaxP in one launch: each workgroup takes its
-// item's patch size (uniform across the workgroup) and shares one LDS block.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+// Every patch size up to kFusedMaxP in one launch of workgroup shape S: each
+// workgroup takes its item's patch size (uniform across the workgroup) and
+// shares one LDS block.
+template <int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kShapeWaves[S])))
 void k_step_batch_fused(const Model* __restrict__ ms, const Buffers* __restrict__ bs,
                         const BatchItem* __restrict__ items, const float* __restrict__ obs) {
-  __shared__ StepLds L;
+  constexpr int T = kShapeTile[S];
+  __shared__ StepLds<T> L;
   const BatchItem it = items[blockIdx.x];
   const Model& m = ms[it.track];
   const Buffers& b = bs[it.track];
   switch (m.P) {
-    case 1: step_spot<1>(m, b, obs, it.idx, L); break;
-    case 3: step_spot<3>(m, b, obs, it.idx, L); break;
-    case 5: step_spot<5>(m, b, obs, it.idx, L); break;
-    case 7: step_spot<7>(m, b, obs, it.idx, L); break;
-    case 9: step_spot<9>(m, b, obs, it.idx, L); break;
-    case 11: step_spot<11>(m, b, obs, it.idx, L); break;
-    case 13: step_spot<13>(m, b, obs, it.idx, L); break;
+    case 1: step_spot<1, false, T>(m, b, obs, it.idx, L); break;
+    case 3: step_spot<3, false, T>(m, b, obs, it.idx, L); break;
+    case 5: step_spot<5, false, T>(m, b, obs, it.idx, L); break;
+    case 7: step_spot<7, false, T>(m, b, obs, it.idx, L); break;
+    case 9: step_spot<9, false, T>(m, b, obs, it.idx, L); break;
+    case 11: step_spot<11, false, T>(m, b, obs, it.idx, L); break;
+    case 13: step_spot<13, false, T>(m, b, obs, it.idx, L); break;
     default: break;  // the host puts only these sizes in a fused launch
   }
 }
@@ -2100,7 +2095,10 @@ template <int P>
 hipError_t launch_spot(const Model& m, const Buffers& b, const float* obs, hipStream_t s) {
   const dim3 grid((unsigned)b.nb), block(kBlock);
   if (m.grad) return launch_k(k_step_spot_grad<P>, grid, block, s, m, b, obs);
-  if constexpr (P <= 13) return launch_k(k_step_spot<P>, grid, block, s, m, b, obs);
+  if constexpr (P <= kFusedMaxP) {
+    if (m.shape == 1) return launch_k(k_step_spot<P, 1>, grid, block, s, m, b, obs);
+    return launch_k(k_step_spot<P, 0>, grid, block, s, m, b, obs);
+  }
   return launch_k(k_step_spot_wide<P>, grid, block, s, m, b, obs);
 }
 
@@ -2109,9 +2107,8 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 template <int P>
 hipError_t launch_spot_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                              int64_t n_items, const float* obs, hipStream_t s) {
-  const dim3 grid((unsigned)n_items), block(kBlock);
-  if constexpr (P <= 13) return launch_k(k_step_batch<P>, grid, block, s, ms, bs, items, obs);
-  return launch_k(k_step_batch_wide<P>, grid, block, s, ms, bs, items, obs);
+  return launch_k(k_step_batch_wide<P>, dim3((unsigned)n_items), dim3(kBlock), s, ms, bs, items,
+                  obs);
 }
 
 }  // namespace
@@ -2203,31 +2200,26 @@ hipError_t launch_init_batch(const Model* ms, const Buffers* bs, const BatchItem
   return launch_k(k_init_batch, dim3((unsigned)n_items), dim3(kBlock), s, ms, bs, items);
 }
 
-hipError_t launch_step_batch_fused(const Model* ms, const Buffers* bs, const BatchItem* items,
-                                   int64_t n_items, const float* obs, hipStream_t s) {
+hipError_t launch_step_batch_fused(int shape, const Model* ms, const Buffers* bs,
+                                   const BatchItem* items, int64_t n_items, const float* obs,
+                                   hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  return launch_k(k_step_batch_fused, dim3((unsigned)n_items), dim3(kBlock), s, ms, bs, items,
-                  obs);
+  const dim3 grid((unsigned)n_items), block(kBlock);
+  if (shape == 1) return launch_k(k_step_batch_fused<1>, grid, block, s, ms, bs, items, obs);
+  return launch_k(k_step_batch_fused<0>, grid, block, s, ms, bs, items, obs);
 }
 
 hipError_t launch_step_batch(int P, const Model* ms, const Buffers* bs, const BatchItem* items,
                              int64_t n_items, const float* obs, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (P) {
-    case 1: return launch_spot_batch<1>(ms, bs, items, n_items, obs, s);
-    case 3: return launch_spot_batch<3>(ms, bs, items, n_items, obs, s);
-    case 5: return launch_spot_batch<5>(ms, bs, items, n_items, obs, s);
-    case 7: return launch_spot_batch<7>(ms, bs, items, n_items, obs, s);
-    case 9: return launch_spot_batch<9>(ms, bs, items, n_items, obs, s);
-    case 11: return launch_spot_batch<11>(ms, bs, items, n_items, obs, s);
-    case 13: return launch_spot_batch<13>(ms, bs, items, n_items, obs, s);
     case 15: return launch_spot_batch<15>(ms, bs, items, n_items, obs, s);
     case 17: return launch_spot_batch<17>(ms, bs, items, n_items, obs, s);
     case 19: return launch_spot_batch<19>(ms, bs, items, n_items, obs, s);
     case 21: return launch_spot_batch<21>(ms, bs, items, n_items, obs, s);
     case 23: return launch_spot_batch<23>(ms, bs, items, n_items, obs, s);
     case 25: return launch_spot_batch<25>(ms, bs, items, n_items, obs, s);
-    default: return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;  // sizes up to kFusedMaxP go to the fused launch
   }
 }
 

@@ -131,6 +131,10 @@ def test_batch_and_grad_argument_checks():
     assert ppf.lib().ppf_step_batched(None, None) == ppf.PPF_ESTATE
     assert ppf.lib().ppf_set_graph(None, 1) == ppf.PPF_ESTATE
     assert ppf.lib().ppf_batch_set_graph(None, 1) == ppf.PPF_ESTATE
+    assert ppf.lib().ppf_set_shape(None, 0) == ppf.PPF_ESTATE
+    assert ppf.lib().ppf_batch_set_shapes(None, 0) == ppf.PPF_ESTATE
+    assert ppf.lib().ppf_autotune(None, None, 1, None, None, None) == ppf.PPF_ESTATE
+    assert ppf.lib().ppf_batch_autotune(None, None, 1, None, None, None) == ppf.PPF_ESTATE
 
 
 def test_product_package_never_imports_the_oracle():

@@ -25,8 +25,9 @@ def ppf():
     return p
 
 
-def run_teacher_forced(ppf, p, m, obs_np, T, rna=False):
+def run_teacher_forced(ppf, p, m, obs_np, T, rna=False, shape=0):
     f = ppf.Filter(p)
+    f.set_shape(shape)
     n = m.n
     obs_t = torch.from_numpy(np.ascontiguousarray(obs_np)).cuda()
     prev, _ = snapshot(f, n, np.full(n, -math.log(n)))
@@ -86,6 +87,14 @@ def test_spot_systematic_every_step(ppf, movie128, n):
     rep = run_teacher_forced(ppf, p, m, movie128.frames, 6)
     print(rep)
     assert all(r[3] == 0 for r in rep), rep  # no mismatch beyond the 1e-10 band
+
+
+@pytest.mark.parametrize("n,s", [(5000, 1.5), (3001, 2.0)])
+def test_spot_workgroup_shape_1(ppf, movie128, n, s):
+    """The six-wave step kernel (1792-double tile) against the oracle."""
+    p, m = pair(ppf, n=n, **dict(SPOT, s=s))
+    rep = run_teacher_forced(ppf, p, m, movie128.frames, 5, shape=1)
+    assert all(r[3] == 0 for r in rep), rep
 
 
 def test_spot_stratified_patch13_ess_threshold(ppf):
