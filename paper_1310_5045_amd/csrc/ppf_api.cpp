@@ -1061,7 +1061,7 @@ int enqueue_batch_step(ppf_batch h, const float* obs_dev) {
   if (rc0) return rc0;
   int rc = h->run(kKMerge, [&] {
     return ppf::launch_merge_batch(h->d_models, h->d_bufs, h->d_chunks,
-                                   (int64_t)bp.chunks.size(), h->stream);
+                                   (int64_t)bp.chunks.size(), h->count, h->stream);
   });
   if (rc) return rc;
   if (!bp.segs.empty()) {

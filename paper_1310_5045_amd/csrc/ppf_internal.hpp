@@ -100,8 +100,7 @@ struct Ctrl {
   int32_t rolled_back;  // steps rolled back since the host last read this
   int32_t do_resample;  // set by the merge for the resampling kernels
   int32_t heavy_count;  // runs queued for k_fill
-  uint32_t ticket;      // arrival counter of the merge kernel's chunks
-  uint32_t pad0;
+  uint64_t pad0;
   double m, log_sum, ess, delta, cum;
   double mean[5];
   double u;             // uniform of the systematic resampling
@@ -234,8 +233,9 @@ hipError_t launch_step_batch(int P, const Model* ms, const Buffers* bs, const Ba
 hipError_t launch_step_batch_fused(int shape, const Model* ms, const Buffers* bs,
                                    const BatchItem* items, int64_t n_items, const float* obs,
                                    hipStream_t s);
+// The chunk merges (items), then one final merge per track.
 hipError_t launch_merge_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
-                              int64_t n_items, hipStream_t s);
+                              int64_t n_items, int32_t n_tracks, hipStream_t s);
 hipError_t launch_anc_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                             int64_t n_items, hipStream_t s);
 hipError_t launch_fill_batch(const Model* ms, const Buffers* bs, const int32_t* tracks,

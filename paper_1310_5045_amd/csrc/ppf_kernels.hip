@@ -373,7 +373,6 @@ __device__ __forceinline__ void init_body(const Model& m, const Buffers& b, int6
     c->rolled_back = 0;
     c->do_resample = 0;
     c->heavy_count = 0;
-    c->ticket = 0;
     c->m = c->log_sum = c->ess = c->delta = c->cum = 0.0;
     for (int d = 0; d < 5; ++d) c->mean[d] = 0.0;
     c->u = 0.0;
@@ -1046,7 +1045,6 @@ __global__ __launch_bounds__(256) void k_records(Model m, Buffers b,
     // the standalone scratch starts uninitialised: clear the counters and
     // flags the following kernels of this call rely on
     Ctrl* c = b.ctrl;
-    c->ticket = 0u;
     c->heavy_count = 0;
     c->do_resample = 0;
     c->total = 0;
@@ -1080,23 +1078,23 @@ __global__ __launch_bounds__(256) void k_records(Model m, Buffers b,
 }
 
 // ------------------------------------------------------------- k_merge
-// Each workgroup merges one chunk of block records relative to the chunk's
-// maximum: the chunk record, and per block the exclusive prefix of the
-// chunk's integer weights q_b = round(B_b exp(m_b - M_c)). The last workgroup
-// to arrive merges the chunk records in a fixed order, takes the statistics
-// of Algorithm 1 (normaliser, ESS, MMSE estimate), decides on resampling,
-// commits or rolls back the step, and for systematic resampling writes each
-// chunk's fixed-point CDF prefix.
-__device__ __forceinline__ void merge_body(const Model& m, const Buffers& b, int standalone,
-                                           double u_given, int64_t ch) {
+// Two launches. Each workgroup of the first merges one chunk of block
+// records relative to the chunk's maximum: the chunk record, and per block
+// the exclusive prefix of the chunk's integer weights q_b = round(B_b
+// exp(m_b - M_c)). One workgroup of the second merges the chunk records in a
+// fixed order, takes the statistics of Algorithm 1 (normaliser, ESS, MMSE
+// estimate), decides on resampling, commits or rolls back the step, and for
+// systematic resampling writes each chunk's fixed-point CDF prefix. (The
+// kernel boundary makes the chunk records visible to it: waiting for the
+// last chunk inside one launch costs a device-scope release and acquire in
+// every workgroup, which write back and invalidate that XCD's L2.)
+__device__ __forceinline__ void merge_chunk_body(const Model& m, const Buffers& b, int standalone,
+                                                 int64_t ch) {
   __shared__ double dsh[4];
   __shared__ double nsh[4 * 7];
   __shared__ double gsh[4 * kNGrad];
   __shared__ uint64_t ush[4];
-  __shared__ int sh_last;
-  __shared__ int sh_pre;
-  __shared__ double sh_delta;
-  Ctrl* c = b.ctrl;
+  const Ctrl* c = b.ctrl;
   const int t = threadIdx.x;
   const int which = standalone ? 0 : (c->cur ^ 1);  // the records this step wrote
   const double* R = which ? b.R1 : b.R0;
@@ -1153,19 +1151,21 @@ __device__ __forceinline__ void merge_body(const Model& m, const Buffers& b, int
 #pragma unroll
       for (int d = 0; d < kNGrad; ++d) b.CRG[ch * kNGrad + d] = gs[d];
   }
-  // arrival: the last workgroup finishes the step
-  __threadfence();
-  __syncthreads();
-  if (t == 0) sh_last = (atomicAdd(&c->ticket, 1u) == (uint32_t)(b.nch - 1));
-  __syncthreads();
-  if (!sh_last) return;
-  __threadfence();
+}
 
+__device__ __forceinline__ void merge_final_body(const Model& m, const Buffers& b, int standalone,
+                                                 double u_given) {
+  __shared__ double dsh[4];
+  __shared__ double nsh[4 * 7];
+  __shared__ double gsh[4 * kNGrad];
+  __shared__ uint64_t ush[4];
+  __shared__ int sh_pre;
+  __shared__ double sh_delta;
+  Ctrl* c = b.ctrl;
+  const int t = threadIdx.x;
   const int64_t nch = b.nch;
   const int per2 = (int)((nch + 255) / 256);
   const int64_t c0 = (int64_t)t * per2;
-  // the device-scope fence above orders these plain loads after every
-  // chunk's record (each chunk fenced before taking its ticket)
   const double* CRd = b.CR;
   auto ld = [&](int64_t idx) { return CRd[idx]; };
   double mx2 = -INFINITY;
@@ -1256,7 +1256,6 @@ __device__ __forceinline__ void merge_body(const Model& m, const Buffers& b, int
     }
     sh_pre = pre;
     sh_delta = c->delta;
-    c->ticket = 0u;
     c->heavy_count = 0;
   }
   __syncthreads();
@@ -1289,9 +1288,13 @@ __device__ __forceinline__ void merge_body(const Model& m, const Buffers& b, int
   if (t == 0) c->total = tot;
 }
 
-__global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalone,
-                                               double u_given) {
-  merge_body(m, b, standalone, u_given, blockIdx.x);
+__global__ __launch_bounds__(256) void k_merge(Model m, Buffers b, int standalone) {
+  merge_chunk_body(m, b, standalone, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_merge_final(Model m, Buffers b, int standalone,
+                                                     double u_given) {
+  merge_final_body(m, b, standalone, u_given);
 }
 
 // --------------------------------------------------- systematic resampling
@@ -1987,7 +1990,13 @@ __global__ __launch_bounds__(256) void k_merge_batch(const Model* __restrict__ m
                                                      const Buffers* __restrict__ bs,
                                                      const BatchItem* __restrict__ items) {
   const BatchItem it = items[blockIdx.x];
-  merge_body(ms[it.track], bs[it.track], 0, 0.0, it.idx);
+  merge_chunk_body(ms[it.track], bs[it.track], 0, it.idx);
+}
+
+// One workgroup per track.
+__global__ __launch_bounds__(256) void k_merge_final_batch(const Model* __restrict__ ms,
+                                                           const Buffers* __restrict__ bs) {
+  merge_final_body(ms[blockIdx.x], bs[blockIdx.x], 0, 0.0);
 }
 
 __global__ __launch_bounds__(256) void k_anc_batch(const Model* __restrict__ ms,
@@ -2224,9 +2233,12 @@ hipError_t launch_step_batch(int P, const Model* ms, const Buffers* bs, const Ba
 }
 
 hipError_t launch_merge_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
-                              int64_t n_items, hipStream_t s) {
+                              int64_t n_items, int32_t n_tracks, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  return launch_k(k_merge_batch, dim3((unsigned)n_items), dim3(256), s, ms, bs, items);
+  const hipError_t e = launch_k(k_merge_batch, dim3((unsigned)n_items), dim3(256), s, ms, bs,
+                                items);
+  if (e != hipSuccess) return e;
+  return launch_k(k_merge_final_batch, dim3((unsigned)n_tracks), dim3(256), s, ms, bs);
 }
 
 hipError_t launch_anc_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
@@ -2267,7 +2279,9 @@ hipError_t launch_dlb_schedule(int32_t kind, const int32_t* counts, int32_t G, i
 
 hipError_t launch_merge(const Model& m, const Buffers& b, int standalone, double u_given,
                         hipStream_t s) {
-  return launch_k(k_merge, dim3((unsigned)b.nch), dim3(256), s, m, b, standalone, u_given);
+  const hipError_t e = launch_k(k_merge, dim3((unsigned)b.nch), dim3(256), s, m, b, standalone);
+  if (e != hipSuccess) return e;
+  return launch_k(k_merge_final, dim3(1), dim3(256), s, m, b, standalone, u_given);
 }
 
 hipError_t launch_anc(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s) {
