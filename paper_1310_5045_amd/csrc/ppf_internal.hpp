@@ -49,7 +49,7 @@ constexpr double kItemToCdf = 0x1p18;
 constexpr int kSegBlocks = 8;
 constexpr int kSegItems = kSegBlocks * kBlock;
 constexpr int kCoopSlots = 1 << 16;
-constexpr int kSlotTile = 4096;  // slots per LDS tile of the segment's writes
+constexpr int kSlotTile = 2048;  // slots per LDS tile of the segment's writes
 constexpr int kFillChunk = 1 << 16;
 constexpr int kFillGrid = 2048;
 constexpr int kFillGridBatch = 64;  // workgroups per track of a batched fill

@@ -1322,25 +1322,63 @@ __device__ __forceinline__ int slot_bound(double C, double u, double nd, int n) 
   const double x = ceil(fma(C, nd, -u));
   return x <= 0.0 ? 0 : (x >= nd ? n : (int)x);
 }
+// The same count clamped to [lo, hi] with 0 <= lo <= hi <= n (the clamp to
+// [0, n] above is then implied); lo and hi as doubles.
+__device__ __forceinline__ int slot_bound_in(double C, double u, double nd, double lo,
+                                             double hi) {
+  return (int)fmin(fmax(ceil(fma(C, nd, -u)), lo), hi);
+}
 
-__device__ __forceinline__ int slot_pad(int e) { return e + (e >> 4); }
+// Slot e of a tile lives at slot_pad(e), one spare word after every 8, so
+// that a thread walking its own 8 consecutive slots (lanes 8 words apart
+// become 9 apart) and the threads of a wave walking consecutive slots both
+// meet distinct banks.
+__device__ __forceinline__ int slot_pad(int e) { return e + (e >> 3); }
+constexpr int kSlotsPerThread = kSlotTile / 256;
+static_assert(kSlotsPerThread == 8, "slot_pad spaces one thread's slots");
 
 struct AncShared {
-  // owner marks of one tile of slots, then their running maximum; slot e
-  // lives at slot_pad(e), one spare word after every 16, so that a thread
-  // walking its own 16 consecutive slots and the threads of a wave walking
-  // consecutive slots both meet distinct banks
-  int A[kSlotTile + kSlotTile / 16];
-  double Pb[kSegBlocks + 1];
-  double d4[4];
-  int i4[4];
-  int i8[4];
+  // owner marks of one tile of slots, then their running maximum
+  int A[kSlotTile + kSlotTile / 8];
+  double Pb[kSegBlocks + 1];  // CDF at the segment's block starts
+  double fb[kSegBlocks];      // blocks' factors from integer weights to the CDF
+  double mb[kSegBlocks];      // blocks' maximum log weights
+  int w4[4];                  // per-wave maxima of the scans
+  int l4[4];                  // per-wave last particles of positive weight
 };
+
+// Inclusive maximum scan over the wave of values >= 0 (each DPP step folds
+// into one v_max_i32: row shifts, whose lanes outside the row read 0, then
+// the row broadcasts into rows 1, 3 and into rows 2, 3). exclusive_of()
+// shifts an inclusive scan one lane up (lane 0 reads 0).
+__device__ __forceinline__ int wave_max_scan(int v) {
+  v = max(v, (int)dpp32<0x111>((uint32_t)v));
+  v = max(v, (int)dpp32<0x112>((uint32_t)v));
+  v = max(v, (int)dpp32<0x114>((uint32_t)v));
+  v = max(v, (int)dpp32<0x118>((uint32_t)v));
+  v = max(v, bcast<0x142, 0xa>(v, 0));
+  return max(v, bcast<0x143, 0xc>(v, 0));
+}
+__device__ __forceinline__ int exclusive_of(int inclusive) {
+  return (int)dpp32<0x138>((uint32_t)inclusive);  // wave_shr:1
+}
+
+// Inclusive sum within each pair of rows (32 lanes) of exact integers held
+// in doubles (lanes outside a row read 0, the identity).
+__device__ __forceinline__ double pair_row_scan_add(double v) {
+  v += shr<1>(v);
+  v += shr<2>(v);
+  v += shr<4>(v);
+  v += shr<8>(v);
+  return pair_rows(v, OpAdd(), 0.0);
+}
 
 // One workgroup per segment of kSegItems particles (eight consecutive per
 // thread): the segment's slot range from its block starts, the particles'
 // CDF from their fixed-point weights, every particle's run of slots, and
-// the slots' particles, written tile by tile.
+// the slots' particles, written tile by tile. Slot bounds are monotone in
+// the CDF, so the running maximum that keeps runs from overlapping is taken
+// over the integer bounds.
 __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const WeightSrc& ws,
                                          int64_t seg) {
   __shared__ AncShared sh;
@@ -1352,29 +1390,32 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
   // loads go out with its (in-bounds reads, discarded when nothing resamples)
   const int do_res = c->do_resample, cur = c->cur;
   const double delta = c->delta, u = c->u;
+  const bool second = ws.use_cur && cur;
+  const double* rec = second ? ws.rec1 : ws.rec0;
   const double pbt = (t <= nbs && b0 + t < b.nb) ? block_P(b, b0 + t) : 1.0;
+  const double mbt = t < nbs ? rec[(b0 + t) * kRec] : -INFINITY;
   if (!do_res) return;
+  if (t <= nbs) sh.Pb[t] = pbt;
+  if (t < nbs) {
+    sh.mb[t] = mbt;
+    sh.fb[t] = (mbt == -INFINITY) ? 0.0 : exp(mbt - delta) * (1.0 / kItemScale);
+  }
+  __syncthreads();
   const int n = (int)m.n;
   const double nd = (double)m.n;
-  if (t <= nbs) sh.Pb[t] = pbt;
-  __syncthreads();
   const int fs = seg == 0 ? 0 : slot_bound(sh.Pb[0], u, nd, n);
   const int fe = seg + 1 >= b.nseg ? n : slot_bound(sh.Pb[nbs], u, nd, n);
   if (fe <= fs) return;  // uniform: no slot falls in this segment
 
-  const bool second = ws.use_cur && cur;
   const float* E = second ? ws.E1 : ws.E0;
-  const double* rec = second ? ws.rec1 : ws.rec0;
   const int64_t ib0 = b0 * kBlock;
   const int64_t ib1 = min(m.n, (b0 + nbs) * kBlock);
   const int64_t j0 = ib0 + 8 * (int64_t)t;
   const bool mine = j0 < ib1;
+  const int lb = (t * 8) / kBlock;  // this thread's block within the segment
   double wi[8], kl[8];
   double tsum = 0.0;
-  double Pblk = 0.0, f = 0.0;
   if (mine) {
-    const int64_t blk = j0 / kBlock;
-    const double mblk = rec[blk * kRec];
     float x[8];
     // vector loads only from 16-byte aligned bases
     if (j0 + 8 <= ib1 && (reinterpret_cast<uintptr_t>(E) & 15) == 0) {
@@ -1388,6 +1429,7 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
         x[q] = (j0 + q < ib1) ? E[j0 + q] : (ws.log_src ? -INFINITY : 0.0f);
     }
     if (ws.log_src) {
+      const double mblk = sh.mb[lb];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         wi[q] = item_weight(x[q] == -INFINITY ? 0.0 : exp((double)x[q] - mblk));
@@ -1400,111 +1442,91 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
       tsum += wi[q];
       kl[q] = tsum;
     }
-    f = (mblk == -INFINITY) ? 0.0 : exp(mblk - delta) * (1.0 / kItemScale);
-    Pblk = sh.Pb[blk - b0];
   } else {
 #pragma unroll
     for (int q = 0; q < 8; ++q) wi[q] = kl[q] = 0.0;
   }
   // prefix of the block's integer weights before this thread's items: the
-  // 32 threads of a block are one half of a wave
-  double inc = row_scan(tsum, lane & 15, OpAdd());
-  const double r0 = readlane(inc, 15), r2 = readlane(inc, 47);
-  if ((lane >> 4) == 1) inc += r0;
-  else if ((lane >> 4) == 3) inc += r2;
-  const double texcl = inc - tsum;  // exact: integers below 2^53
-  double cq[8];
-  double tmax = 0.0;
-  int lp = -1;
+  // 32 threads of a block are one half of a wave (exact: integers < 2^53)
+  const double texcl = pair_row_scan_add(tsum) - tsum;
+  const double f = sh.fb[lb], Pblk = sh.Pb[lb];
+  // each particle's slot bound at its CDF value (0, below every bound, for
+  // a particle of zero weight), and the last particle of positive weight
+  int rb[8];
+  int tmax = 0, lp = -1;
+  const double fsd = (double)fs, fed = (double)fe;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    double v = 0.0;
-    if (wi[q] > 0.0) {
-      v = fma(texcl + kl[q], f, Pblk);
-      lp = 8 * t + q;
-    }
-    tmax = fmax(tmax, v);
-    cq[q] = v;
+    const int bq = slot_bound_in(fma(texcl + kl[q], f, Pblk), u, nd, fsd, fed);
+    rb[q] = wi[q] > 0.0 ? bq : 0;
+    lp = wi[q] > 0.0 ? 8 * t + q : lp;
+    tmax = max(tmax, rb[q]);
   }
-  // running maximum of the CDF across the threads, from the segment's start
-  const double winc = wave_scan(tmax, lane, OpMax());
-  double wex = __shfl_up(winc, 1, 64);
-  if (lane == 0) wex = 0.0;
-  if (lane == 63) sh.d4[w] = winc;
-  const int lpw = wave_reduce(lp, lane, OpMax());
-  if (lane == 0) sh.i4[w] = lpw;
+  const int winc = wave_max_scan(tmax);
+  const int wlp = wave_reduce_last(lp, OpMax(), -1);
+  if (lane == 63) {
+    sh.w4[w] = winc;
+    sh.l4[w] = wlp;
+  }
   __syncthreads();
-  double carry = sh.Pb[0];
-  for (int q = 0; q < w; ++q) carry = fmax(carry, sh.d4[q]);
-  carry = fmax(carry, wex);
-  const int last_pos = max(max(sh.i4[0], sh.i4[1]), max(sh.i4[2], sh.i4[3]));
-  // runs: particle 8t+q owns the slots [st[q], hq[q]) with hq the bound of
-  // the running CDF; the last particle of positive weight (and every
-  // particle after it) ends at the segment's end
+  int hprev = max(fs, exclusive_of(winc));
+  for (int q = 0; q < w; ++q) hprev = max(hprev, sh.w4[q]);
+  const int last_pos = max(max(sh.l4[0], sh.l4[1]), max(sh.l4[2], sh.l4[3]));
+  // runs: particle 8t+q owns the slots [st[q], hq[q]); the last particle of
+  // positive weight (and every particle after it) ends at the segment's end
   int st[8], hq[8];
-  {
-    int hprev = min(max(slot_bound(carry, u, nd, n), fs), fe);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      carry = fmax(carry, cq[q]);
-      const int idx = 8 * t + q;
-      int lo = hprev, hv = hprev;
-      if (idx > last_pos) {
-        lo = hv = fe;  // after the last particle of positive weight: no slots
-      } else if (idx == last_pos) {
-        hv = fe;
-      } else if (wi[q] > 0.0) {
-        hv = min(max(slot_bound(carry, u, nd, n), fs), fe);
-      }
-      st[q] = lo;
-      hq[q] = hv;
-      hprev = hv;
-    }
+  for (int q = 0; q < 8; ++q) {
+    const int idx = 8 * t + q;
+    int lo = hprev, hv = max(hprev, rb[q]);
+    if (idx > last_pos) lo = hv = fe;  // no slots after the last positive weight
+    else if (idx == last_pos) hv = fe;
+    st[q] = lo;
+    hq[q] = hv;
+    hprev = hv;
   }
   const int M = fe - fs;
   int32_t* anc = m.rpa ? b.asys : b.anc;  // RPA routes the systematic result afterwards
   if (M <= kCoopSlots) {
-    // tiles of slots: each run marks its first slot with its particle; the
-    // running maximum of the marks (particles increase with slots) is then
-    // every slot's particle
-    int carry_item = -1;
-    constexpr int kk = kSlotTile / 256;
+    // tiles of slots: each run marks its first slot with its particle + 1;
+    // the running maximum of the marks (particles increase with slots) is
+    // then every slot's particle + 1
+    constexpr int kk = kSlotsPerThread;
+    int carry_item = 0;
     for (int c0 = fs; c0 < fe; c0 += kSlotTile) {
       const int cn = min(kSlotTile, fe - c0);
 #pragma unroll
-      for (int k = 0; k < kk; ++k) sh.A[slot_pad(k * 256 + t)] = -1;
+      for (int k = 0; k < kk; ++k) sh.A[slot_pad(k * 256 + t)] = 0;
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (hq[q] > st[q] && st[q] >= c0 && st[q] < c0 + cn) sh.A[slot_pad(st[q] - c0)] = 8 * t + q;
+        if (hq[q] > st[q] && st[q] >= c0 && st[q] < c0 + cn)
+          sh.A[slot_pad(st[q] - c0)] = 8 * t + q + 1;
       __syncthreads();
       int v[kk];
-      int run = -1;
+      int run = 0;
 #pragma unroll
       for (int k = 0; k < kk; ++k) {
         run = max(run, sh.A[slot_pad(t * kk + k)]);
         v[k] = run;
       }
-      const int winc2 = wave_scan(run, lane, OpMax());
-      int wex2 = __shfl_up(winc2, 1, 64);
-      if (lane == 0) wex2 = -1;
-      if (lane == 63) sh.i8[w] = winc2;
+      const int winc2 = wave_max_scan(run);
+      if (lane == 63) sh.w4[w] = winc2;
       __syncthreads();
-      int before = carry_item;
-      for (int q = 0; q < w; ++q) before = max(before, sh.i8[q]);
-      before = max(before, wex2);
+      int before = max(carry_item, exclusive_of(winc2));
+      for (int q = 0; q < w; ++q) before = max(before, sh.w4[q]);
       // the particles back into the tile, then stored with consecutive
       // threads on consecutive slots
 #pragma unroll
-      for (int k = 0; k < kk; ++k) sh.A[slot_pad(t * kk + k)] = max(max(before, v[k]), 0);
-      carry_item = max(max(carry_item, max(sh.i8[0], sh.i8[1])), max(sh.i8[2], sh.i8[3]));
+      for (int k = 0; k < kk; ++k) sh.A[slot_pad(t * kk + k)] = max(before, v[k]);
+      carry_item = max(carry_item, max(max(sh.w4[0], sh.w4[1]), max(sh.w4[2], sh.w4[3])));
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < kk; ++k) {
         const int e = k * 256 + t;
-        if (e < cn) anc[c0 + e] = (int32_t)(ib0 + sh.A[slot_pad(e)]);
+        if (e < cn) anc[c0 + e] = (int32_t)(ib0 + max(sh.A[slot_pad(e)] - 1, 0));
       }
-      __syncthreads();  // sh.A and sh.i8 are rewritten by the next tile
+      __syncthreads();  // sh.A and sh.w4 are rewritten by the next tile
     }
   } else if (mine) {
     // too many slots for one workgroup: queue this thread's runs for k_fill
