@@ -1,17 +1,18 @@
 // HIP kernels of the SIR filter step for gfx950 (CDNA4, wave64).
 //
-// One step of Algorithm 1 (Section 2) is three or four launches on one
-// stream, with every decision taken on the device:
-//   k_step       gather parent + propagate (Section 6.1) + patch likelihood
-//                (Eqs. 3-4, Section 5.5) + per-block normalisation record
-//   k_merge      fixed-order merge of the records; its last workgroup takes
-//                the normaliser, ESS, MMSE estimate, resampling decision and
-//                uniform, commits or rolls back the step, and writes the
-//                fixed-point CDF prefixes of the record chunks
-//   k_anc        systematic resampling: per segment of 2048 particles, each
-//                particle's run of output slots from the segment's CDF
-//   k_fill       long runs of slots queued by k_anc (concentrated weights)
-//   (or k_rna    RNA of Section 3: one workgroup per group of particles)
+// One step of Algorithm 1 (Section 2) is four or five launches on one
+// stream, with every decision taken on the device (so the same sequence
+// serves every step, and a HIP graph of it can be replayed):
+//   k_step         gather parent + propagate (Section 6.1) + patch likelihood
+//                  (Eqs. 3-4, Section 5.5) + per-block normalisation record
+//   k_merge        merge of the block records per chunk
+//   k_merge_final  fixed-order merge of the chunks: the normaliser, ESS, MMSE
+//                  estimate, resampling decision and uniform; commits or rolls
+//                  back the step; the fixed-point CDF prefixes of the chunks
+//   k_anc          systematic resampling: per segment of 2048 particles, each
+//                  particle's run of output slots from the segment's CDF
+//   k_fill         long runs of slots queued by k_anc (concentrated weights)
+//   (or k_rna      RNA of Section 3: one workgroup per group of particles)
 #include "ppf_internal.hpp"
 
 #include <array>
