@@ -679,38 +679,48 @@ struct Moments {
 
 template <int P>
 __device__ __forceinline__ void moments_row(const double (&d)[P], const double (&gx)[P], int dy,
-                                            double gy, bool row_in, bool sq_pix, Moments& mo) {
+                                            double gy, bool row_in, bool pix_sq, bool pix_sum,
+                                            Moments& mo) {
   constexpr int h = (P - 1) / 2;
-  double r0 = 0.0, r1 = 0.0, r2 = 0.0, s1 = 0.0;
+  // u = D g_x along the row. s0 = sum u (the plain step's order), and the
+  // running sums of running sums s1 = sum_j u_j m_j, s2 = sum_j u_j m_j
+  // (m_j + 1) / 2 with m_j = P - j give the moments in a = j - h = c0 - m_j
+  // (c0 = h + 1) without a product per pixel:
+  //   sum u a = c0 s0 - s1,   sum u a^2 = c0^2 s0 - 2 c0 s1 + 2 s2 - s1.
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, sd = 0.0;
 #pragma unroll
   for (int dx = 0; dx < P; ++dx) {
-    r0 = fma(d[dx], gx[dx], r0);
-    const double tt = d[dx] * gx[dx];
-    r1 = fma(tt, (double)(dx - h), r1);
-    r2 = fma(tt, (double)((dx - h) * (dx - h)), r2);
-    s1 += d[dx];
-    if (sq_pix) mo.sd2 = fma(d[dx], d[dx], mo.sd2);
+    s0 = fma(d[dx], gx[dx], s0);
+    s1 += s0;
+    s2 += s1;
+    if (pix_sum) sd += d[dx];
+    if (pix_sq) mo.sd2 = fma(d[dx], d[dx], mo.sd2);
   }
+  constexpr double c0 = (double)(h + 1);
+  const double r1 = fma(c0, s0, -s1);
+  const double r2 = fma(c0 * c0, s0, fma(-2.0 * c0, s1, 2.0 * s2 - s1));
   const double c = (double)(dy - h);
-  mo.X0 = fma(gy, r0, mo.X0);
+  mo.X0 = fma(gy, s0, mo.X0);
   mo.X1 = fma(gy, r1, mo.X1);
   mo.X2 = fma(gy, r2, mo.X2);
-  const double gr = gy * r0;
+  const double gr = gy * s0;
   mo.Y1 = fma(gr, c, mo.Y1);
   mo.Y2 = fma(gr, c * c, mo.Y2);
   mo.B0 = fma(gy, gy, mo.B0);
   const double g2 = gy * gy;
   mo.B1 = fma(g2, c, mo.B1);
   mo.B2 = fma(g2, c * c, mo.B2);
-  mo.SD += s1;
+  if (pix_sum) mo.SD += sd;
   if (row_in) mo.Gin += gy;
 }
 
-// Rows from the LDS tile (TAB: sum D^2 from the row-sum table) or from the
-// frame; v0 is the frame row of the patch's first row.
-template <int P, bool TAB, bool GLOBAL>
+// Rows from the LDS tile (TAB: sum D^2 of each row from the row-sum table
+// hrow; SUMTAB: sum D from hsum as well) or from the frame; v0 is the frame
+// row of the patch's first row.
+template <int P, bool TAB, bool SUMTAB, bool GLOBAL>
 __device__ __forceinline__ void patch_moments(const double* __restrict__ p0, int tw,
-                                              const double* __restrict__ hrow, int hs,
+                                              const double* __restrict__ hrow,
+                                              const double* __restrict__ hsum, int hs,
                                               const float* __restrict__ obs, int u0, double bsub,
                                               int W, int H, int64_t v0,
                                               const double (&gx)[P], double gy, double by,
@@ -732,8 +742,9 @@ __device__ __forceinline__ void patch_moments(const double* __restrict__ p0, int
 #pragma unroll
       for (int dx = 0; dx < P; ++dx) d[dx] = row[dx];
     }
-    moments_row<P>(d, gx, dy, gy, row_in, !TAB, mo);
+    moments_row<P>(d, gx, dy, gy, row_in, !TAB, !SUMTAB, mo);
     if (TAB) mo.sd2 += hrow[dy * hs];
+    if (SUMTAB) mo.SD += hsum[dy * hs];
     gy *= gstep[dy] * by;
   }
 }
@@ -855,6 +866,11 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   const int64_t acx = (int64_t)mxx - mnx + 1;
   const int64_t nH = th64 * acx;
   const bool use_tab = use_lds && nH <= kSqCap;
+  // gradient mode also tables the row sums of D, in the upper half, when both
+  // fit (the D^2 table is used exactly when the plain step uses it, so the log
+  // weights stay the plain step's)
+  constexpr int kTab = kSqCap / 2;
+  const bool use_sum = GRAD && use_lds && nH <= kTab;
   // Row stride ts = tw padded to ts = acx (mod 16): a patch row of the centre
   // (cx, cy) then starts at the double (cy - mny) acx + (cx - mnx) (mod 16),
   // so lanes at up to 16 distinct centres of an acx-wide box read distinct
@@ -882,7 +898,8 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   __syncthreads();
   if (use_tab) {
     // sq[r * acx + c] = sum_dx (Z[r][c + dx] - b)^2 over the tile's rows r and
-    // the centres' columns c
+    // the centres' columns c (gradient mode: sq[kTab + r * acx + c] = sum_dx
+    // (Z[r][c + dx] - b), both in the per-pixel order)
     const int ax = (int)acx, nh = (int)nH;
     const float rcp = 1.0f / (float)ax;
     for (int e = t; e < nh; e += 256) {
@@ -890,10 +907,14 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
       if (r * ax > e) --r;
       else if ((r + 1) * ax <= e) ++r;
       const double* src = tile + r * ts + (e - r * ax);
-      double sacc = 0.0;
+      double sacc = 0.0, dsum = 0.0;
 #pragma unroll
-      for (int dx = 0; dx < P; ++dx) sacc = fma(src[dx], src[dx], sacc);
+      for (int dx = 0; dx < P; ++dx) {
+        sacc = fma(src[dx], src[dx], sacc);
+        if (GRAD) dsum += src[dx];
+      }
       sq[e] = sacc;
+      if (GRAD && use_sum) sq[kTab + e] = dsum;
     }
   }
   __syncthreads();
@@ -908,16 +929,20 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     // frame row of the patch's first row; centres far outside are clamped,
     // as for the addresses (every row of such a patch is outside the frame)
     const int64_t v0 = (int64_t)fmin(fmax(ry, -(double)P - 1.0), (double)m.H + P + 1.0) - h;
-    if (use_tab)
-      patch_moments<P, true, false>(p0, ts, sq + (int64_t)(cy - mny) * acx + (cx - mnx),
-                                    (int)acx, obs, 0, m.b, m.W, m.H, v0, gx, gy0, by, m.gstep,
-                                    mo);
-    else if (use_lds)
-      patch_moments<P, false, false>(p0, ts, sq, 0, obs, 0, m.b, m.W, m.H, v0, gx, gy0, by,
-                                     m.gstep, mo);
-    else
-      patch_moments<P, false, true>(p0, 0, sq, 0, obs, cx - h, m.b, m.W, m.H, v0, gx, gy0, by,
-                                    m.gstep, mo);
+    const int64_t at = (int64_t)(cy - mny) * acx + (cx - mnx);
+    if (use_sum) {
+      patch_moments<P, true, true, false>(p0, ts, sq + at, sq + kTab + at, (int)acx, obs, 0,
+                                          m.b, m.W, m.H, v0, gx, gy0, by, m.gstep, mo);
+    } else if (use_tab) {
+      patch_moments<P, true, false, false>(p0, ts, sq + at, sq, (int)acx, obs, 0, m.b, m.W,
+                                           m.H, v0, gx, gy0, by, m.gstep, mo);
+    } else if (use_lds) {
+      patch_moments<P, false, false, false>(p0, ts, sq, sq, 0, obs, 0, m.b, m.W, m.H, v0, gx,
+                                            gy0, by, m.gstep, mo);
+    } else {
+      patch_moments<P, false, false, true>(p0, 0, sq, sq, 0, obs, cx - h, m.b, m.W, m.H, v0, gx,
+                                           gy0, by, m.gstep, mo);
+    }
     const double I = (double)o.I;
     const double ssq = mo.sd2 - 2.0 * I * mo.X0 + I * I * (G2x * mo.B0);
     l = o.lw - ssq * m.inv2sig2 - m.lognorm_obs;
