@@ -594,9 +594,10 @@ __device__ __forceinline__ double finish_block(const Buffers& b, int cur, int64_
   return e;
 }
 
-// LDS of one step workgroup: the tile of D = Z - b (its first 7 x 256
-// doubles double as the record exchange), the table of row sums of D^2, and
-// the reduction scratch. Kernels that run several patch sizes declare it once.
+// LDS of one step workgroup: two copies of the tile of D = Z - b, each in
+// one half of `tile` (its first 7 x 256 doubles double as the record
+// exchange), the table of row sums of D^2, and the reduction scratch.
+// Kernels that run several patch sizes declare it once.
 template <int TILE>
 struct StepLds {
   static_assert(TILE >= 7 * kBlock, "the tile doubles as the record exchange buffer");
@@ -608,7 +609,7 @@ struct StepLds {
 };
 
 // Patch sums of one particle over P rows of an LDS tile of D = Z - b (0
-// outside the frame) with row stride tw:
+// outside the frame) with row stride tw, every row starting on 16 bytes:
 //   X   += sum_dy g_y(dy) sum_dx D g_x(dx)    (Gaussian-weighted residual sum)
 //   G2y += g_y^2
 //   sd2 += sum D^2, from the table of row sums hrow (stride hs) when TAB,
@@ -622,7 +623,7 @@ __device__ __forceinline__ void patch_lds(const double* __restrict__ p0, int tw,
                                           double& sd2) {
 #pragma unroll
   for (int dy = 0; dy < P; ++dy) {
-    const double* row = p0 + dy * tw;
+    const double* row = static_cast<const double*>(__builtin_assume_aligned(p0 + dy * tw, 16));
     double rd = 0.0;
 #pragma unroll
     for (int dx = 0; dx < P; ++dx) {
@@ -738,7 +739,8 @@ __device__ __forceinline__ void patch_moments(const double* __restrict__ p0, int
         d[dx] = (row_in && (unsigned)u < (unsigned)W) ? (double)row[u] - bsub : 0.0;
       }
     } else {
-      const double* row = p0 + dy * tw;
+      const double* row =
+          static_cast<const double*>(__builtin_assume_aligned(p0 + dy * tw, 16));
 #pragma unroll
       for (int dx = 0; dx < P; ++dx) d[dx] = row[dx];
     }
@@ -859,8 +861,19 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   const int mxx = max(max(ish[4], ish[5]), max(ish[6], ish[7]));
   const int mny = min(min(ish[8], ish[9]), min(ish[10], ish[11]));
   const int mxy = max(max(ish[12], ish[13]), max(ish[14], ish[15]));
+  // The tile is staged twice, copy B shifted one column left of copy A, each
+  // in half of the LDS block with an even row stride: a patch row starting
+  // at an even column is read from A, one starting at an odd column from B,
+  // so every row starts on 16 bytes and is read with 128-bit LDS loads.
+  // 128-bit reads meet the banks in 16-byte granules, 16 granules to a bank
+  // row; copy B starts 8 granules after the half, so that the patch rows of
+  // two neighbouring centres (one in each copy) fall 8 granules apart.
+  constexpr int kCopy = TILE / 2;  // doubles per half
+  constexpr int kOffB = 16;        // copy B's start within its half, in doubles
+  static_assert(kCopy % 2 == 0, "copies must keep 16-byte alignment");
   const int64_t tw64 = (int64_t)mxx - mnx + P, th64 = (int64_t)mxy - mny + P;
-  const bool use_lds = tw64 * th64 <= TILE;  // uniform across the workgroup
+  const int64_t ts2min = (tw64 + 1) >> 1;  // row stride in pairs of doubles
+  const bool use_lds = 2 * ts2min * th64 <= kCopy - kOffB;  // uniform across the workgroup
   const int tw = (int)tw64, th = (int)th64;
   const int tx0 = mnx - h, ty0 = mny - h;
   const int64_t acx = (int64_t)mxx - mnx + 1;
@@ -871,15 +884,17 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   // weights stay the plain step's)
   constexpr int kTab = kSqCap / 2;
   const bool use_sum = GRAD && use_lds && nH <= kTab;
-  // Row stride ts = tw padded to ts = acx (mod 16): a patch row of the centre
-  // (cx, cy) then starts at the double (cy - mny) acx + (cx - mnx) (mod 16),
-  // so lanes at up to 16 distinct centres of an acx-wide box read distinct
-  // pairs of the 32 four-byte LDS banks.
-  int ts = tw;
+  // Row stride ts = 2 ts2, with ts2 padded to ceil(acx / 2) (mod 16): the
+  // granule where a patch row of the centre (cx, cy) starts is then
+  // (cy - mny) ceil(acx / 2) + (cx - mnx) / 2 (+ 8 in copy B) (mod 16), so
+  // lanes at distinct centres of a small box meet distinct granules (this
+  // layout measured a fifth of the bank-conflict cycles of 8-granule rules).
+  int ts2 = (int)ts2min;
   {
-    const int padw = ((int)(acx & 15) - (tw & 15)) & 15;
-    if ((int64_t)(tw + padw) * th <= TILE) ts = tw + padw;
+    const int padh = ((int)(((acx + 1) >> 1) & 15) - (ts2 & 15)) & 15;
+    if ((int64_t)2 * (ts2 + padh) * th <= kCopy - kOffB) ts2 += padh;
   }
+  const int ts = 2 * ts2;
   if (use_lds) {
     // one pass over the tile's pixels (row r = e / tw from a float reciprocal,
     // corrected by one step: e < 2^11, so the estimate is off by at most 1)
@@ -890,9 +905,11 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
       if (r * tw > e) --r;
       else if ((r + 1) * tw <= e) ++r;
       const int c = e - r * tw, v = ty0 + r, u = tx0 + c;
-      tile[r * ts + c] = ((unsigned)v < (unsigned)m.H && (unsigned)u < (unsigned)m.W)
-                             ? (double)obs[(int64_t)v * m.W + u] - m.b
-                             : 0.0;
+      const double dv = ((unsigned)v < (unsigned)m.H && (unsigned)u < (unsigned)m.W)
+                            ? (double)obs[(int64_t)v * m.W + u] - m.b
+                            : 0.0;
+      tile[r * ts + c] = dv;
+      if (c > 0) tile[kCopy + kOffB + r * ts + c - 1] = dv;
     }
   }
   __syncthreads();
@@ -923,8 +940,11 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   // n - 1's); finish_block ignores the tail lanes' l
   double l;
   double gth[GRAD ? kNGrad : 1] = {};
+  // the particle's first patch row in copy A (even first column) or B (odd)
+  const int col0 = cx - h - tx0;
+  const double* p0 =
+      tile + ((cy - h - ty0) * ts + (col0 & ~1) + ((col0 & 1) ? kCopy + kOffB : 0));
   if (GRAD) {
-    const double* p0 = tile + (cy - h - ty0) * ts + (cx - h - tx0);
     Moments mo{};
     // frame row of the patch's first row; centres far outside are clamped,
     // as for the addresses (every row of such a patch is outside the frame)
@@ -982,7 +1002,6 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     gth[8] = lI;
   } else {
     double X = 0.0, G2y = 0.0, sd2 = 0.0;
-    const double* p0 = tile + (cy - h - ty0) * ts + (cx - h - tx0);
     if (use_tab) {
       patch_lds<P, true>(p0, ts, sq + (int64_t)(cy - mny) * acx + (cx - mnx), (int)acx, gx, gy0,
                          by, m.gstep, X, G2y, sd2);
