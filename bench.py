@@ -17,11 +17,13 @@ bounded sample of the same workload on the host.
 
 `roofline.traffic` is the HBM traffic of one k_step launch in bytes, taken
 from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE) of this script
-with `--copy-probe-mib`, each counter scaled by what it reads for a plain
-device copy of known size. `--traffic-from FETCH_DB WRITE_DB` turns the two
-databases into profiles/traffic_<kernel>_<workload>.json, stamped with a hash
-of the kernel sources; a run reports the figure only while the hash still
-matches (null otherwise).
+with `--copy-probe-mib` and a fixed `--shape`, each counter scaled by what it
+reads for a plain device copy of known size. The step kernel's workgroup
+shapes differ in traffic (one may spill registers to scratch memory), so each
+shape has its own record: `--traffic-from FETCH_DB WRITE_DB --shape S` turns
+the two databases into profiles/traffic_k_step_shape<S>_<workload>.json,
+stamped with a hash of the kernel sources; a run reports the record of the
+shape its steps ran with, while the hash still matches (null otherwise).
 """
 import argparse
 import glob
@@ -50,8 +52,8 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def traffic_path(kernel, workload):
-    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+def traffic_path(kernel, workload, shape):
+    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_shape{shape}_{workload}.json")
 
 
 def _counter_per_dispatch(db, counter):
@@ -63,17 +65,22 @@ def _counter_per_dispatch(db, counter):
     return {d: (k, v) for d, k, c, v in rows if c == counter}
 
 
-def traffic_from(fetch_db, write_db, workload, copy_mib, warmup, steps, kernel="k_step",
+def traffic_from(fetch_db, write_db, workload, copy_mib, warmup, steps, shape, kernel="k_step",
                  match="k_step_spot"):
-    """Writes the traffic record of `kernel` from a FETCH_SIZE and a WRITE_SIZE
-    counter database of `bench.py --copy-probe-mib copy_mib` runs with the
-    given warm-up and timed steps; the average covers the timed launches (the
-    last `steps` of the kernel; warm-up and autotuner launches come first)."""
+    """Writes the traffic record of `kernel` in workgroup shape `shape` from a
+    FETCH_SIZE and a WRITE_SIZE counter database of `bench.py --copy-probe-mib
+    copy_mib --shape shape` runs with the given warm-up and timed steps; the
+    average covers the timed launches (the last `steps` of the kernel)."""
     copy_bytes = copy_mib * (1 << 20)
     per = {}
     for name, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
         d = _counter_per_dispatch(db, name)
+        names = [d[i][0] for i in sorted(d) if match in d[i][0]]
         ker = [d[i][1] for i in sorted(d) if match in d[i][0]]
+        # k_step_spot<P, S>: the timed launches must all be of shape S
+        tag = f", {shape}>"
+        if not names or any(tag not in nm for nm in names[-steps:]):
+            raise SystemExit(f"{db}: the timed {match} launches are not all of shape {shape}")
         if len(ker) < steps + warmup:
             raise SystemExit(f"{db}: {len(ker)} {match} dispatches, expected at least "
                              f"{steps + warmup}")
@@ -88,21 +95,22 @@ def traffic_from(fetch_db, write_db, workload, copy_mib, warmup, steps, kernel="
         per[name] = dict(kernel_kib_avg=sum(ker) / len(ker), launches=len(ker), copy_kib=kib_copy,
                          scale=copy_bytes / (kib_copy * 1024.0))
     traffic = sum(per[c]["kernel_kib_avg"] * 1024.0 * per[c]["scale"] for c in per)
-    rec = {"kernel": kernel, "workload": workload, "source_sha256": kernel_source_hash(),
+    rec = {"kernel": kernel, "shape": shape, "workload": workload,
+           "source_sha256": kernel_source_hash(),
            "traffic_bytes_per_launch": traffic, "copy_probe_bytes": copy_bytes,
            "counters": per,
            "command": [f"rocprofv3 --kernel-trace --pmc {c} -d <dir> -o run -- python3 bench.py "
                        f"--steps {steps} --warmup {warmup} --no-cpu-baseline "
-                       f"--copy-probe-mib {copy_mib}" for c in per]}
-    with open(traffic_path(kernel, workload), "w") as fh:
+                       f"--copy-probe-mib {copy_mib} --shape {shape}" for c in per]}
+    with open(traffic_path(kernel, workload, shape), "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     return rec
 
 
-def load_traffic(kernel, workload):
+def load_traffic(kernel, workload, shape):
     try:
-        with open(traffic_path(kernel, workload)) as fh:
+        with open(traffic_path(kernel, workload, shape)) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -172,7 +180,7 @@ def run_multitrack(args, w):
     frames = torch.from_numpy(mv.frames).cuda()
     b = ppf.Batch(ps)
     graph = args.launch == "graph"
-    gpu_ms, wall, kt, tuned = timed_steps(torch, b, frames, K, Wm, T, graph, not args.no_autotune)
+    gpu_ms, wall, kt, tuned, _ = timed_steps(torch, b, frames, K, Wm, T, graph, args.shape)
     sts = b.stats()
     ntot = sum(int(p.n_particles) for p in ps)
     flops = sum(4 * ppf.patch_size(p) ** 2 * int(p.n_particles) for p in ps)
@@ -226,17 +234,21 @@ def make_params(ppf, w, init_kind, grad=0):
                       rna_group=group, dlb=dlb)
 
 
-def timed_steps(torch, f, frames, K, Wm, T, graph, tune):
+def timed_steps(torch, f, frames, K, Wm, T, graph, shape):
     """K steps of filter or batch f from a fresh initial cloud, after Wm
     warm-up steps: (GPU ms of the K steps between two events on f's stream,
-    wall s, per-kernel times, autotuner result or None). With tune=True the
-    autotuner picks the step kernel's workgroup shape on the warm filter two
-    steps before the end of the warm-up (so that a graph is recorded again
-    before the timed steps). With graph=True the timed steps replay the
-    step's HIP graph, and the per-kernel times come from a second pass over
-    the same K steps with plain launches and kernel timing on (the two
+    wall s, per-kernel times, autotuner result or None, shape the steps ran
+    with). With shape=None the autotuner picks the step kernel's workgroup
+    shape on the warm filter two steps before the end of the warm-up (so that
+    a graph is recorded again before the timed steps); otherwise the given
+    shape is set before the warm-up. With graph=True the timed steps replay
+    the step's HIP graph, and the per-kernel times come from a second pass
+    over the same K steps with plain launches and kernel timing on (the two
     exclude each other)."""
     f.graph(graph)
+    tune = shape is None
+    if not tune:
+        (f.set_shape if hasattr(f, "set_shape") else f.set_shapes)(shape)
     tuned = None
     tune_at = max(Wm - 2, 0)
     for k in range(Wm):
@@ -247,6 +259,7 @@ def timed_steps(torch, f, frames, K, Wm, T, graph, tune):
     if tune and tuned is None:
         ms, chosen = f.autotune(frames[0], reps=5)
         tuned = {"ms_per_launch": ms, "chosen": chosen}
+    ran = tuned["chosen"] if tune else shape
     f.reset()
     torch.cuda.synchronize()
     if not graph:
@@ -270,7 +283,7 @@ def timed_steps(torch, f, frames, K, Wm, T, graph, tune):
         for k in range(K):
             f.step(frames[k % T])
     kt = f.kernel_times()
-    return gpu_ms, wall, kt, tuned
+    return gpu_ms, wall, kt, tuned, ran
 
 
 def cpu_baseline(w, frames, sample_n, sample_t, init_kind):
@@ -305,8 +318,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="stream", choices=["stream", "graph"],
                     help="timed steps as plain launches or as replays of one HIP graph")
+    ap.add_argument("--shape", type=int, default=None,
+                    help="step-kernel workgroup shape (batched: shape candidate) for every "
+                         "step; default: the autotuner picks it during the warm-up")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default step-kernel workgroup shape")
+                    help="the same as --shape 0")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -314,12 +330,16 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the k_step traffic record from two counter databases and exit")
     args = ap.parse_args()
+    if args.no_autotune and args.shape is None:
+        args.shape = 0
     if args.traffic_from:
+        if args.shape is None:
+            raise SystemExit("--traffic-from needs the --shape the counter runs used")
         dbs = []
         for p in args.traffic_from:
             dbs.append(p if p.endswith(".db") else sorted(glob.glob(os.path.join(p, "*.db")))[0])
         rec = traffic_from(dbs[0], dbs[1], args.workload, args.copy_probe_mib or 1024,
-                           args.warmup, args.steps)
+                           args.warmup, args.steps, args.shape)
         print(json.dumps(rec))
         return
     if args.gpus != 1:
@@ -356,13 +376,13 @@ def main():
     if w.get("grad"):
         # the same configuration without derivatives, for the ratio
         pf = ppf.Filter(make_params(ppf, w, init_kind))
-        pms, _, pkt, _ = timed_steps(torch, pf, frames, K, Wm, T, False, not args.no_autotune)
+        pms, _, pkt, _, _ = timed_steps(torch, pf, frames, K, Wm, T, False, args.shape)
         pf.close()
         plain = {"value": w["n"] * K / (pms / 1e3), "ms_per_step": pms / K,
                  "k_step_ms": pkt.get("k_step", (1, 0.0))[1] / K}
     f = ppf.Filter(make_params(ppf, w, init_kind, grad=w.get("grad", 0)))
     graph = args.launch == "graph"
-    gpu_ms, wall, kt, tuned = timed_steps(torch, f, frames, K, Wm, T, graph, not args.no_autotune)
+    gpu_ms, wall, kt, tuned, ran = timed_steps(torch, f, frames, K, Wm, T, graph, args.shape)
     st = f.stats()
     err = float(np.linalg.norm(st["mean"][:2] - mv.truth[(K - 1) % T, 0]))
     n = w["n"]
@@ -401,11 +421,11 @@ def main():
                                   + ("" if w["thr"] == float("inf")
                                      else f" when ESS < {w['thr']:.0f}")),
                    "init": args.init, "frames_timed": K, "launch": args.launch,
-                   "autotune": tuned},
+                   "autotune": tuned, "shape": ran},
         "roofline": {"bound": "alu", "kernel": "k_step", "achieved": achieved_tf,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": load_traffic("k_step", args.workload),
+                     "traffic": load_traffic("k_step", args.workload, ran),
                      "avg_launch_ms": step_avg_s * 1e3, "flops_per_particle": flops_per_particle,
                      "hbm_gbs_at_48B_per_particle": step_gbs},
         "roofline_resample": {"bound": "hbm", "kernel": "k_anc+k_fill", "achieved": res_gbs,

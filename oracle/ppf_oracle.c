@@ -624,7 +624,8 @@ static void sort_desc(int32_t* idx, int64_t m, const int64_t* key) {
  * counts[g] > n, receivers those with counts[g] < n, each listed in group
  * order (GS) or by surplus / deficit descending (SGS, LGS; ties by group).
  * Writes up to `cap` entries (sender group, receiver group, particles) to
- * sched (3 per entry) and returns their number (-1 if cap is too small).
+ * sched (3 per entry) and returns their number (-1 if cap is too small or
+ * the working lists cannot be allocated).
  *   GS/SGS: each sender in turn fills the current receiver; a filled
  *           receiver is skipped and the next one taken (the printed loop
  *           resets j to 0 and never ends on a filled receiver; the reading
@@ -636,10 +637,18 @@ static void sort_desc(int32_t* idx, int64_t m, const int64_t* key) {
  */
 int64_t orc_dlb_schedule(int kind, int64_t G, int32_t n, const int32_t* counts, int64_t cap,
                          int32_t* sched) {
-  int64_t* surplus = (int64_t*)malloc((size_t)G * sizeof(int64_t));
-  int64_t* deficit = (int64_t*)malloc((size_t)G * sizeof(int64_t));
+  if (G <= 0) return 0;
+  int64_t* surplus = (int64_t*)calloc((size_t)G, sizeof(int64_t));
+  int64_t* deficit = (int64_t*)calloc((size_t)G, sizeof(int64_t));
   int32_t* S = (int32_t*)malloc((size_t)G * sizeof(int32_t));
   int32_t* R = (int32_t*)malloc((size_t)G * sizeof(int32_t));
+  if (!surplus || !deficit || !S || !R) {
+    free(surplus);
+    free(deficit);
+    free(S);
+    free(R);
+    return -1;
+  }
   int64_t ns = 0, nr = 0, m = 0;
   for (int64_t g = 0; g < G; ++g) {
     surplus[g] = counts[g] > n ? (int64_t)counts[g] - n : 0;

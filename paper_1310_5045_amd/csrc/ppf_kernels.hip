@@ -181,6 +181,10 @@ __device__ __forceinline__ T ror(T v) {
 }
 
 __device__ __forceinline__ int readlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+// The wave's index within its workgroup, as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+}
 __device__ __forceinline__ uint64_t readlane(uint64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
@@ -432,31 +436,37 @@ __global__ __launch_bounds__(256) void k_init(Model m, Buffers b) { init_body(m,
 // Parent, carried log weight and propagated state of particle i.
 struct Prop {
   float x, y, vx, vy, I;
-  double lw;
 };
 
-// zo (5 normals) and po (the parent) are optional outputs for the tangents.
-__device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int cur, int mode,
-                                          double delta, int64_t i, uint32_t k,
-                                          float* zo = nullptr, int64_t* po = nullptr) {
-  const float* Xin = cur ? b.X1 : b.X0;
-  int64_t p = i;
-  double lw;
-  if (mode == kModeSys || mode == kModeRna) p = b.anc[i];
+// The particle's log weight before the new observation: its stored weight
+// carried over (no resampling this step), its group's weight after RNA, a
+// caller-set weight, or -log N after systematic resampling. Kept out of
+// propagate so that kernels compute it only where the likelihood is added,
+// instead of holding it across the patch sums.
+__device__ __forceinline__ double prior_lw(const Model& m, const Buffers& b, int cur, int mode,
+                                           double delta, int64_t i) {
   if (mode == kModeNone) {
     const float* Ein = cur ? b.E1 : b.E0;
     const double* Rin = cur ? b.R1 : b.R0;
-    lw = log((double)Ein[i]) + Rin[(i / kBlock) * kRec] - delta;
-  } else if (mode == kModeRna) {
+    return log((double)Ein[i]) + Rin[(i / kBlock) * kRec] - delta;
+  }
+  if (mode == kModeRna) {
     const int64_t g = i / m.group;
     const int64_t l = i - g * m.group;
     const int64_t src = (l >= m.group - m.moved) ? (g + m.G - 1) % m.G : g;
-    lw = b.lwg[src];
-  } else if (mode == kModeSet) {
-    lw = b.lw64[i];
-  } else {
-    lw = -m.log_n;
+    return b.lwg[src];
   }
+  if (mode == kModeSet) return b.lw64[i];
+  return -m.log_n;
+}
+
+// zo (5 normals) and po (the parent) are optional outputs for the tangents.
+__device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int cur, int mode,
+                                          int64_t i, uint32_t k, float* zo = nullptr,
+                                          int64_t* po = nullptr) {
+  const float* Xin = cur ? b.X1 : b.X0;
+  int64_t p = i;
+  if (mode == kModeSys || mode == kModeRna) p = b.anc[i];
   const int64_t n = m.n;
   const float px = Xin[p], py = Xin[n + p], pvx = Xin[2 * n + p], pvy = Xin[3 * n + p],
               pI = Xin[4 * n + p];
@@ -484,7 +494,6 @@ __device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int 
   o.vx = fmaf(m.q[2], z2, pvx);
   o.vy = fmaf(m.q[3], z3, pvy);
   o.I = fmaf(m.q[4], z4, pI);
-  o.lw = lw;
   return o;
 }
 
@@ -543,17 +552,18 @@ __device__ __forceinline__ float exp_neg_f32(double x) {
 __device__ __forceinline__ double finish_block(const Buffers& b, int cur, int64_t i, bool active,
                                                double l, const Prop& o, double* red,
                                                double* dsh, int* ksh) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // lane tests compare t with wave-uniform values, so no lane index stays live
+  const int t = threadIdx.x, w = wave_index(), t0 = 64 * w;
   const bool bad = active && (isnan(l) || l == INFINITY);
   const bool ok = active && !bad;
   const int wk = wave_reduce_last(ok ? ord_key_up(l) : ord_key(-INFINITY), OpMax(), INT_MIN);
-  if (lane == 63) ksh[w] = wk;
+  if (t == t0 + 63) ksh[w] = wk;
   __syncthreads();
   const float mf = ord_val(max(max(ksh[0], ksh[1]), max(ksh[2], ksh[3])));
   double mb = (double)mf;
   if (mf != -INFINITY && !(fabsf(mf) < 0x1p20f)) {  // uniform across the workgroup
     const double wm = wave_reduce_last(ok ? l : -INFINITY, OpMax(), (double)-INFINITY);
-    if (lane == 63) dsh[w] = wm;
+    if (t == t0 + 63) dsh[w] = wm;
     __syncthreads();
     mb = fmax(fmax(dsh[0], dsh[1]), fmax(dsh[2], dsh[3]));
   }
@@ -588,8 +598,8 @@ __device__ __forceinline__ double finish_block(const Buffers& b, int cur, int64_
   // value 2w in row 1 of wave w, value 2w + 1 in row 3
   s = pair_rows(row_allreduce(s, OpAdd()), OpAdd(), 0.0);
   double* R = (cur ? b.R0 : b.R1) + (i / kBlock) * kRec;
-  if (lane == 16) R[1 + 2 * w] = s;
-  if (lane == 48 && 2 * w + 1 < 7) R[2 + 2 * w] = s;
+  if (t == t0 + 16) R[1 + 2 * w] = s;
+  if (t == t0 + 48 && 2 * w + 1 < 7) R[2 + 2 * w] = s;
   if (t == 0) R[0] = mb;
   return e;
 }
@@ -615,6 +625,8 @@ struct StepLds {
 //   sd2 += sum D^2, from the table of row sums hrow (stride hs) when TAB,
 //          else pixel by pixel.
 // g_y is advanced by the exact recurrence g(d+1) = g(d) gstep(d) exp(f/s^2).
+// gx[0] is 1, so each row's sum starts at its first pixel (an fma with a zero
+// addend would cost an add, to turn -0 into +0; D = Z - b is never -0 here).
 template <int P, bool TAB>
 __device__ __forceinline__ void patch_lds(const double* __restrict__ p0, int tw,
                                           const double* __restrict__ hrow, int hs,
@@ -624,9 +636,10 @@ __device__ __forceinline__ void patch_lds(const double* __restrict__ p0, int tw,
 #pragma unroll
   for (int dy = 0; dy < P; ++dy) {
     const double* row = static_cast<const double*>(__builtin_assume_aligned(p0 + dy * tw, 16));
-    double rd = 0.0;
+    double rd = row[0];
+    if (!TAB) sd2 = fma(rd, rd, sd2);
 #pragma unroll
-    for (int dx = 0; dx < P; ++dx) {
+    for (int dx = 1; dx < P; ++dx) {
       const double d = row[dx];
       rd = fma(d, gx[dx], rd);
       if (!TAB) sd2 = fma(d, d, sd2);
@@ -655,7 +668,7 @@ __device__ __forceinline__ void patch_global(const float* __restrict__ obs, int 
     for (int dx = 0; dx < P; ++dx) {
       const int u = u0 + dx;
       const double d = (row_in && (unsigned)u < (unsigned)W) ? (double)row[u] - bsub : 0.0;
-      rd = fma(d, gx[dx], rd);
+      rd = dx == 0 ? d : fma(d, gx[dx], rd);
       sd2 = fma(d, d, sd2);
     }
     X = fma(gy, rd, X);
@@ -688,9 +701,11 @@ __device__ __forceinline__ void moments_row(const double (&d)[P], const double (
   // (m_j + 1) / 2 with m_j = P - j give the moments in a = j - h = c0 - m_j
   // (c0 = h + 1) without a product per pixel:
   //   sum u a = c0 s0 - s1,   sum u a^2 = c0^2 s0 - 2 c0 s1 + 2 s2 - s1.
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, sd = 0.0;
+  // (gx[0] = 1: the sums start at the first pixel, as in patch_lds)
+  double s0 = d[0], s1 = s0, s2 = s0, sd = d[0];
+  if (pix_sq) mo.sd2 = fma(d[0], d[0], mo.sd2);
 #pragma unroll
-  for (int dx = 0; dx < P; ++dx) {
+  for (int dx = 1; dx < P; ++dx) {
     s0 = fma(d[dx], gx[dx], s0);
     s1 += s0;
     s2 += s1;
@@ -775,7 +790,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   const int cur = cp->cur, mode = cp->mode;
   const double cdelta = cp->delta;
   const uint32_t k = (uint32_t)(cp->k + 1);
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int t = threadIdx.x, w = wave_index();
   const int64_t i = blk * kBlock + t;
   const bool active = i < m.n;
   // Lanes past the last particle (the tail of the last workgroup) repeat the
@@ -788,7 +803,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   if (GRAD) {
     float z[5];
     int64_t p;
-    o = propagate(m, b, cur, mode, cdelta, ia, k, z, &p);
+    o = propagate(m, b, cur, mode, ia, k, z, &p);
     // tangents along the ancestral line (see kNTan): dx'/dq_x = dx/dq_x +
     // z_x, dx'/dq_vx = dx/dq_vx + dvx/dq_vx (the parent's), and alike
     const float* Tin = cur ? b.T1 : b.T0;
@@ -807,7 +822,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
 #pragma unroll
       for (int d = 0; d < kNTan; ++d) Tout[(int64_t)d * m.n + i] = tg[d];
   } else {
-    o = propagate(m, b, cur, mode, cdelta, ia, k);
+    o = propagate(m, b, cur, mode, ia, k);
   }
   if (active) store_state(m, b, cur, i, o);
   // patch centre: pixel nearest to (x, y); the offset f is exact in fp64
@@ -849,7 +864,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     const uint32_t pneg = (uint32_t)(uint16_t)-ox | ((uint32_t)(uint16_t)-oy << 16);
     const uint32_t rmin = wave_reduce_last(pmin, OpMin16x2(), 0x7fff7fffu);
     const uint32_t rneg = wave_reduce_last(pneg, OpMin16x2(), 0x7fff7fffu);
-    if (lane == 63) {
+    if (t == 64 * w + 63) {
       ish[w] = bx0 + (int16_t)(rmin & 0xffffu);
       ish[4 + w] = bx0 - (int16_t)(rneg & 0xffffu);
       ish[8 + w] = by0 + (int16_t)(rmin >> 16);
@@ -949,7 +964,8 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     // frame row of the patch's first row; centres far outside are clamped,
     // as for the addresses (every row of such a patch is outside the frame)
     const int64_t v0 = (int64_t)fmin(fmax(ry, -(double)P - 1.0), (double)m.H + P + 1.0) - h;
-    const int64_t at = (int64_t)(cy - mny) * acx + (cx - mnx);
+    // table index of the centre (below nH <= kSqCap where a table is used)
+    const int at = use_tab ? (cy - mny) * (int)acx + (cx - mnx) : 0;
     if (use_sum) {
       patch_moments<P, true, true, false>(p0, ts, sq + at, sq + kTab + at, (int)acx, obs, 0,
                                           m.b, m.W, m.H, v0, gx, gy0, by, m.gstep, mo);
@@ -965,7 +981,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     }
     const double I = (double)o.I;
     const double ssq = mo.sd2 - 2.0 * I * mo.X0 + I * I * (G2x * mo.B0);
-    l = o.lw - ssq * m.inv2sig2 - m.lognorm_obs;
+    l = prior_lw(m, b, cur, mode, cdelta, ia) - ssq * m.inv2sig2 - m.lognorm_obs;
     // 1-D moments of g_x^2 and the in-frame sum of g_x (true centre rx)
     double A1 = 0.0, A2 = 0.0, Gin_x = 0.0;
 #pragma unroll
@@ -1003,7 +1019,8 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   } else {
     double X = 0.0, G2y = 0.0, sd2 = 0.0;
     if (use_tab) {
-      patch_lds<P, true>(p0, ts, sq + (int64_t)(cy - mny) * acx + (cx - mnx), (int)acx, gx, gy0,
+      // the table index is below nH <= kSqCap: 32-bit arithmetic
+      patch_lds<P, true>(p0, ts, sq + ((cy - mny) * (int)acx + (cx - mnx)), (int)acx, gx, gy0,
                          by, m.gstep, X, G2y, sd2);
     } else if (use_lds) {
       patch_lds<P, false>(p0, ts, sq, 0, gx, gy0, by, m.gstep, X, G2y, sd2);
@@ -1012,7 +1029,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     }
     const double I = (double)o.I;
     const double ssq = sd2 - 2.0 * I * X + I * I * (G2x * G2y);
-    l = o.lw - ssq * m.inv2sig2 - m.lognorm_obs;
+    l = prior_lw(m, b, cur, mode, cdelta, ia) - ssq * m.inv2sig2 - m.lognorm_obs;
   }
   const double e = finish_block(b, cur, i, active, l, o, tile, dsh, L.ksh);
   if (GRAD) {
@@ -1067,11 +1084,11 @@ __global__ __launch_bounds__(256) void k_step_lg(Model m, Buffers b,
   Prop o{};
   double l = -INFINITY;
   if (active) {
-    o = propagate(m, b, cur, mode, cdelta, i, k);
+    o = propagate(m, b, cur, mode, i, k);
     store_state(m, b, cur, i, o);
     const double ex = (double)obs[0] - (double)o.x, ey = (double)obs[1] - (double)o.y,
                  eI = (double)obs[2] - (double)o.I;
-    l = o.lw - ex * ex * m.lg_inv2r2[0] - ey * ey * m.lg_inv2r2[1] - eI * eI * m.lg_inv2r2[2] -
+    l = prior_lw(m, b, cur, mode, cdelta, i) - ex * ex * m.lg_inv2r2[0] - ey * ey * m.lg_inv2r2[1] - eI * eI * m.lg_inv2r2[2] -
         m.lg_norm;
   }
   finish_block(b, cur, i, active, l, o, red, dsh, ksh);
