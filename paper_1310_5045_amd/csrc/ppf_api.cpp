@@ -122,6 +122,9 @@ Model make_model(const ppf_params* p) {
   m.inv2s2 = 1.0 / (2.0 * s * s);
   m.inv2sig2 = 1.0 / (2.0 * sg * sg);
   m.lognorm_obs = (double)m.P * (double)m.P * std::log(sg * std::sqrt(2.0 * M_PI));
+  m.clo[0] = m.clo[1] = -(double)m.P;
+  m.chi[0] = (double)m.W + m.P;
+  m.chi[1] = (double)m.H + m.P;
   // ratio of consecutive 1-D Gaussian factors at unit pixel steps from -h
   const int h = (m.P - 1) / 2;
   for (int d = 0; d < ppf::kMaxPatch; ++d)

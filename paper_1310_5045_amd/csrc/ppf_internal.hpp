@@ -148,6 +148,7 @@ struct Model {
   int32_t shape;         // step workgroup shape (patches up to kFusedMaxP)
   double s_psf;          // s
   double sig;            // sigma_xi
+  double clo[2], chi[2]; // patch-centre clamp (x, y): -P and W + P, H + P
 };
 
 // Device buffers carved from the caller's workspace (or a scratch area).

@@ -830,11 +830,11 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   const double ry = floor((double)o.y + 0.5);
   const double fx = (double)o.x - rx;
   const double fy = (double)o.y - ry;
-  // addresses only: far-away centres are clamped where the whole patch
-  // already lies outside the frame (their pixels read as background)
-  const double lox = -(double)P, hix = (double)m.W + P, loy = -(double)P, hiy = (double)m.H + P;
-  const int cx = (rx >= lox && rx <= hix) ? (int)rx : (rx > hix ? (int)hix : (int)lox);
-  const int cy = (ry >= loy && ry <= hiy) ? (int)ry : (ry > hiy ? (int)hiy : (int)loy);
+  // addresses only: far-away centres are clamped to [-P, W + P] x [-P, H + P],
+  // where the whole patch already lies outside the frame (its pixels read as
+  // background); a NaN centre goes to the low corner
+  const int cx = (int)fmin(fmax(rx, m.clo[0]), m.chi[0]);
+  const int cy = (int)fmin(fmax(ry, m.clo[1]), m.chi[1]);
   // The 1-D Gaussian factors of Eq. 3 at the patch's pixel offsets. Only
   // their products g_x g_y enter the likelihood, so g_x is taken relative to
   // its first value, which moves into the first g_y: three exps per particle
@@ -911,10 +911,11 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   }
   const int ts = 2 * ts2;
   if (use_lds) {
-    // one pass over the tile's pixels (row r = e / tw from a float reciprocal,
-    // corrected by one step: e < 2^11, so the estimate is off by at most 1)
+    // one pass over the tile's pixels (row r = e / tw from the hardware
+    // reciprocal, corrected by one step: e < 2^11 and the reciprocal is
+    // within 1 ulp, so the estimate is off by at most 1)
     const int nt = tw * th;
-    const float rcpw = 1.0f / (float)tw;
+    const float rcpw = __builtin_amdgcn_rcpf((float)tw);
     for (int e = t; e < nt; e += 256) {
       int r = (int)((float)e * rcpw);
       if (r * tw > e) --r;
@@ -933,7 +934,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     // the centres' columns c (gradient mode: sq[kTab + r * acx + c] = sum_dx
     // (Z[r][c + dx] - b), both in the per-pixel order)
     const int ax = (int)acx, nh = (int)nH;
-    const float rcp = 1.0f / (float)ax;
+    const float rcp = __builtin_amdgcn_rcpf((float)ax);
     for (int e = t; e < nh; e += 256) {
       int r = (int)((float)e * rcp);
       if (r * ax > e) --r;
