@@ -1385,12 +1385,6 @@ __device__ __forceinline__ int slot_bound(double C, double u, double nd, int n) 
   const double x = ceil(fma(C, nd, -u));
   return x <= 0.0 ? 0 : (x >= nd ? n : (int)x);
 }
-// The same count clamped to [lo, hi] with 0 <= lo <= hi <= n (the clamp to
-// [0, n] above is then implied); lo and hi as doubles.
-__device__ __forceinline__ int slot_bound_in(double C, double u, double nd, double lo,
-                                             double hi) {
-  return (int)fmin(fmax(ceil(fma(C, nd, -u)), lo), hi);
-}
 
 // Slot e of a tile lives at slot_pad(e), one spare word after every 8, so
 // that a thread walking its own 8 consecutive slots (lanes 8 words apart
@@ -1457,6 +1451,27 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
   const double* rec = second ? ws.rec1 : ws.rec0;
   const double pbt = (t <= nbs && b0 + t < b.nb) ? block_P(b, b0 + t) : 1.0;
   const double mbt = t < nbs ? rec[(b0 + t) * kRec] : -INFINITY;
+  // this thread's eight weights, loaded alongside the block records rather
+  // than after the barrier (discarded when the segment owns no slots)
+  const float* E = second ? ws.E1 : ws.E0;
+  const int64_t ib0 = b0 * kBlock;
+  const int64_t ib1 = min(m.n, (b0 + nbs) * kBlock);
+  const int64_t j0 = ib0 + 8 * (int64_t)t;
+  const bool mine = j0 < ib1;
+  float x[8];
+  if (mine) {
+    // vector loads only from 16-byte aligned bases
+    if (j0 + 8 <= ib1 && (reinterpret_cast<uintptr_t>(E) & 15) == 0) {
+      const float4 v0 = *reinterpret_cast<const float4*>(E + j0);
+      const float4 v1 = *reinterpret_cast<const float4*>(E + j0 + 4);
+      x[0] = v0.x; x[1] = v0.y; x[2] = v0.z; x[3] = v0.w;
+      x[4] = v1.x; x[5] = v1.y; x[6] = v1.z; x[7] = v1.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        x[q] = (j0 + q < ib1) ? E[j0 + q] : (ws.log_src ? -INFINITY : 0.0f);
+    }
+  }
   if (!do_res) return;
   if (t <= nbs) sh.Pb[t] = pbt;
   if (t < nbs) {
@@ -1470,27 +1485,10 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
   const int fe = seg + 1 >= b.nseg ? n : slot_bound(sh.Pb[nbs], u, nd, n);
   if (fe <= fs) return;  // uniform: no slot falls in this segment
 
-  const float* E = second ? ws.E1 : ws.E0;
-  const int64_t ib0 = b0 * kBlock;
-  const int64_t ib1 = min(m.n, (b0 + nbs) * kBlock);
-  const int64_t j0 = ib0 + 8 * (int64_t)t;
-  const bool mine = j0 < ib1;
   const int lb = (t * 8) / kBlock;  // this thread's block within the segment
   double wi[8], kl[8];
   double tsum = 0.0;
   if (mine) {
-    float x[8];
-    // vector loads only from 16-byte aligned bases
-    if (j0 + 8 <= ib1 && (reinterpret_cast<uintptr_t>(E) & 15) == 0) {
-      const float4 v0 = *reinterpret_cast<const float4*>(E + j0);
-      const float4 v1 = *reinterpret_cast<const float4*>(E + j0 + 4);
-      x[0] = v0.x; x[1] = v0.y; x[2] = v0.z; x[3] = v0.w;
-      x[4] = v1.x; x[5] = v1.y; x[6] = v1.z; x[7] = v1.w;
-    } else {
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        x[q] = (j0 + q < ib1) ? E[j0 + q] : (ws.log_src ? -INFINITY : 0.0f);
-    }
     if (ws.log_src) {
       const double mblk = sh.mb[lb];
 #pragma unroll
@@ -1513,14 +1511,21 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
   // 32 threads of a block are one half of a wave (exact: integers < 2^53)
   const double texcl = pair_row_scan_add(tsum) - tsum;
   const double f = sh.fb[lb], Pblk = sh.Pb[lb];
-  // each particle's slot bound at its CDF value (0, below every bound, for
-  // a particle of zero weight), and the last particle of positive weight
+  // each particle's slot bound at its CDF value C = Pblk + (texcl + kl) f,
+  // ceil(C n - u) clamped to [fs, fe], evaluated as one fma per particle:
+  // kl (n f) + (texcl (n f) + Pblk n - u). Rounding may move a bound by one
+  // where C n - u is within a few ulps of an integer; the running maximum
+  // below keeps the runs disjoint and ordered regardless. A particle of zero
+  // weight gets 0, below every bound; lp is the last particle of positive
+  // weight.
   int rb[8];
   int tmax = 0, lp = -1;
   const double fsd = (double)fs, fed = (double)fe;
+  const double fn = f * nd;
+  const double g = fma(texcl, fn, fma(Pblk, nd, -u));
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int bq = slot_bound_in(fma(texcl + kl[q], f, Pblk), u, nd, fsd, fed);
+    const int bq = (int)fmin(fmax(ceil(fma(kl[q], fn, g)), fsd), fed);
     rb[q] = wi[q] > 0.0 ? bq : 0;
     lp = wi[q] > 0.0 ? 8 * t + q : lp;
     tmax = max(tmax, rb[q]);
@@ -1536,15 +1541,13 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
   for (int q = 0; q < w; ++q) hprev = max(hprev, sh.w4[q]);
   const int last_pos = max(max(sh.l4[0], sh.l4[1]), max(sh.l4[2], sh.l4[3]));
   // runs: particle 8t+q owns the slots [st[q], hq[q]); the last particle of
-  // positive weight (and every particle after it) ends at the segment's end
+  // positive weight ends at the segment's end (the particles after it have
+  // zero weight, bound 0, and so empty runs)
   int st[8], hq[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int idx = 8 * t + q;
-    int lo = hprev, hv = max(hprev, rb[q]);
-    if (idx > last_pos) lo = hv = fe;  // no slots after the last positive weight
-    else if (idx == last_pos) hv = fe;
-    st[q] = lo;
+    const int hv = (8 * t + q == last_pos) ? fe : max(hprev, rb[q]);
+    st[q] = hprev;
     hq[q] = hv;
     hprev = hv;
   }
@@ -1584,10 +1587,13 @@ __device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const
       for (int k = 0; k < kk; ++k) sh.A[slot_pad(t * kk + k)] = max(before, v[k]);
       carry_item = max(carry_item, max(max(sh.w4[0], sh.w4[1]), max(sh.w4[2], sh.w4[3])));
       __syncthreads();
+      // (particle indices and slots are below n < 2^31)
+      int32_t* const out = anc + c0;
+      const int32_t base = (int32_t)ib0;
 #pragma unroll
       for (int k = 0; k < kk; ++k) {
         const int e = k * 256 + t;
-        if (e < cn) anc[c0 + e] = (int32_t)(ib0 + max(sh.A[slot_pad(e)] - 1, 0));
+        if (e < cn) out[e] = base + max(sh.A[slot_pad(e)] - 1, 0);
       }
       __syncthreads();  // sh.A and sh.w4 are rewritten by the next tile
     }
