@@ -67,6 +67,7 @@ def lib():
         L.orc_u53.argtypes = [u32, u32]
         L.orc_u53.restype = d
         L.orc_box_muller.argtypes = [u32, u32, P(d), P(d)]
+        L.orc_normal_fields.argtypes = [vp, vp, vp]
         L.orc_resample_uniform.argtypes = [P(_Model), i64]
         L.orc_resample_uniform.restype = d
         L.orc_rna_uniform.argtypes = [P(_Model), i64, i64]
@@ -178,9 +179,19 @@ def u53(a: int, b: int) -> float:
     return lib().orc_u53(a, b)
 
 
-def box_muller(a: int, b: int):
+def normal_fields(r) -> tuple:
+    """(radius fields, angle fields) of one Philox block of 4 words."""
+    w = np.ascontiguousarray(r, dtype=np.uint32).reshape(4)
+    rad = np.empty(3, dtype=np.uint32)
+    ang = np.empty(3, dtype=np.uint32)
+    lib().orc_normal_fields(_ptr(w), _ptr(rad), _ptr(ang))
+    return [int(v) for v in rad], [int(v) for v in ang]
+
+
+def box_muller(rad: int, ang: int):
+    """Box-Muller pair from a 24-bit radius field and an 18-bit angle field."""
     z0, z1 = ctypes.c_double(), ctypes.c_double()
-    lib().orc_box_muller(a, b, ctypes.byref(z0), ctypes.byref(z1))
+    lib().orc_box_muller(rad, ang, ctypes.byref(z0), ctypes.byref(z1))
     return z0.value, z1.value
 
 

@@ -87,10 +87,29 @@ double orc_u53(uint32_t a, uint32_t b) {
   return ldexp((double)a * 2097152.0 + (double)(b >> 11), -53);
 }
 
-/* Box-Muller: radius from a uniform in (0, 1], angle from one in [0, 1). */
-void orc_box_muller(uint32_t a, uint32_t b, double* z0, double* z1) {
-  const double radius = sqrt(-2.0 * log(orc_u24_open_lo(a)));
-  const double angle = 2.0 * M_PI * orc_u24_open_hi(b);
+/* The bit fields of one Philox block (words r[0..3], r[0] lowest) that the
+ * five normals take: three radius fields of 24 bits and three angle fields
+ * of 18 bits, laid end to end from bit 0 as radius 0, angle 0, radius 1,
+ * angle 1, radius 2, angle 2 (126 bits; the top two bits are unused). */
+void orc_normal_fields(const uint32_t r[4], uint32_t rad[3], uint32_t ang[3]) {
+  int pos = 0;
+  for (int f = 0; f < 6; ++f) {
+    const int width = f % 2 == 0 ? 24 : 18;
+    uint32_t v = 0;
+    for (int b = 0; b < width; ++b, ++pos)
+      v |= ((r[pos / 32] >> (pos % 32)) & 1u) << b;
+    if (f % 2 == 0)
+      rad[f / 2] = v;
+    else
+      ang[f / 2] = v;
+  }
+}
+
+/* Box-Muller from a 24-bit radius field (uniform (rad + 1) / 2^24 in (0, 1])
+ * and an 18-bit angle field (uniform ang / 2^18 in [0, 1)). */
+void orc_box_muller(uint32_t rad, uint32_t ang, double* z0, double* z1) {
+  const double radius = sqrt(-2.0 * log(ldexp((double)rad + 1.0, -24)));
+  const double angle = 2.0 * M_PI * ldexp((double)ang, -18);
   *z0 = radius * cos(angle);
   *z1 = radius * sin(angle);
 }
@@ -107,17 +126,18 @@ double orc_rna_uniform(const orc_model* m, int64_t g, int64_t k) {
   return orc_u53(r[0], r[1]);
 }
 
-/* Five standard normals for (index, k, purpose): words 0,1 and 2,3 of block
- * 0 give two pairs; words 0,1 of block 1 give the fifth (cosine branch). */
+/* Five standard normals for (index, k, purpose) from one Philox block: the
+ * field pairs (radius 0, angle 0) and (radius 1, angle 1) give z0, z1 and
+ * z2, z3; (radius 2, angle 2) gives z4 (cosine branch). */
 static void five_normals(const orc_model* m, uint32_t index, uint32_t k, uint32_t purpose,
                          double z[5]) {
-  uint32_t r0[4], r1[4];
+  uint32_t r[4], rad[3], ang[3];
   double unused;
-  draw(m, index, k, purpose, 0u, r0);
-  draw(m, index, k, purpose, 1u, r1);
-  orc_box_muller(r0[0], r0[1], &z[0], &z[1]);
-  orc_box_muller(r0[2], r0[3], &z[2], &z[3]);
-  orc_box_muller(r1[0], r1[1], &z[4], &unused);
+  draw(m, index, k, purpose, 0u, r);
+  orc_normal_fields(r, rad, ang);
+  orc_box_muller(rad[0], ang[0], &z[0], &z[1]);
+  orc_box_muller(rad[1], ang[1], &z[2], &z[3]);
+  orc_box_muller(rad[2], ang[2], &z[4], &unused);
 }
 
 /* ------------------------------------------------------ initialisation */

@@ -51,7 +51,10 @@ void orc_philox_many(uint64_t seed, int64_t n, const uint32_t* ctr, uint32_t* ou
 double orc_u24_open_hi(uint32_t a);   /* (a >> 8) / 2^24, in [0, 1)        */
 double orc_u24_open_lo(uint32_t a);   /* ((a >> 8) + 1) / 2^24, in (0, 1]  */
 double orc_u53(uint32_t a, uint32_t b); /* 53-bit uniform in [0, 1)        */
-void orc_box_muller(uint32_t a, uint32_t b, double* z0, double* z1);
+/* Radius (24-bit) and angle (18-bit) fields of one block, and Box-Muller
+ * from one radius field and one angle field. */
+void orc_normal_fields(const uint32_t r[4], uint32_t rad[3], uint32_t ang[3]);
+void orc_box_muller(uint32_t rad, uint32_t ang, double* z0, double* z1);
 
 /* Uniform of the systematic resampling at frame k; of RNA group g at k. */
 double orc_resample_uniform(const orc_model* m, int64_t k);

@@ -53,23 +53,42 @@ __device__ __forceinline__ uint4 draw(const Model& m, uint32_t index, uint32_t k
 
 // Uniforms from the top 24 bits: [0, 1) and (0, 1], exact in fp32.
 __device__ __forceinline__ float u24_open_hi(uint32_t a) { return (float)(a >> 8) * 0x1p-24f; }
-__device__ __forceinline__ float u24_open_lo(uint32_t a) {
-  return (float)((a >> 8) + 1u) * 0x1p-24f;
-}
 __device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
   return ((double)a * 2097152.0 + (double)(b >> 11)) * 0x1p-53;
 }
 
-// Box-Muller in fp32. The radius sqrt(-2 ln u), u in (0, 1], uses the
-// hardware log2 and square root (measured over all 2^24 uniforms: at most
-// 1.9 ulp for ln u, 0.9 ulp for the root). The angle 2 pi t, t in [0, 1),
-// is reduced exactly: x = 4 t, q = rint(x), r = x - q in [-1/2, 1/2], and
-// sin, cos(2 pi t) are sin, cos(pi/2 r) rotated by the quadrant q, from the
-// Taylor series in r to degree 9 and 10 (truncation below 2e-9; measured at
-// most 8.8e-8 absolute with fp32 rounding).
-__device__ __forceinline__ float bm_radius(uint32_t a) {
+// The five normals of a particle come from one Philox block: three radius
+// fields of 24 bits and three angle fields of 18 bits, laid end to end from
+// bit 0 of word x as radius 0, angle 0, radius 1, angle 1, radius 2, angle 2
+// (126 of the 128 bits). A radius field r is the uniform (r + 1) / 2^24 in
+// (0, 1] and an angle field a the uniform a / 2^18 in [0, 1), both exact in
+// fp32.
+struct NormalFields {
+  uint32_t r0, a0, r1, a1, r2, a2;
+};
+__device__ __forceinline__ NormalFields normal_fields(uint4 w) {
+  NormalFields f;
+  f.r0 = w.x & 0xFFFFFFu;                                           // bits 0-23
+  f.a0 = __builtin_amdgcn_alignbit(w.y, w.x, 24) & 0x3FFFFu;        // bits 24-41
+  f.r1 = __builtin_amdgcn_alignbit(w.z, w.y, 10) & 0xFFFFFFu;       // bits 42-65
+  f.a1 = __builtin_amdgcn_ubfe(w.z, 2, 18);                         // bits 66-83
+  f.r2 = __builtin_amdgcn_alignbit(w.w, w.z, 20) & 0xFFFFFFu;       // bits 84-107
+  f.a2 = __builtin_amdgcn_ubfe(w.w, 12, 18);                        // bits 108-125
+  return f;
+}
+
+// Box-Muller in fp32 from a radius field r and an angle field a. The radius
+// sqrt(-2 ln u), u in (0, 1], uses the hardware log2 and square root
+// (measured over all 2^24 uniforms: at most 1.9 ulp for ln u, 0.9 ulp for
+// the root). The angle 2 pi t, t in [0, 1), is reduced exactly: x = 4 t,
+// q = rint(x), r = x - q in [-1/2, 1/2], and sin, cos(2 pi t) are
+// sin, cos(pi/2 r) rotated by the quadrant q, from the Taylor series in r to
+// degree 9 and 10 (truncation below 2e-9; measured at most 8.8e-8 absolute
+// with fp32 rounding).
+__device__ __forceinline__ float bm_radius(uint32_t r) {
   // -2 ln u = -(2 ln 2) log2 u
-  return __builtin_amdgcn_sqrtf(-0x1.62e430p+0f * __builtin_amdgcn_logf(u24_open_lo(a)));
+  return __builtin_amdgcn_sqrtf(-0x1.62e430p+0f *
+                                __builtin_amdgcn_logf((float)(r + 1u) * 0x1p-24f));
 }
 
 __device__ __forceinline__ float sin_halfpi(float r, float r2) {
@@ -90,9 +109,9 @@ __device__ __forceinline__ float cos_halfpi(float r2) {
   return fmaf(p, r2, 1.0f);
 }
 
-__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
-  const float rad = bm_radius(a);
-  const float x = (float)(b >> 8) * 0x1p-22f;  // 4 t, exact
+__device__ __forceinline__ void box_muller(uint32_t rf, uint32_t af, float& z0, float& z1) {
+  const float rad = bm_radius(rf);
+  const float x = (float)af * 0x1p-16f;  // 4 t, exact
   const float q = rintf(x);
   const float r = x - q, r2 = r * r;
   const float sn = sin_halfpi(r, r2), cs = cos_halfpi(r2);
@@ -103,9 +122,9 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
 }
 
 // The cosine branch alone.
-__device__ __forceinline__ float box_muller_cos(uint32_t a, uint32_t b) {
-  const float rad = bm_radius(a);
-  const float x = (float)(b >> 8) * 0x1p-22f;
+__device__ __forceinline__ float box_muller_cos(uint32_t rf, uint32_t af) {
+  const float rad = bm_radius(rf);
+  const float x = (float)af * 0x1p-16f;
   const float q = rintf(x);
   const float r = x - q, r2 = r * r;
   const int qi = (int)q & 3;
@@ -113,10 +132,10 @@ __device__ __forceinline__ float box_muller_cos(uint32_t a, uint32_t b) {
   return rad * (((qi + 1) & 2) ? -cc : cc);
 }
 
-__device__ __forceinline__ void box_muller64(uint32_t a, uint32_t b, double& z0, double& z1) {
-  const double rad = sqrt(-2.0 * log((double)u24_open_lo(a)));
+__device__ __forceinline__ void box_muller64(uint32_t r, uint32_t a, double& z0, double& z1) {
+  const double rad = sqrt(-2.0 * log(((double)r + 1.0) * 0x1p-24));
   double s, c;
-  sincospi(2.0 * (double)u24_open_hi(b), &s, &c);
+  sincospi((double)a * 0x1p-17, &s, &c);  // 2 t
   z0 = rad * c;
   z1 = rad * s;
 }
@@ -392,9 +411,10 @@ __device__ __forceinline__ void init_body(const Model& m, const Buffers& b, int6
   double x[5];
   if (m.init_kind == 1) {  // Gaussian
     double z[5], unused;
-    box_muller64(r0.x, r0.y, z[0], z[1]);
-    box_muller64(r0.z, r0.w, z[2], z[3]);
-    box_muller64(r1.x, r1.y, z[4], unused);
+    const NormalFields nf = normal_fields(r0);
+    box_muller64(nf.r0, nf.a0, z[0], z[1]);
+    box_muller64(nf.r1, nf.a1, z[2], z[3]);
+    box_muller64(nf.r2, nf.a2, z[4], unused);
 #pragma unroll
     for (int d = 0; d < 5; ++d) x[d] = (double)m.init_a[d] + (double)m.init_b[d] * z[d];
   } else {
@@ -470,12 +490,11 @@ __device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int 
   const int64_t n = m.n;
   const float px = Xin[p], py = Xin[n + p], pvx = Xin[2 * n + p], pvy = Xin[3 * n + p],
               pI = Xin[4 * n + p];
-  const uint4 r0 = draw(m, (uint32_t)i, k, kPropagate, 0u);
-  const uint4 r1 = draw(m, (uint32_t)i, k, kPropagate, 1u);
+  const NormalFields nf = normal_fields(draw(m, (uint32_t)i, k, kPropagate, 0u));
   float z0, z1, z2, z3;
-  box_muller(r0.x, r0.y, z0, z1);
-  box_muller(r0.z, r0.w, z2, z3);
-  const float z4 = box_muller_cos(r1.x, r1.y);
+  box_muller(nf.r0, nf.a0, z0, z1);
+  box_muller(nf.r1, nf.a1, z2, z3);
+  const float z4 = box_muller_cos(nf.r2, nf.a2);
   if (zo) {
     zo[0] = z0;
     zo[1] = z1;

@@ -89,17 +89,60 @@ def test_uniform_conversions_exact(orc):
     assert orc.u53(0, (1 << 11) - 1) == 0.0
 
 
+WIDTHS = (24, 18, 24, 18, 24, 18)  # radius 0, angle 0, radius 1, angle 1, radius 2, angle 2
+
+
+def fields_flat(orc, words):
+    rad, ang = orc.normal_fields(np.array(words, dtype=np.uint32))
+    return [rad[0], ang[0], rad[1], ang[1], rad[2], ang[2]]
+
+
+def test_normal_fields_partition_the_block(orc):
+    # every one of the low 126 bits of the block moves exactly one bit of
+    # exactly one field, in order; the top two bits move nothing
+    rng = np.random.default_rng(8)
+    base = [int(x) for x in rng.integers(0, 2**32, 4, dtype=np.uint64)]
+    f0 = fields_flat(orc, base)
+    for f, w in zip(f0, WIDTHS):
+        assert 0 <= f < (1 << w)
+    seen = []
+    for bit in range(128):
+        words = list(base)
+        words[bit // 32] ^= 1 << (bit % 32)
+        diff = [(i, a ^ b) for i, (a, b) in enumerate(zip(f0, fields_flat(orc, words))) if a != b]
+        if bit >= 126:
+            assert diff == []
+            continue
+        assert len(diff) == 1 and bin(diff[0][1]).count("1") == 1
+        seen.append((diff[0][0], diff[0][1].bit_length() - 1))
+    # bits 0..125 map to (field, bit) in lexicographic order: a bijection
+    assert seen == [(i, b) for i, w in enumerate(WIDTHS) for b in range(w)]
+    # the same fields read from the block as one 128-bit integer
+    for words in rng.integers(0, 2**32, (50, 4), dtype=np.uint64):
+        X = sum(int(v) << (32 * j) for j, v in enumerate(words))
+        off, ref = 0, []
+        for w in WIDTHS:
+            ref.append((X >> off) & ((1 << w) - 1))
+            off += w
+        assert fields_flat(orc, [int(v) for v in words]) == ref
+
+
 def test_box_muller_polar_identities(orc):
     rng = np.random.default_rng(5)
-    for a, b in rng.integers(0, 2**32, (500, 2), dtype=np.uint64):
-        a, b = int(a), int(b)
-        z0, z1 = orc.box_muller(a, b)
-        u1, u2 = orc.u24_open_lo(a), orc.u24_open_hi(b)
+    for rad, ang in zip(rng.integers(0, 2**24, 500), rng.integers(0, 2**18, 500)):
+        rad, ang = int(rad), int(ang)
+        z0, z1 = orc.box_muller(rad, ang)
+        u1, u2 = (rad + 1) / 2.0**24, ang / 2.0**18
         assert math.isclose(z0 * z0 + z1 * z1, -2.0 * math.log(u1), rel_tol=1e-12, abs_tol=1e-300)
         if z0 * z0 + z1 * z1 > 1e-20:
-            ang = math.atan2(z1, z0) % (2 * math.pi)
-            d = abs(ang - 2 * math.pi * u2)
+            a = math.atan2(z1, z0) % (2 * math.pi)
+            d = abs(a - 2 * math.pi * u2)
             assert min(d, 2 * math.pi - d) < 1e-9
+    # the extreme fields: radius field 2^24 - 1 is u = 1 (z = 0), field 0 the
+    # largest radius; angle field 0 is angle 0
+    assert orc.box_muller(2**24 - 1, 12345) == (0.0, 0.0)
+    z0, z1 = orc.box_muller(0, 0)
+    assert z1 == 0.0 and math.isclose(z0, math.sqrt(-2.0 * math.log(2.0**-24)), rel_tol=1e-15)
 
 
 def test_box_muller_is_standard_normal(orc):
@@ -107,7 +150,12 @@ def test_box_muller_is_standard_normal(orc):
     ctr = np.zeros((n, 4), dtype=np.uint32)
     ctr[:, 0] = np.arange(n)
     w = orc.philox(11, ctr)
-    z = np.array([orc.box_muller(int(r[0]), int(r[1])) for r in w]).ravel()
+    z = []
+    for r in w:
+        rad, ang = orc.normal_fields(r)
+        for j in range(3):
+            z.extend(orc.box_muller(rad[j], ang[j]))
+    z = np.array(z)
     assert stats.kstest(z, "norm").pvalue > 1e-3
     assert abs(z.mean()) < 0.03 and abs(z.std() - 1) < 0.02
     # truncation of the tail at sqrt(-2 log 2^-24)
