@@ -52,7 +52,7 @@ constexpr int kCoopSlots = 1 << 16;
 constexpr int kSlotTile = 2048;  // slots per LDS tile of the segment's writes
 constexpr int kFillChunk = 1 << 16;
 constexpr int kFillGrid = 2048;
-constexpr int kFillGridBatch = 64;  // workgroups per track of a batched fill
+constexpr int kFillGridBatch = 8;  // workgroups per track of a batched fill (a heavy fill gets 2048 threads; most frames queue nothing)
 // Batched steps run every patch size up to this one in a single launch (the
 // sizes that fit five waves per SIMD); wider patches launch per size.
 constexpr int kFusedMaxP = 13;
