@@ -529,9 +529,11 @@ __device__ __forceinline__ void store_state(const Model& m, const Buffers& b, in
 
 // Fixed-point weight of a particle whose weight relative to its block
 // maximum is e in [0, 1]: round(e 2^44), an exact integer held in a double
-// (the fma rounds once, the subtraction is exact).
+// (e 2^44 is an exact exponent shift below 2^52; rint rounds it once, half
+// to even).
 __device__ __forceinline__ double item_weight(double e) {
-  return fma(e, kItemScale, 0x1p52) - 0x1p52;
+  static_assert(kItemScale == 0x1p44, "the scale is applied as an exponent shift");
+  return rint(ldexp(e, 44));
 }
 
 // e^x for x <= 0 rounded to fp32 (0 below -104, where e^x is under half the
