@@ -33,6 +33,9 @@
  *     purpose << 24 | block, track_id) with purposes INIT=1, PROPAGATE=2,
  *     RESAMPLE=3, RNA=4, so every draw of a run is a pure function of
  *     (seed, track_id, k, index): a run is reproducible and restartable.
+ *     A particle's five process-noise normals come from one block (block 0):
+ *     three 24-bit radius and three 18-bit angle fields, laid end to end from
+ *     bit 0 of word 0, through Box-Muller.
  */
 #ifndef PPF_H
 #define PPF_H
