@@ -1054,16 +1054,36 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     l = prior_lw(m, b, cur, mode, cdelta, ia) - ssq * m.inv2sig2 - m.lognorm_obs;
   }
   const double e = finish_block(b, cur, i, active, l, o, tile, dsh, L.ksh);
-  if (GRAD) {
-    // the block's sum_i E_i d l_i / d theta, weighted like the MMSE sums
-    __shared__ double gsh[4 * kNGrad];
+  if constexpr (GRAD) {
+    // the block's sum_i E_i d l_i / d theta, weighted like the MMSE sums and
+    // reduced the same way: derivatives 0-7 through the tile, 8 through the
+    // table's space, eight consecutive entries per thread, then rows
+    static_assert(kNGrad == 9 && TILE >= 8 * kBlock && kSqCap >= kBlock,
+                  "eight derivatives fill the tile, the ninth goes to the table");
     double v[kNGrad];
 #pragma unroll
     for (int d = 0; d < kNGrad; ++d) v[d] = (e > 0.0) ? e * gth[d] : 0.0;
-    block_sum_n<kNGrad>(v, gsh);
-    if (t == 0)
+    __syncthreads();  // every thread is past finish_block's reads of the tile
 #pragma unroll
-      for (int d = 0; d < kNGrad; ++d) b.RG[blk * kNGrad + d] = v[d];
+    for (int d = 0; d < 8; ++d) tile[d * kBlock + t] = v[d];
+    sq[t] = v[8];
+    __syncthreads();
+    const double* p = tile + (t >> 5) * kBlock + (t & 31) * 8;
+    double s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+    s = pair_rows(row_allreduce(s, OpAdd()), OpAdd(), 0.0);
+    double* RGb = b.RG + blk * kNGrad;
+    // derivative 2w in row 1 of wave w, 2w + 1 in row 3
+    if (t == 64 * w + 16) RGb[2 * w] = s;
+    if (t == 64 * w + 48) RGb[2 * w + 1] = s;
+    if (w == 0) {  // uniform: the first wave sums derivative 8
+      double s8 = 0.0;
+      if (t < 32) {
+        const double* q = sq + t * 8;
+        s8 = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+      }
+      s8 = pair_rows(row_allreduce(s8, OpAdd()), OpAdd(), 0.0);
+      if (t == 16) RGb[8] = s8;
+    }
   }
 }
 
