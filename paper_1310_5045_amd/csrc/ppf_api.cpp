@@ -953,6 +953,8 @@ struct ppf_batch_ctx : Runner {
   // The step launches of every track (one range after another).
   hipError_t launch_steps(const float* obs) {
     hipError_t e = hipSuccess;
+    // each range steps its own tracks: in a graph the launches may overlap
+    ppf::launch_group_begin();
     for (const auto& r : plan.step_ranges) {
       const ppf::BatchItem* it = d_blocks + r.first;
       e = r.P == 0 ? ppf::launch_step_batch_fused(r.shape, d_models, d_bufs, it, r.count, obs,
@@ -960,6 +962,7 @@ struct ppf_batch_ctx : Runner {
                    : ppf::launch_step_batch(r.P, d_models, d_bufs, it, r.count, obs, stream);
       if (e != hipSuccess) break;
     }
+    ppf::launch_group_end();
     return e;
   }
   // Fused step launches per tuning candidate: 0 every fused size in shape 0,

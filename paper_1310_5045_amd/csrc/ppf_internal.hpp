@@ -269,6 +269,10 @@ class StepGraph {
   hipError_t add(const void* fn, dim3 grid, dim3 block, std::unique_ptr<Args> args,
                  std::vector<void*> argv, std::vector<const float**> frame_slots);
   const float* frame() const { return frame_; }
+  // Nodes added between group_begin and group_end depend only on what came
+  // before the group, and the first node after it on all of them.
+  void group_begin();
+  void group_end();
 
  private:
   struct Node {
@@ -282,6 +286,14 @@ class StepGraph {
   hipGraphExec_t exec_ = nullptr;
   std::vector<Node> nodes_;
   const float* frame_ = nullptr;
+  std::vector<hipGraphNode_t> deps_;   // what the next node depends on
+  bool in_group_ = false;
+  std::vector<hipGraphNode_t> group_;  // the nodes of the open group
 };
+
+// Launches between these two calls may run concurrently when a graph records
+// them (they must touch disjoint data); on a stream they run in order.
+void launch_group_begin();
+void launch_group_end();
 
 }  // namespace ppf

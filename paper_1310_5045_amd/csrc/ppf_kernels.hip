@@ -2289,12 +2289,34 @@ hipError_t StepGraph::add(const void* fn, dim3 grid, dim3 block, std::unique_ptr
   n.params.sharedMemBytes = 0;
   n.params.kernelParams = n.argv.data();  // moving the vector keeps its storage
   n.params.extra = nullptr;
-  hipGraphNode_t dep = nodes_.empty() ? nullptr : nodes_.back().node;
-  const hipError_t e =
-      hipGraphAddKernelNode(&n.node, graph_, dep ? &dep : nullptr, dep ? 1 : 0, &n.params);
+  const hipGraphNode_t* deps = deps_.empty() ? nullptr : deps_.data();
+  const hipError_t e = hipGraphAddKernelNode(&n.node, graph_, deps, deps_.size(), &n.params);
   if (e != hipSuccess) return e;
+  if (in_group_)
+    group_.push_back(n.node);
+  else
+    deps_.assign(1, n.node);
   nodes_.push_back(std::move(n));
   return hipSuccess;
+}
+
+void StepGraph::group_begin() {
+  in_group_ = true;
+  group_.clear();
+}
+
+void StepGraph::group_end() {
+  in_group_ = false;
+  if (!group_.empty()) deps_ = group_;
+  group_.clear();
+}
+
+void launch_group_begin() {
+  if (t_rec) t_rec->group_begin();
+}
+
+void launch_group_end() {
+  if (t_rec) t_rec->group_end();
 }
 
 hipError_t StepGraph::set_frame(const float* frame) {
