@@ -976,6 +976,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   // every lane's patch lies in the tile (the tail lanes' is particle
   // n - 1's); finish_block ignores the tail lanes' l
   double l;
+  int64_t il = i;  // the particle index where the record is written
   double gth[GRAD ? kNGrad : 1] = {};
   // the particle's first patch row in copy A (even first column) or B (odd)
   const int col0 = cx - h - tx0;
@@ -1049,11 +1050,20 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     } else {
       patch_global<P>(obs, cx - h, cy - h, m.W, m.H, m.b, gx, gy0, by, m.gstep, X, G2y, sd2);
     }
+    if constexpr (TILE < kTileCap) {
+      // the six-wave shape: the particle index again, from a fresh copy of
+      // the thread index, instead of two registers held across the patch
+      // sums (they made 13 x 13 spill there)
+      int tl = t;
+      asm volatile("" : "+v"(tl));
+      il = blk * kBlock + tl;
+    }
+    const int64_t ial = il < m.n ? il : m.n - 1;
     const double I = (double)o.I;
     const double ssq = sd2 - 2.0 * I * X + I * I * (G2x * G2y);
-    l = prior_lw(m, b, cur, mode, cdelta, ia) - ssq * m.inv2sig2 - m.lognorm_obs;
+    l = prior_lw(m, b, cur, mode, cdelta, ial) - ssq * m.inv2sig2 - m.lognorm_obs;
   }
-  const double e = finish_block(b, cur, i, active, l, o, tile, dsh, L.ksh);
+  const double e = finish_block(b, cur, il, active, l, o, tile, dsh, L.ksh);
   if constexpr (GRAD) {
     // the block's sum_i E_i d l_i / d theta, weighted like the MMSE sums and
     // reduced the same way: derivatives 0-7 through the tile, 8 through the
