@@ -8,7 +8,17 @@ normalisation/ESS + resampling for all N particles. Frames are synthetic
 (paper_1310_5045_amd.synth) and resident on the GPU before timing starts;
 filter initialisation is outside the timed region.
 
-Prints one JSON line. `value` is N * steps / wall time of the timed steps.
+Prints one JSON line. `value` is N * steps / GPU time of the timed steps
+(two HIP events on the filter's stream around them).
+
+No figure is printed (exit status 3) when the filter's output fails a check:
+after the timed steps the final ESS, the tracking error, the normalisation,
+ESS and estimate against the particles' own weights, and the resampling
+invariants of the last step are checked on the GPU's output; the
+cpu_baseline leg then runs one more step and checks it against the oracle on
+sampled particles (propagation, log weights, every ancestor). The same
+workload is also timed from the other initial cloud (`init_alternative`:
+uniform when the headline uses the stratified cloud, and the reverse).
 `roofline` covers the dominant kernel (k_step) against the fp64 vector peak;
 `roofline_resample` covers the ancestor passes against HBM bandwidth; both
 use algorithmic work per launch / average launch time measured with HIP
@@ -53,7 +63,8 @@ def kernel_source_hash():
 
 
 def traffic_path(kernel, workload, shape):
-    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_shape{shape}_{workload}.json")
+    tag = f"_shape{shape}" if shape is not None else ""
+    return os.path.join(ROOT, "profiles", f"traffic_{kernel}{tag}_{workload}.json")
 
 
 def _counter_per_dispatch(db, counter):
@@ -65,58 +76,81 @@ def _counter_per_dispatch(db, counter):
     return {d: (k, v) for d, k, c, v in rows if c == counter}
 
 
-def traffic_from(fetch_db, write_db, workload, copy_mib, warmup, steps, shape, kernel="k_step",
-                 match="k_step_spot"):
-    """Writes the traffic record of `kernel` in workgroup shape `shape` from a
-    FETCH_SIZE and a WRITE_SIZE counter database of `bench.py --copy-probe-mib
-    copy_mib --shape shape` runs with the given warm-up and timed steps; the
-    average covers the timed launches (the last `steps` of the kernel)."""
+# Kernel groups with traffic records: the kernel names a group's dispatches
+# carry, and whether the record depends on the step kernel's workgroup shape.
+TRAFFIC_GROUPS = {
+    "k_step": dict(match=("k_step_spot",), per_shape=True),
+    # the resampling pair: the ancestor pass and its long-run fill, per step
+    "k_resample": dict(match=("k_anc", "k_fill"), per_shape=False),
+}
+
+
+def traffic_from(fetch_db, write_db, workload, copy_mib, warmup, steps, shape, kernel="k_step"):
+    """Writes the traffic record of kernel group `kernel` (TRAFFIC_GROUPS)
+    from a FETCH_SIZE and a WRITE_SIZE counter database of `bench.py
+    --copy-probe-mib copy_mib --shape shape` runs with the given warm-up and
+    timed steps: each counter's average over the timed launches (the last
+    `steps` dispatches of each kernel of the group, summed over the group's
+    kernels), scaled by what the counter reads for the device copy of
+    copy_mib MiB."""
+    grp = TRAFFIC_GROUPS[kernel]
     copy_bytes = copy_mib * (1 << 20)
     per = {}
     for name, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
         d = _counter_per_dispatch(db, name)
-        names = [d[i][0] for i in sorted(d) if match in d[i][0]]
-        ker = [d[i][1] for i in sorted(d) if match in d[i][0]]
-        # k_step_spot<P, S>: the timed launches must all be of shape S
-        tag = f", {shape}>"
-        if not names or any(tag not in nm for nm in names[-steps:]):
-            raise SystemExit(f"{db}: the timed {match} launches are not all of shape {shape}")
-        if len(ker) < steps + warmup:
-            raise SystemExit(f"{db}: {len(ker)} {match} dispatches, expected at least "
-                             f"{steps + warmup}")
-        ker = ker[-steps:]
+        avg_kib, launches = 0.0, {}
+        for match in grp["match"]:
+            names = [d[i][0] for i in sorted(d) if match in d[i][0]]
+            ker = [d[i][1] for i in sorted(d) if match in d[i][0]]
+            if grp["per_shape"]:
+                # k_step_spot<P, S>: the timed launches must all be of shape S
+                tag = f", {shape}>"
+                if not names or any(tag not in nm for nm in names[-steps:]):
+                    raise SystemExit(f"{db}: the timed {match} launches are not all of shape "
+                                     f"{shape}")
+            if len(ker) < steps + warmup:
+                raise SystemExit(f"{db}: {len(ker)} {match} dispatches, expected at least "
+                                 f"{steps + warmup}")
+            ker = ker[-steps:]
+            avg_kib += sum(ker) / len(ker)
+            launches[match] = len(ker)
         # the probe copies copy_bytes: the largest reading among the kernels
         # named like a copy
         cp = ([v for k, v in d.values() if "copy" in k.lower()] or
               [v for k, v in d.values() if "elementwise" in k.lower()])
-        if not ker or not cp:
-            raise SystemExit(f"{db}: no {match} or copy dispatches with {name}")
+        if not cp:
+            raise SystemExit(f"{db}: no copy dispatches with {name}")
         kib_copy = max(cp)
-        per[name] = dict(kernel_kib_avg=sum(ker) / len(ker), launches=len(ker), copy_kib=kib_copy,
+        per[name] = dict(kernel_kib_avg=avg_kib, launches=launches, copy_kib=kib_copy,
                          scale=copy_bytes / (kib_copy * 1024.0))
     traffic = sum(per[c]["kernel_kib_avg"] * 1024.0 * per[c]["scale"] for c in per)
-    rec = {"kernel": kernel, "shape": shape, "workload": workload,
+    shp = shape if grp["per_shape"] else None
+    rec = {"kernel": kernel, "shape": shp, "workload": workload,
            "source_sha256": kernel_source_hash(),
            "traffic_bytes_per_launch": traffic, "copy_probe_bytes": copy_bytes,
            "counters": per,
            "command": [f"rocprofv3 --kernel-trace --pmc {c} -d <dir> -o run -- python3 bench.py "
-                       f"--steps {steps} --warmup {warmup} --no-cpu-baseline "
+                       f"--steps {steps} --warmup {warmup} --no-cpu-baseline --no-alt-init "
                        f"--copy-probe-mib {copy_mib} --shape {shape}" for c in per]}
-    with open(traffic_path(kernel, workload, shape), "w") as fh:
+    with open(traffic_path(kernel, workload, shp), "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     return rec
 
 
 def load_traffic(kernel, workload, shape):
+    """Bytes per launch of a traffic record, while its kernel sources match
+    (None otherwise)."""
+    shp = shape if TRAFFIC_GROUPS[kernel]["per_shape"] else None
     try:
-        with open(traffic_path(kernel, workload, shape)) as fh:
+        with open(traffic_path(kernel, workload, shp)) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256") != kernel_source_hash():
         return None
     return rec["traffic_bytes_per_launch"]
+
 
 WORKLOADS = {
     # frame size, frames, particles, spot width, patch, resampling threshold
@@ -167,6 +201,8 @@ def multitrack_setup(ppf, synth, w):
 
 
 def run_multitrack(args, w):
+    import math
+
     import numpy as np
     import torch
 
@@ -188,6 +224,11 @@ def run_multitrack(args, w):
     achieved_tf = flops / (step_ms / 1e3) / 1e12 if step_ms > 0 else 0.0
     err = [float(np.linalg.norm(sts[t]["mean"][:2] - mv.truth[(K - 1) % T, t]))
            for t in range(len(ps))]
+    bad = [t for t in range(len(ps)) if not (math.isfinite(sts[t]["ess"]) and sts[t]["ess"] > 1.0)]
+    if bad:
+        raise GateError(f"tracks {bad[:8]} end with ESS <= 1 or not finite")
+    if not float(np.median(err)) <= 1.0:
+        raise GateError(f"median tracking error {np.median(err):.3f} px")
     out = {
         "metric": "particle updates/s, 256 independent tracks batched on 1 GPU",
         "value": ntot * K / (gpu_ms / 1e3),
@@ -215,8 +256,23 @@ def run_multitrack(args, w):
         "kernel_launches": {k: v[0] for k, v in kt.items()},
         "wall_s": wall,
         "tracking_error_px_median": float(np.median(err)),
+        "checks": "passed",
     }
     b.close()
+    del b
+    # plain SIR on the same GPU (the 38M single-filter workload), for the ratio
+    pw = WORKLOADS["sir_1024x1024_n38m_p13"]
+    pmv = synth.render_movie(pw["W"], pw["H"], pw["T"], intensity=30.0, sigma=pw["s"],
+                             background=10.0, noise_sd=3.0, seed=1)
+    pframes = torch.from_numpy(pmv.frames).cuda()
+    pf = ppf.Filter(make_params(ppf, pw, ppf.INIT_STRATIFIED))
+    pms, _, _, _, _ = timed_steps(torch, pf, pframes, K, Wm, pw["T"], False, None)
+    check_state(ppf, pf, pw, pmv, (K - 1) % pw["T"], 0)
+    pf.close()
+    plain = pw["n"] * K / (pms / 1e3)
+    out["plain_sir"] = {"workload": "sir_1024x1024_n38m_p13", "value": plain,
+                        "ms_per_step": pms / K}
+    out["ratio_to_plain"] = out["value"] / plain
     print(json.dumps(out), flush=True)
 
 
@@ -286,23 +342,170 @@ def timed_steps(torch, f, frames, K, Wm, T, graph, shape):
     return gpu_ms, wall, kt, tuned, ran
 
 
-def cpu_baseline(w, frames, sample_n, sample_t, init_kind):
-    """The oracle as it stands, single-threaded, on a bounded sample: the
-    first `sample_t` frames of the same movie with `sample_n` particles."""
+def host_cpu():
+    """(CPU model name, logical cores this process may run on)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def oracle_model(w, n, init_kind):
+    """The oracle's model of a single-filter workload with n particles."""
     import oracle
     x0, x1, y0, y1 = w.get("box", (0, w["W"], 0, w["H"]))
     I = w.get("I", 30.0)
-    m = oracle.Model(n=sample_n, width=w["W"], height=w["H"], s=w["s"], b=10.0, sigma=3.0,
-                     patch=w["P"], init_kind=init_kind, init_a=(x0, y0, -1, -1, I / 2),
-                     init_b=(x1, y1, 1, 1, 1.5 * I), ess_threshold=w["thr"], seed=1)
-    t0 = time.perf_counter()
-    r = oracle.run(m, frames[:sample_t], sample_t)
-    dt = time.perf_counter() - t0
-    assert r.status == 0
-    return {"value": sample_n * sample_t / dt, "unit": "particle updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{sample_t} frames x {sample_n} particles of the same workload "
-                      f"(fp64, one thread, {dt:.1f} s)"}
+    resample, group, _ = w.get("scheme", (0, 256, 0))
+    return oracle.Model(n=n, width=w["W"], height=w["H"], s=w["s"], b=10.0, sigma=3.0,
+                        patch=w["P"], init_kind=init_kind, init_a=(x0, y0, -1, -1, I / 2),
+                        init_b=(x1, y1, 1, 1, 1.5 * I), ess_threshold=w["thr"], seed=1,
+                        resample=1 if resample == 1 else 0, rna_group=group)
+
+
+def cpu_baseline(w, frames, sample_n, sample_t, init_kind, threads):
+    """The oracle as it stands on a bounded sample (the first `sample_t`
+    frames of the same movie with `sample_n` particles), once on one host
+    thread and once on `threads` (its per-particle loops of propagation and
+    Eq. 4 in parallel, every reduction sequential: the same results)."""
+    import oracle
+    model, _ = host_cpu()
+    out = {}
+    for th, n_s in ((1, sample_n), (threads, sample_n * max(1, min(threads, 16)) // 4)):
+        used = oracle.set_threads(th)
+        m = oracle_model(w, n_s, init_kind)
+        t0 = time.perf_counter()
+        r = oracle.run(m, frames[:sample_t], sample_t)
+        dt = time.perf_counter() - t0
+        if r.status != 0:
+            raise SystemExit(f"oracle run failed ({r.status})")
+        out[used] = {"value": n_s * sample_t / dt, "unit": "particle updates/s", "cores": used,
+                     "kind": "oracle",
+                     "sample": f"{sample_t} frames x {n_s} particles of the same workload "
+                               f"(fp64, {used} host thread{'s' if used > 1 else ''}, {dt:.1f} s)",
+                     "cpu_model": model}
+    best = out[max(out)]
+    best["single_thread"] = {k: v for k, v in out[1].items() if k != "cpu_model"}
+    return best
+
+
+class GateError(Exception):
+    """The filter's output failed a correctness check: no figure is printed."""
+
+
+def check_state(ppf, f, w, mv, k_truth, scheme):
+    """Checks on the GPU's own output after the timed steps, none of which
+    uses the oracle: the final ESS, the tracking error against the synthetic
+    truth (single spot, proportional resampling: at most 1 px), the
+    normalised weights summing to one with the reported ESS and estimate,
+    and the resampling invariants of the last step (systematic: ancestors
+    non-decreasing; systematic and RPA: each particle's offspring count
+    within one of N w; RNA: every slot's ancestor in its own group, or in the
+    group before for the exchanged tail)."""
+    import math
+
+    import numpy as np
+    st = f.stats()
+    n = f.n
+    if not (math.isfinite(st["ess"]) and st["ess"] > 1.0):
+        raise GateError(f"final ESS {st['ess']}")
+    err = float(np.linalg.norm(st["mean"][:2] - mv.truth[k_truth, 0]))
+    if scheme != 1 and not err <= 1.0:
+        raise GateError(f"tracking error {err:.3f} px")
+    x, lw, anc = f.particles()
+    wt = np.exp(lw)
+    tot = math.fsum(wt)
+    if not abs(tot - 1.0) < 1e-5:
+        raise GateError(f"weights sum to {tot}")
+    if not math.isclose(1.0 / float(np.dot(wt, wt)), st["ess"], rel_tol=1e-4):
+        raise GateError("ESS does not match the weights")
+    mean = np.array([np.dot(wt, x[d].astype(np.float64)) for d in range(5)])
+    if not np.abs(mean - st["mean"]).max() <= 1e-3:
+        raise GateError(f"estimate {st['mean']} does not match the weights {mean}")
+    if st["resampled"]:
+        if anc.min() < 0 or anc.max() >= n:
+            raise GateError("ancestor out of range")
+        if scheme == 1:
+            g = np.arange(n) // w["scheme"][1]
+            grp, moved = w["scheme"][1], int(math.floor(float(np.float32(0.1)) * w["scheme"][1]))
+            tail = (np.arange(n) % grp) >= grp - moved
+            src = np.where(tail, (g - 1) % (n // grp), g)
+            if not np.array_equal(anc // grp, src):
+                raise GateError("RNA ancestor outside its group")
+        else:
+            if scheme == 0 and np.any(np.diff(anc) < 0):
+                raise GateError("systematic ancestors not non-decreasing")
+            cnt = np.bincount(anc, minlength=n)
+            if np.any(np.abs(cnt - n * wt) >= 2.0) or np.any(cnt[wt == 0] > 0):
+                raise GateError("offspring counts off their floor/ceil of N w")
+    return err, st
+
+
+def oracle_check_step(f, w, frames, frames_dev, T, init_kind):
+    """One more step after the timed ones, checked against the oracle on
+    sampled particles: their propagation from the GPU's parents, their log
+    weights (Eq. 4 plus the carried weight, against the GPU's log weight plus
+    its normaliser; relative 1e-5 where it matters), and, for systematic
+    resampling, every ancestor (the oracle's resampling of the GPU's weights
+    with the same uniform: identical outside a 1e-9 band around the CDF
+    steps)."""
+    import math
+
+    import numpy as np
+
+    import oracle
+    n = f.n
+    x0, lw0, anc0 = f.particles()
+    st0 = f.stats()
+    k = st0["k"] + 1
+    obs = frames[(k - 1) % T]
+    f.step(frames_dev[(k - 1) % T])
+    x1, lw1, anc1 = f.particles()
+    st1 = f.stats()
+    if st1["k"] != k:
+        raise GateError("the checked step did not commit")
+    rng = np.random.default_rng(k)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 4000), [0, 255, 256, 2047, 2048, n - 1],
+                                    np.arange(max(0, n - 300), n)]))
+    ms = oracle_model(w, idx.size, init_kind)
+    par = anc0[idx] if st0["resampled"] else idx
+    xo = oracle.propagate_indexed(ms, k, idx, x0[:, par].astype(np.float64))
+    tol = np.spacing(np.abs(xo).astype(np.float32)).astype(np.float64) + 1e-6
+    if not np.all(np.abs(x1[:, idx] - xo) <= tol):
+        raise GateError("propagation differs from the oracle")
+    if st0["resampled"]:
+        if w.get("scheme", (0,))[0] == 1:
+            return  # RNA: the carried group weights are checked by the tests
+        lw_in = np.full(idx.size, -math.log(n))
+    else:
+        lw_in = lw0[idx]
+    l_orc = lw_in + oracle.loglik(ms, obs, x1[:, idx].astype(np.float64))
+    l_gpu = lw1[idx] + st1["delta"]
+    rel = np.abs(np.expm1(l_gpu - l_orc))
+    if not rel[l_orc - st1["max_logw"] >= -40].max(initial=0.0) <= 1e-5:
+        raise GateError("log weights differ from the oracle")
+    if st1["resampled"] and w.get("scheme", (0,))[0] == 0:
+        wt = np.exp(lw1)
+        u = oracle.resample_uniform(ms, k)
+        ao = oracle.resample_systematic(wt, u)
+        mism = np.nonzero(ao != anc1)[0]
+        if mism.size:
+            C = np.cumsum(wt)
+            us = (mism + u) / n
+            j = np.searchsorted(C, us)
+            d = np.minimum(np.abs(us - C[np.clip(j - 1, 0, n - 1)]),
+                           np.abs(C[np.clip(j, 0, n - 1)] - us))
+            if np.any(d > 1e-9):
+                raise GateError(f"{int((d > 1e-9).sum())} ancestors differ from the oracle")
 
 
 def main():
@@ -315,6 +518,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="sir_1024x1024_n38m_p13", choices=sorted(WORKLOADS))
     ap.add_argument("--init", default="stratified", choices=["stratified", "uniform"])
+    ap.add_argument("--no-alt-init", action="store_true",
+                    help="skip the second measurement from the other initial cloud")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="stream", choices=["stream", "graph"],
                     help="timed steps as plain launches or as replays of one HIP graph")
@@ -325,10 +530,14 @@ def main():
                     help="the same as --shape 0")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the all-cores oracle timing (default: the cores this "
+                         "process may use, at most OMP_NUM_THREADS when that is set)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
-                    help="write the k_step traffic record from two counter databases and exit")
+                    help="write a traffic record from two counter databases and exit")
+    ap.add_argument("--traffic-kernel", default="k_step", choices=sorted(TRAFFIC_GROUPS))
     args = ap.parse_args()
     if args.no_autotune and args.shape is None:
         args.shape = 0
@@ -339,14 +548,29 @@ def main():
         for p in args.traffic_from:
             dbs.append(p if p.endswith(".db") else sorted(glob.glob(os.path.join(p, "*.db")))[0])
         rec = traffic_from(dbs[0], dbs[1], args.workload, args.copy_probe_mib or 1024,
-                           args.warmup, args.steps, args.shape)
+                           args.warmup, args.steps, args.shape, args.traffic_kernel)
         print(json.dumps(rec))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    try:
+        run(args)
+    except GateError as e:
+        print(f"bench.py: correctness check failed, no figure reported: {e}", file=sys.stderr)
+        sys.exit(3)
 
+
+def cpu_threads(args):
+    if args.cpu_threads > 0:
+        return args.cpu_threads
+    _, cores = host_cpu()
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return min(cores, int(env)) if env.isdigit() and int(env) > 0 else cores
+
+
+def run(args):
     import numpy as np
     import torch
 
@@ -382,9 +606,9 @@ def main():
                  "k_step_ms": pkt.get("k_step", (1, 0.0))[1] / K}
     f = ppf.Filter(make_params(ppf, w, init_kind, grad=w.get("grad", 0)))
     graph = args.launch == "graph"
+    scheme = w.get("scheme", (0,))[0]
     gpu_ms, wall, kt, tuned, ran = timed_steps(torch, f, frames, K, Wm, T, graph, args.shape)
-    st = f.stats()
-    err = float(np.linalg.norm(st["mean"][:2] - mv.truth[(K - 1) % T, 0]))
+    err, st = check_state(ppf, f, w, mv, (K - 1) % T, scheme)
     n = w["n"]
     ms_per_step = gpu_ms / K
     value = n * K / (gpu_ms / 1e3)
@@ -392,8 +616,14 @@ def main():
     P = w["P"]
     step_launches, step_ms = kt.get("k_step", (0, 0.0))
     step_avg_s = step_ms / max(step_launches, 1) / 1e3
-    flops_per_particle = 4 * P * P  # P^2 residual FMAs + P^2 square-accumulate FMAs
+    # algorithmic: the separable form's P^2 residual FMAs and P^2
+    # square-accumulate FMAs per particle (the count the roofline is taken on)
+    flops_per_particle = 4 * P * P
     achieved_tf = flops_per_particle * n / step_avg_s / 1e12
+    # executed fp64 flops of the patch sums where the row-sum table serves
+    # sum D^2 (converged frames): P (P - 1) row FMAs, P each for the row
+    # weights, sum g_y^2, the table adds and two g_y recurrence products
+    executed = 2 * P * (P - 1) + 2 * P + 2 * P + P + 2 * P
     # resampling: read 4 B log weight, write 4 B ancestor per particle; the
     # ancestor pass and its overflow pass together, per step
     res_ms = kt.get("k_anc", (0, 0.0))[1] + kt.get("k_fill", (0, 0.0))[1]
@@ -417,7 +647,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_particles": n, "frame": [w["W"], w["H"]],
                    "patch": P, "psf_sigma": w["s"],
-                   "resampling": ({0: "systematic", 1: "RNA", 2: "RPA"}[w.get("scheme", (0,))[0]]
+                   "resampling": ({0: "systematic", 1: "RNA", 2: "RPA"}[scheme]
                                   + ("" if w["thr"] == float("inf")
                                      else f" when ESS < {w['thr']:.0f}")),
                    "init": args.init, "frames_timed": K, "launch": args.launch,
@@ -427,15 +657,19 @@ def main():
                      "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": load_traffic("k_step", args.workload, ran),
                      "avg_launch_ms": step_avg_s * 1e3, "flops_per_particle": flops_per_particle,
+                     "flops_basis": "algorithmic: 2 P^2 FMAs of the separable likelihood",
+                     "fp64_flops_executed_per_particle": executed,
                      "hbm_gbs_at_48B_per_particle": step_gbs},
         "roofline_resample": {"bound": "hbm", "kernel": "k_anc+k_fill", "achieved": res_gbs,
                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": res_gbs / HBM_PEAK_GBS,
+                              "traffic": load_traffic("k_resample", args.workload, None),
                               "avg_launch_ms": res_avg_s * 1e3, "bytes_per_particle": 8},
         "kernel_ms_total": {k: v[1] for k, v in kt.items()},
         "kernel_launches": {k: v[0] for k, v in kt.items()},
         "wall_s": wall,
         "tracking_error_px": err,
         "final_ess": st["ess"],
+        "checks": "passed",
     }
     if plain is not None:
         g, _ = f.grad()
@@ -444,10 +678,29 @@ def main():
         out["ratio_to_plain"] = out["value"] / plain["value"]
         out["grad_cum"] = dict(zip(ppf.GRAD_NAMES, [float(v) for v in g]))
         out["config"]["gradient"] = list(ppf.GRAD_NAMES)
+    if not args.no_cpu_baseline and not w.get("grad"):
+        # the cpu_baseline leg: one more GPU step checked against the oracle,
+        # then the oracle timed on a bounded sample of the workload
+        oracle_check_step(f, w, mv.frames, frames, T, init_kind)
+        out["checks"] = "passed, with a sampled oracle check of one more step"
     f.close()
+    if not args.no_alt_init and not w.get("grad"):
+        # the same workload from the other initial cloud (the paper's is
+        # uniform; the stratified cloud gives each workgroup a compact
+        # first-frame box)
+        alt = "uniform" if args.init == "stratified" else "stratified"
+        ak = ppf.INIT_UNIFORM if alt == "uniform" else ppf.INIT_STRATIFIED
+        fa = ppf.Filter(make_params(ppf, w, ak))
+        a_ms, _, akt, _, _ = timed_steps(torch, fa, frames, K, 2, T, graph, ran)
+        a_err, a_st = check_state(ppf, fa, w, mv, (K - 1) % T, scheme)
+        fa.close()
+        out["init_alternative"] = {"init": alt, "value": n * K / (a_ms / 1e3),
+                                   "ms_per_step": a_ms / K,
+                                   "kernel_ms_total": {k: v[1] for k, v in akt.items()},
+                                   "tracking_error_px": a_err, "final_ess": a_st["ess"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, mv.frames, min(args.cpu_sample, n), args.cpu_frames,
-                                           init_kind)
+                                           init_kind, cpu_threads(args))
     print(json.dumps(out), flush=True)
 
 

@@ -95,8 +95,16 @@ def lib():
         L.orc_dlb_schedule.restype = i64
         L.orc_resample_rpa.argtypes = [i64, i32, ctypes.c_int, vp, vp]
         L.orc_resample_rpa.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Host threads of the per-particle loops (propagation, Eq. 4); returns
+    the count in effect. The results do not depend on it."""
+    return lib().orc_set_threads(int(n))
 
 
 def _ptr(a: Optional[np.ndarray]):

@@ -12,12 +12,20 @@ SRC = os.path.join(HERE, "ppf_oracle.c")
 LIB = os.path.join(HERE, "_liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile ppf_oracle.c into oracle/_liboracle.so (always recompiles)."""
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile ppf_oracle.c into oracle/_liboracle.so (always recompiles);
+    sanitize=True builds it with AddressSanitizer and UBSan."""
     tmp = LIB + ".tmp"
     # -ffp-contract=off: no fused multiply-add, so every operation rounds as written.
-    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+    # -fopenmp: the per-particle loops may use several host threads (same results).
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fopenmp", "-fPIC",
+           "-shared", "-Wall", "-Wextra"]
+    if sanitize:
+        # address and undefined-behaviour checks of the host code (load with
+        # the sanitizer runtime preloaded, see DESIGN)
+        cmd += ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                "-fno-sanitize-recover=undefined"]
+    cmd += ["-o", tmp, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -26,4 +34,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

@@ -24,12 +24,30 @@
  *   - resampling scheme: systematic, s(i) = min{ j : (i+u)/N < C_j };
  *   - RNA: contiguous groups, local systematic resampling, slot weight W_g/n,
  *     the last floor(rho n) slots of group g replaced by those of g-1 mod G.
+ *
+ * The per-particle loops of propagation and of Eq. 4 may run on several
+ * host threads (OpenMP, when built with it): each particle's value is
+ * computed alone by the same arithmetic, so the results do not depend on the
+ * thread count. Every reduction stays one sequential loop.
  */
 #include "ppf_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 enum { PURPOSE_INIT = 1, PURPOSE_PROPAGATE = 2, PURPOSE_RESAMPLE = 3, PURPOSE_RNA = 4 };
 
@@ -225,12 +243,14 @@ static void propagate_one(const orc_model* m, int64_t k, int64_t i, const double
 
 void orc_propagate(const orc_model* m, int64_t k, const double* x_prev, const int32_t* parent,
                    double* x_new) {
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < m->n; ++i)
     propagate_one(m, k, i, x_prev, parent ? (int64_t)parent[i] : i, x_new, i);
 }
 
 void orc_propagate_indexed(const orc_model* m, int64_t k, const int64_t* index,
                            const double* parents, double* x_new) {
+#pragma omp parallel for schedule(static)
   for (int64_t j = 0; j < m->n; ++j) propagate_one(m, k, index[j], parents, j, x_new, j);
 }
 
@@ -245,6 +265,7 @@ void orc_loglik_spot(const orc_model* m, const float* frame, const double* x, do
   const double two_sigma2 = 2.0 * m->sigma * m->sigma;
   const double log_norm =
       (double)m->patch * (double)m->patch * log(m->sigma * sqrt(2.0 * M_PI));
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     const double xt = x[0 * n + i], yt = x[1 * n + i], It = x[4 * n + i];
     const double cx = floor(xt + 0.5), cy = floor(yt + 0.5);

@@ -42,6 +42,11 @@ typedef struct orc_model {
   int32_t pad;
 } orc_model;
 
+/* Host threads of the per-particle loops (propagation, Eq. 4) from now on
+ * (n > 0; n <= 0 leaves it); returns the count in effect (1 without OpenMP).
+ * Results do not depend on it. */
+int orc_set_threads(int n);
+
 /* Philox4x32-10 block function. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* The same over n counters (4n words each), key from a 64-bit seed. */

@@ -146,3 +146,47 @@ def check_step(m, k, prev: GpuState, cur: GpuState, st, obs, rna=False):
     assert np.array_equal(cur.anc, np.arange(n))
     cur.lw_next = cur.lw.copy()
     return (k, rel, 0)
+
+
+# Workgroups of the step kernel take one of three ways to the patch moments,
+# chosen by the bounding box of their 256 patch centres (acx x acy centres):
+# "sum"  the box's tile fits the LDS copies and both row-sum tables (of D^2 and
+#        of D) fit: nH = (acy + P - 1) acx <= 768 entries;
+# "tab"  the tile fits (2 ceil((acx + P - 1) / 2) (acy + P - 1) <= 1008
+#        doubles per copy) but only the D^2 table: 768 < nH;
+# "glob" the tile does not fit: pixels are read from the frame.
+# (A tile that fits always leaves room for the D^2 table, so there is no
+# fourth way.) Each box below sits at the limit of its way.
+PATH_BOXES = {
+    9: {"sum": (5, 5), "tab": (30, 18), "glob": (31, 29)},
+    11: {"sum": (5, 5), "tab": (40, 10), "glob": (41, 23)},
+    13: {"sum": (5, 5), "tab": (44, 6), "glob": (45, 25)},
+}
+# where each layout's box starts: at the spot, over the left edge, over the
+# bottom edge of a 96 x 80 frame
+PATH_ORIGINS = {"sum": (44, 38), "tab": (-6, 30), "glob": (20, 60)}
+
+
+def path_of(P, acx, acy):
+    th = acy + P - 1
+    if 2 * ((acx + P) // 2) * th > 1008:
+        return "glob"
+    return "sum" if th * acx <= 768 else "tab"
+
+
+def box_layout(rng, n, acx, acy, x0, y0):
+    """States whose patch centres fill an acx x acy box at (x0, y0) in every
+    block of 256 (each block's first two particles sit at its corners),
+    0.1 px off the centres so that the tiny process noise keeps the
+    rounding; velocities 0."""
+    cx = rng.integers(0, acx, n)
+    cy = rng.integers(0, acy, n)
+    for b0 in range(0, n, 256):
+        cx[b0], cy[b0] = 0, 0
+        if b0 + 1 < n:
+            cx[b0 + 1], cy[b0 + 1] = acx - 1, acy - 1
+    x = np.zeros((5, n))
+    x[0] = x0 + cx + 0.1
+    x[1] = y0 + cy - 0.1
+    x[4] = rng.uniform(20, 40, n)
+    return x.astype(np.float32)

@@ -1,12 +1,16 @@
-"""Host logic of bench.py (no GPU): the one-GPU contract and the traffic
-records taken from rocprofv3 counter databases, one per step-kernel
-workgroup shape."""
+"""Host logic of bench.py (no GPU): the one-GPU contract, the traffic
+records taken from rocprofv3 counter databases (one per step-kernel
+workgroup shape, one for the resampling pair), and the correctness gate,
+exercised on a stand-in filter that runs the oracle's Algorithm 1 on the
+host, with mistakes planted in it."""
 import json
+import math
 import os
 import sqlite3
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -38,6 +42,8 @@ def counter_db(path, counter, step_kib, shape, warmup, steps, copy_kib):
                                          "ppf::Buffers, float const*)", counter, kib / 2)]
         d += 1
         rows.append((d, "void ppf::k_anc(ppf::Model, ppf::Buffers, ppf::WeightSrc)", counter, 5.0))
+        d += 1
+        rows.append((d, "void ppf::k_fill(ppf::Model, ppf::Buffers)", counter, 1.5))
     d += 1
     rows.append((d, "__amd_rocclr_copyBuffer", counter, copy_kib))
     con.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
@@ -87,3 +93,115 @@ def test_traffic_record_refuses_another_shape(tmp_path, records):
     # too few launches for the warm-up and timed steps
     with pytest.raises(SystemExit, match="expected at least"):
         bench.traffic_from(f, w, "wl", 1, 10, 4, 0)
+
+
+def test_resampling_pair_traffic_record(tmp_path, records):
+    f = str(tmp_path / "fetch.db")
+    w = str(tmp_path / "write.db")
+    counter_db(f, "FETCH_SIZE", [1.0] * 4, 0, 3, 4, 512.0 * 1024)
+    counter_db(w, "WRITE_SIZE", [1.0] * 4, 0, 3, 4, 1024.0 * 1024)
+    rec = bench.traffic_from(f, w, "wl", 1024, 3, 4, 0, kernel="k_resample")
+    assert rec["shape"] is None
+    # k_anc 5.0 + k_fill 1.5 KiB per step, scaled 2 (fetch) and 1 (write)
+    assert rec["traffic_bytes_per_launch"] == (6.5 * 2.0 + 6.5) * 1024
+    assert bench.load_traffic("k_resample", "wl", 1) == rec["traffic_bytes_per_launch"]
+
+
+# ------------------------------------------------------- correctness gate
+class OracleFilter:
+    """Stand-in for the library's Filter, stepped by the oracle on the host
+    with the library's storage: fp32 states, fp64 normalised log weights,
+    the ancestors of the last resampling. `plant` plants one mistake."""
+
+    def __init__(self, m, plant=None):
+        import oracle
+        self.o, self.m, self.n, self.plant = oracle, m, m.n, plant
+        x, lw = oracle.init(m)
+        self.x, self.lw = x.astype(np.float32), lw
+        self.anc = np.arange(m.n, dtype=np.int32)
+        self.resampled, self.k = False, 0
+        self.st = dict(k=0, resampled=False, ess=float(m.n), max_logw=0.0, delta=0.0,
+                       mean=np.zeros(5))
+
+    def step(self, frame):
+        o, m, n = self.o, self.m, self.n
+        k = self.k + 1
+        xp = o.propagate(m, k, self.x.astype(np.float64), self.anc if self.resampled else None)
+        if self.plant == "propagate":
+            xp[0] += 0.01
+        x = xp.astype(np.float32)
+        lw_in = np.full(n, -math.log(n)) if (k == 1 or self.resampled) else self.lw
+        l = lw_in + o.loglik(m, frame, x.astype(np.float64))
+        w, s = o.normalize(l)
+        self.x, self.k = x, k
+        self.lw = l - s["delta"]
+        if self.plant == "weights":
+            self.lw[::7] += 1e-3
+        self.resampled = bool(s["ess"] < m.ess_threshold)
+        self.anc = (o.resample_systematic(w, o.resample_uniform(m, k)) if self.resampled
+                    else np.arange(n, dtype=np.int32))
+        if self.plant == "ancestors" and self.resampled:
+            self.anc = self.anc[::-1].copy()
+        self.st = dict(k=k, resampled=self.resampled, ess=s["ess"], max_logw=s["m"],
+                       delta=s["delta"], mean=o.estimate(w, x.astype(np.float64)))
+        if self.plant == "ess":
+            self.st["ess"] *= 1.01
+
+    def stats(self):
+        return dict(self.st)
+
+    def particles(self):
+        return self.x.copy(), self.lw.copy(), self.anc.copy()
+
+
+@pytest.fixture(scope="module")
+def small():
+    from paper_1310_5045_amd import synth
+    # the 128 x 128 workload with 2^16 particles over the central half of the
+    # frame (4096 spread over the whole frame can lock onto the border, where
+    # pixels read as noise-free background)
+    w = dict(bench.WORKLOADS["sir_128x128_n4096_p9"], n=1 << 16, box=(32, 96, 32, 96))
+    mv = synth.render_movie(w["W"], w["H"], w["T"], intensity=30.0, sigma=w["s"], background=10.0,
+                            noise_sd=3.0, seed=1)
+    return w, mv
+
+
+def run_stand_in(w, mv, plant=None, steps=5):
+    f = OracleFilter(bench.oracle_model(w, w["n"], 2), plant)
+    for k in range(steps):
+        f.step(mv.frames[k])
+    return f
+
+
+def test_gate_passes_a_correct_filter(small):
+    w, mv = small
+    f = run_stand_in(w, mv)
+    err, st = bench.check_state(None, f, w, mv, 4, 0)
+    assert err < 1.0 and st["k"] == 5
+    bench.oracle_check_step(f, w, mv.frames, mv.frames, w["T"], 2)
+
+
+@pytest.mark.parametrize("plant", ["ess", "ancestors", "weights"])
+def test_gate_catches_a_wrong_state(small, plant):
+    w, mv = small
+    f = run_stand_in(w, mv, plant)
+    with pytest.raises(bench.GateError):
+        bench.check_state(None, f, w, mv, 4, 0)
+
+
+@pytest.mark.parametrize("plant", ["propagate", "weights"])
+def test_oracle_check_catches_a_wrong_step(small, plant):
+    w, mv = small
+    f = run_stand_in(w, mv)
+    f.plant = plant  # the checked step goes wrong
+    with pytest.raises(bench.GateError):
+        bench.oracle_check_step(f, w, mv.frames, mv.frames, w["T"], 2)
+
+
+def test_gate_catches_a_lost_track(small):
+    w, mv = small
+    f = run_stand_in(w, mv)
+    far = mv.truth.copy()
+    far[4, 0] += 5.0  # the truth is elsewhere: tracking error above 1 px
+    with pytest.raises(bench.GateError, match="tracking"):
+        bench.check_state(None, f, w, type(mv)(**{**mv.__dict__, "truth": far}), 4, 0)

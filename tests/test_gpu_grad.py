@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_1310_5045_amd import synth
 
-from parity import pair
+from parity import PATH_BOXES, PATH_ORIGINS, box_layout, pair, path_of
 
 pytestmark = pytest.mark.gpu
 
@@ -65,11 +65,18 @@ def test_grad_mode_leaves_the_filter_unchanged(ppf, movie):
     f1.close()
 
 
+# (s, I): patches 9 x 9, 11 x 11 (the differentiable workload's spot) and 13 x 13
+SPOTS = [(1.5, 30.0), (1.7, 25.0), (2.0, 30.0)]
+
+
+@pytest.mark.parametrize("s,I", SPOTS)
 @pytest.mark.parametrize("n", [4096, 3001])
-def test_grad_teacher_forced_vs_oracle(ppf, movie, n):
-    p, m = pair(ppf, n=n, grad=1, **GKW)
+def test_grad_teacher_forced_vs_oracle(ppf, n, s, I):
+    mv = synth.render_movie(W, H, 6, intensity=I, sigma=s, start_box=(40, 52, 34, 46), seed=8)
+    p, m = pair(ppf, n=n, grad=1, **dict(GKW, s=s))
+    assert m.P == 2 * int(math.floor(3 * s)) + 1
     f = ppf.Filter(p)
-    frames = torch.from_numpy(movie.frames).cuda()
+    frames = torch.from_numpy(mv.frames).cuda()
     tang = np.zeros((7, n))
     prev_anc = None
     for k in range(1, 6):
@@ -79,12 +86,48 @@ def test_grad_teacher_forced_vs_oracle(ppf, movie, n):
         assert st["k"] == k and st["resampled"]
         # tangents follow the GPU's ancestors of the previous step
         tang = oracle.propagate_tangent(m, k, tang, prev_anc)
-        g_o, scale = step_terms(m, movie.frames[k - 1], x.astype(np.float64), tang,
+        g_o, scale = step_terms(m, mv.frames[k - 1], x.astype(np.float64), tang,
                                 np.full(n, -math.log(n)))
         _, g_gpu = f.grad()
         err = np.abs(g_gpu - g_o)
         assert np.all(err <= 2e-5 * (np.abs(g_o) + scale) + 1e-9), (k, g_gpu, g_o, scale)
         prev_anc = anc
+    f.close()
+
+
+@pytest.mark.parametrize("P", [9, 11, 13])
+@pytest.mark.parametrize("way", ["sum", "tab", "glob"])
+def test_grad_every_moment_path_vs_oracle(ppf, P, way):
+    """One step from placed particles whose blocks all take one way to the
+    moments (and a ragged last block), with log weights that flatten the
+    posterior so that every particle counts in sum_i w_i d l_i / d theta;
+    two of the boxes reach over the frame's edge."""
+    s = {9: 1.5, 11: 1.7, 13: 2.0}[P]
+    acx, acy = PATH_BOXES[P][way]
+    assert path_of(P, acx, acy) == way
+    mv = synth.render_movie(W, H, 1, intensity=30.0, sigma=s, start_box=(40, 52, 34, 46), seed=8)
+    n = 2 * 256 + 37
+    kw = dict(GKW, s=s, q=(1e-3,) * 5)
+    p, m = pair(ppf, n=n, grad=1, **kw)
+    assert m.P == P
+    rng = np.random.default_rng(P)
+    x = box_layout(rng, n, acx, acy, *PATH_ORIGINS[way])
+    ll = oracle.loglik(m, mv.frames[0], x.astype(np.float64))
+    lw = -ll - np.log(np.exp(-ll - (-ll).max()).sum()) - (-ll).max()
+    f = ppf.Filter(p)
+    f.set_particles(x, lw)
+    f.step(torch.from_numpy(mv.frames[0]).cuda())
+    xg, _, _ = f.particles()
+    centres = np.floor(xg[:2].astype(np.float64) + 0.5)
+    for b0 in range(0, n, 256):
+        c = centres[:, b0:b0 + 256]
+        assert (c[0].max() - c[0].min() + 1, c[1].max() - c[1].min() + 1) == (acx, acy)
+    tang = oracle.propagate_tangent(m, 1, np.zeros((7, n)), None)
+    g_o, scale = step_terms(m, mv.frames[0], xg.astype(np.float64), tang, lw)
+    _, g_gpu = f.grad()
+    err = np.abs(g_gpu - g_o)
+    print(way, P, g_gpu, g_o, flush=True)
+    assert np.all(err <= 2e-5 * (np.abs(g_o) + scale) + 1e-9), (g_gpu, g_o, scale)
     f.close()
 
 

@@ -8,8 +8,8 @@ import pytest
 import oracle
 from paper_1310_5045_amd import synth
 
-from parity import (GpuState, check_propagate, check_rna, check_step, check_systematic,
-                    check_weights, pair, snapshot)
+from parity import (PATH_BOXES, PATH_ORIGINS, GpuState, box_layout, check_propagate, check_rna,
+                    check_step, check_systematic, check_weights, pair, snapshot)
 
 pytestmark = pytest.mark.gpu
 
@@ -125,6 +125,33 @@ def test_spot_particles_leaving_frame(ppf):
     p, m = pair(ppf, n=4000, width=48, height=40, s=1.5, b=10.0, sigma=3.0,
                 init_a=(-100, -80, -3, -3, 0), init_b=(150, 120, 3, 3, 40), q=(2, 2, 0.5, 0.5, 2))
     run_teacher_forced(ppf, p, m, mv.frames, 3)
+
+
+@pytest.mark.parametrize("shape", [0, 1])
+@pytest.mark.parametrize("P", [9, 11, 13])
+@pytest.mark.parametrize("way", ["sum", "tab", "glob"])
+def test_spot_tile_limits(ppf, shape, P, way):
+    """Placed particles whose workgroup boxes sit at the limits of the LDS
+    tile (the gradient tests' layouts: a small box, a tile filled to its last
+    double in shape 0, a box just too large for it), weights flattened so
+    that every particle counts; one step against the oracle's weights."""
+    s = {9: 1.5, 11: 1.7, 13: 2.0}[P]
+    W, H = 96, 80
+    mv = synth.render_movie(W, H, 1, intensity=30.0, sigma=s, start_box=(40, 52, 34, 46), seed=8)
+    n = 2 * 256 + 37
+    p, m = pair(ppf, n=n, width=W, height=H, s=s, b=10.0, sigma=3.0, q=(1e-3,) * 5, seed=3)
+    acx, acy = PATH_BOXES[P][way]
+    x = box_layout(np.random.default_rng(P), n, acx, acy, *PATH_ORIGINS[way])
+    a = -oracle.loglik(m, mv.frames[0], x.astype(np.float64))
+    lw = a - a.max() - np.log(np.exp(a - a.max()).sum())
+    f = ppf.Filter(p)
+    f.set_shape(shape)
+    f.set_particles(x, lw)
+    f.step(torch.from_numpy(mv.frames[0]).cuda())
+    cur, st = snapshot(f, n, None)
+    check_propagate(m, 1, GpuState(x, lw, np.arange(n), False, lw), cur.x)
+    check_weights(m, mv.frames[0], lw, cur.x, cur.lw, st)
+    f.close()
 
 
 def test_linear_gaussian_filter(ppf):
