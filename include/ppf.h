@@ -389,6 +389,25 @@ int ppf_resample_systematic(const float* logw_dev, int64_t n, double u, int32_t*
                             void* scratch, size_t scratch_bytes, void* hip_stream);
 
 /*
+ * The same systematic resampling without caller scratch and without any
+ * allocation, for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The scratch is a device array of PPF_STATIC_SCRATCH_BYTES bytes inside the
+ * library, one per device, looked up on the first call on a device and held
+ * until the process ends. Arguments as ppf_resample_systematic; async.
+ *   n   1 <= n <= PPF_STATIC_MAX_N (EINVAL beyond: the array's limit).
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (the kernels write every scratch value they read before
+ * reading it, so nothing carries over): calls that overlap on one device
+ * (other streams, other threads) race on it and must not be issued.
+ * EDEVICE when the array's address cannot be obtained.
+ */
+#define PPF_STATIC_MAX_N (1 << 22)
+#define PPF_STATIC_SCRATCH_BYTES (4u << 20)
+int ppf_resample_systematic_static(const float* logw_dev, int64_t n, double u, int32_t* anc_dev,
+                                   void* hip_stream);
+
+/*
  * RNA resampling (Section 3): groups g of `group` consecutive weights are
  * resampled locally and systematically with uniform u_dev[g]; group g's slot
  * weight becomes W_g / group (W_g its share of the normalised weight); then

@@ -27,6 +27,7 @@ PPF_OK, PPF_EINVAL, PPF_ENOMEM, PPF_EDEVICE, PPF_ESTATE, PPF_ENUMERIC, PPF_ENOTI
 RESAMPLE_SYSTEMATIC, RESAMPLE_RNA, RESAMPLE_RPA = 0, 1, 2
 DLB_GS, DLB_SGS, DLB_LGS = 0, 1, 2
 DLB_MAX_SORTED = 4096
+STATIC_MAX_N = 1 << 22  # weights the allocation-free resampler takes
 OBS_SPOT, OBS_LINEAR_GAUSSIAN = 0, 1
 INIT_UNIFORM, INIT_GAUSSIAN, INIT_STRATIFIED = 0, 1, 2
 MAX_PATCH = 25
@@ -136,6 +137,9 @@ _SIGS = {
     "ppf_resample_systematic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                                ctypes.c_void_p]),
+    "ppf_resample_systematic_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64,
+                                                      ctypes.c_double, ctypes.c_void_p,
+                                                      ctypes.c_void_p]),
     "ppf_resample_rna": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
@@ -603,6 +607,28 @@ def resample_systematic(logw, u: float, stream=None):
                                          ctypes.c_void_p(scr.data_ptr()), nbytes,
                                          ctypes.c_void_p(_stream_ptr(s))))
     anc._ppf_scratch = scr  # keep the scratch alive until the caller syncs
+    return anc
+
+
+def resample_systematic_static(logw, u: float, anc=None, stream=None):
+    """Systematic resampling like resample_systematic, through the entry
+    point that allocates nothing (its scratch is the library's own device
+    array; at most STATIC_MAX_N weights). `anc`: an optional int32 output
+    tensor (else one is made here). Calls on one device must not overlap."""
+    import torch
+    if logw.dtype != torch.float32 or not logw.is_contiguous() or logw.dim() != 1:
+        raise TypeError("logw must be a contiguous 1-D float32 CUDA tensor")
+    n = logw.numel()
+    if n > STATIC_MAX_N:
+        raise ValueError(f"at most {STATIC_MAX_N} weights (the static scratch's limit)")
+    if anc is None:
+        anc = torch.empty(n, dtype=torch.int32, device=logw.device)
+    if anc.dtype != torch.int32 or not anc.is_contiguous() or anc.numel() != n:
+        raise TypeError("anc must be a contiguous int32 tensor of n elements")
+    s = stream if stream is not None else torch.cuda.current_stream(logw.device)
+    _check(lib().ppf_resample_systematic_static(ctypes.c_void_p(logw.data_ptr()), n, float(u),
+                                                ctypes.c_void_p(anc.data_ptr()),
+                                                ctypes.c_void_p(_stream_ptr(s))))
     return anc
 
 

@@ -786,12 +786,26 @@ int ppf_resample_systematic(const float* logw_dev, int64_t n, double u, int32_t*
   if (rc) return rc;
   b.anc = anc_dev;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // every scratch field the kernels read is written earlier in the same call
+  // (the records by k_records, which also clears the counters of the
+  // control block; the prefixes by the merge), so nothing is cleared first
   const ppf::WeightSrc w{logw_dev, logw_dev, b.R0, b.R0, 0, 1};
   hipError_t e = ppf::launch_records(m, b, logw_dev, s);
   if (e == hipSuccess) e = ppf::launch_merge(m, b, 1, u, s);
   if (e == hipSuccess) e = ppf::launch_anc(m, b, w, s);
   if (e == hipSuccess) e = ppf::launch_fill(m, b, s);
   return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
+}
+
+int ppf_resample_systematic_static(const float* logw_dev, int64_t n, double u, int32_t* anc_dev,
+                                   void* hip_stream) {
+  if (!logw_dev || !anc_dev || !(u >= 0.0 && u < 1.0)) return PPF_EINVAL;
+  if (n < 1 || n > PPF_STATIC_MAX_N) return PPF_EINVAL;
+  void* base = nullptr;
+  size_t cap = 0;
+  if (ppf::static_scratch(&base, &cap) != hipSuccess) return PPF_EDEVICE;
+  if (carve_scratch(n, nullptr, nullptr) > cap) return PPF_ENOMEM;  // ruled out by the limit
+  return ppf_resample_systematic(logw_dev, n, u, anc_dev, base, cap, hip_stream);
 }
 
 int ppf_resample_rna(const float* logw_dev, int64_t n, int32_t group, int32_t moved,

@@ -57,6 +57,10 @@ constexpr int kFillGridBatch = 8;  // workgroups per track of a batched fill (a 
 // sizes that fit five waves per SIMD); wider patches launch per size.
 constexpr int kFusedMaxP = 13;
 constexpr int kDlbMaxSorted = 4096;  // groups of a sorted DLB schedule (LDS sort)
+// The allocation-free standalone resampler keeps its scratch in a device
+// array of this many bytes, one per device for the life of the process.
+constexpr size_t kStaticScratchBytes = size_t(4) << 20;
+constexpr int kMaxDevices = 64;
 
 // One work item of a batched launch: the track, and the index of the track's
 // block, merge chunk, resampling segment or RNA group.
@@ -215,6 +219,10 @@ hipError_t launch_set_mode(const Buffers& b, int32_t mode, hipStream_t s);
 hipError_t launch_records(const Model& m, const Buffers& b, const float* logw, hipStream_t s);
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
                          hipStream_t s);
+
+// Device address and size of the current device's static scratch array
+// (kStaticScratchBytes, 256-byte aligned), looked up once per device.
+hipError_t static_scratch(void** ptr, size_t* bytes);
 
 // RPA: the balancing plan and the routed ancestors of one filter.
 hipError_t launch_rpa(const Model& m, const Buffers& b, hipStream_t s);

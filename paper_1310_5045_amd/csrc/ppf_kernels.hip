@@ -19,6 +19,7 @@
 #include <cfloat>
 #include <climits>
 #include <cmath>
+#include <mutex>
 #include <tuple>
 #include <utility>
 
@@ -2339,6 +2340,36 @@ hipError_t StepGraph::set_frame(const float* frame) {
     if (e != hipSuccess) return e;
   }
   frame_ = frame;
+  return hipSuccess;
+}
+
+// Scratch of the allocation-free standalone resampler: every device that
+// runs it holds one copy until the process ends. Host code must not use the
+// array's name as a device address (on the host it names a stand-in): the
+// device address comes from hipGetSymbolAddress, per device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** ptr, size_t* bytes) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    // with this device current: its own copy of the array
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  *bytes = kStaticScratchBytes;
   return hipSuccess;
 }
 

@@ -145,3 +145,23 @@ def test_product_package_never_imports_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 for needle in ("import oracle", "from oracle", "ppf_oracle", "_liboracle", "orc_"):
                     assert needle not in text, (f, needle)
+
+
+def test_static_resampler_limits_without_a_gpu():
+    """The allocation-free resampler's array holds the scratch of its largest
+    input, and arguments outside its limits are refused before any device
+    work."""
+    L = ppf.lib()
+    n = ctypes.c_size_t()
+    assert L.ppf_resample_scratch_bytes(ppf.STATIC_MAX_N, ctypes.byref(n)) == ppf.PPF_OK
+    text = open(os.path.join(ROOT, "include", "ppf.h")).read()
+    assert "#define PPF_STATIC_SCRATCH_BYTES (4u << 20)" in text
+    assert "#define PPF_STATIC_MAX_N (1 << 22)" in text
+    assert n.value <= 4 << 20
+    assert ppf.STATIC_MAX_N == 1 << 22
+    f = L.ppf_resample_systematic_static
+    dummy = ctypes.c_void_p(256)  # never dereferenced: each call fails its checks first
+    assert f(dummy, ppf.STATIC_MAX_N + 1, 0.5, dummy, None) == ppf.PPF_EINVAL
+    assert f(dummy, 0, 0.5, dummy, None) == ppf.PPF_EINVAL
+    assert f(None, 16, 0.5, dummy, None) == ppf.PPF_EINVAL
+    assert f(dummy, 16, 1.0, dummy, None) == ppf.PPF_EINVAL
