@@ -44,7 +44,9 @@ class _Model(ctypes.Structure):
         ("rna_moved", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("track", ctypes.c_uint32),
-        ("pad", ctypes.c_int32),
+        ("arna_mu_min", ctypes.c_int32),
+        ("arna_track", ctypes.c_double),
+        ("arna_lost", ctypes.c_double),
     ]
 
 
@@ -83,7 +85,7 @@ def lib():
         L.orc_estimate.argtypes = [i64, vp, vp, vp]
         L.orc_resample_systematic.argtypes = [i64, vp, d, vp]
         L.orc_resample_rna.argtypes = [i64, i32, i32, vp, vp, vp, vp, vp]
-        L.orc_run.argtypes = [P(_Model), i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_run.argtypes = [P(_Model), i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_run.restype = ctypes.c_int
         L.orc_propagate_tangent.argtypes = [P(_Model), i64, vp, vp, vp]
         L.orc_loglik_spot_grad.argtypes = [P(_Model), vp, vp, vp]
@@ -95,6 +97,11 @@ def lib():
         L.orc_dlb_schedule.restype = i64
         L.orc_resample_rpa.argtypes = [i64, i32, ctypes.c_int, vp, vp]
         L.orc_resample_rpa.restype = ctypes.c_int
+        L.orc_ring_order.argtypes = [P(_Model), i64, i64, vp]
+        L.orc_arna_lost.argtypes = [P(_Model), d, d]
+        L.orc_arna_lost.restype = ctypes.c_int
+        L.orc_resample_arna.argtypes = [i64, i32, i32, i32, d, vp, vp, vp, vp, vp, vp, P(i32),
+                                        P(i32)]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = ctypes.c_int
         _lib = L
@@ -128,12 +135,15 @@ class Model:
     init_a: Sequence[float] = (0.0, 0.0, -1.0, -1.0, 15.0)
     init_b: Sequence[float] = (128.0, 128.0, 1.0, 1.0, 45.0)
     lg_r: Sequence[float] = (1.0, 1.0, 1.0)
-    resample: int = 0             # 0 systematic, 1 RNA
+    resample: int = 0             # 0 systematic, 1 RNA, 2 ARNA
     ess_threshold: float = math.inf
     rna_group: int = 256
-    rna_exchange: float = 0.1
+    rna_exchange: float = 0.1     # RNA: rho; ARNA: the largest exchange ratio
     seed: int = 1
     track: int = 0
+    arna_min: float = 0.0         # ARNA: the smallest exchange ratio
+    arna_track: float = 0.5       # ARNA: a group tracks when W_g >= arna_track / G
+    arna_lost: float = 3.0        # ARNA: kappa of the lost test
 
     @property
     def P(self) -> int:
@@ -142,6 +152,10 @@ class Model:
     @property
     def rna_moved(self) -> int:
         return int(math.floor(float(np.float32(self.rna_exchange)) * self.rna_group))
+
+    @property
+    def arna_mu_min(self) -> int:
+        return int(math.floor(float(np.float32(self.arna_min)) * self.rna_group))
 
     def c(self) -> _Model:
         f = lambda v: float(np.float32(v))  # noqa: E731  (exact widening of the fp32 value)
@@ -164,6 +178,9 @@ class Model:
         m.rna_moved = self.rna_moved
         m.seed = self.seed
         m.track = self.track
+        m.arna_mu_min = self.arna_mu_min
+        m.arna_track = f(self.arna_track)
+        m.arna_lost = f(self.arna_lost)
         return m
 
 
@@ -301,6 +318,39 @@ def resample_rna(w: np.ndarray, group: int, moved: int, u_g: np.ndarray):
     return anc, lwg, lws
 
 
+# ------------------------------------------------------------ ARNA
+def ring_order(m: Model, key: int, G: int) -> np.ndarray:
+    """ARNA's ring: the group at each ring position (key 0: index order)."""
+    out = np.empty(G, dtype=np.int64)
+    lib().orc_ring_order(ctypes.byref(m.c()), int(key), int(G), _ptr(out))
+    return out
+
+
+def arna_lost(m: Model, delta: float, ref: float) -> bool:
+    """ARNA's lost test of a frame's log-likelihood increment against that of
+    the last frame that was not lost."""
+    return bool(lib().orc_arna_lost(ctypes.byref(m.c()), float(delta), float(ref)))
+
+
+def resample_arna(w: np.ndarray, group: int, mu_min: int, mu_max: int, theta: float,
+                  u_g: np.ndarray, order: np.ndarray):
+    """(ancestors, log(W_g / n), per-slot log weights, tracking groups, slots
+    exchanged) of ARNA's resampling with ring `order`."""
+    n = w.size
+    ww = np.ascontiguousarray(w, dtype=np.float64)
+    ug = np.ascontiguousarray(u_g, dtype=np.float64)
+    od = np.ascontiguousarray(order, dtype=np.int64)
+    anc = np.empty(n, dtype=np.int32)
+    lwg = np.empty(n // group)
+    lws = np.empty(n)
+    t, mu = ctypes.c_int32(), ctypes.c_int32()
+    with np.errstate(divide="ignore"):
+        lib().orc_resample_arna(n, group, mu_min, mu_max, float(theta), _ptr(ww), _ptr(ug),
+                                _ptr(od), _ptr(anc), _ptr(lwg), _ptr(lws), ctypes.byref(t),
+                                ctypes.byref(mu))
+    return anc, lwg, lws, t.value, mu.value
+
+
 @dataclass
 class RunResult:
     mean: np.ndarray
@@ -327,9 +377,11 @@ def run(m: Model, obs: np.ndarray, T: Optional[int] = None) -> RunResult:
     x = np.zeros((5, m.n))
     lw = np.zeros(m.n)
     anc = np.zeros(m.n, dtype=np.int32)
+    arna = np.zeros((T, 3), dtype=np.int64)
     st = lib().orc_run(ctypes.byref(c), T, _ptr(z), _ptr(mean), _ptr(ess), _ptr(delta), _ptr(res),
-                       _ptr(x), _ptr(lw), _ptr(anc))
-    return RunResult(mean, ess, delta, res, x, lw, anc, st)
+                       _ptr(x), _ptr(lw), _ptr(anc), _ptr(arna))
+    extra = {"arna": arna} if m.resample == 2 else {}
+    return RunResult(mean, ess, delta, res, x, lw, anc, st, extra)
 
 
 # ------------------------------------------------------------ derivatives

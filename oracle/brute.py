@@ -112,3 +112,35 @@ def rna_pieces(w: Sequence[Fraction], group: int, moved: int):
         anc, wslot = rna_at(w, group, moved, [lo for lo, _ in combo])
         out.append((prob, anc, wslot))
     return out
+
+
+def arna_at(w: Sequence[Fraction], group: int, mu_min: int, mu_max: int, theta: Fraction,
+            us: Sequence[Fraction], order: Sequence[int]):
+    """ARNA's resampling for one choice of group uniforms and a ring order
+    (order[j]: the group at ring position j): RNA's local resampling, G_t =
+    #{g : W_g >= theta / G}, mu = mu_min + floor((mu_max - mu_min)(G - G_t)/G),
+    the last mu slots of each group from its ring predecessor. Returns
+    (ancestors, slot weights, G_t, mu)."""
+    n = len(w)
+    G = n // group
+    local, Wg = [], []
+    for g in range(G):
+        ws = w[g * group:(g + 1) * group]
+        W = sum(ws, Fraction(0))
+        Wg.append(W)
+        if W == 0:
+            local.extend(range(g * group, (g + 1) * group))
+        else:
+            loc = systematic_at([x / W for x in ws], us[g])
+            local.extend(g * group + j for j in loc)
+    t = sum(1 for W in Wg if W >= theta / G)
+    mu = mu_min + ((mu_max - mu_min) * (G - t)) // G
+    pos = {g: j for j, g in enumerate(order)}
+    anc, wslot = [], []
+    for g in range(G):
+        pred = order[(pos[g] - 1) % G]
+        for l in range(group):
+            src = pred if l >= group - mu else g
+            anc.append(local[src * group + l])
+            wslot.append(Wg[src] / group)
+    return tuple(anc), tuple(wslot), t, mu

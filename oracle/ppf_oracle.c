@@ -23,7 +23,14 @@
  *     Eq. 1 (the log-likelihood increment) is an absolute quantity;
  *   - resampling scheme: systematic, s(i) = min{ j : (i+u)/N < C_j };
  *   - RNA: contiguous groups, local systematic resampling, slot weight W_g/n,
- *     the last floor(rho n) slots of group g replaced by those of g-1 mod G.
+ *     the last floor(rho n) slots of group g replaced by those of g-1 mod G;
+ *   - ARNA (Section 6.4 names its three rules only): a group tracks when its
+ *     weight share is at least theta / G; the exchange shrinks linearly with
+ *     the share of tracking groups, from floor(rho n) (none tracks) to
+ *     floor(rho_min n) (all track); the ring order is redrawn as a keyed
+ *     permutation at every frame whose log-likelihood increment drops well
+ *     below that of the last frame that tracked (the object is lost), and
+ *     kept until the next loss.
  *
  * The per-particle loops of propagation and of Eq. 4 may run on several
  * host threads (OpenMP, when built with it): each particle's value is
@@ -49,7 +56,8 @@ int orc_set_threads(int n) {
 #endif
 }
 
-enum { PURPOSE_INIT = 1, PURPOSE_PROPAGATE = 2, PURPOSE_RESAMPLE = 3, PURPOSE_RNA = 4 };
+enum { PURPOSE_INIT = 1, PURPOSE_PROPAGATE = 2, PURPOSE_RESAMPLE = 3, PURPOSE_RNA = 4,
+       PURPOSE_RING = 5 };
 
 /* ------------------------------------------------------------- Philox */
 
@@ -388,8 +396,109 @@ void orc_resample_rna(int64_t n, int32_t group, int32_t moved, const double* w,
 
 /* ------------------------------------------------------------ the filter */
 
+/* ---------------------------------------------------------------- ARNA */
+
+/* One pass of the ring's keyed permutation of [0, 2^(2 half)): eight Feistel
+ * rounds on the halves (L, R) -> (R, L xor F_r(R)), F_r(R) the low `half`
+ * bits of word 0 of the Philox block with counter (R, key, RING << 24 | r,
+ * track). A Feistel network is a bijection whatever its round function;
+ * eight rounds (rather than four) because the halves are tiny for small
+ * rings: with four, the orders of 5 groups were measurably uneven. */
+static uint32_t ring_feistel(const orc_model* m, uint32_t key, int half, uint32_t x) {
+  const uint32_t mask = (1u << half) - 1u;
+  uint32_t L = x >> half, R = x & mask;
+  for (uint32_t r = 0; r < 8; ++r) {
+    uint32_t f[4];
+    draw(m, R, key, PURPOSE_RING, r, f);
+    const uint32_t nl = R, nr = L ^ (f[0] & mask);
+    L = nl;
+    R = nr;
+  }
+  return (L << half) | R;
+}
+
+void orc_ring_order(const orc_model* m, int64_t key, int64_t G, int64_t* order) {
+  if (key == 0 || G < 2) {
+    for (int64_t j = 0; j < G; ++j) order[j] = j;
+    return;
+  }
+  /* the smallest even width b with 2^b >= G; then the permutation of
+   * [0, 2^b) restricted to [0, G) by cycle walking: apply it again until the
+   * value falls below G (a bijection of [0, G), since every cycle of the
+   * permutation that meets [0, G) is walked in the same direction) */
+  int b = 2;
+  while (((int64_t)1 << b) < G) b += 2;
+  for (int64_t j = 0; j < G; ++j) {
+    uint32_t x = (uint32_t)j;
+    do {
+      x = ring_feistel(m, (uint32_t)key, b / 2, x);
+    } while ((int64_t)x >= G);
+    order[j] = (int64_t)x;
+  }
+}
+
+int orc_arna_lost(const orc_model* m, double delta, double ref) {
+  return delta < ref - m->arna_lost * (double)m->patch;
+}
+
+void orc_resample_arna(int64_t n, int32_t group, int32_t mu_min, int32_t mu_max, double theta,
+                       const double* w, const double* u_g, const int64_t* order, int32_t* anc,
+                       double* lwg, double* lw_slot, int32_t* tracking, int32_t* moved) {
+  const int64_t G = n / group;
+  int32_t* local = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  int64_t* pos = (int64_t*)malloc((size_t)G * sizeof(int64_t));
+  double* W = (double*)malloc((size_t)G * sizeof(double));
+  /* local systematic resampling inside each group, as RNA */
+  int64_t t = 0;
+  for (int64_t g = 0; g < G; ++g) {
+    const int64_t base = g * group;
+    double Wg = 0.0;
+    for (int32_t l = 0; l < group; ++l) Wg += w[base + l];
+    W[g] = Wg;
+    lwg[g] = log(Wg / (double)group);
+    if (Wg >= theta / (double)G) ++t;
+    if (!(Wg > 0.0)) {
+      for (int32_t l = 0; l < group; ++l) local[base + l] = (int32_t)(base + l);
+      continue;
+    }
+    int32_t j = 0;
+    double cum = w[base];
+    for (int32_t l = 0; l < group; ++l) {
+      const double ul = ((double)l + u_g[g]) / (double)group;
+      while (j < group - 1 && cum / Wg <= ul) {
+        ++j;
+        cum += w[base + j];
+      }
+      local[base + l] = (int32_t)(base + j);
+    }
+  }
+  /* the exchange shrinks as more groups track */
+  const int64_t mu = mu_min + ((int64_t)(mu_max - mu_min) * (G - t)) / G;
+  /* each group's ring predecessor */
+  for (int64_t j = 0; j < G; ++j) pos[order[j]] = j;
+  for (int64_t g = 0; g < G; ++g) {
+    const int64_t pred = order[(pos[g] + G - 1) % G];
+    for (int32_t l = 0; l < group; ++l) {
+      const int64_t i = g * group + l;
+      if (l >= group - mu) {
+        anc[i] = local[pred * group + l];
+        lw_slot[i] = lwg[pred];
+      } else {
+        anc[i] = local[i];
+        lw_slot[i] = lwg[g];
+      }
+    }
+  }
+  *tracking = (int32_t)t;
+  *moved = (int32_t)mu;
+  free(W);
+  free(pos);
+  free(local);
+}
+
 int orc_run(const orc_model* m, int32_t T, const float* obs, double* mean, double* ess,
-            double* delta, int32_t* resampled, double* x_out, double* lw_out, int32_t* anc_out) {
+            double* delta, int32_t* resampled, double* x_out, double* lw_out, int32_t* anc_out,
+            int64_t* arna_out) {
   const int64_t n = m->n;
   double* x = (double*)malloc((size_t)(5 * n) * sizeof(double));
   double* xn = (double*)malloc((size_t)(5 * n) * sizeof(double));
@@ -399,6 +508,9 @@ int orc_run(const orc_model* m, int32_t T, const float* obs, double* mean, doubl
   int32_t* parent = (int32_t*)malloc((size_t)n * sizeof(int32_t));
   double* lwg = (double*)malloc((size_t)n * sizeof(double));
   double* ug = (double*)malloc((size_t)n * sizeof(double));
+  int64_t* order = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int64_t ring_key = 0;
+  double delta_ref = -INFINITY;
   int have_parent = 0, status = 0;
   const int64_t frame_len = m->obs_model == 0 ? (int64_t)m->width * m->height : 3;
 
@@ -424,6 +536,14 @@ int orc_run(const orc_model* m, int32_t T, const float* obs, double* mean, doubl
     if (resampled) resampled[k - 1] = do_resample;
     if (lw_out && k == T)
       for (int64_t i = 0; i < n; ++i) lw_out[i] = ll[i] - st[3];
+    /* ARNA: a lost object draws a new ring order, kept until the next loss */
+    if (m->resample == 2) {
+      if (orc_arna_lost(m, st[3], delta_ref))
+        ring_key = k;
+      else
+        delta_ref = st[3];
+    }
+    int32_t arna_t = 0, arna_mu = 0;
     if (do_resample) {
       if (m->resample == 0) {
         orc_resample_systematic(n, w, orc_resample_uniform(m, k), parent);
@@ -431,12 +551,23 @@ int orc_run(const orc_model* m, int32_t T, const float* obs, double* mean, doubl
       } else {
         const int64_t G = n / m->rna_group;
         for (int64_t g = 0; g < G; ++g) ug[g] = orc_rna_uniform(m, g, k);
-        orc_resample_rna(n, m->rna_group, m->rna_moved, w, ug, parent, lwg, lw);
+        if (m->resample == 2) {
+          orc_ring_order(m, ring_key, G, order);
+          orc_resample_arna(n, m->rna_group, m->arna_mu_min, m->rna_moved, m->arna_track, w, ug,
+                            order, parent, lwg, lw, &arna_t, &arna_mu);
+        } else {
+          orc_resample_rna(n, m->rna_group, m->rna_moved, w, ug, parent, lwg, lw);
+        }
       }
       have_parent = 1;
     } else {
       for (int64_t i = 0; i < n; ++i) lw[i] = ll[i] - st[3];
       have_parent = 0;
+    }
+    if (arna_out && m->resample == 2) {
+      arna_out[3 * (k - 1)] = ring_key;
+      arna_out[3 * (k - 1) + 1] = arna_t;
+      arna_out[3 * (k - 1) + 2] = arna_mu;
     }
     double* t = x;
     x = xn;
@@ -455,6 +586,7 @@ int orc_run(const orc_model* m, int32_t T, const float* obs, double* mean, doubl
   free(parent);
   free(lwg);
   free(ug);
+  free(order);
   return status;
 }
 

@@ -30,7 +30,7 @@ typedef struct orc_model {
   double sigma;         /* sigma_xi (Eq. 4)                                   */
   double q[5];          /* process-noise sds of (x, y, vx, vy, I0)            */
   int32_t init_kind;    /* 0 uniform [a,b), 1 Gaussian N(a,b^2), 2 stratified  */
-  int32_t resample;     /* 0 = systematic, 1 = RNA                            */
+  int32_t resample;     /* 0 = systematic, 1 = RNA, 2 = ARNA                  */
   double init_a[5];
   double init_b[5];
   double lg_r[3];       /* linear-Gaussian observation sds of (x, y, I0)      */
@@ -39,7 +39,9 @@ typedef struct orc_model {
   int32_t rna_moved;    /* slots moved to the ring neighbour per group        */
   uint64_t seed;        /* Philox key                                         */
   uint32_t track;       /* Philox counter word 3                              */
-  int32_t pad;
+  int32_t arna_mu_min;  /* ARNA: least slots exchanged per group (rna_moved the most) */
+  double arna_track;    /* ARNA: a group tracks when W_g >= arna_track / G     */
+  double arna_lost;     /* ARNA: kappa of the lost test (see orc_arna_lost)    */
 } orc_model;
 
 /* Host threads of the per-particle loops (propagation, Eq. 4) from now on
@@ -103,13 +105,39 @@ void orc_resample_systematic(int64_t n, const double* w, double u, int32_t* anc)
 void orc_resample_rna(int64_t n, int32_t group, int32_t moved, const double* w,
                       const double* u_g, int32_t* anc, double* lwg, double* lw_slot);
 
+/* ARNA (adaptive RNA, Section 6.4; the reading of its rules is in the
+ * design notes). Ring order of G groups under ring key `key`: order[j] is the
+ * group at ring position j, group order[j] passing particles to
+ * order[j + 1 mod G]. Key 0 is the index order. */
+void orc_ring_order(const orc_model* m, int64_t key, int64_t G, int64_t* order);
+/* The object counts as lost at a frame whose log-likelihood increment delta
+ * falls more than kappa P below ref (kappa = arna_lost), ref being the
+ * increment of the latest frame at which it was not lost (-inf before the
+ * first frame). P is the scale of the frame-to-frame spread of a good fit:
+ * the residual sum / sigma_xi^2 of Eq. 4 at the true state is chi-square with
+ * P^2 degrees of freedom, standard deviation P sqrt(2), so its log-likelihood
+ * varies by about P / sqrt(2). Returns 1 when lost. */
+int orc_arna_lost(const orc_model* m, double delta, double ref);
+/* ARNA resampling: RNA's local systematic resampling per group (uniforms
+ * u_g), then G_t = #{g : W_g >= theta / G} tracking groups, the exchange
+ * mu = mu_min + floor((mu_max - mu_min) (G - G_t) / G), and the last mu slots
+ * of each group taken (ancestors and weight) from the same slots of its ring
+ * predecessor in `order`. Outputs as orc_resample_rna, plus G_t and mu. */
+void orc_resample_arna(int64_t n, int32_t group, int32_t mu_min, int32_t mu_max, double theta,
+                       const double* w, const double* u_g, const int64_t* order, int32_t* anc,
+                       double* lwg, double* lw_slot, int32_t* tracking, int32_t* moved);
+
 /* A whole filter run of T frames (Algorithm 1). obs: T frames of H*W fp32
  * (spot) or T*3 fp32 (linear-Gaussian). Per-frame outputs may be NULL.
  * x_out (5n), lw_out (n: normalised log weights of the last frame before
  * resampling), anc_out (n: last ancestors or identity) may be NULL.
  * Returns 0, or -k when frame k had no finite normaliser. */
 int orc_run(const orc_model* m, int32_t T, const float* obs, double* mean, double* ess,
-            double* delta, int32_t* resampled, double* x_out, double* lw_out, int32_t* anc_out);
+            double* delta, int32_t* resampled, double* x_out, double* lw_out, int32_t* anc_out,
+            int64_t* arna_out);
+/* arna_out (ARNA only, may be NULL): per frame the ring key, the tracking
+ * groups G_t and the slots exchanged (both 0 when the frame did not
+ * resample), T * 3 values. */
 
 /* Derivatives of log p^ = sum_k delta_k with respect to theta = (s, b,
  * sigma_xi, q_x, q_y, q_vx, q_vy, q_I, I0), noise and ancestors fixed. */
