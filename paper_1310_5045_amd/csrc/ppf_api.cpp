@@ -981,18 +981,32 @@ struct ppf_batch_ctx : Runner {
   }
   // Fused step launches per tuning candidate: 0 every fused size in shape 0,
   // 1 all in shape 1, 2 sizes below kFusedMaxP in shape 1 and kFusedMaxP
-  // itself in shape 0. Re-orders the step items on the device; syncs.
+  // itself in shape 0. Re-orders the step items on the device; syncs. The
+  // host plan changes only once the new order is on the device.
+  int candidate = 0;
   int set_shapes(int cand) {
     if (cand < 0 || cand > 2) return fail(PPF_EINVAL, "shape candidate must be 0, 1 or 2");
     std::array<int, ppf::kFusedMaxP + 1> sh{};
     for (int P = 0; P <= ppf::kFusedMaxP; ++P)
       sh[P] = cand == 0 ? 0 : (cand == 1 ? 1 : (P < ppf::kFusedMaxP ? 1 : 0));
-    order_steps(&plan, sh);
-    hipError_t e = hipMemcpyAsync(base + plan.off_blocks, plan.blocks.data(),
-                                  sizeof(ppf::BatchItem) * plan.blocks.size(),
+    BatchPlan next = plan;
+    order_steps(&next, sh);
+    hipError_t e = hipMemcpyAsync(base + plan.off_blocks, next.blocks.data(),
+                                  sizeof(ppf::BatchItem) * next.blocks.size(),
                                   hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e, "uploading the step items");
+    if (e != hipSuccess) {
+      // the device items may be partly rewritten: put the current order back
+      (void)hipMemcpyAsync(base + plan.off_blocks, plan.blocks.data(),
+                           sizeof(ppf::BatchItem) * plan.blocks.size(), hipMemcpyHostToDevice,
+                           stream);
+      (void)hipStreamSynchronize(stream);
+      return hip_fail(e, "uploading the step items");
+    }
+    plan.blocks = std::move(next.blocks);
+    plan.step_ranges = std::move(next.step_ranges);
+    plan.shape_of = next.shape_of;
+    candidate = cand;
     graph.reset();
     return PPF_OK;
   }
@@ -1132,11 +1146,17 @@ int ppf_batch_autotune(ppf_batch h, const float* obs_dev, int32_t reps, double* 
     below = below || m.P < ppf::kFusedMaxP;
   }
   const int n = (top && below) ? 3 : 2;
+  const int keep = h->candidate;
   double ms[3] = {};
   for (int c = 0; c < n; ++c) {
     int rc = h->set_shapes(c);
     if (!rc) rc = h->time_launches(reps, [&] { return h->launch_steps(obs_dev); }, &ms[c]);
-    if (rc) return rc;
+    if (rc) {
+      const std::string why = h->err;
+      (void)h->set_shapes(keep);  // leave the batch in the shapes it had
+      h->err = why;
+      return rc;
+    }
   }
   int best = 0;
   for (int c = 1; c < n; ++c)

@@ -1098,9 +1098,10 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   }
 }
 
-// Patches up to 13 x 13 come in two workgroup shapes: five waves per SIMD
-// (no spills) or six with a smaller tile (13 x 13 spills three registers
-// there); wider patches keep the compiler's default budget.
+// Patches up to 13 x 13 come in two workgroup shapes: five waves per SIMD, or
+// six with a smaller tile (13 x 13 fits six waves' registers without spilling
+// because step_spot recomputes the particle index after the patch sums);
+// wider patches keep the compiler's default budget.
 template <int P, int S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kShapeWaves[S])))
 void k_step_spot(Model m, Buffers b, const float* __restrict__ obs) {
