@@ -160,6 +160,8 @@ WORKLOADS = {
     # the same with the distributed schemes over groups of 256 (4096 groups)
     "rna_512x512_n1m_p9": dict(W=512, H=512, T=50, n=1 << 20, s=1.5, P=9, thr=float(1 << 19),
                                scheme=(1, 256, 0)),
+    "arna_512x512_n1m_p9": dict(W=512, H=512, T=50, n=1 << 20, s=1.5, P=9, thr=float(1 << 19),
+                                scheme=(3, 256, 0), rho=0.5, rho_min=0.05),
     "rpa_gs_512x512_n1m_p9": dict(W=512, H=512, T=50, n=1 << 20, s=1.5, P=9,
                                   thr=float(1 << 19), scheme=(2, 256, 0)),
     "rpa_sgs_512x512_n1m_p9": dict(W=512, H=512, T=50, n=1 << 20, s=1.5, P=9,
@@ -287,7 +289,8 @@ def make_params(ppf, w, init_kind, grad=0):
                       background=10.0, noise_sigma=3.0, patch=w["P"], init_kind=init_kind,
                       init_a=(x0, y0, -1, -1, I / 2), init_b=(x1, y1, 1, 1, 1.5 * I),
                       ess_threshold=w["thr"], seed=1, grad=grad, resample=resample,
-                      rna_group=group, dlb=dlb)
+                      rna_group=group, dlb=dlb, rna_exchange=w.get("rho", 0.1),
+                      arna_min=w.get("rho_min", 0.0))
 
 
 def timed_steps(torch, f, frames, K, Wm, T, graph, shape):
@@ -369,7 +372,8 @@ def oracle_model(w, n, init_kind):
     return oracle.Model(n=n, width=w["W"], height=w["H"], s=w["s"], b=10.0, sigma=3.0,
                         patch=w["P"], init_kind=init_kind, init_a=(x0, y0, -1, -1, I / 2),
                         init_b=(x1, y1, 1, 1, 1.5 * I), ess_threshold=w["thr"], seed=1,
-                        resample=1 if resample == 1 else 0, rna_group=group)
+                        resample={1: 1, 3: 2}.get(resample, 0), rna_group=group,
+                        rna_exchange=w.get("rho", 0.1), arna_min=w.get("rho_min", 0.0))
 
 
 def cpu_baseline(w, frames, sample_n, sample_t, init_kind, threads):
@@ -419,7 +423,7 @@ def check_state(ppf, f, w, mv, k_truth, scheme):
     if not (math.isfinite(st["ess"]) and st["ess"] > 1.0):
         raise GateError(f"final ESS {st['ess']}")
     err = float(np.linalg.norm(st["mean"][:2] - mv.truth[k_truth, 0]))
-    if scheme != 1 and not err <= 1.0:
+    if scheme not in (1, 3) and not err <= 1.0:
         raise GateError(f"tracking error {err:.3f} px")
     x, lw, anc = f.particles()
     wt = np.exp(lw)
@@ -434,13 +438,18 @@ def check_state(ppf, f, w, mv, k_truth, scheme):
     if st["resampled"]:
         if anc.min() < 0 or anc.max() >= n:
             raise GateError("ancestor out of range")
-        if scheme == 1:
-            g = np.arange(n) // w["scheme"][1]
-            grp, moved = w["scheme"][1], int(math.floor(float(np.float32(0.1)) * w["scheme"][1]))
+        if scheme in (1, 3):
+            grp = w["scheme"][1]
+            g = np.arange(n) // grp
+            if scheme == 1:
+                moved = int(math.floor(float(np.float32(w.get("rho", 0.1))) * grp))
+                src = (g - 1) % (n // grp)
+            else:  # ARNA: the tail of each group from one other group (its ring predecessor)
+                moved = f.arna_state()["moved"]
+                src = (anc // grp).reshape(-1, grp)[:, -1][g] if moved else g
             tail = (np.arange(n) % grp) >= grp - moved
-            src = np.where(tail, (g - 1) % (n // grp), g)
-            if not np.array_equal(anc // grp, src):
-                raise GateError("RNA ancestor outside its group")
+            if not np.array_equal(anc // grp, np.where(tail, src, g)):
+                raise GateError("RNA ancestor outside its group or its ring predecessor")
         else:
             if scheme == 0 and np.any(np.diff(anc) < 0):
                 raise GateError("systematic ancestors not non-decreasing")
@@ -483,8 +492,8 @@ def oracle_check_step(f, w, frames, frames_dev, T, init_kind):
     if not np.all(np.abs(x1[:, idx] - xo) <= tol):
         raise GateError("propagation differs from the oracle")
     if st0["resampled"]:
-        if w.get("scheme", (0,))[0] == 1:
-            return  # RNA: the carried group weights are checked by the tests
+        if w.get("scheme", (0,))[0] in (1, 3):
+            return  # RNA, ARNA: the carried group weights are checked by the tests
         lw_in = np.full(idx.size, -math.log(n))
     else:
         lw_in = lw0[idx]
@@ -647,7 +656,7 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": args.workload, "n_particles": n, "frame": [w["W"], w["H"]],
                    "patch": P, "psf_sigma": w["s"],
-                   "resampling": ({0: "systematic", 1: "RNA", 2: "RPA"}[scheme]
+                   "resampling": ({0: "systematic", 1: "RNA", 2: "RPA", 3: "ARNA"}[scheme]
                                   + ("" if w["thr"] == float("inf")
                                      else f" when ESS < {w['thr']:.0f}")),
                    "init": args.init, "frames_timed": K, "launch": args.launch,

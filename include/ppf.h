@@ -58,7 +58,8 @@ enum {
   PPF_ENOTIMPL = -6   /* option recognised but not built                    */
 };
 
-enum { PPF_RESAMPLE_SYSTEMATIC = 0, PPF_RESAMPLE_RNA = 1, PPF_RESAMPLE_RPA = 2 };
+enum { PPF_RESAMPLE_SYSTEMATIC = 0, PPF_RESAMPLE_RNA = 1, PPF_RESAMPLE_RPA = 2,
+       PPF_RESAMPLE_ARNA = 3 };
 /* DLB schedules of Section 4: Greedy (Alg. 2), Sorted Greedy (Alg. 3),
  * Largest Gradient (Alg. 4). */
 enum { PPF_DLB_GS = 0, PPF_DLB_SGS = 1, PPF_DLB_LGS = 2 };
@@ -121,10 +122,35 @@ typedef struct ppf_ctx* ppf_handle;
  * rna_exchange  rho in [0, 1): after local resampling the last floor(rho * n)
  *               slots of group g take the particles (and weight) of the same
  *               slots of group g-1 mod G (Section 3, ring of processes).
+ *               Under ARNA: the largest exchange ratio.
+ *               PPF_RESAMPLE_ARNA, adaptive RNA (Section 6.4, which names its
+ *               rules without defining them; this is the library's reading):
+ *               RNA's local resampling over groups of rna_group, where
+ *               - group g tracks when its share W_g of the normalised weight
+ *                 is at least arna_track / G, G_t groups in all;
+ *               - mu = mu_min + floor((mu_max - mu_min) (G - G_t) / G) slots
+ *                 move per group, mu_max = floor(rna_exchange n), mu_min =
+ *                 floor(arna_min n): the more groups track, the fewer move;
+ *               - the last mu slots of each group take the particles (and
+ *                 weight) of the same slots of its predecessor on a ring of
+ *                 the groups. The object counts as lost at a frame whose
+ *                 log-likelihood increment falls more than arna_lost * P
+ *                 below that of the last frame at which it was not lost;
+ *                 each loss redraws the ring order (a permutation keyed by
+ *                 the seed, track_id and the frame of the loss: an 8-round
+ *                 Feistel network on Philox4x32-10 over the smallest even
+ *                 number of bits b with 2^b >= G, restricted to the groups by
+ *                 cycle walking), which is kept until the next loss; before
+ *                 any loss the ring is the index order g-1 -> g of RNA.
+ *               With arna_min = rna_exchange and no loss, ARNA is RNA.
  * seed          Philox key.
  * track_id      Philox counter word 3 (distinguishes independent filters).
  * dlb           PPF_DLB_GS or PPF_DLB_SGS: the schedule of RPA.
  * reserved      must be 0.
+ * arna_min      ARNA: the smallest exchange ratio, 0 <= arna_min <= rna_exchange.
+ * arna_track    ARNA: theta > 0 of the tracking test W_g >= theta / G.
+ * arna_lost     ARNA: kappa >= 0 of the lost test (+INFINITY: never lost).
+ * arna_pad      must be 0.
  * grad          1: every step also accumulates the derivatives of log p^ in
  *               theta (see ppf_grad). Needs the spot model, systematic
  *               resampling and ess_threshold = +INFINITY; the workspace then
@@ -155,6 +181,10 @@ typedef struct ppf_params {
   int32_t grad; /* 0, or 1: also accumulate d log p^ / d theta (ppf_grad) */
   int32_t dlb;      /* PPF_DLB_* schedule of RPA */
   int32_t reserved; /* must be 0 */
+  float arna_min;   /* ARNA: smallest exchange ratio */
+  float arna_track; /* ARNA: tracking share theta */
+  float arna_lost;  /* ARNA: lost-test kappa */
+  int32_t arna_pad; /* must be 0 */
 } ppf_params;
 
 /* Scalars of the last committed step (see ppf_stats). */
@@ -312,6 +342,14 @@ int ppf_loglik(ppf_handle h, double* cum, double* last);
  */
 #define PPF_NGRAD 9
 int ppf_grad(ppf_handle h, double cum[PPF_NGRAD], double last[PPF_NGRAD]);
+
+/* ARNA state after the last committed step (PPF_RESAMPLE_ARNA only, EINVAL
+ * otherwise); syncs. ring_key: the frame of the latest loss, which keys the
+ * ring order (0: no loss yet, the index ring); lost: 1 if that step found the
+ * object lost; tracking: G_t and moved: mu of its resampling (both 0 when it
+ * did not resample). Any pointer may be NULL. */
+int ppf_arna_state(ppf_handle h, int64_t* ring_key, int32_t* lost, int32_t* tracking,
+                   int32_t* moved);
 
 /* All scalars of the last committed step; syncs and clears the roll-back
  * report (returns PPF_OK even if steps were rolled back: see rolled_back). */

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libppf.so")
 
 PPF_OK, PPF_EINVAL, PPF_ENOMEM, PPF_EDEVICE, PPF_ESTATE, PPF_ENUMERIC, PPF_ENOTIMPL = (
     0, -1, -2, -3, -4, -5, -6)
-RESAMPLE_SYSTEMATIC, RESAMPLE_RNA, RESAMPLE_RPA = 0, 1, 2
+RESAMPLE_SYSTEMATIC, RESAMPLE_RNA, RESAMPLE_RPA, RESAMPLE_ARNA = 0, 1, 2, 3
 DLB_GS, DLB_SGS, DLB_LGS = 0, 1, 2
 DLB_MAX_SORTED = 4096
 STATIC_MAX_N = 1 << 22  # weights the allocation-free resampler takes
@@ -62,6 +62,10 @@ class Params(ctypes.Structure):
         ("grad", ctypes.c_int32),
         ("dlb", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("arna_min", ctypes.c_float),
+        ("arna_track", ctypes.c_float),
+        ("arna_lost", ctypes.c_float),
+        ("arna_pad", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -120,6 +124,10 @@ _SIGS = {
     "ppf_loglik": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]),
     "ppf_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ppf_arna_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]),
     "ppf_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ppf_get_particles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]),
@@ -319,6 +327,15 @@ class Filter:
         s = Stats()
         _check(lib().ppf_stats(self.handle, ctypes.byref(s)), self.handle)
         return _stats_dict(s)
+
+    def arna_state(self) -> dict:
+        """ARNA after the last committed step: ring_key (the frame of the
+        latest loss, 0 before any), lost, tracking groups and slots exchanged
+        of its resampling. Syncs."""
+        key, lost, t, mu = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().ppf_arna_state(self.handle, ctypes.byref(key), ctypes.byref(lost),
+                                    ctypes.byref(t), ctypes.byref(mu)), self.handle)
+        return dict(ring_key=key.value, lost=bool(lost.value), tracking=t.value, moved=mu.value)
 
     def grad(self) -> Tuple[np.ndarray, np.ndarray]:
         """(d cum / d theta, the last step's term), theta as GRAD_NAMES; the

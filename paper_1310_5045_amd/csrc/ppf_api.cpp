@@ -54,9 +54,17 @@ std::string validate(const ppf_params* p) {
   if (p->init_kind < PPF_INIT_UNIFORM || p->init_kind > PPF_INIT_STRATIFIED)
     return "unknown init_kind";
   if (p->resample != PPF_RESAMPLE_SYSTEMATIC && p->resample != PPF_RESAMPLE_RNA &&
-      p->resample != PPF_RESAMPLE_RPA)
+      p->resample != PPF_RESAMPLE_RPA && p->resample != PPF_RESAMPLE_ARNA)
     return "unknown resample scheme";
-  if (p->reserved != 0) return "reserved must be 0";
+  if (p->reserved != 0 || p->arna_pad != 0) return "reserved must be 0";
+  if (p->resample == PPF_RESAMPLE_ARNA) {
+    if (p->obs_model != PPF_OBS_SPOT) return "ARNA needs the spot model";
+    if (!(p->arna_min >= 0.0f && p->arna_min <= p->rna_exchange))
+      return "ARNA: arna_min must be in [0, rna_exchange]";
+    if (!(p->arna_track > 0.0f) || !std::isfinite(p->arna_track))
+      return "ARNA: arna_track must be > 0";
+    if (!(p->arna_lost >= 0.0f)) return "ARNA: arna_lost must be >= 0";
+  }
   if (p->resample == PPF_RESAMPLE_RPA) {
     if (p->rna_group < 1 || p->n_particles % p->rna_group != 0)
       return "RPA: n_particles must be a multiple of rna_group";
@@ -87,7 +95,7 @@ std::string validate(const ppf_params* p) {
     for (int d = 0; d < 3; ++d)
       if (!(p->lg_r[d] > 0.0f) || !std::isfinite(p->lg_r[d])) return "lg_r must be > 0";
   }
-  if (p->resample == PPF_RESAMPLE_RNA) {
+  if (p->resample == PPF_RESAMPLE_RNA || p->resample == PPF_RESAMPLE_ARNA) {
     if (p->rna_group < 1 || p->rna_group > ppf::kMaxGroup) return "rna_group out of range";
     if (p->n_particles % p->rna_group != 0) return "n_particles must be a multiple of rna_group";
     if (!(p->rna_exchange >= 0.0f && p->rna_exchange < 1.0f)) return "rna_exchange not in [0,1)";
@@ -136,11 +144,17 @@ Model make_model(const ppf_params* p) {
     m.lg_norm += r > 0.0 ? std::log(r * std::sqrt(2.0 * M_PI)) : 0.0;
   }
   m.thr = p->ess_threshold;
-  if (p->resample == PPF_RESAMPLE_RNA) {
+  if (p->resample == PPF_RESAMPLE_RNA || p->resample == PPF_RESAMPLE_ARNA) {
     m.group = p->rna_group;
     m.moved = (int32_t)std::floor((double)p->rna_exchange * (double)p->rna_group);
     m.G = (int32_t)(m.n / m.group);
     m.inv_group = 1.0 / (double)m.group;
+  }
+  if (p->resample == PPF_RESAMPLE_ARNA) {
+    m.arna = 1;
+    m.arna_mu_min = (int32_t)std::floor((double)p->arna_min * (double)p->rna_group);
+    m.arna_share = (double)p->arna_track / (double)m.G;
+    m.arna_drop = (double)p->arna_lost * (double)m.P;
   }
   m.key0 = (uint32_t)p->seed;
   m.key1 = (uint32_t)(p->seed >> 32);
@@ -190,7 +204,8 @@ size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) 
   const int64_t n = p->n_particles;
   Buffers bb{};
   shape(n, &bb);
-  const int64_t G = p->resample == PPF_RESAMPLE_RNA ? n / p->rna_group : 1;
+  const bool groups = p->resample == PPF_RESAMPLE_RNA || p->resample == PPF_RESAMPLE_ARNA;
+  const int64_t G = groups ? n / p->rna_group : 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char* ptr = base ? base + off : nullptr;
@@ -222,6 +237,11 @@ size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) 
     bb.rns = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2));
     bb.rrank = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2 * Gr));
     bb.rsorted = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2 * Gr));
+  }
+  if (p->resample == PPF_RESAMPLE_ARNA) {
+    bb.aloc = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
+    bb.Wg = reinterpret_cast<double*>(take(sizeof(double) * G));
+    bb.lwt = reinterpret_cast<double*>(take(sizeof(double) * G));
   }
   if (p->grad) {
     bb.T0 = reinterpret_cast<float*>(take(sizeof(float) * ppf::kNTan * n));
@@ -403,7 +423,8 @@ struct Runner {
       if (rc) return rc;
       e = hipMemcpyAsync(logw_host, b.lw64, sizeof(double) * n, hipMemcpyDeviceToHost, stream);
     }
-    const bool resampled = c.mode == ppf::kModeSys || c.mode == ppf::kModeRna;
+    const bool resampled =
+        c.mode == ppf::kModeSys || c.mode == ppf::kModeRna || c.mode == ppf::kModeArna;
     if (e == hipSuccess && anc_host && resampled)
       e = hipMemcpyAsync(anc_host, b.anc, sizeof(int32_t) * n, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -482,6 +503,9 @@ int ppf_params_default(ppf_params* p) {
   p->rna_exchange = 0.1f;
   p->seed = 1;
   p->track_id = 0;
+  p->arna_min = 0.0f;
+  p->arna_track = 0.5f;
+  p->arna_lost = 3.0f;
   return PPF_OK;
 }
 
@@ -530,6 +554,8 @@ int enqueue_step(ppf_handle h, const float* obs_dev) {
   const ppf::WeightSrc w = h->filter_weights();
   if (h->p.resample == PPF_RESAMPLE_RNA)
     return h->run(kKRna, [&] { return ppf::launch_rna(h->m, h->b, w, nullptr, h->stream); });
+  if (h->p.resample == PPF_RESAMPLE_ARNA)
+    return h->run(kKRna, [&] { return ppf::launch_arna(h->m, h->b, h->stream); });
   rc = h->run(kKAnc, [&] { return ppf::launch_anc(h->m, h->b, w, h->stream); });
   if (rc) return rc;
   rc = h->run(kKFill, [&] { return ppf::launch_fill(h->m, h->b, h->stream); });
@@ -652,6 +678,20 @@ int ppf_grad(ppf_handle h, double cum[PPF_NGRAD], double last[PPF_NGRAD]) {
     if (last) last[d] = c.grad_last[d];
   }
   return rc;
+}
+
+int ppf_arna_state(ppf_handle h, int64_t* ring_key, int32_t* lost, int32_t* tracking,
+                   int32_t* moved) {
+  if (!h) return PPF_ESTATE;
+  if (!h->m.arna) return h->fail(PPF_EINVAL, "the filter does not use ARNA");
+  Ctrl c;
+  const int rc = h->read_ctrl(&c);
+  if (rc) return rc;
+  if (ring_key) *ring_key = c.ring_key;
+  if (lost) *lost = c.lost;
+  if (tracking) *tracking = c.resampled ? c.arna_tracking : 0;
+  if (moved) *moved = c.resampled ? c.arna_moved : 0;
+  return PPF_OK;
 }
 
 int ppf_stats(ppf_handle h, ppf_stats_t* out) {
@@ -868,8 +908,8 @@ std::string validate_batch(const ppf_params* p, int32_t count) {
     if (p[t].obs_model != PPF_OBS_SPOT)
       return "track " + std::to_string(t) + ": batches take the spot model only";
     if (p[t].grad) return "track " + std::to_string(t) + ": batches do not take grad = 1";
-    if (p[t].resample == PPF_RESAMPLE_RPA)
-      return "track " + std::to_string(t) + ": batches do not take RPA";
+    if (p[t].resample == PPF_RESAMPLE_RPA || p[t].resample == PPF_RESAMPLE_ARNA)
+      return "track " + std::to_string(t) + ": batches do not take RPA or ARNA";
     if (p[t].width != p[0].width || p[t].height != p[0].height)
       return "track " + std::to_string(t) + ": frame size differs from track 0";
   }

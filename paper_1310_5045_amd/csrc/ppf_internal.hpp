@@ -77,7 +77,7 @@ struct FillRun {
   int32_t pad;
 };
 
-enum Purpose : uint32_t { kInit = 1, kPropagate = 2, kResample = 3, kRna = 4 };
+enum Purpose : uint32_t { kInit = 1, kPropagate = 2, kResample = 3, kRna = 4, kRing = 5 };
 
 // What the next k_step reads for the parent and the carried log weight.
 enum Mode : int32_t {
@@ -85,7 +85,9 @@ enum Mode : int32_t {
   kModeNone = 1,  // parents identity, log w = stored normalised log weight
   kModeSys = 2,   // parents = ancestors, log w = -log N
   kModeRna = 3,   // parents = ancestors, log w = log(W_g / n) of the slot's group
-  kModeSet = 4    // parents identity, log w = caller-supplied fp64 values
+  kModeSet = 4,   // parents identity, log w = caller-supplied fp64 values
+  kModeArna = 5   // parents = ancestors, log w = log(W_g / n) of the slot's group, or
+                  // of its ring predecessor for the last arna_moved slots
 };
 
 // Derivatives of log p^ kept in gradient mode, theta = (s, b, sigma_xi,
@@ -111,7 +113,17 @@ struct Ctrl {
   uint64_t total;       // fixed-point total weight (2^62 scale) of the CDF
   double grad_cum[kNGrad];   // d cum / d theta over committed steps
   double grad_last[kNGrad];  // the last committed step's term
-  double pad1[13];
+  // ARNA: the frame of the latest loss (keys the ring order; 0: index ring),
+  // the log-likelihood increment of the last frame that was not lost, whether
+  // the last step lost the object, and its resampling's tracking groups
+  // (counted by k_arna_local) and slots exchanged
+  int64_t ring_key;
+  double delta_ref;
+  int32_t lost;
+  int32_t arna_tracking;
+  int32_t arna_moved;
+  int32_t pad2;
+  double pad1[9];
 };
 static_assert(sizeof(Ctrl) == 384, "Ctrl must stay 384 bytes");
 
@@ -153,6 +165,11 @@ struct Model {
   double s_psf;          // s
   double sig;            // sigma_xi
   double clo[2], chi[2]; // patch-centre clamp (x, y): -P and W + P, H + P
+  // ARNA (group, G and moved = the largest exchange as for RNA)
+  int32_t arna;          // adaptive RNA
+  int32_t arna_mu_min;   // the smallest exchange, floor(arna_min n)
+  double arna_share;     // a group tracks when W_g >= arna_share (= theta / G)
+  double arna_drop;      // lost when delta < delta_ref - arna_drop (= kappa P)
 };
 
 // Device buffers carved from the caller's workspace (or a scratch area).
@@ -183,6 +200,9 @@ struct Buffers {
   int32_t* rns;      // RPA: number of senders
   int32_t* rrank;    // RPA with SGS: rank of each group among senders, then receivers (2G)
   int32_t* rsorted;  // RPA with SGS: groups in sender order, then receiver order (2G)
+  int32_t* aloc;     // ARNA: each group's local resampling (n global indices)
+  double* Wg;        // ARNA: each group's share of the normalised weight
+  double* lwt;       // ARNA: per group, the weight log(W_pred / n) of its exchanged slots
   int64_t hq_cap;   // entries of hq
   int64_t nb;       // block records = ceil(n / kBlock)
   int64_t chunk;    // records per merge chunk (multiple of 256, at most 2048)
@@ -223,6 +243,9 @@ hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int6
 // Device address and size of the current device's static scratch array
 // (kStaticScratchBytes, 256-byte aligned), looked up once per device.
 hipError_t static_scratch(void** ptr, size_t* bytes);
+
+// ARNA: local resampling per group, then the exchange along the ring.
+hipError_t launch_arna(const Model& m, const Buffers& b, hipStream_t s);
 
 // RPA: the balancing plan and the routed ancestors of one filter.
 hipError_t launch_rpa(const Model& m, const Buffers& b, hipStream_t s);

@@ -403,6 +403,11 @@ __device__ __forceinline__ void init_body(const Model& m, const Buffers& b, int6
     c->u = 0.0;
     c->total = 0;
     for (int d = 0; d < kNGrad; ++d) c->grad_cum[d] = c->grad_last[d] = 0.0;
+    c->ring_key = 0;
+    c->delta_ref = -INFINITY;
+    c->lost = 0;
+    c->arna_tracking = 0;
+    c->arna_moved = 0;
   }
   if (i >= m.n) return;
   if (m.grad)
@@ -464,8 +469,9 @@ struct Prop {
 // caller-set weight, or -log N after systematic resampling. Kept out of
 // propagate so that kernels compute it only where the likelihood is added,
 // instead of holding it across the patch sums.
+// amv: the slots exchanged by the last ARNA resampling (the control block's).
 __device__ __forceinline__ double prior_lw(const Model& m, const Buffers& b, int cur, int mode,
-                                           double delta, int64_t i) {
+                                           double delta, int amv, int64_t i) {
   if (mode == kModeNone) {
     const float* Ein = cur ? b.E1 : b.E0;
     const double* Rin = cur ? b.R1 : b.R0;
@@ -477,6 +483,11 @@ __device__ __forceinline__ double prior_lw(const Model& m, const Buffers& b, int
     const int64_t src = (l >= m.group - m.moved) ? (g + m.G - 1) % m.G : g;
     return b.lwg[src];
   }
+  if (mode == kModeArna) {
+    const int64_t g = i / m.group;
+    const int64_t l = i - g * m.group;
+    return (l >= m.group - amv) ? b.lwt[g] : b.lwg[g];
+  }
   if (mode == kModeSet) return b.lw64[i];
   return -m.log_n;
 }
@@ -487,7 +498,7 @@ __device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int 
                                           int64_t* po = nullptr) {
   const float* Xin = cur ? b.X1 : b.X0;
   int64_t p = i;
-  if (mode == kModeSys || mode == kModeRna) p = b.anc[i];
+  if (mode == kModeSys || mode == kModeRna || mode == kModeArna) p = b.anc[i];
   const int64_t n = m.n;
   const float px = Xin[p], py = Xin[n + p], pvx = Xin[2 * n + p], pvy = Xin[3 * n + p],
               pI = Xin[4 * n + p];
@@ -809,7 +820,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   double* const dsh = L.dsh;
   int* const ish = L.ish;
   const Ctrl* cp = b.ctrl;
-  const int cur = cp->cur, mode = cp->mode;
+  const int cur = cp->cur, mode = cp->mode, amv = cp->arna_moved;
   const double cdelta = cp->delta;
   const uint32_t k = (uint32_t)(cp->k + 1);
   const int t = threadIdx.x, w = wave_index();
@@ -1005,7 +1016,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     }
     const double I = (double)o.I;
     const double ssq = mo.sd2 - 2.0 * I * mo.X0 + I * I * (G2x * mo.B0);
-    l = prior_lw(m, b, cur, mode, cdelta, ia) - ssq * m.inv2sig2 - m.lognorm_obs;
+    l = prior_lw(m, b, cur, mode, cdelta, amv, ia) - ssq * m.inv2sig2 - m.lognorm_obs;
     // 1-D moments of g_x^2 and the in-frame sum of g_x (true centre rx)
     double A1 = 0.0, A2 = 0.0, Gin_x = 0.0;
 #pragma unroll
@@ -1062,7 +1073,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     const int64_t ial = il < m.n ? il : m.n - 1;
     const double I = (double)o.I;
     const double ssq = sd2 - 2.0 * I * X + I * I * (G2x * G2y);
-    l = prior_lw(m, b, cur, mode, cdelta, ial) - ssq * m.inv2sig2 - m.lognorm_obs;
+    l = prior_lw(m, b, cur, mode, cdelta, amv, ial) - ssq * m.inv2sig2 - m.lognorm_obs;
   }
   const double e = finish_block(b, cur, il, active, l, o, tile, dsh, L.ksh);
   if constexpr (GRAD) {
@@ -1131,7 +1142,7 @@ __global__ __launch_bounds__(256) void k_step_lg(Model m, Buffers b,
   __shared__ double dsh[4];
   __shared__ int ksh[4];
   const Ctrl* cp = b.ctrl;
-  const int cur = cp->cur, mode = cp->mode;
+  const int cur = cp->cur, mode = cp->mode, amv = cp->arna_moved;
   const double cdelta = cp->delta;
   const uint32_t k = (uint32_t)(cp->k + 1);
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1143,7 +1154,7 @@ __global__ __launch_bounds__(256) void k_step_lg(Model m, Buffers b,
     store_state(m, b, cur, i, o);
     const double ex = (double)obs[0] - (double)o.x, ey = (double)obs[1] - (double)o.y,
                  eI = (double)obs[2] - (double)o.I;
-    l = prior_lw(m, b, cur, mode, cdelta, i) - ex * ex * m.lg_inv2r2[0] - ey * ey * m.lg_inv2r2[1] - eI * eI * m.lg_inv2r2[2] -
+    l = prior_lw(m, b, cur, mode, cdelta, amv, i) - ex * ex * m.lg_inv2r2[0] - ey * ey * m.lg_inv2r2[1] - eI * eI * m.lg_inv2r2[2] -
         m.lg_norm;
   }
   finish_block(b, cur, i, active, l, o, red, dsh, ksh);
@@ -1363,7 +1374,20 @@ __device__ __forceinline__ void merge_final_body(const Model& m, const Buffers& 
         }
       c->resampled = res ? 1 : 0;
       c->do_resample = res ? 1 : 0;
-      c->mode = res ? (m.group > 0 ? kModeRna : kModeSys) : kModeNone;
+      c->mode = res ? (m.arna ? kModeArna : (m.group > 0 ? kModeRna : kModeSys)) : kModeNone;
+      if (m.arna) {
+        // the object is lost when this increment falls well below that of
+        // the last frame that tracked it; each loss keys a new ring order
+        const double inc = M + logS;
+        const bool lost = inc < c->delta_ref - m.arna_drop;
+        if (lost)
+          c->ring_key = k;
+        else
+          c->delta_ref = inc;
+        c->lost = lost ? 1 : 0;
+        c->arna_tracking = 0;  // counted by k_arna_local
+        c->arna_moved = 0;     // set by k_arna_exchange
+      }
       const uint4 rr = draw(m, 0u, (uint32_t)k, kResample, 0u);
       c->u = u53(rr.x, rr.y);
       pre = (res && m.group == 0) ? 1 : 0;
@@ -1707,6 +1731,78 @@ __device__ __forceinline__ double wave_sum_d(double v, int lane) {
 // group's normalised weights, slot weight W_g / n, and the last `moved` slots
 // taken from group g-1's local resampling (recomputed here, so no workgroup
 // waits for another).
+// The normalised weights of group gg's ng particles (E relative to its
+// block maximum, or absolute fp32 log weights), their sum W (returned) and
+// their local CDF in 2^60 fixed point, C[0..ng), by one 256-thread
+// workgroup; dsum and wsum are 4 entries of LDS scratch each.
+__device__ __forceinline__ double group_cdf(const WeightSrc& ws, const float* E, const double* rec,
+                                            double lognorm, int64_t gg, int ng, uint64_t* C,
+                                            double* dsum, uint64_t* wsum) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int ipt = (ng + 255) / 256;
+  const int64_t base = gg * ng;
+  double wl[4];
+  double part = 0.0;
+  for (int j = 0; j < ipt; ++j) {
+    const int li = t * ipt + j;
+    wl[j] = 0.0;
+    if (li < ng) {
+      const int64_t idx = base + li;
+      if (ws.log_src) {
+        wl[j] = exp((double)E[idx] - lognorm);
+      } else {
+        const double mb = rec[(idx / kBlock) * kRec];
+        wl[j] = mb == -INFINITY ? 0.0 : (double)E[idx] * exp(mb - lognorm);
+      }
+      part += wl[j];
+    }
+  }
+  part = wave_sum_d(part, lane);
+  if (lane == 0) dsum[w] = part;
+  __syncthreads();
+  const double W = (dsum[0] + dsum[1]) + (dsum[2] + dsum[3]);
+  __syncthreads();
+  uint64_t run = 0, v[4];
+  for (int j = 0; j < ipt; ++j) {
+    const uint64_t wf = (W > 0.0) ? __double2ull_rn(wl[j] / W * 0x1p60) : 0ull;
+    run += wf;
+    v[j] = run;
+  }
+  const uint64_t incl = wave_scan(run, lane, OpAdd());
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint64_t before = 0;
+  for (int j = 0; j < w; ++j) before += wsum[j];
+  for (int j = 0; j < ipt; ++j) {
+    const int li = t * ipt + j;
+    if (li < ng) C[li] = before + incl - run + v[j];
+  }
+  __syncthreads();
+  return W;
+}
+
+// Local systematic resampling of slot l of a group with CDF C (ng entries)
+// and uniform u: the first j with C_j > (l + u) / ng in 2^60 fixed point (the
+// identity when the group has no weight).
+__device__ __forceinline__ int local_slot(const uint64_t* C, int ng, double inv_ng, double W,
+                                          double u, int l) {
+  if (!(W > 0.0)) return l;
+  const uint64_t us = (uint64_t)(((double)l + u) * inv_ng * 0x1p60);
+  int lo = 0, hi = ng - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (C[mid] > us)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
+// One workgroup per group g (Section 3): local systematic resampling of the
+// group's normalised weights, slot weight W_g / n, and the last `moved` slots
+// taken from group g-1's local resampling (recomputed here, so no workgroup
+// waits for another).
 __device__ __forceinline__ void rna_body(const Model& m, const Buffers& b, const WeightSrc& ws,
                                          const double* __restrict__ u_dev, int64_t g) {
   __shared__ uint64_t C[2][kMaxGroup];
@@ -1721,51 +1817,12 @@ __device__ __forceinline__ void rna_body(const Model& m, const Buffers& b, const
   const int64_t G = m.G;
   const int64_t prev = (g + G - 1) % G;
   const double lognorm = c->delta;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int ipt = (ng + 255) / 256;
+  const int t = threadIdx.x;
   double Wg[2];
   double ug[2];
   for (int side = 0; side < 2; ++side) {
     const int64_t gg = side ? prev : g;
-    const int64_t base = gg * ng;
-    double wl[4];
-    double part = 0.0;
-    for (int j = 0; j < ipt; ++j) {
-      const int li = t * ipt + j;
-      wl[j] = 0.0;
-      if (li < ng) {
-        const int64_t idx = base + li;
-        if (ws.log_src) {
-          wl[j] = exp((double)E[idx] - lognorm);
-        } else {
-          const double mb = rec[(idx / kBlock) * kRec];
-          wl[j] = mb == -INFINITY ? 0.0 : (double)E[idx] * exp(mb - lognorm);
-        }
-        part += wl[j];
-      }
-    }
-    part = wave_sum_d(part, lane);
-    if (lane == 0) dsum[w] = part;
-    __syncthreads();
-    const double W = (dsum[0] + dsum[1]) + (dsum[2] + dsum[3]);
-    __syncthreads();
-    uint64_t run = 0, v[4];
-    for (int j = 0; j < ipt; ++j) {
-      const uint64_t wf = (W > 0.0) ? __double2ull_rn(wl[j] / W * 0x1p60) : 0ull;
-      run += wf;
-      v[j] = run;
-    }
-    const uint64_t incl = wave_scan(run, lane, OpAdd());
-    if (lane == 63) wsum[w] = incl;
-    __syncthreads();
-    uint64_t before = 0;
-    for (int j = 0; j < w; ++j) before += wsum[j];
-    for (int j = 0; j < ipt; ++j) {
-      const int li = t * ipt + j;
-      if (li < ng) C[side][li] = before + incl - run + v[j];
-    }
-    __syncthreads();
-    Wg[side] = W;
+    Wg[side] = group_cdf(ws, E, rec, lognorm, gg, ng, C[side], dsum, wsum);
     if (u_dev) {
       ug[side] = u_dev[gg];
     } else {
@@ -1777,19 +1834,7 @@ __device__ __forceinline__ void rna_body(const Model& m, const Buffers& b, const
   for (int l = t; l < ng; l += 256) {
     const int side = (l >= ng - m.moved) ? 1 : 0;
     const int64_t gg = side ? prev : g;
-    int j = l;
-    if (Wg[side] > 0.0) {
-      const uint64_t us = (uint64_t)(((double)l + ug[side]) * m.inv_group * 0x1p60);
-      int lo = 0, hi = ng - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (C[side][mid] > us)
-          hi = mid;
-        else
-          lo = mid + 1;
-      }
-      j = lo;
-    }
+    const int j = local_slot(C[side], ng, m.inv_group, Wg[side], ug[side], l);
     b.anc[g * ng + l] = (int32_t)(gg * ng + j);
   }
   if (t == 0) b.lwg[g] = log(Wg[0] / (double)ng);
@@ -1798,6 +1843,119 @@ __device__ __forceinline__ void rna_body(const Model& m, const Buffers& b, const
 __global__ __launch_bounds__(256) void k_rna(Model m, Buffers b, WeightSrc ws,
                                              const double* __restrict__ u_dev) {
   rna_body(m, b, ws, u_dev, blockIdx.x);
+}
+
+// ------------------------------------------------------------------ ARNA
+// Adaptive RNA (Section 6.4 names its rules; the reading): RNA's local
+// resampling per group; G_t groups track (share W_g >= theta / G); mu =
+// mu_min + floor((mu_max - mu_min) (G - G_t) / G) slots move per group, from
+// its predecessor on a ring of the groups whose order is redrawn whenever the
+// object is lost (k_merge_final keys it by the frame of the loss).
+
+// One round value of the ring's Feistel network: the low `half` bits of word
+// 0 of the Philox block with counter (R, key, RING << 24 | r, track).
+__device__ __forceinline__ uint32_t ring_f(const Model& m, uint32_t key, uint32_t r, uint32_t R,
+                                           uint32_t mask) {
+  return draw(m, R, key, kRing, r).x & mask;
+}
+
+// Eight Feistel rounds (L, R) -> (R, L xor F_r(R)) on the two halves of x,
+// and their inverse: a keyed permutation of [0, 2^(2 half)).
+__device__ __forceinline__ uint32_t ring_fwd(const Model& m, uint32_t key, int half, uint32_t x) {
+  const uint32_t mask = (1u << half) - 1u;
+  uint32_t L = x >> half, R = x & mask;
+  for (uint32_t r = 0; r < 8; ++r) {
+    const uint32_t nl = R;
+    R = L ^ ring_f(m, key, r, R, mask);
+    L = nl;
+  }
+  return (L << half) | R;
+}
+__device__ __forceinline__ uint32_t ring_back(const Model& m, uint32_t key, int half, uint32_t x) {
+  const uint32_t mask = (1u << half) - 1u;
+  uint32_t L = x >> half, R = x & mask;
+  for (int r = 7; r >= 0; --r) {
+    const uint32_t pl = R ^ ring_f(m, key, (uint32_t)r, L, mask);
+    R = L;
+    L = pl;
+  }
+  return (L << half) | R;
+}
+
+// The ring predecessor of group g among G groups under ring key `key`: the
+// ring order is the permutation of [0, 2^b) (b the smallest even width with
+// 2^b >= G) restricted to [0, G) by cycle walking; g's ring position comes
+// from walking the inverse, its predecessor's group from walking forward.
+// Key 0: the index ring (g - 1 mod G).
+__device__ int64_t ring_pred(const Model& m, uint32_t key, int64_t G, int64_t g) {
+  if (key == 0 || G < 2) return (g + G - 1) % G;
+  int b = 2;
+  while (((int64_t)1 << b) < G) b += 2;
+  const int half = b / 2;
+  uint32_t x = (uint32_t)g;
+  do {
+    x = ring_back(m, key, half, x);
+  } while ((int64_t)x >= G);
+  uint32_t y = (uint32_t)(((int64_t)x + G - 1) % G);
+  do {
+    y = ring_fwd(m, key, half, y);
+  } while ((int64_t)y >= G);
+  return (int64_t)y;
+}
+
+// One workgroup per group: W_g, the local systematic resampling (global
+// indices into aloc), and the tracking count.
+__device__ __forceinline__ void arna_local_body(const Model& m, const Buffers& b, int64_t g) {
+  __shared__ uint64_t C[kMaxGroup];
+  __shared__ double dsum[4];
+  __shared__ uint64_t wsum[4];
+  Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int cur = c->cur;
+  const WeightSrc ws{b.E0, b.E1, b.R0, b.R1, 1, 0};
+  const float* E = cur ? b.E1 : b.E0;
+  const double* rec = cur ? b.R1 : b.R0;
+  const int ng = m.group;
+  const double W = group_cdf(ws, E, rec, c->delta, g, ng, C, dsum, wsum);
+  const uint4 rr = draw(m, (uint32_t)g, (uint32_t)c->k, kRna, 0u);
+  const double u = u53(rr.x, rr.y);
+  for (int l = threadIdx.x; l < ng; l += 256)
+    b.aloc[g * ng + l] = (int32_t)(g * ng + local_slot(C, ng, m.inv_group, W, u, l));
+  if (threadIdx.x == 0) {
+    b.Wg[g] = W;
+    if (W >= m.arna_share) atomicAdd(&c->arna_tracking, 1);
+  }
+}
+
+// One workgroup per group: the exchange along the ring and the slot weights.
+__device__ __forceinline__ void arna_exchange_body(const Model& m, const Buffers& b, int64_t g) {
+  __shared__ int64_t sh_pred;
+  Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int64_t G = m.G;
+  const int ng = m.group;
+  const int64_t mu =
+      m.arna_mu_min + ((int64_t)(m.moved - m.arna_mu_min) * (G - c->arna_tracking)) / G;
+  if (threadIdx.x == 0) sh_pred = ring_pred(m, (uint32_t)c->ring_key, G, g);
+  __syncthreads();
+  const int64_t pred = sh_pred;
+  for (int l = threadIdx.x; l < ng; l += 256) {
+    const int64_t src = (l >= ng - mu) ? pred : g;
+    b.anc[g * ng + l] = b.aloc[src * ng + l];
+  }
+  if (threadIdx.x == 0) {
+    b.lwg[g] = log(b.Wg[g] / (double)ng);
+    b.lwt[g] = log(b.Wg[pred] / (double)ng);
+    if (g == 0) c->arna_moved = (int32_t)mu;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_arna_local(Model m, Buffers b) {
+  arna_local_body(m, b, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_arna_exchange(Model m, Buffers b) {
+  arna_exchange_body(m, b, blockIdx.x);
 }
 
 // ------------------------------------------------------------------- RPA
@@ -2175,7 +2333,7 @@ __global__ __launch_bounds__(256) void k_gather(Model m, Buffers b, float* __res
   const Ctrl* c = b.ctrl;
   const float* X = c->cur ? b.X1 : b.X0;
   const int mode = c->mode;
-  const int64_t p = (mode == kModeSys || mode == kModeRna) ? b.anc[i] : i;
+  const int64_t p = (mode == kModeSys || mode == kModeRna || mode == kModeArna) ? b.anc[i] : i;
 #pragma unroll
   for (int d = 0; d < 5; ++d) out[d * m.n + i] = X[d * m.n + p];
 }
@@ -2455,6 +2613,12 @@ hipError_t launch_rna_batch(const Model* ms, const Buffers* bs, const BatchItem*
                             int64_t n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   return launch_k(k_rna_batch, dim3((unsigned)n_items), dim3(256), s, ms, bs, items);
+}
+
+hipError_t launch_arna(const Model& m, const Buffers& b, hipStream_t s) {
+  const hipError_t e = launch_k(k_arna_local, dim3((unsigned)m.G), dim3(256), s, m, b);
+  if (e != hipSuccess) return e;
+  return launch_k(k_arna_exchange, dim3((unsigned)m.G), dim3(256), s, m, b);
 }
 
 hipError_t launch_rpa(const Model& m, const Buffers& b, hipStream_t s) {

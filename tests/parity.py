@@ -126,6 +126,60 @@ def check_rna(w_gpu, group, moved, u_g, anc_gpu, band=1e-9):
     return int(mism.sum()), lws
 
 
+def local_band(w_gpu, group, u_g):
+    """Per slot, the distance of its local uniform to the nearest step of its
+    own group's local CDF (inf for a group without weight)."""
+    n = w_gpu.size
+    G = n // group
+    local = np.empty(n)
+    for g in range(G):
+        ws = w_gpu[g * group:(g + 1) * group]
+        W = ws.sum()
+        if W > 0:
+            C = np.cumsum(ws) / W
+            ul = (np.arange(group) + u_g[g]) / group
+            local[g * group:(g + 1) * group] = band_distance(ul, C[:-1])
+        else:
+            local[g * group:(g + 1) * group] = np.inf
+    return local
+
+
+def check_arna(m, k, w_gpu, anc_gpu, arna_gpu, ring_key, band=1e-9):
+    """ARNA's resampling of the GPU's weights by the oracle with the ring of
+    `ring_key`: the tracking count (up to groups within 1e-9 of the share
+    theta / G), the slots exchanged, and the ancestors (identical outside the
+    band, through each slot's source group). Returns (mismatches, slot log
+    weights for the next step)."""
+    n, group = w_gpu.size, m.rna_group
+    G = n // group
+    order = oracle.ring_order(m, ring_key, G)
+    u_g = oracle.rna_uniforms(m, k)
+    theta = float(np.float32(m.arna_track))
+    _, _, _, t, _ = oracle.resample_arna(w_gpu, group, m.arna_mu_min, m.rna_moved, theta, u_g,
+                                         order)
+    W = w_gpu.reshape(G, group).sum(1)
+    amb = int(np.sum(np.abs(W - theta / G) <= 1e-9 * theta / G))
+    t_gpu = arna_gpu["tracking"]
+    assert abs(t_gpu - t) <= amb, (arna_gpu, t, amb)
+    mu = m.arna_mu_min + (m.rna_moved - m.arna_mu_min) * (G - t_gpu) // G
+    assert arna_gpu["moved"] == mu, (arna_gpu, mu)
+    # the oracle's resampling with the GPU's exchange size
+    ao, lwg, lws, _, _ = oracle.resample_arna(w_gpu, group, mu, mu, theta, u_g, order)
+    mism = ao != anc_gpu
+    if mism.any():
+        pos = np.empty(G, dtype=np.int64)
+        pos[order] = np.arange(G)
+        pred = order[(pos - 1) % G]
+        local = local_band(w_gpu, group, u_g)
+        g = np.arange(n) // group
+        tail = (np.arange(n) % group) >= group - mu
+        src = np.where(tail, pred[g], g)
+        d = local[src * group + np.arange(n) % group]
+        outside = mism & (d > band)
+        assert not outside.any(), f"ARNA ancestors: {outside.sum()} mismatches outside band"
+    return int(mism.sum()), lws
+
+
 def check_step(m, k, prev: GpuState, cur: GpuState, st, obs, rna=False):
     """All checks of step k (propagate, weights, then the resampling or the
     carried weights); sets cur.lw_next and returns a report tuple."""

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_layout_and_defaults():
     L = ppf.lib()
-    assert L.ppf_params_size() == ctypes.sizeof(ppf.Params) == 160
+    assert L.ppf_params_size() == ctypes.sizeof(ppf.Params) == 176
     p = ppf.params()
     assert p.state_dim == 5 and p.n_particles == 4096 and p.width == 128
     assert math.isinf(p.ess_threshold) and p.resample == ppf.RESAMPLE_SYSTEMATIC
@@ -47,6 +47,9 @@ def test_params_layout_and_defaults():
     dict(resample=1, rna_exchange=1.0), dict(obs_model=7), dict(init_kind=9),
     dict(q=(0.5, 0.5, -0.1, 0.1, 1.0)), dict(ess_threshold=float("nan")),
     dict(psf_sigma=0.2, patch=25), dict(obs_model=1, lg_r=(1.0, 0.0, 1.0)), dict(grad=2), dict(reserved=1), dict(resample=2, rna_group=300), dict(resample=2, dlb=2), dict(resample=2, rna_group=1, n_particles=8192, dlb=1), dict(grad=1, resample=1), dict(grad=1, ess_threshold=1e3), dict(grad=1, obs_model=1),
+    dict(resample=4), dict(arna_pad=1), dict(resample=3, rna_group=2048, n_particles=4096),
+    dict(resample=3, arna_min=0.2), dict(resample=3, arna_track=0.0),
+    dict(resample=3, arna_lost=-1.0), dict(resample=3, obs_model=1), dict(resample=3, rna_group=300),
 ])
 def test_invalid_parameters_are_rejected(bad):
     p = ppf.params(**bad)
