@@ -21,8 +21,9 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fopenmp", "-fPIC",
            "-shared", "-Wall", "-Wextra"]
     if sanitize:
-        # address and undefined-behaviour checks of the host code (load with
-        # the sanitizer runtime preloaded, see DESIGN)
+        # address and undefined-behaviour checks of the host code; a Python
+        # process loads this build only with libasan and libubsan preloaded
+        # (LD_PRELOAD) and ASAN_OPTIONS=detect_leaks=0
         cmd += ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
                 "-fno-sanitize-recover=undefined"]
     cmd += ["-o", tmp, SRC, "-lm"]

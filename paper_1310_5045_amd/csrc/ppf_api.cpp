@@ -183,11 +183,16 @@ int64_t merge_chunk(int64_t nb) {
   return 256 * per;
 }
 int64_t seg_count(int64_t n) { return (n + ppf::kSegItems - 1) / ppf::kSegItems; }
-// Runs spill only from segments with more than kCoopSlots slots, each adding
-// at most one entry per particle (kSegItems) plus one per kFillChunk slots.
+// Tile chunks queued by heavy segments (more than kCoopTiles tiles each).
+// With S = kSlotTile and C = kChunkTiles: a segment with M slots spans
+// ntiles <= (M + 3) / S + 1 tiles (its first tile starts up to 3 slots
+// early) and queues ceil(ntiles / C) <= (M + 3) / (C S) + 1 <= M / (C S) + 2
+// chunks; a heavy one has ntiles >= kCoopTiles + 1, so M >= kCoopTiles S - 2,
+// and there are at most H = n / (kCoopTiles S - 2) of them. The queue holds
+// at most n / (C S) + 2 H entries; the capacity adds a margin.
 int64_t queue_cap(int64_t n) {
-  const int64_t spilling = n / ppf::kCoopSlots + 1;
-  return spilling * ppf::kSegItems + n / ppf::kFillChunk + 16;
+  const int64_t heavy = n / ((int64_t)ppf::kCoopTiles * ppf::kSlotTile - 2) + 1;
+  return n / ((int64_t)ppf::kChunkTiles * ppf::kSlotTile) + 3 * heavy + 16;
 }
 
 void shape(int64_t n, Buffers* bb) {
@@ -225,7 +230,7 @@ size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) 
   bb.anc = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
   bb.lw64 = reinterpret_cast<double*>(take(sizeof(double) * n));
   bb.lwg = reinterpret_cast<double*>(take(sizeof(double) * G));
-  bb.hq = reinterpret_cast<ppf::FillRun*>(take(sizeof(ppf::FillRun) * queue_cap(n)));
+  bb.hq = reinterpret_cast<ppf::TileRun*>(take(sizeof(ppf::TileRun) * queue_cap(n)));
   bb.hq_cap = queue_cap(n);
   if (p->resample == PPF_RESAMPLE_RPA) {
     const int64_t Gr = n / p->rna_group;
@@ -268,7 +273,7 @@ size_t carve_scratch(int64_t n, char* base, Buffers* b) {
   bb.pfx = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * bb.nb));
   bb.CR = reinterpret_cast<double*>(take(sizeof(double) * ppf::kRec * bb.nch));
   bb.cpre = reinterpret_cast<ppf::ChunkPre*>(take(sizeof(ppf::ChunkPre) * bb.nch));
-  bb.hq = reinterpret_cast<ppf::FillRun*>(take(sizeof(ppf::FillRun) * queue_cap(n)));
+  bb.hq = reinterpret_cast<ppf::TileRun*>(take(sizeof(ppf::TileRun) * queue_cap(n)));
   bb.hq_cap = queue_cap(n);
   if (b) *b = bb;
   return off;
@@ -558,7 +563,7 @@ int enqueue_step(ppf_handle h, const float* obs_dev) {
     return h->run(kKRna, [&] { return ppf::launch_arna(h->m, h->b, h->stream); });
   rc = h->run(kKAnc, [&] { return ppf::launch_anc(h->m, h->b, w, h->stream); });
   if (rc) return rc;
-  rc = h->run(kKFill, [&] { return ppf::launch_fill(h->m, h->b, h->stream); });
+  rc = h->run(kKFill, [&] { return ppf::launch_fill(h->m, h->b, w, h->stream); });
   if (rc || !h->m.rpa) return rc;
   return h->run(kKRpa, [&] { return ppf::launch_rpa(h->m, h->b, h->stream); });
 }
@@ -833,7 +838,7 @@ int ppf_resample_systematic(const float* logw_dev, int64_t n, double u, int32_t*
   hipError_t e = ppf::launch_records(m, b, logw_dev, s);
   if (e == hipSuccess) e = ppf::launch_merge(m, b, 1, u, s);
   if (e == hipSuccess) e = ppf::launch_anc(m, b, w, s);
-  if (e == hipSuccess) e = ppf::launch_fill(m, b, s);
+  if (e == hipSuccess) e = ppf::launch_fill(m, b, w, s);
   return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
 }
 

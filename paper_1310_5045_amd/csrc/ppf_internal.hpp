@@ -42,17 +42,18 @@ constexpr double kCdfScale = 0x1p62;    // fixed-point scale of the global CDF
 // Chunk prefixes map 2^44-scaled weights to the 2^62-scaled CDF.
 constexpr double kItemToCdf = 0x1p18;
 
-// Systematic resampling: one workgroup per segment of kSegBlocks blocks
-// writes the segment's output slots itself when they are at most kCoopSlots;
-// beyond that its particles' runs of slots go to a global fill queue in
-// pieces of at most kFillChunk slots.
-constexpr int kSegBlocks = 8;
+// Systematic resampling: one wave per segment of kSegBlocks blocks writes the
+// segment's output slots itself when they span at most kCoopTiles tiles of
+// kSlotTile slots; a heavier segment queues its tiles in chunks of
+// kChunkTiles for k_fill (kFillGrid one-wave workgroups, each taking chunks
+// in turn).
+constexpr int kSegBlocks = 2;
 constexpr int kSegItems = kSegBlocks * kBlock;
-constexpr int kCoopSlots = 1 << 16;
-constexpr int kSlotTile = 2048;  // slots per LDS tile of the segment's writes
-constexpr int kFillChunk = 1 << 16;
-constexpr int kFillGrid = 2048;
-constexpr int kFillGridBatch = 8;  // workgroups per track of a batched fill (a heavy fill gets 2048 threads; most frames queue nothing)
+constexpr int kSlotTile = kSegItems;  // slots per LDS tile of the segment's writes
+constexpr int kCoopTiles = 8;
+constexpr int kChunkTiles = 4;
+constexpr int kFillGrid = 4096;
+constexpr int kFillGridBatch = 2048;  // waves of a batched fill, over all tracks' queues
 // Batched steps run every patch size up to this one in a single launch (the
 // sizes that fit five waves per SIMD); wider patches launch per size.
 constexpr int kFusedMaxP = 13;
@@ -69,11 +70,12 @@ struct BatchItem {
   int32_t idx;
 };
 
-// One entry of the fill queue: slots [lo, lo + len) take particle `item`.
-struct FillRun {
-  int32_t item;
-  int32_t lo;
-  int32_t len;
+// One entry of the fill queue: the tiles [tile_lo, tile_hi) of a heavy
+// resampling segment.
+struct TileRun {
+  int32_t seg;
+  int32_t tile_lo;
+  int32_t tile_hi;
   int32_t pad;
 };
 
@@ -105,7 +107,7 @@ struct Ctrl {
   int32_t resampled;    // last committed step resampled
   int32_t rolled_back;  // steps rolled back since the host last read this
   int32_t do_resample;  // set by the merge for the resampling kernels
-  int32_t heavy_count;  // runs queued for k_fill
+  int32_t heavy_count;  // tile chunks queued for k_fill
   uint64_t pad0;
   double m, log_sum, ess, delta, cum;
   double mean[5];
@@ -187,7 +189,7 @@ struct Buffers {
   int32_t* anc;  // ancestors of the last resampling
   double* lw64;  // fp64 per-particle log weights (caller-set, or output staging)
   double* lwg;   // RNA per-group log(W_g / n)
-  FillRun* hq;   // queued long runs of output slots
+  TileRun* hq;   // queued tile chunks of heavy resampling segments
   float* T0;     // gradient mode: tangents, kNTan*n SoA, double-buffered with X
   float* T1;
   double* RG;    // gradient mode: per block sum E d l / d theta (kNGrad doubles)
@@ -230,7 +232,7 @@ hipError_t launch_step(const Model& m, const Buffers& b, const float* obs, hipSt
 hipError_t launch_merge(const Model& m, const Buffers& b, int standalone, double u_given,
                         hipStream_t s);
 hipError_t launch_anc(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s);
-hipError_t launch_fill(const Model& m, const Buffers& b, hipStream_t s);
+hipError_t launch_fill(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s);
 hipError_t launch_rna(const Model& m, const Buffers& b, const WeightSrc& w, const double* u_dev,
                       hipStream_t s);
 hipError_t launch_gather(const Model& m, const Buffers& b, float* out, hipStream_t s);

@@ -11,7 +11,8 @@
 //                  back the step; the fixed-point CDF prefixes of the chunks
 //   k_anc          systematic resampling: per segment of 2048 particles, each
 //                  particle's run of output slots from the segment's CDF
-//   k_fill         long runs of slots queued by k_anc (concentrated weights)
+//   k_fill         the slots of heavy segments queued by k_anc (concentrated
+//                  weights), in chunks of tiles
 //   (or k_rna      RNA of Section 3: one workgroup per group of particles)
 #include "ppf_internal.hpp"
 
@@ -1448,12 +1449,9 @@ __global__ __launch_bounds__(256) void k_merge_final(Model m, Buffers b, int sta
 // so particles of zero weight own no slots, and the segment's last particle
 // of positive weight takes the segment's remaining slots.
 
-// CDF position of the start of block blk, as a fraction of the total.
-__device__ __forceinline__ double block_P(const Buffers& b, int64_t blk) {
-  // chunk = 256 per with per <= 8 and blk < 2^23: a 32-bit quotient
-  const ChunkPre cp = b.cpre[(uint32_t)(blk >> 8) / (uint32_t)(b.chunk >> 8)];
-  const uint64_t P = cp.P + (uint64_t)rint((double)b.pfx[blk] * cp.phi);
-  return (double)P * (1.0 / kCdfScale);
+// The CDF at a block start from its block prefix and its chunk's record.
+__device__ __forceinline__ double block_cdf(const ChunkPre& cp, uint64_t pfx) {
+  return (double)(cp.P + (uint64_t)rint((double)pfx * cp.phi)) * (1.0 / kCdfScale);
 }
 
 // Number of slots s in [0, n) with (s + u) / n < C: ceil(C n - u), clamped.
@@ -1464,23 +1462,21 @@ __device__ __forceinline__ int slot_bound(double C, double u, double nd, int n) 
   return x <= 0.0 ? 0 : (x >= nd ? n : (int)x);
 }
 
-// Slot e of a tile lives at slot_pad(e), one spare word after every 8, so
-// that a thread walking its own 8 consecutive slots (lanes 8 words apart
-// become 9 apart) and the threads of a wave walking consecutive slots both
-// meet distinct banks.
-__device__ __forceinline__ int slot_pad(int e) { return e + (e >> 3); }
-constexpr int kSlotsPerThread = kSlotTile / 256;
-static_assert(kSlotsPerThread == 8, "slot_pad spaces one thread's slots");
-
-struct AncShared {
-  // owner marks of one tile of slots, then their running maximum
-  int A[kSlotTile + kSlotTile / 8];
-  double Pb[kSegBlocks + 1];  // CDF at the segment's block starts
-  double fb[kSegBlocks];      // blocks' factors from integer weights to the CDF
-  double mb[kSegBlocks];      // blocks' maximum log weights
-  int w4[4];                  // per-wave maxima of the scans
-  int l4[4];                  // per-wave last particles of positive weight
-};
+// Systematic resampling runs one wavefront per segment of kSegItems
+// particles (kPerThread consecutive per lane, so the 256 particles of a
+// block are two rows of 16 lanes): every scan and maximum of the segment is
+// a DPP operation within the wave and no barrier waits for other waves, so
+// each wave streams its weights and ancestors at its own pace.
+constexpr int kWave = 64;
+constexpr int kPerThread = kSegItems / kWave;  // particles, and slots of a tile, per lane
+static_assert(kPerThread == 8 && kSlotTile == kSegItems && kSegBlocks == 2,
+              "a segment is two blocks, eight particles and slots per lane");
+// A tile's slot e lives at word slot_word(e) of the LDS tile, four spare
+// words after every eight, so that each lane reads its slots with two
+// 128-bit loads 48 bytes from its neighbour's (sixteen lanes then cover the
+// 64 banks once).
+constexpr int kTileWords = kSlotTile / kPerThread * (kPerThread + 4);
+__device__ __forceinline__ int slot_word(int e) { return e + ((e >> 3) << 2); }
 
 // Inclusive maximum scan over the wave of values >= 0 (each DPP step folds
 // into one v_max_i32: row shifts, whose lanes outside the row read 0, then
@@ -1498,9 +1494,10 @@ __device__ __forceinline__ int exclusive_of(int inclusive) {
   return (int)dpp32<0x138>((uint32_t)inclusive);  // wave_shr:1
 }
 
-// Inclusive sum within each pair of rows (32 lanes) of exact integers held
-// in doubles (lanes outside a row read 0, the identity).
-__device__ __forceinline__ double pair_row_scan_add(double v) {
+// Inclusive sum of exact integers held in doubles over the lanes of one
+// block, two rows of 16 lanes (rows 1 and 3 add the last lane of rows 0 and
+// 2). Lanes outside a row read 0, the identity.
+__device__ __forceinline__ double block_scan_add(double v) {
   v += shr<1>(v);
   v += shr<2>(v);
   v += shr<4>(v);
@@ -1508,218 +1505,304 @@ __device__ __forceinline__ double pair_row_scan_add(double v) {
   return pair_rows(v, OpAdd(), 0.0);
 }
 
-// One workgroup per segment of kSegItems particles (eight consecutive per
-// thread): the segment's slot range from its block starts, the particles'
-// CDF from their fixed-point weights, every particle's run of slots, and
-// the slots' particles, written tile by tile. Slot bounds are monotone in
-// the CDF, so the running maximum that keeps runs from overlapping is taken
-// over the integer bounds.
-__device__ __forceinline__ void anc_body(const Model& m, const Buffers& b, const WeightSrc& ws,
-                                         int64_t seg) {
-  __shared__ AncShared sh;
-  Ctrl* c = b.ctrl;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+// The resampling of one segment by one wave: the segment's slot range from
+// its block starts, the particles' CDF from their fixed-point weights, every
+// particle's run of slots, and the slots' particles, written tile by tile.
+// Slot bounds are monotone in the CDF, so the running maximum that keeps
+// runs from overlapping is taken over the integer bounds. LOG: the weights
+// are caller log weights (standalone resampling), else the filter's stored
+// E.
+//
+// k_anc runs each segment whose slots span at most kCoopTiles tiles; a
+// heavier segment (concentrated weights) queues its tiles in chunks of
+// kChunkTiles for k_fill, whose waves each recompute the segment's runs and
+// write one chunk, so that heavy segments spread over many waves.
+// queued: called by k_fill for the tiles [tile_lo, tile_hi) of the segment.
+// One segment's loads, raw: its lanes' weights and its block records. Every
+// lane loads (indices clamped into the arrays, values masked at use), so no
+// load sits in a divergent branch that would consume it at once.
+struct SegIn {
+  float x[kPerThread];
+  uint64_t pfx;  // the block prefix of block b0 + min(lane, nbs) (clamped)
+  ChunkPre cp;   // its chunk's prefix and factor
+  double mbt;    // the record maximum of block b0 + min(lane, nbs - 1)
+};
+
+__device__ __forceinline__ SegIn load_seg(const Model& m, const Buffers& b, const float* E,
+                                          const double* rec, bool log_src, int64_t seg) {
+  SegIn in;
+  const int lane = threadIdx.x;
   const int64_t b0 = seg * kSegBlocks;
   const int nbs = (int)min((int64_t)kSegBlocks, b.nb - b0);
-  // the block starts of the CDF do not depend on the control block: their
-  // loads go out with its (in-bounds reads, discarded when nothing resamples)
-  const int do_res = c->do_resample, cur = c->cur;
-  const double delta = c->delta, u = c->u;
-  const bool second = ws.use_cur && cur;
-  const double* rec = second ? ws.rec1 : ws.rec0;
-  const double pbt = (t <= nbs && b0 + t < b.nb) ? block_P(b, b0 + t) : 1.0;
-  const double mbt = t < nbs ? rec[(b0 + t) * kRec] : -INFINITY;
-  // this thread's eight weights, loaded alongside the block records rather
-  // than after the barrier (discarded when the segment owns no slots)
-  const float* E = second ? ws.E1 : ws.E0;
+  const int64_t bp = min(b0 + min(lane, nbs), b.nb - 1);
+  // chunk = 256 per with per <= 8 and blk < 2^23: a 32-bit quotient
+  in.cp = b.cpre[(uint32_t)(bp >> 8) / (uint32_t)(b.chunk >> 8)];
+  in.pfx = b.pfx[bp];
+  in.mbt = rec[(b0 + min(lane, nbs - 1)) * kRec];
   const int64_t ib0 = b0 * kBlock;
   const int64_t ib1 = min(m.n, (b0 + nbs) * kBlock);
-  const int64_t j0 = ib0 + 8 * (int64_t)t;
-  const bool mine = j0 < ib1;
-  float x[8];
-  if (mine) {
-    // vector loads only from 16-byte aligned bases
-    if (j0 + 8 <= ib1 && (reinterpret_cast<uintptr_t>(E) & 15) == 0) {
-      const float4 v0 = *reinterpret_cast<const float4*>(E + j0);
-      const float4 v1 = *reinterpret_cast<const float4*>(E + j0 + 4);
-      x[0] = v0.x; x[1] = v0.y; x[2] = v0.z; x[3] = v0.w;
-      x[4] = v1.x; x[5] = v1.y; x[6] = v1.z; x[7] = v1.w;
-    } else {
+  const int64_t j0 = ib0 + kPerThread * (int64_t)lane;
+  if (ib1 - ib0 == kSegItems && (reinterpret_cast<uintptr_t>(E) & 15) == 0) {
+    // a whole segment (uniform)
+    const float4* v = reinterpret_cast<const float4*>(E + j0);
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        x[q] = (j0 + q < ib1) ? E[j0 + q] : (ws.log_src ? -INFINITY : 0.0f);
-    }
-  }
-  if (!do_res) return;
-  if (t <= nbs) sh.Pb[t] = pbt;
-  if (t < nbs) {
-    sh.mb[t] = mbt;
-    sh.fb[t] = (mbt == -INFINITY) ? 0.0 : exp(mbt - delta) * (1.0 / kItemScale);
-  }
-  __syncthreads();
-  const int n = (int)m.n;
-  const double nd = (double)m.n;
-  const int fs = seg == 0 ? 0 : slot_bound(sh.Pb[0], u, nd, n);
-  const int fe = seg + 1 >= b.nseg ? n : slot_bound(sh.Pb[nbs], u, nd, n);
-  if (fe <= fs) return;  // uniform: no slot falls in this segment
-
-  const int lb = (t * 8) / kBlock;  // this thread's block within the segment
-  double wi[8], kl[8];
-  double tsum = 0.0;
-  if (mine) {
-    if (ws.log_src) {
-      const double mblk = sh.mb[lb];
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        wi[q] = item_weight(x[q] == -INFINITY ? 0.0 : exp((double)x[q] - mblk));
-    } else {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) wi[q] = item_weight((double)x[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      tsum += wi[q];
-      kl[q] = tsum;
+    for (int q4 = 0; q4 < kPerThread / 4; ++q4) {
+      const float4 f = v[q4];
+      in.x[4 * q4] = f.x;
+      in.x[4 * q4 + 1] = f.y;
+      in.x[4 * q4 + 2] = f.z;
+      in.x[4 * q4 + 3] = f.w;
     }
   } else {
+    // the ragged end: weight 0 past the last particle
 #pragma unroll
-    for (int q = 0; q < 8; ++q) wi[q] = kl[q] = 0.0;
+    for (int q = 0; q < kPerThread; ++q) {
+      const float v = E[min(j0 + q, ib1 - 1)];
+      in.x[q] = (j0 + q < ib1) ? v : (log_src ? -INFINITY : 0.0f);
+    }
   }
-  // prefix of the block's integer weights before this thread's items: the
-  // 32 threads of a block are one half of a wave (exact: integers < 2^53)
-  const double texcl = pair_row_scan_add(tsum) - tsum;
-  const double f = sh.fb[lb], Pblk = sh.Pb[lb];
+  return in;
+}
+
+// The control block's values a resampling pass reads.
+struct ResIn {
+  int do_res;
+  double delta, u;
+};
+
+template <bool LOG>
+__device__ __forceinline__ void anc_segment(const Model& m, const Buffers& b, const ResIn& ci,
+                                            int64_t seg, const SegIn& in, bool queued,
+                                            int tile_lo, int tile_hi) {
+  __shared__ __align__(16) int A[kTileWords];
+  Ctrl* c = b.ctrl;
+  const int lane = threadIdx.x;
+  const int64_t b0 = seg * kSegBlocks;
+  const int nbs = (int)min((int64_t)kSegBlocks, b.nb - b0);
+  const int64_t ib0 = b0 * kBlock;
+  const int64_t j0 = ib0 + kPerThread * (int64_t)lane;
+  const double delta = ci.delta, u = ci.u;
+  // lanes 0..nbs: the CDF at the block starts (blocks past the data read as
+  // its end); lanes 0..nbs-1: the blocks' maximum log weights
+  const double pbt = (lane <= nbs && b0 + lane < b.nb) ? block_cdf(in.cp, in.pfx) : 1.0;
+  const double mbt = lane < nbs ? in.mbt : -INFINITY;
+  float x[kPerThread];
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) x[q] = in.x[q];
+  // the blocks' factors from integer weights to the CDF (lanes 0 and 1)
+  const double fbt = (lane < nbs && mbt != -INFINITY) ? exp(mbt - delta) * (1.0 / kItemScale) : 0.0;
+  const double Pb0 = readlane(pbt, 0), Pb1 = readlane(pbt, 1), Pb2 = readlane(pbt, 2);
+  const int n = (int)m.n;
+  const double nd = (double)m.n;
+  const int fs = seg == 0 ? 0 : slot_bound(Pb0, u, nd, n);
+  const int fe = seg + 1 >= b.nseg ? n : slot_bound(nbs == 2 ? Pb2 : Pb1, u, nd, n);
+  if (fe <= fs) return;  // uniform: no slot falls in this segment
+  const int T0 = fs & ~3;  // tiles start on 16 bytes of anc
+  const int ntiles = (fe - T0 + kSlotTile - 1) / kSlotTile;
+  if (!queued && ntiles > kCoopTiles) {
+    // a heavy segment: its tiles go to k_fill in chunks
+    const int chunks = (ntiles + kChunkTiles - 1) / kChunkTiles;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&c->heavy_count, chunks);
+    base = readlane(base, 0);
+    for (int q = lane; q < chunks; q += kWave)
+      if (base >= 0 && (int64_t)base + q < b.hq_cap)  // the queue's size rules out overflow
+        b.hq[base + q] = TileRun{(int32_t)seg, q * kChunkTiles,
+                                 min(ntiles, (q + 1) * kChunkTiles), 0};
+    return;
+  }
+
+  const int lb = lane >> 5;  // this lane's block within the segment
+  // (readlane takes a lane index uniform across the wave)
+  const double mblk = LOG ? (lb ? readlane(mbt, 1) : readlane(mbt, 0)) : 0.0;
+  double kl[kPerThread];
+  double tsum = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    double wi;
+    if (LOG)
+      wi = item_weight(x[q] == -INFINITY ? 0.0 : exp((double)x[q] - mblk));
+    else
+      wi = item_weight((double)x[q]);
+    tsum += wi;
+    kl[q] = tsum;
+  }
+  // prefix of the block's integer weights before this lane's particles
+  // (exact: integers < 2^53)
+  const double texcl = block_scan_add(tsum) - tsum;
+  const double fb0 = readlane(fbt, 0), fb1 = readlane(fbt, 1);
+  const double f = lb ? fb1 : fb0;
+  const double Pblk = lb ? Pb1 : Pb0;
   // each particle's slot bound at its CDF value C = Pblk + (texcl + kl) f,
   // ceil(C n - u) clamped to [fs, fe], evaluated as one fma per particle:
   // kl (n f) + (texcl (n f) + Pblk n - u). Rounding may move a bound by one
   // where C n - u is within a few ulps of an integer; the running maximum
   // below keeps the runs disjoint and ordered regardless. A particle of zero
-  // weight gets 0, below every bound; lp is the last particle of positive
-  // weight.
-  int rb[8];
-  int tmax = 0, lp = -1;
-  const double fsd = (double)fs, fed = (double)fe;
+  // weight gets 0, below every bound, so its run is empty (computing its
+  // bound would repeat its predecessor's, except across lanes, where the two
+  // fmas round apart).
   const double fn = f * nd;
   const double g = fma(texcl, fn, fma(Pblk, nd, -u));
+  int rb[kPerThread];
+  int lp = -1;  // this lane's last particle of positive weight
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int bq = (int)fmin(fmax(ceil(fma(kl[q], fn, g)), fsd), fed);
-    rb[q] = wi[q] > 0.0 ? bq : 0;
-    lp = wi[q] > 0.0 ? 8 * t + q : lp;
-    tmax = max(tmax, rb[q]);
+  for (int q = 0; q < kPerThread; ++q) {
+    // |C n - u| stays far inside the int range (C in [0, 1], n < 2^31)
+    const int bq = (int)ceil(fma(kl[q], fn, g));
+    const bool pos = kl[q] > (q ? kl[q - 1] : 0.0);
+    rb[q] = pos ? min(max(bq, fs), fe) : 0;
+    lp = pos ? q : lp;
   }
-  const int winc = wave_max_scan(tmax);
-  const int wlp = wave_reduce_last(lp, OpMax(), -1);
-  if (lane == 63) {
-    sh.w4[w] = winc;
-    sh.l4[w] = wlp;
-  }
-  __syncthreads();
-  int hprev = max(fs, exclusive_of(winc));
-  for (int q = 0; q < w; ++q) hprev = max(hprev, sh.w4[q]);
-  const int last_pos = max(max(sh.l4[0], sh.l4[1]), max(sh.l4[2], sh.l4[3]));
-  // runs: particle 8t+q owns the slots [st[q], hq[q]); the last particle of
-  // positive weight ends at the segment's end (the particles after it have
-  // zero weight, bound 0, and so empty runs)
-  int st[8], hq[8];
+  int tmax = 0;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int hv = (8 * t + q == last_pos) ? fe : max(hprev, rb[q]);
-    st[q] = hprev;
-    hq[q] = hv;
-    hprev = hv;
+  for (int q = 0; q < kPerThread; ++q) tmax = max(tmax, rb[q]);
+  const int h0 = max(fs, exclusive_of(wave_max_scan(tmax)));
+  // the segment's last particle of positive weight ends its runs at fe
+  // (those after it have zero weight and empty runs), so every slot has an
+  // owner whatever the rounding of the last bounds
+  const int last_pos =
+      readlane(wave_reduce_last(lp >= 0 ? kPerThread * lane + lp : -1, OpMax(), -1), 63);
+  const int lastq = last_pos - kPerThread * lane;
+  // particle kPerThread lane + q owns [e_{q-1}, e_q), e_q = max(e_{q-1},
+  // rb[q]) (fe for the last particle of positive weight), e_{-1} = h0. Each
+  // non-empty run marks its first slot with the particle; a slot's particle
+  // is then the largest mark at or before it. mw: the LDS word of the mark
+  // in tile coordinates from T0 (tile j: subtract j kTileWords), or -1.
+  int mw[kPerThread];
+  int prev = h0;
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int e = q == lastq ? fe : max(prev, rb[q]);
+    mw[q] = e > prev ? slot_word(prev - T0) : -1;
+    prev = e;
   }
-  const int M = fe - fs;
   int32_t* anc = m.rpa ? b.asys : b.anc;  // RPA routes the systematic result afterwards
-  if (M <= kCoopSlots) {
-    // tiles of slots: each run marks its first slot with its particle + 1;
-    // the running maximum of the marks (particles increase with slots) is
-    // then every slot's particle + 1
-    constexpr int kk = kSlotsPerThread;
-    int carry_item = 0;
-    for (int c0 = fs; c0 < fe; c0 += kSlotTile) {
-      const int cn = min(kSlotTile, fe - c0);
+  const bool vec = (reinterpret_cast<uintptr_t>(anc) & 15) == 0;
+  const int p0 = (int)j0;  // particle indices are below n < 2^31
+  const int jt0 = queued ? tile_lo : 0, jt1 = queued ? min(tile_hi, ntiles) : ntiles;
+  // the tiles before this call's first: the largest mark among them
+  int carry = 0;
+  if (jt0 > 0) {
+    const int lim = jt0 * kTileWords;  // marks at earlier words precede the first tile
 #pragma unroll
-      for (int k = 0; k < kk; ++k) sh.A[slot_pad(k * 256 + t)] = 0;
-      __syncthreads();
+    for (int q = 0; q < kPerThread; ++q)
+      if (mw[q] >= 0 && mw[q] < lim) carry = p0 + q;  // the largest such (mw increases with q)
+    carry = readlane(wave_reduce_last(carry, OpMax(), 0), 63);
+  }
+  // the tile starts cleared; each tile's reads clear it again
+  {
+    uint4* A4 = reinterpret_cast<uint4*>(A);
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (hq[q] > st[q] && st[q] >= c0 && st[q] < c0 + cn)
-          sh.A[slot_pad(st[q] - c0)] = 8 * t + q + 1;
-      __syncthreads();
-      int v[kk];
-      int run = 0;
+    for (int r = 0; r < kTileWords / 4 / kWave; ++r)
+      A4[r * kWave + lane] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  for (int j = jt0; j < jt1; ++j) {
+    const int c0 = T0 + j * kSlotTile, wbase = j * kTileWords;
+    __syncthreads();  // one wave: orders the LDS accesses of the lanes
 #pragma unroll
-      for (int k = 0; k < kk; ++k) {
-        run = max(run, sh.A[slot_pad(t * kk + k)]);
-        v[k] = run;
-      }
-      const int winc2 = wave_max_scan(run);
-      if (lane == 63) sh.w4[w] = winc2;
-      __syncthreads();
-      int before = max(carry_item, exclusive_of(winc2));
-      for (int q = 0; q < w; ++q) before = max(before, sh.w4[q]);
-      // the particles back into the tile, then stored with consecutive
-      // threads on consecutive slots
-#pragma unroll
-      for (int k = 0; k < kk; ++k) sh.A[slot_pad(t * kk + k)] = max(before, v[k]);
-      carry_item = max(carry_item, max(max(sh.w4[0], sh.w4[1]), max(sh.w4[2], sh.w4[3])));
-      __syncthreads();
-      // (particle indices and slots are below n < 2^31)
-      int32_t* const out = anc + c0;
-      const int32_t base = (int32_t)ib0;
-#pragma unroll
-      for (int k = 0; k < kk; ++k) {
-        const int e = k * 256 + t;
-        if (e < cn) out[e] = base + max(sh.A[slot_pad(e)] - 1, 0);
-      }
-      __syncthreads();  // sh.A and sh.w4 are rewritten by the next tile
+    for (int q = 0; q < kPerThread; ++q) {
+      const int ew = mw[q] - wbase;
+      if ((unsigned)ew < (unsigned)kTileWords) A[ew] = p0 + q;
     }
-  } else if (mine) {
-    // too many slots for one workgroup: queue this thread's runs for k_fill
+    __syncthreads();
+    // this lane's slots, their running maximum (particles increase with
+    // slots), then the maximum over the lanes before it; 0 (the cleared
+    // tile, and DPP's fill) is below every mark that precedes a slot from fs
+    // on. Reading a slot clears it for the next tile.
+    int v[kPerThread];
+    uint4* mine = reinterpret_cast<uint4*>(A + (kPerThread + 4) * lane);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int lo = st[q], len = hq[q] - st[q];
-      if (len > 0) {
-        const int32_t item = (int32_t)(j0 + q);
-        const int pieces = (len + kFillChunk - 1) / kFillChunk;
-        const int base = atomicAdd(&c->heavy_count, pieces);
-        for (int pc = 0; pc < pieces; ++pc) {
-          const int plo = lo + pc * kFillChunk;
-          const int plen = min(kFillChunk, len - pc * kFillChunk);
-          if (base >= 0 && (int64_t)base + pc < b.hq_cap) {
-            b.hq[base + pc] = FillRun{item, plo, plen, 0};
-          } else {
-            for (int r = 0; r < plen; ++r) anc[plo + r] = item;  // ruled out by the queue's size
-          }
-        }
-      }
+    for (int r = 0; r < kPerThread / 4; ++r) {
+      const uint4 a = mine[r];
+      v[4 * r] = (int)a.x;
+      v[4 * r + 1] = (int)a.y;
+      v[4 * r + 2] = (int)a.z;
+      v[4 * r + 3] = (int)a.w;
+    }
+#pragma unroll
+    for (int r = 0; r < kPerThread / 4; ++r) mine[r] = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int q = 1; q < kPerThread; ++q) v[q] = max(v[q], v[q - 1]);
+    const int winc = wave_max_scan(v[kPerThread - 1]);
+    const int before = max(carry, exclusive_of(winc));
+    carry = max(carry, readlane(winc, 63));
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) v[q] = max(before, v[q]);
+    const int s0 = c0 + kPerThread * lane;
+    int32_t* out = anc + s0;
+    if (vec && s0 >= fs && s0 + kPerThread <= fe) {
+      int4* o4 = reinterpret_cast<int4*>(out);
+#pragma unroll
+      for (int r = 0; r < kPerThread / 4; ++r)
+        o4[r] = make_int4(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < kPerThread; ++q)
+        if (s0 + q >= fs && s0 + q < fe) out[q] = v[q];
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_anc(Model m, Buffers b, WeightSrc ws) {
-  anc_body(m, b, ws, blockIdx.x);
+__device__ __forceinline__ ResIn res_in(const Ctrl* c) {
+  ResIn ci;
+  ci.do_res = c->do_resample;
+  ci.delta = c->delta;
+  ci.u = c->u;
+  return ci;
 }
 
-// Long runs queued by k_anc: each workgroup fills whole runs, coalesced.
-__device__ __forceinline__ void fill_body(const Model& m, const Buffers& b, int64_t q0,
-                                          int64_t qstep) {
+// One wave per segment.
+template <bool LOG>
+__device__ __forceinline__ void anc_seg(const Model& m, const Buffers& b, const WeightSrc& ws,
+                                        int64_t seg) {
   const Ctrl* c = b.ctrl;
-  if (!c->do_resample) return;
-  const int64_t nh = min((int64_t)c->heavy_count, b.hq_cap);
-  for (int64_t q = q0; q < nh; q += qstep) {
-    const FillRun r = b.hq[q];
-    if (r.lo < 0 || r.len <= 0 || (int64_t)r.lo + r.len > m.n || r.item < 0 ||
-        (int64_t)r.item >= m.n)
-      continue;
-    int32_t* out = (m.rpa ? b.asys : b.anc) + r.lo;
-    for (int k = threadIdx.x; k < r.len; k += 256) out[k] = r.item;
-  }
+  const ResIn ci = res_in(c);
+  if (!ci.do_res || seg >= b.nseg) return;
+  const bool second = ws.use_cur && c->cur;
+  const SegIn in = load_seg(m, b, second ? ws.E1 : ws.E0, second ? ws.rec1 : ws.rec0, LOG, seg);
+  anc_segment<LOG>(m, b, ci, seg, in, false, 0, 0);
 }
 
-__global__ __launch_bounds__(256) void k_fill(Model m, Buffers b) {
-  fill_body(m, b, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(kWave) void k_anc(Model m, Buffers b, WeightSrc ws) {
+  anc_seg<false>(m, b, ws, blockIdx.x);
+}
+
+// The same on caller log weights (standalone resampling).
+__global__ __launch_bounds__(kWave) void k_anc_log(Model m, Buffers b, WeightSrc ws) {
+  anc_seg<true>(m, b, ws, blockIdx.x);
+}
+
+// The tile chunks of heavy segments queued by k_anc: each wave takes queue
+// entries in turn.
+// Queue entry q of one filter: its chunk of tiles, then a barrier (the next
+// entry clears the tile again).
+template <bool LOG>
+__device__ __forceinline__ void fill_entry(const Model& m, const Buffers& b, const WeightSrc& ws,
+                                           const ResIn& ci, int64_t q) {
+  const TileRun r = b.hq[q];
+  if (r.seg < 0 || (int64_t)r.seg >= b.nseg || r.tile_lo < 0 || r.tile_hi <= r.tile_lo)
+    return;  // uniform across the wave
+  const bool second = ws.use_cur && b.ctrl->cur;
+  const SegIn in = load_seg(m, b, second ? ws.E1 : ws.E0, second ? ws.rec1 : ws.rec0, LOG, r.seg);
+  anc_segment<LOG>(m, b, ci, r.seg, in, true, r.tile_lo, r.tile_hi);
+  __syncthreads();
+}
+
+template <bool LOG>
+__device__ __forceinline__ void fill_body(const Model& m, const Buffers& b, const WeightSrc& ws,
+                                          int64_t q0, int64_t qstep) {
+  const ResIn ci = res_in(b.ctrl);
+  if (!ci.do_res) return;
+  const int64_t nh = min((int64_t)b.ctrl->heavy_count, b.hq_cap);
+  for (int64_t q = q0; q < nh; q += qstep) fill_entry<LOG>(m, b, ws, ci, q);
+}
+
+__global__ __launch_bounds__(kWave) void k_fill(Model m, Buffers b, WeightSrc ws) {
+  fill_body<false>(m, b, ws, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kWave) void k_fill_log(Model m, Buffers b, WeightSrc ws) {
+  fill_body<true>(m, b, ws, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------- RNA
@@ -2302,20 +2385,64 @@ __global__ __launch_bounds__(256) void k_merge_final_batch(const Model* __restri
   merge_final_body(ms[blockIdx.x], bs[blockIdx.x], 0, 0.0);
 }
 
-__global__ __launch_bounds__(256) void k_anc_batch(const Model* __restrict__ ms,
+__global__ __launch_bounds__(kWave) void k_anc_batch(const Model* __restrict__ ms,
                                                    const Buffers* __restrict__ bs,
                                                    const BatchItem* __restrict__ items) {
   const BatchItem it = items[blockIdx.x];
   const Buffers& b = bs[it.track];
-  anc_body(ms[it.track], b, own_weights(b), it.idx);
+  anc_seg<false>(ms[it.track], b, own_weights(b), it.idx);
 }
 
-// blockIdx.y selects the track (from `tracks`); blockIdx.x strides its queue.
-__global__ __launch_bounds__(256) void k_fill_batch(const Model* __restrict__ ms,
+// The queued chunks of all the tracks in `tracks` as one list, track after
+// track (a track that did not resample this step has none). Wave w takes the
+// list entries w, w + gridDim.x, ..., so a track whose weights collapsed gets
+// as many waves as its chunks need. The tracks are counted kFillTracks at a
+// time, their loads issued together.
+constexpr int kFillTracks = 4 * kWave;
+__global__ __launch_bounds__(kWave) void k_fill_batch(const Model* __restrict__ ms,
                                                     const Buffers* __restrict__ bs,
-                                                    const int32_t* __restrict__ tracks) {
-  const int32_t tr = tracks[blockIdx.y];
-  fill_body(ms[tr], bs[tr], blockIdx.x, gridDim.x);
+                                                    const int32_t* __restrict__ tracks,
+                                                    int32_t n_tracks) {
+  const int lane = threadIdx.x;
+  const int64_t G = gridDim.x;
+  int64_t base = 0;  // list entries of the tracks before this pass's
+  for (int32_t j0 = 0; j0 < n_tracks; j0 += kFillTracks) {
+    int32_t tr[4];
+    int cnt[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t j = j0 + u * kWave + lane;
+      tr[u] = j < n_tracks ? tracks[j] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      cnt[u] = 0;
+      if (tr[u] >= 0) {
+        const Buffers& b = bs[tr[u]];
+        const Ctrl* c = b.ctrl;
+        if (c->do_resample) cnt[u] = (int)max((int64_t)0, min((int64_t)c->heavy_count, b.hq_cap));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int incl = wave_scan(cnt[u], lane, OpAdd());
+      const int tot = readlane(incl, 63);
+      // the first list entry at or after base that is this wave's
+      int64_t off = ((int64_t)blockIdx.x - base % G) % G;
+      if (off < 0) off += G;
+      for (int64_t q = base + off; q < base + tot; q += G) {
+        const int r = (int)(q - base);
+        // the lane whose entries [incl - cnt, incl) hold r: the lanes below
+        // it are those whose entries end at or before r
+        const int owner = __popcll(__ballot(incl <= r));
+        const int32_t t_own = readlane(tr[u], owner);
+        const int first = readlane(incl - cnt[u], owner);
+        const Buffers& b = bs[t_own];
+        fill_entry<false>(ms[t_own], b, own_weights(b), res_in(b.ctrl), r - first);
+      }
+      base += tot;
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_rna_batch(const Model* __restrict__ ms,
@@ -2599,14 +2726,13 @@ hipError_t launch_merge_batch(const Model* ms, const Buffers* bs, const BatchIte
 hipError_t launch_anc_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
                             int64_t n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  return launch_k(k_anc_batch, dim3((unsigned)n_items), dim3(256), s, ms, bs, items);
+  return launch_k(k_anc_batch, dim3((unsigned)n_items), dim3(kWave), s, ms, bs, items);
 }
 
 hipError_t launch_fill_batch(const Model* ms, const Buffers* bs, const int32_t* tracks,
                              int32_t n_tracks, hipStream_t s) {
   if (n_tracks <= 0) return hipSuccess;
-  return launch_k(k_fill_batch, dim3(kFillGridBatch, (unsigned)n_tracks), dim3(256), s, ms, bs,
-                  tracks);
+  return launch_k(k_fill_batch, dim3(kFillGridBatch), dim3(kWave), s, ms, bs, tracks, n_tracks);
 }
 
 hipError_t launch_rna_batch(const Model* ms, const Buffers* bs, const BatchItem* items,
@@ -2646,12 +2772,14 @@ hipError_t launch_merge(const Model& m, const Buffers& b, int standalone, double
 }
 
 hipError_t launch_anc(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s) {
-  return launch_k(k_anc, dim3((unsigned)b.nseg), dim3(256), s, m, b, w);
+  if (w.log_src) return launch_k(k_anc_log, dim3((unsigned)b.nseg), dim3(kWave), s, m, b, w);
+  return launch_k(k_anc, dim3((unsigned)b.nseg), dim3(kWave), s, m, b, w);
 }
 
-hipError_t launch_fill(const Model& m, const Buffers& b, hipStream_t s) {
+hipError_t launch_fill(const Model& m, const Buffers& b, const WeightSrc& w, hipStream_t s) {
   const unsigned grid = (unsigned)(b.hq_cap < kFillGrid ? b.hq_cap : kFillGrid);
-  return launch_k(k_fill, dim3(grid), dim3(256), s, m, b);
+  if (w.log_src) return launch_k(k_fill_log, dim3(grid), dim3(kWave), s, m, b, w);
+  return launch_k(k_fill, dim3(grid), dim3(kWave), s, m, b, w);
 }
 
 hipError_t launch_rna(const Model& m, const Buffers& b, const WeightSrc& w, const double* u_dev,

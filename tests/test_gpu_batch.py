@@ -178,3 +178,41 @@ def test_batch_many_small_tracks(ppf, movie):
         assert bst[t]["delta"] == f.stats()["delta"]
         f.close()
     b.close()
+
+
+def test_batch_heavy_fill_across_tracks(ppf, movie):
+    """Tracks whose weights collapse onto a few particles queue chunks of
+    slot tiles for the long-run fill, several tracks in the same step; the
+    batch's fill takes them from one list over all tracks. Each track must
+    equal its single filter."""
+    frames = movie.frames.copy()
+    spec = [(65536, 0), (40000, 1), (100003, 2), (3000, 3), (1, 4), (70001, 5)]
+    ps = []
+    for n, j in spec:
+        x0, y0 = movie.truth[0, j]
+        # a sharp, bright likelihood over a small box: the weight collapses
+        ps.append(ppf.params(n_particles=n, width=W, height=H, psf_sigma=1.2, background=10.0,
+                             noise_sigma=1.0, seed=9, track_id=j,
+                             init_a=(x0 - 3, y0 - 3, -1, -1, 150.0),
+                             init_b=(x0 + 3, y0 + 3, 1, 1, 250.0)))
+    frames = (frames - 10.0) * 6.0 + 10.0  # brighter spots on the same background
+    ft = torch.from_numpy(frames).cuda()
+    b = ppf.Batch(ps)
+    singles = [ppf.Filter(p) for p in ps]
+    heavy_steps = 0
+    for k in range(3):
+        b.step(ft[k])
+        for f in singles:
+            f.step(ft[k])
+        assert_same_as_single(b, singles)
+        # tracks with a 512-particle segment of more than 4 x 512 slots (queued)
+        heavy = 0
+        for t, (n, _) in enumerate(spec):
+            _, _, anc = b.particles(t)
+            if b.stats()[t]["resampled"] and np.bincount(anc // 512).max() > 2048:
+                heavy += 1
+        heavy_steps += heavy >= 2
+    assert heavy_steps >= 1, "no step queued chunks in two tracks"
+    b.close()
+    for f in singles:
+        f.close()
