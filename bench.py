@@ -280,6 +280,191 @@ def run_multitrack(args, w):
     print(json.dumps(out), flush=True)
 
 
+# The differentiable-SIR experiment: 512 x 512, T = 30, N = 262,144, P = 11,
+# one spot rendered with s = 1.7, I = 25, b = 10, sigma_xi = 3 and a truth
+# that follows the filter's own motion model (position, velocity and
+# intensity random walks with the sds q), so that every parameter of theta
+# has a generating value; the start point moves each by 20 % (I0, the offset
+# of the initial intensity range, by 20 % of I).
+C5 = dict(W=512, H=512, T=30, n=1 << 18, P=11, s=1.7, I=25.0, b=10.0, sigma=3.0,
+          q=(0.5, 0.5, 0.1, 0.1, 1.0), movie_seed=5, filter_seed=1,
+          start=(1.2, 0.8, 1.2, 0.8, 1.2, 0.8, 1.2, 0.8), I0_start=0.2)
+
+
+def c5_setup(ppf, synth):
+    """(movie, base params at the generating theta, theta_true, theta_start)
+    of the differentiable-SIR experiment; the initial cloud covers +-5 px
+    around the spot's first position, velocities in [-1, 1], intensities in
+    [I/2, 3 I/2] (+ I0)."""
+    c = C5
+    mv = synth.render_movie(c["W"], c["H"], c["T"], intensity=c["I"], sigma=c["s"],
+                            background=c["b"], noise_sd=c["sigma"], jitter=c["q"][0],
+                            vel_jitter=c["q"][2], int_jitter=c["q"][4], seed=c["movie_seed"])
+    x0, y0 = mv.truth[0, 0]
+    base = ppf.params(n_particles=c["n"], width=c["W"], height=c["H"], psf_sigma=c["s"],
+                      patch=c["P"], background=c["b"], noise_sigma=c["sigma"], q=c["q"],
+                      init_a=(x0 - 5, y0 - 5, -1, -1, c["I"] / 2),
+                      init_b=(x0 + 5, y0 + 5, 1, 1, 1.5 * c["I"]),
+                      ess_threshold=float("inf"), seed=c["filter_seed"])
+    true = [float(v) for v in ppf.theta_of(base)]
+    start = [t * f for t, f in zip(true[:8], c["start"])] + [c["I0_start"] * c["I"]]
+    return mv, base, true, start
+
+
+def grad_run(ppf, p, frames, means=None):
+    """One run of the filter p (gradient mode) over frames: (log p^, d log p^
+    / d theta, the ancestors of every step); `means` (a list) receives each
+    step's MMSE estimate."""
+    import numpy as np
+    f = ppf.Filter(p)
+    ancs = []
+    for k in range(frames.shape[0]):
+        f.step(frames[k])
+        ancs.append(f.particles()[2])
+        if means is not None:
+            means.append(np.asarray(f.stats()["mean"], dtype=np.float64))
+    cum, _ = f.loglik()
+    g, _ = f.grad()
+    f.close()
+    return cum, np.asarray(g, dtype=np.float64), np.stack(ancs)
+
+
+def replay_run(ppf, p, frames, ancs, centres=None):
+    """log p^ of the filter p over frames with the given ancestors instead of
+    its own: after each step the resampled cloud x~_k[anc_k] is set back with
+    log weights -log N, so the next step propagates particle i from it with
+    its own Philox draws, as the recorded run did. `centres` (a list)
+    receives each step's patch centres round(x~), (2, N) int32."""
+    import math
+
+    import numpy as np
+    n = int(p.n_particles)
+    q = ppf.Params.from_buffer_copy(p)
+    q.grad = 0
+    f = ppf.Filter(q)
+    lw = np.full(n, -math.log(n))
+    for k in range(frames.shape[0]):
+        f.step(frames[k])
+        if k + 1 < frames.shape[0] or centres is not None:
+            x, _, _ = f.particles()
+            if centres is not None:
+                centres.append(np.floor(x[:2].astype(np.float64) + 0.5).astype(np.int32))
+            if k + 1 < frames.shape[0]:
+                f.set_particles(np.ascontiguousarray(x[:, ancs[k]]), lw)
+    cum, _ = f.loglik()
+    f.close()
+    return cum
+
+
+def run_grad_check(args):
+    """The differentiable-SIR experiment on the GPU: the derivatives at the
+    start point against central differences of log p^ with the start point's
+    ancestors replayed (h = 1e-3 of each parameter, of I for I0), then 50
+    Adam steps of gradient ascent from the start point (in log theta for the
+    positive parameters, in I0 / I for I0)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_1310_5045_amd as ppf
+    from paper_1310_5045_amd import synth
+
+    torch.cuda.set_device(0)
+    mv, base, true, start = c5_setup(ppf, synth)
+    frames = torch.from_numpy(mv.frames).cuda()
+    c = C5
+    p0 = ppf.params_at(base, start)
+    cum0, g0, ancs = grad_run(ppf, p0, frames)
+    rep0 = replay_run(ppf, p0, frames, ancs)
+    names = list(ppf.GRAD_NAMES)
+    fd, moved = [], []
+    for j in range(9):
+        h = 1e-3 * (abs(start[j]) if j < 8 else c["I"])
+        tp = list(start)
+        tm = list(start)
+        tp[j] += h
+        tm[j] -= h
+        cp, cm = [], []
+        lp = replay_run(ppf, ppf.params_at(base, tp), frames, ancs, cp)
+        lm = replay_run(ppf, ppf.params_at(base, tm), frames, ancs, cm)
+        fd.append((lp - lm) / (2 * h))
+        # particle-steps whose patch centre differs between the two runs
+        moved.append(int(sum(int(np.sum(np.any(a != b, axis=0))) for a, b in zip(cp, cm))))
+        print(f"fd {names[j]}: {fd[-1]:.6g} (gradient {g0[j]:.6g}, {moved[-1]} patches moved)",
+              file=sys.stderr, flush=True)
+        del cp, cm
+    fd = np.array(fd)
+    # ascent: u_j = log theta_j (j < 8), u_8 = I0 / I
+    scale = np.array([1.0] * 8 + [c["I"]])
+
+    def to_u(th):
+        return np.array([math.log(v) for v in th[:8]] + [th[8] / c["I"]])
+
+    def to_theta(u):
+        return [math.exp(v) for v in u[:8]] + [u[8] * c["I"]]
+
+    u = to_u(start)
+    m1 = np.zeros(9)
+    m2 = np.zeros(9)
+    lr, b1, b2 = 0.03, 0.9, 0.999
+    trace = []
+    for it in range(1, args.ascent_steps + 1):
+        th = to_theta(u)
+        L, g, _ = grad_run(ppf, ppf.params_at(base, th), frames)
+        du = np.array([th[j] * g[j] for j in range(8)] + [g[8] * scale[8]])
+        trace.append({"step": it - 1, "theta": th, "loglik": L})
+        m1 = b1 * m1 + (1 - b1) * du
+        m2 = b2 * m2 + (1 - b2) * du * du
+        step = lr * (0.95 ** (it - 1)) * (m1 / (1 - b1 ** it)) / (np.sqrt(m2 / (1 - b2 ** it)) + 1e-12)
+        u = u + step
+        print(f"ascent {it - 1}: L {L:.3f} theta {np.round(th, 4).tolist()}", file=sys.stderr,
+              flush=True)
+    th_end = to_theta(u)
+    mean_end, mean_true, mean_start = [], [], []
+    L_end, _, _ = grad_run(ppf, ppf.params_at(base, th_end), frames, mean_end)
+    trace.append({"step": args.ascent_steps, "theta": th_end, "loglik": L_end})
+    L_true, _, _ = grad_run(ppf, ppf.params_at(base, true), frames, mean_true)
+    grad_run(ppf, p0, frames, mean_start)
+
+    def track_err(means):
+        """RMS over the frames of the MMSE estimate's error in position (px)
+        and in intensity against the generator's truth."""
+        mm = np.stack(means)
+        dp = mm[:, :2] - mv.truth[:, 0]
+        dI = mm[:, 4] - mv.intensity_track[:, 0]
+        return {"position_px": float(np.sqrt(np.mean(np.sum(dp * dp, axis=1)))),
+                "intensity": float(np.sqrt(np.mean(dI * dI)))}
+    rel = np.abs(fd - g0) / np.maximum(np.abs(g0), 1e-12)
+    out = {
+        "experiment": "differentiable SIR: d log p^ / d theta, central differences, ascent",
+        "config": {"workload": "grad_c5_512x512_n262k_p11", "n_particles": c["n"],
+                   "frame": [c["W"], c["H"]], "frames": c["T"], "patch": c["P"],
+                   "generator": {"s": c["s"], "I": c["I"], "b": c["b"], "sigma": c["sigma"],
+                                 "q": list(c["q"]), "seed": c["movie_seed"]},
+                   "resampling": "systematic every step, ancestors held fixed in the derivative"},
+        "theta_names": names,
+        "theta_true": true,
+        "theta_start": start,
+        "start": {"loglik": cum0, "gradient": g0.tolist(), "central_difference": fd.tolist(),
+                  "fd_h": [1e-3 * (abs(start[j]) if j < 8 else c["I"]) for j in range(9)],
+                  "rel_diff": rel.tolist(), "patches_moved_between_runs": moved,
+                  "particle_steps": c["n"] * c["T"],
+                  "replay_loglik_minus_run": rep0 - cum0},
+        "ascent": {"method": f"Adam, lr {lr} x 0.95^t, {args.ascent_steps} steps, log theta "
+                             "(I0 / I for I0)",
+                   "trace": trace, "theta_end": th_end, "loglik_end": L_end,
+                   "loglik_at_theta_true": L_true,
+                   "rel_error_start": [abs(a - b) / abs(b) if b else abs(a) / c["I"]
+                                       for a, b in zip(start, true)],
+                   "rel_error_end": [abs(a - b) / abs(b) if b else abs(a) / c["I"]
+                                     for a, b in zip(th_end, true)],
+                   "tracking_rms": {"start": track_err(mean_start), "end": track_err(mean_end),
+                                    "true": track_err(mean_true)}},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def make_params(ppf, w, init_kind, grad=0):
     """The filter of a single-filter workload: the initial cloud covers the
     spot's start box (default the whole frame), intensity within a factor
@@ -551,6 +736,10 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write a traffic record from two counter databases and exit")
     ap.add_argument("--traffic-kernel", default="k_step", choices=sorted(TRAFFIC_GROUPS))
+    ap.add_argument("--grad-check", action="store_true",
+                    help="the differentiable-SIR experiment (derivatives against central "
+                         "differences, gradient ascent) instead of a throughput figure")
+    ap.add_argument("--ascent-steps", type=int, default=50)
     args = ap.parse_args()
     if args.no_autotune and args.shape is None:
         args.shape = 0
@@ -563,6 +752,9 @@ def main():
         rec = traffic_from(dbs[0], dbs[1], args.workload, args.copy_probe_mib or 1024,
                            args.warmup, args.steps, args.shape, args.traffic_kernel)
         print(json.dumps(rec))
+        return
+    if args.grad_check:
+        run_grad_check(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -10,9 +10,15 @@ neither imports the other; this module is shared by both only as a source of
 inputs.
 
 Recipe (numpy float64, stored as float32):
-  truth   p_1 ~ U(start box); v ~ U[-vmax, vmax]^2 per spot;
-          p_k = p_{k-1} + v + eta_k, eta_k ~ N(0, jitter^2 I_2); I constant.
-  frame   Z_k[y][x] = b + sum_spots I exp(-((x - px)^2 + (y - py)^2) / (2 s^2))
+  truth   p_1 ~ U(start box); v_1 ~ U[-vmax, vmax]^2 per spot; I_1 = I;
+          p_k = p_{k-1} + v_{k-1} + eta_k, eta_k ~ N(0, jitter^2 I_2);
+          v_k = v_{k-1} + zeta_k, zeta_k ~ N(0, vel_jitter^2 I_2);
+          I_k = I_{k-1} + iota_k, iota_k ~ N(0, int_jitter^2)
+          (vel_jitter = int_jitter = 0 by default: constant velocity and
+          intensity; with all three set, the truth follows the filter's own
+          near-constant-velocity model with q = (jitter, jitter, vel_jitter,
+          vel_jitter, int_jitter)).
+  frame   Z_k[y][x] = b + sum_spots I_k exp(-((x - px)^2 + (y - py)^2) / (2 s^2))
           + noise_sd * N(0, 1), pixel (x, y) at integer coordinates.
 """
 from dataclasses import dataclass
@@ -27,12 +33,14 @@ class Movie:
     truth: np.ndarray       # (T, n_spots, 2) float64 spot centres per frame
     intensity: np.ndarray   # (n_spots,) float64
     sigma: np.ndarray       # (n_spots,) float64 PSF widths
-    velocity: np.ndarray    # (n_spots, 2) float64
+    velocity: np.ndarray    # (n_spots, 2) float64 initial velocities
+    intensity_track: Optional[np.ndarray] = None  # (T, n_spots) per-frame intensities
 
 
 def render_movie(width: int, height: int, T: int, *, n_spots: int = 1,
                  intensity=30.0, sigma=1.5, background: float = 10.0,
                  noise_sd: float = 3.0, vmax: float = 1.0, jitter: float = 0.3,
+                 vel_jitter: float = 0.0, int_jitter: float = 0.0,
                  start_box: Optional[Sequence[float]] = None, seed: int = 1) -> Movie:
     """Render T frames. intensity/sigma: a number or a (lo, hi) range drawn
     uniformly per spot. start_box: (x0, x1, y0, y1); default the central half
@@ -51,12 +59,21 @@ def render_movie(width: int, height: int, T: int, *, n_spots: int = 1,
     p = np.stack([rng.uniform(start_box[0], start_box[1], n_spots),
                   rng.uniform(start_box[2], start_box[3], n_spots)], axis=1)
     vel = rng.uniform(-vmax, vmax, (n_spots, 2))
+    vel0 = vel.copy()
+    Ik = I.copy()
     truth = np.zeros((T, n_spots, 2))
+    itrack = np.zeros((T, n_spots))
     frames = np.empty((T, height, width), dtype=np.float32)
     for k in range(T):
         if k > 0:
             p = p + vel + rng.normal(0.0, jitter, (n_spots, 2))
+            # (no draws when the walks are off, so default movies are unchanged)
+            if vel_jitter > 0.0:
+                vel = vel + rng.normal(0.0, vel_jitter, (n_spots, 2))
+            if int_jitter > 0.0:
+                Ik = Ik + rng.normal(0.0, int_jitter, n_spots)
         truth[k] = p
+        itrack[k] = Ik
         img = np.full((height, width), float(background))
         for j in range(n_spots):
             r = int(np.ceil(8.0 * s[j]))
@@ -69,10 +86,10 @@ def render_movie(width: int, height: int, T: int, *, n_spots: int = 1,
             ys = np.arange(y0, y1, dtype=np.float64)
             gx = np.exp(-((xs - p[j, 0]) ** 2) / (2.0 * s[j] ** 2))
             gy = np.exp(-((ys - p[j, 1]) ** 2) / (2.0 * s[j] ** 2))
-            img[y0:y1, x0:x1] += I[j] * gy[:, None] * gx[None, :]
+            img[y0:y1, x0:x1] += Ik[j] * gy[:, None] * gx[None, :]
         img += noise_sd * rng.standard_normal((height, width))
         frames[k] = img.astype(np.float32)
-    return Movie(frames, truth, I, s, vel)
+    return Movie(frames, truth, I, s, vel0, itrack)
 
 
 @dataclass
