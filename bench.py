@@ -166,6 +166,12 @@ WORKLOADS = {
                                   thr=float(1 << 19), scheme=(2, 256, 0)),
     "rpa_sgs_512x512_n1m_p9": dict(W=512, H=512, T=50, n=1 << 20, s=1.5, P=9,
                                    thr=float(1 << 19), scheme=(2, 256, 1)),
+    # the 38M workload with RPA over groups of 250 (152,000 groups; 38 M is
+    # not a multiple of 256)
+    "rpa_gs_1024x1024_n38m_p13": dict(W=1024, H=1024, T=20, n=38_000_000, s=2.0, P=13,
+                                      thr=float("inf"), scheme=(2, 250, 0)),
+    "rpa_sgs_1024x1024_n38m_p13": dict(W=1024, H=1024, T=20, n=38_000_000, s=2.0, P=13,
+                                       thr=float("inf"), scheme=(2, 250, 1)),
     "sir_128x128_n4096_p9": dict(W=128, H=128, T=10, n=4096, s=1.5, P=9, thr=float("inf")),
     # forward pass with the derivatives of log p^ in (s, b, sigma, q, I0)
     "grad_512x512_n262k_p11": dict(W=512, H=512, T=30, n=1 << 18, s=1.7, P=11, thr=float("inf"),

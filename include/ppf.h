@@ -63,7 +63,7 @@ enum { PPF_RESAMPLE_SYSTEMATIC = 0, PPF_RESAMPLE_RNA = 1, PPF_RESAMPLE_RPA = 2,
 /* DLB schedules of Section 4: Greedy (Alg. 2), Sorted Greedy (Alg. 3),
  * Largest Gradient (Alg. 4). */
 enum { PPF_DLB_GS = 0, PPF_DLB_SGS = 1, PPF_DLB_LGS = 2 };
-#define PPF_DLB_MAX_SORTED 4096 /* groups a sorted schedule accepts */
+#define PPF_DLB_MAX_SORTED 4096 /* groups ppf_dlb_schedule accepts */
 enum { PPF_OBS_SPOT = 0, PPF_OBS_LINEAR_GAUSSIAN = 1 };
 enum { PPF_INIT_UNIFORM = 0, PPF_INIT_GAUSSIAN = 1, PPF_INIT_STRATIFIED = 2 };
 
@@ -116,8 +116,8 @@ typedef struct ppf_ctx* ppf_handle;
  * ess_threshold resample iff ESS < ess_threshold (Algorithm 1); +INFINITY
  *               resamples every step, 0 never.
  * rna_group     n, particles per RNA group (one workgroup each); N % n == 0,
- *               1 <= n <= 1024. For RPA the group size: N % n == 0, and at
- *               most PPF_DLB_MAX_SORTED groups under SGS. Ignored for
+ *               1 <= n <= 1024. For RPA the group size: N % n == 0 (any
+ *               number of groups, under GS and SGS alike). Ignored for
  *               systematic resampling.
  * rna_exchange  rho in [0, 1): after local resampling the last floor(rho * n)
  *               slots of group g take the particles (and weight) of the same

@@ -69,8 +69,6 @@ std::string validate(const ppf_params* p) {
     if (p->rna_group < 1 || p->n_particles % p->rna_group != 0)
       return "RPA: n_particles must be a multiple of rna_group";
     if (p->dlb != PPF_DLB_GS && p->dlb != PPF_DLB_SGS) return "RPA: dlb must be GS or SGS";
-    if (p->dlb == PPF_DLB_SGS && p->n_particles / p->rna_group > PPF_DLB_MAX_SORTED)
-      return "RPA with SGS: too many groups";
   }
   for (int d = 0; d < 5; ++d) {
     if (!std::isfinite(p->q[d]) || p->q[d] < 0.0f) return "q must be finite and >= 0";
@@ -240,8 +238,17 @@ size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) 
     bb.rsend = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * Gr));
     bb.rscum = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (Gr + 1)));
     bb.rns = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2));
-    bb.rrank = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2 * Gr));
-    bb.rsorted = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2 * Gr));
+    const int64_t nt = (2 * Gr + ppf::kSortTile - 1) / ppf::kSortTile;
+    const int64_t nt2 = (Gr + ppf::kSortTile - 1) / ppf::kSortTile;
+    if (p->dlb == PPF_DLB_SGS) {
+      bb.rkey0 = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 2 * Gr));
+      bb.rkey1 = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 2 * Gr));
+      bb.rval0 = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2 * Gr));
+      bb.rval1 = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2 * Gr));
+      bb.rhist = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 256 * nt));
+      bb.rrow = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 256));
+    }
+    bb.rtsum = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * 4 * nt2));
   }
   if (p->resample == PPF_RESAMPLE_ARNA) {
     bb.aloc = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));

@@ -57,7 +57,8 @@ constexpr int kFillGridBatch = 2048;  // waves of a batched fill, over all track
 // Batched steps run every patch size up to this one in a single launch (the
 // sizes that fit five waves per SIMD); wider patches launch per size.
 constexpr int kFusedMaxP = 13;
-constexpr int kDlbMaxSorted = 4096;  // groups of a sorted DLB schedule (LDS sort)
+constexpr int kDlbMaxSorted = 4096;  // groups of a standalone DLB schedule (LDS sort)
+constexpr int kSortTile = 1024;      // pairs per tile of the radix sort and list scans
 // The allocation-free standalone resampler keeps its scratch in a device
 // array of this many bytes, one per device for the life of the process.
 constexpr size_t kStaticScratchBytes = size_t(4) << 20;
@@ -200,8 +201,13 @@ struct Buffers {
   int32_t* rsend;    // RPA: sender groups in schedule order
   int64_t* rscum;    // RPA: exclusive prefix of the senders' surplus (ns + 1)
   int32_t* rns;      // RPA: number of senders
-  int32_t* rrank;    // RPA with SGS: rank of each group among senders, then receivers (2G)
-  int32_t* rsorted;  // RPA with SGS: groups in sender order, then receiver order (2G)
+  uint32_t* rkey0;   // RPA with SGS: radix-sort keys of the 2G list entries, ping
+  uint32_t* rkey1;   //   and pong
+  int32_t* rval0;    // RPA with SGS: their groups (after the sort: senders in order,
+  int32_t* rval1;    //   then receivers in order), ping and pong
+  uint32_t* rhist;   // RPA with SGS: digit counts per sort tile (256 x tiles)
+  uint32_t* rrow;    // RPA with SGS: digit totals (256)
+  uint64_t* rtsum;   // RPA: per list tile, the sum of the values and the count present
   int32_t* aloc;     // ARNA: each group's local resampling (n global indices)
   double* Wg;        // ARNA: each group's share of the normalised weight
   double* lwt;       // ARNA: per group, the weight log(W_pred / n) of its exchanged slots

@@ -2101,116 +2101,223 @@ __global__ __launch_bounds__(256) void k_rpa_first(Model m, Buffers b) {
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t N = m.n, G = m.rpa_G;
   if (g <= G) b.rfirst[g] = g == G ? N : lower_bound_i32(b.asys, N, g * (int64_t)m.rpa_group);
-  if (m.dlb == 1 && g < G) {  // SGS: the ranks are summed by k_rpa_rank
-    b.rrank[g] = 0;
-    b.rrank[G + g] = 0;
-  }
-  if (m.dlb == 1 && g < 2) b.rns[g] = 0;
 }
 
-// Sort key of group g for the senders (side 0: surplus) or the receivers
-// (side 1: deficit): descending size, ties by group; ~0 when absent.
-__device__ __forceinline__ uint64_t rpa_key(const Buffers& b, int64_t n, int64_t g, int side) {
-  const int64_t cg = b.rfirst[g + 1] - b.rfirst[g];
-  return desc_key(side == 0 ? cg - n : n - cg, g);
+// Surplus (side 0) or deficit (side 1) of group g; 0 when it is not a
+// sender (receiver).
+__device__ __forceinline__ uint64_t rpa_value(const Buffers& b, int64_t n, int64_t g, int side) {
+  const int64_t cg = rpa_count(b, g);
+  const int64_t v = side == 0 ? cg - n : n - cg;
+  return v > 0 ? (uint64_t)v : 0;
 }
 
-// SGS order by counting: the rank of a present key is the number of keys
-// below it (keys are distinct); workgroup (x, y, side) adds the count over
-// the y-th slice of 1024 keys for 256 groups.
-__global__ __launch_bounds__(256) void k_rpa_rank(Model m, Buffers b) {
-  __shared__ uint64_t ks[1024];
-  const Ctrl* c = b.ctrl;
-  if (!c->do_resample) return;
-  const int side = blockIdx.z;
-  const int64_t n = m.rpa_group, G = m.rpa_G;
-  const int64_t h0 = (int64_t)blockIdx.y * 1024;
-  for (int i = threadIdx.x; i < 1024; i += 256)
-    ks[i] = h0 + i < G ? rpa_key(b, n, h0 + i, side) : ~0ull;
-  __syncthreads();
-  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (g >= G) return;
-  const uint64_t kg = rpa_key(b, n, g, side);
-  if (kg == ~0ull) return;
-  int cnt = 0;
-  for (int i = 0; i < 1024; ++i) cnt += ks[i] < kg ? 1 : 0;
-  if (cnt) atomicAdd(&b.rrank[side * G + g], cnt);
-  if (blockIdx.y == 0) atomicAdd(&b.rns[side], 1);  // present keys of this side
-}
-
-// One workgroup: the sender order with the prefix of their surplus, and each
-// receiver's first surplus particle.
-__global__ __launch_bounds__(256) void k_rpa_plan(Model m, Buffers b) {
-  __shared__ uint64_t ush[4];
-  const Ctrl* c = b.ctrl;
-  if (!c->do_resample) return;
+// ------------------------------------------------------------ radix sort
+// Stable least-significant-digit sort of (uint32 key, int32 value) pairs,
+// eight bits per pass, in tiles of kSortTile pairs (256 threads x 4 rounds).
+// A pass: the digit's count per tile (k_radix_hist), each digit's row of
+// tile counts turned into exclusive prefixes (k_radix_rowscan, one workgroup
+// per digit), then every pair written to digit start + tile prefix + its
+// rank among the tile's pairs of the same digit in input order
+// (k_radix_scatter). `gate`, when given, skips the pass on steps that do not
+// resample.
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ key,
+                                                    int64_t count, int shift,
+                                                    uint32_t* __restrict__ hist, int32_t ntiles,
+                                                    const Ctrl* gate) {
+  if (gate && !gate->do_resample) return;
+  __shared__ uint32_t h[256];
   const int t = threadIdx.x;
-  const int64_t n = m.rpa_group, G = m.rpa_G;
-  if (m.dlb == 0) {
-    // GS: both lists in group order
-    uint64_t cs = 0, cr = 0, cns = 0;
-    for (int64_t g0 = 0; g0 < G; g0 += 256) {
-      const int64_t g = g0 + t;
-      const int64_t cg = g < G ? rpa_count(b, g) : n;
-      const uint64_t su = cg > n ? (uint64_t)(cg - n) : 0, de = cg < n ? (uint64_t)(n - cg) : 0;
-      uint64_t tsu, tde, tfl;
-      const uint64_t esu = block_excl_sum(su, ush, &tsu);
-      const uint64_t ede = block_excl_sum(de, ush, &tde);
-      const uint64_t efl = block_excl_sum(su > 0 ? 1 : 0, ush, &tfl);
-      if (g < G) {
-        b.rdbase[g] = (int64_t)(cr + ede);
-        if (su > 0) {
-          b.rsend[cns + efl] = (int32_t)g;
-          b.rscum[cns + efl] = (int64_t)(cs + esu);
-        }
-      }
-      cs += tsu;
-      cr += tde;
-      cns += tfl;
-    }
-    if (t == 0) {
-      *b.rns = (int32_t)cns;
-      b.rscum[cns] = (int64_t)cs;
-    }
-    return;
-  }
-  // SGS: both lists by size descending, ties by group, placed by the ranks
-  // of k_rpa_rank
-  const int64_t nside[2] = {b.rns[0], b.rns[1]};
+  h[t] = 0;
   __syncthreads();
-  for (int side = 0; side < 2; ++side) {
-    for (int64_t g = t; g < G; g += 256)
-      if (rpa_key(b, n, g, side) != ~0ull) b.rsorted[side * G + b.rrank[side * G + g]] = (int32_t)g;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortTile / 256; ++r) {
+    const int64_t j = base + r * 256 + t;
+    if (j < count) atomicAdd(&h[(key[j] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)t * ntiles + blockIdx.x] = h[t];
+}
+
+__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ hist, int32_t ntiles,
+                                                       uint32_t* __restrict__ rowtot,
+                                                       const Ctrl* gate) {
+  if (gate && !gate->do_resample) return;
+  __shared__ uint64_t sh[4];
+  uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
+  uint64_t carry = 0;
+  for (int32_t i0 = 0; i0 < ntiles; i0 += 256) {
+    const int32_t i = i0 + (int32_t)threadIdx.x;
+    const uint64_t v = i < ntiles ? row[i] : 0;
+    uint64_t tot;
+    const uint64_t ex = block_excl_sum(v, sh, &tot);
+    if (i < ntiles) row[i] = (uint32_t)(carry + ex);
+    carry += tot;
+  }
+  if (threadIdx.x == 0) rowtot[blockIdx.x] = (uint32_t)carry;
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    int32_t* __restrict__ vout, int64_t count, int shift, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ rowtot, int32_t ntiles, const Ctrl* gate) {
+  if (gate && !gate->do_resample) return;
+  __shared__ uint32_t run[256];      // the tile's pairs of each digit in earlier rounds
+  __shared__ uint32_t wcnt[4][256];  // this round's pairs per wave and digit
+  __shared__ uint32_t start[256];    // each digit's first position for this tile
+  __shared__ uint64_t sh[4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  uint64_t total;
+  const uint64_t dstart = block_excl_sum((uint64_t)rowtot[t], sh, &total);
+  start[t] = (uint32_t)dstart + hist[(int64_t)t * ntiles + blockIdx.x];
+  run[t] = 0;
+  const int64_t tb = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortTile / 256; ++r) {
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) wcnt[ww][t] = 0;
     __syncthreads();
-    uint64_t carry = 0, cnt = 0;
-    for (int64_t k0 = 0; k0 < G; k0 += 256) {
-      const int64_t k = k0 + t;
-      const bool here = k < nside[side];
-      const int64_t g = here ? (int64_t)b.rsorted[side * G + k] : 0;
-      uint64_t v = 0;
-      if (here) {
-        const int64_t cg = rpa_count(b, g);
-        v = (uint64_t)(side == 0 ? cg - n : n - cg);
-      }
-      uint64_t tv, tc;
-      const uint64_t ev = block_excl_sum(v, ush, &tv);
-      const uint64_t ec = block_excl_sum(here ? 1 : 0, ush, &tc);
-      if (here) {
-        if (side == 0) {
-          b.rsend[cnt + ec] = (int32_t)g;
-          b.rscum[cnt + ec] = (int64_t)(carry + ev);
-        } else {
-          b.rdbase[g] = (int64_t)(carry + ev);
-        }
-      }
-      carry += tv;
-      cnt += tc;
+    const int64_t j = tb + r * 256 + t;
+    const bool in = j < count;
+    const uint32_t key = in ? kin[j] : 0u;
+    const int32_t val = in ? vin[j] : 0;
+    const uint32_t d = (key >> shift) & 255u;
+    // the lanes of this wave holding the same digit
+    uint64_t peers = __ballot(in);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool set = (d >> bit) & 1u;
+      const uint64_t bb = __ballot(set);
+      peers &= set ? bb : ~bb;
     }
-    if (side == 0 && t == 0) {
-      *b.rns = (int32_t)cnt;
-      b.rscum[cnt] = (int64_t)carry;
+    const uint32_t rank = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+    if (in && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (in) {
+      uint32_t off = start[d] + run[d] + rank;
+      for (int ww = 0; ww < w; ++ww) off += wcnt[ww][d];
+      kout[off] = key;
+      vout[off] = val;
     }
     __syncthreads();
+    run[t] += (wcnt[0][t] + wcnt[1][t]) + (wcnt[2][t] + wcnt[3][t]);
+  }
+}
+
+// SGS: the sort keys of the 2G list entries, senders (side 0) then
+// receivers (side 1), each side by value descending; absent entries (value
+// 0) sort last in their side, ties (stable) by group.
+__global__ __launch_bounds__(256) void k_rpa_keys(Model m, Buffers b) {
+  const Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int64_t G = m.rpa_G;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= 2 * G) return;
+  const int side = j >= G ? 1 : 0;
+  const int64_t g = j - side * G;
+  // values are below N < 2^31
+  const uint64_t v = rpa_value(b, m.rpa_group, g, side);
+  b.rkey0[j] = ((uint32_t)side << 31) | (v > 0 ? (uint32_t)(0x7fffffffu - (uint32_t)v) : 0x7fffffffu);
+  b.rval0[j] = (int32_t)g;
+}
+
+// Group at position k of one side's list: group order (GS) or the sorted
+// order (SGS: the sort's result is back in the ping buffers).
+__device__ __forceinline__ int64_t rpa_at(const Model& m, const Buffers& b, int side, int64_t k) {
+  return m.dlb == 1 ? (int64_t)b.rval0[side * (int64_t)m.rpa_G + k] : k;
+}
+
+// The plan: over each side's list in schedule order, the exclusive prefix of
+// the values (and, for the senders, of their count), in three launches:
+// per tile of kSortTile positions the sum and the count present
+// (k_rpa_plan_tiles), their exclusive prefixes over the tiles
+// (k_rpa_plan_scan, one workgroup per side), then each position's prefixes
+// (k_rpa_plan_apply): the senders in order with the prefix of their surplus,
+// each receiver's first surplus particle.
+__global__ __launch_bounds__(256) void k_rpa_plan_tiles(Model m, Buffers b) {
+  __shared__ uint64_t sh[4];
+  const Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int side = blockIdx.y;
+  const int64_t G = m.rpa_G, n = m.rpa_group;
+  const int64_t nt2 = (G + kSortTile - 1) / kSortTile;
+  const int64_t k0 = (int64_t)blockIdx.x * kSortTile + 4 * threadIdx.x;
+  uint64_t sv = 0, sp = 0;
+  for (int i = 0; i < 4; ++i) {
+    const int64_t k = k0 + i;
+    if (k < G) {
+      const uint64_t v = rpa_value(b, n, rpa_at(m, b, side, k), side);
+      sv += v;
+      sp += v > 0 ? 1 : 0;
+    }
+  }
+  uint64_t tv, tp;
+  block_excl_sum(sv, sh, &tv);
+  block_excl_sum(sp, sh, &tp);
+  if (threadIdx.x == 0) {
+    b.rtsum[2 * (side * nt2 + blockIdx.x)] = tv;
+    b.rtsum[2 * (side * nt2 + blockIdx.x) + 1] = tp;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rpa_plan_scan(Model m, Buffers b) {
+  __shared__ uint64_t sh[4];
+  const Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int side = blockIdx.x;
+  const int64_t G = m.rpa_G;
+  const int64_t nt2 = (G + kSortTile - 1) / kSortTile;
+  uint64_t* ts = b.rtsum + 2 * side * nt2;
+  uint64_t cv = 0, cp = 0;
+  for (int64_t i0 = 0; i0 < nt2; i0 += 256) {
+    const int64_t i = i0 + threadIdx.x;
+    const uint64_t v = i < nt2 ? ts[2 * i] : 0, p = i < nt2 ? ts[2 * i + 1] : 0;
+    uint64_t tv, tp;
+    const uint64_t ev = block_excl_sum(v, sh, &tv);
+    const uint64_t ep = block_excl_sum(p, sh, &tp);
+    if (i < nt2) {
+      ts[2 * i] = cv + ev;
+      ts[2 * i + 1] = cp + ep;
+    }
+    cv += tv;
+    cp += tp;
+  }
+  if (side == 0 && threadIdx.x == 0) {
+    b.rns[0] = (int32_t)cp;
+    b.rscum[cp] = (int64_t)cv;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rpa_plan_apply(Model m, Buffers b) {
+  __shared__ uint64_t sh[4];
+  const Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int side = blockIdx.y;
+  const int64_t G = m.rpa_G, n = m.rpa_group;
+  const int64_t nt2 = (G + kSortTile - 1) / kSortTile;
+  const int64_t k0 = (int64_t)blockIdx.x * kSortTile + 4 * threadIdx.x;
+  int64_t g[4];
+  uint64_t v[4];
+  uint64_t sv = 0, sp = 0;
+  for (int i = 0; i < 4; ++i) {
+    const int64_t k = k0 + i;
+    g[i] = k < G ? rpa_at(m, b, side, k) : 0;
+    v[i] = k < G ? rpa_value(b, n, g[i], side) : 0;
+    sv += v[i];
+    sp += v[i] > 0 ? 1 : 0;
+  }
+  uint64_t tv, tp;
+  uint64_t pv = block_excl_sum(sv, sh, &tv) + b.rtsum[2 * (side * nt2 + blockIdx.x)];
+  uint64_t pp = block_excl_sum(sp, sh, &tp) + b.rtsum[2 * (side * nt2 + blockIdx.x) + 1];
+  for (int i = 0; i < 4; ++i) {
+    if (v[i] > 0) {
+      if (side == 0) {
+        b.rsend[pp] = (int32_t)g[i];
+        b.rscum[pp] = (int64_t)pv;
+      } else {
+        b.rdbase[g[i]] = (int64_t)pv;
+      }
+      pv += v[i];
+      pp += 1;
+    }
   }
 }
 
@@ -2748,12 +2855,32 @@ hipError_t launch_arna(const Model& m, const Buffers& b, hipStream_t s) {
 }
 
 hipError_t launch_rpa(const Model& m, const Buffers& b, hipStream_t s) {
-  hipError_t e =
-      launch_k(k_rpa_first, dim3(grid_for((int64_t)m.rpa_G + 1, 256)), dim3(256), s, m, b);
-  if (e == hipSuccess && m.dlb == 1)
-    e = launch_k(k_rpa_rank, dim3(grid_for(m.rpa_G, 256), grid_for(m.rpa_G, 1024), 2), dim3(256),
-                 s, m, b);
-  if (e == hipSuccess) e = launch_k(k_rpa_plan, dim3(1), dim3(256), s, m, b);
+  const int64_t G = m.rpa_G;
+  hipError_t e = launch_k(k_rpa_first, dim3(grid_for(G + 1, 256)), dim3(256), s, m, b);
+  if (e == hipSuccess && m.dlb == 1) {
+    const int64_t cnt = 2 * G;
+    const int32_t nt = (int32_t)((cnt + kSortTile - 1) / kSortTile);
+    e = launch_k(k_rpa_keys, dim3(grid_for(cnt, 256)), dim3(256), s, m, b);
+    for (int pass = 0; pass < 4 && e == hipSuccess; ++pass) {
+      // ping -> pong on even passes, back on odd ones: the result lands in ping
+      const uint32_t* kin = pass & 1 ? b.rkey1 : b.rkey0;
+      const int32_t* vin = pass & 1 ? b.rval1 : b.rval0;
+      uint32_t* kout = pass & 1 ? b.rkey0 : b.rkey1;
+      int32_t* vout = pass & 1 ? b.rval0 : b.rval1;
+      const Ctrl* gate = b.ctrl;
+      e = launch_k(k_radix_hist, dim3((unsigned)nt), dim3(256), s, kin, cnt, 8 * pass, b.rhist,
+                   nt, gate);
+      if (e == hipSuccess)
+        e = launch_k(k_radix_rowscan, dim3(256), dim3(256), s, b.rhist, nt, b.rrow, gate);
+      if (e == hipSuccess)
+        e = launch_k(k_radix_scatter, dim3((unsigned)nt), dim3(256), s, kin, vin, kout, vout, cnt,
+                     8 * pass, (const uint32_t*)b.rhist, (const uint32_t*)b.rrow, nt, gate);
+    }
+  }
+  const unsigned nt2 = (unsigned)((G + kSortTile - 1) / kSortTile);
+  if (e == hipSuccess) e = launch_k(k_rpa_plan_tiles, dim3(nt2, 2), dim3(256), s, m, b);
+  if (e == hipSuccess) e = launch_k(k_rpa_plan_scan, dim3(2), dim3(256), s, m, b);
+  if (e == hipSuccess) e = launch_k(k_rpa_plan_apply, dim3(nt2, 2), dim3(256), s, m, b);
   if (e == hipSuccess) e = launch_k(k_rpa_route, dim3(grid_for(m.n, 256)), dim3(256), s, m, b);
   return e;
 }

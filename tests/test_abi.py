@@ -46,7 +46,7 @@ def test_params_layout_and_defaults():
     dict(resample=1, rna_group=300), dict(resample=1, rna_group=2048, n_particles=4096),
     dict(resample=1, rna_exchange=1.0), dict(obs_model=7), dict(init_kind=9),
     dict(q=(0.5, 0.5, -0.1, 0.1, 1.0)), dict(ess_threshold=float("nan")),
-    dict(psf_sigma=0.2, patch=25), dict(obs_model=1, lg_r=(1.0, 0.0, 1.0)), dict(grad=2), dict(reserved=1), dict(resample=2, rna_group=300), dict(resample=2, dlb=2), dict(resample=2, rna_group=1, n_particles=8192, dlb=1), dict(grad=1, resample=1), dict(grad=1, ess_threshold=1e3), dict(grad=1, obs_model=1),
+    dict(psf_sigma=0.2, patch=25), dict(obs_model=1, lg_r=(1.0, 0.0, 1.0)), dict(grad=2), dict(reserved=1), dict(resample=2, rna_group=300), dict(resample=2, dlb=2), dict(grad=1, resample=1), dict(grad=1, ess_threshold=1e3), dict(grad=1, obs_model=1),
     dict(resample=4), dict(arna_pad=1), dict(resample=3, rna_group=2048, n_particles=4096),
     dict(resample=3, arna_min=0.2), dict(resample=3, arna_track=0.0),
     dict(resample=3, arna_lost=-1.0), dict(resample=3, obs_model=1), dict(resample=3, rna_group=300),
@@ -168,3 +168,9 @@ def test_static_resampler_limits_without_a_gpu():
     assert f(dummy, 0, 0.5, dummy, None) == ppf.PPF_EINVAL
     assert f(None, 16, 0.5, dummy, None) == ppf.PPF_EINVAL
     assert f(dummy, 16, 1.0, dummy, None) == ppf.PPF_EINVAL
+
+
+def test_sorted_schedule_takes_many_groups():
+    """RPA with the sorted greedy schedule has no group limit (radix sort)."""
+    p = ppf.params(resample=2, rna_group=1, n_particles=8192, dlb=1)
+    assert ppf.workspace_bytes(p) > 0

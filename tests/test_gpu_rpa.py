@@ -82,3 +82,30 @@ def test_rpa_filter(ppf, dlb, n, group):
         cur.lw_next = np.full(n, -math.log(n))
         prev = cur
     f.close()
+
+
+@pytest.mark.parametrize("dlb", [0, 1])
+@pytest.mark.parametrize("group", [64, 8])
+def test_rpa_filter_many_groups(ppf, dlb, group):
+    """2^20 particles in 16,384 or 131,072 groups (the sorted schedule's radix
+    sort and the list scans over many tiles): the resampled multiset is the
+    systematic one and the placement the oracle's routing."""
+    n = 1 << 20
+    mv = synth.render_movie(256, 256, 3, intensity=30.0, sigma=1.5, start_box=(96, 160, 96, 160),
+                            seed=23)
+    p, m = pair(ppf, n=n, width=256, height=256, s=1.5, b=10.0, sigma=3.0,
+                init_a=(64, 64, -1, -1, 15), init_b=(192, 192, 1, 1, 45), resample=0, seed=6)
+    p.resample = ppf.RESAMPLE_RPA
+    p.rna_group = group
+    p.dlb = dlb
+    f = ppf.Filter(p)
+    frames = torch.from_numpy(mv.frames).cuda()
+    for k in range(1, 3):
+        f.step(frames[k - 1])
+        x, lw, anc = f.particles()
+        assert f.stats()["resampled"]
+        sys_anc = np.sort(anc)
+        check_systematic(np.exp(lw), oracle.resample_uniform(m, k), sys_anc)
+        routed = oracle.route_rpa(sys_anc, group, dlb)
+        assert np.array_equal(anc, routed), (k, int(np.sum(anc != routed)))
+    f.close()
