@@ -235,7 +235,6 @@ size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) 
     bb.asys = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
     bb.rfirst = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (Gr + 1)));
     bb.rdbase = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * Gr));
-    bb.rsend = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * Gr));
     bb.rscum = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (Gr + 1)));
     bb.rns = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2));
     const int64_t nt = (2 * Gr + ppf::kSortTile - 1) / ppf::kSortTile;
@@ -249,6 +248,8 @@ size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) 
       bb.rrow = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 256));
     }
     bb.rtsum = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * 4 * nt2));
+    bb.rsidx = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * Gr));
+    bb.rstream = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
   }
   if (p->resample == PPF_RESAMPLE_ARNA) {
     bb.aloc = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));

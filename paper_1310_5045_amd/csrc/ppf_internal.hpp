@@ -198,7 +198,6 @@ struct Buffers {
   int32_t* asys;     // RPA: ancestors of the global systematic resampling
   int64_t* rfirst;   // RPA: first systematic slot of each group's offspring (G + 1)
   int64_t* rdbase;   // RPA: per receiver group, its first surplus particle
-  int32_t* rsend;    // RPA: sender groups in schedule order
   int64_t* rscum;    // RPA: exclusive prefix of the senders' surplus (ns + 1)
   int32_t* rns;      // RPA: number of senders
   uint32_t* rkey0;   // RPA with SGS: radix-sort keys of the 2G list entries, ping
@@ -208,6 +207,8 @@ struct Buffers {
   uint32_t* rhist;   // RPA with SGS: digit counts per sort tile (256 x tiles)
   uint32_t* rrow;    // RPA with SGS: digit totals (256)
   uint64_t* rtsum;   // RPA: per list tile, the sum of the values and the count present
+  int32_t* rsidx;    // RPA: each sender group's position in the sender order (G)
+  int32_t* rstream;  // RPA: the senders' surplus offspring in schedule order (N)
   int32_t* aloc;     // ARNA: each group's local resampling (n global indices)
   double* Wg;        // ARNA: each group's share of the normalised weight
   double* lwt;       // ARNA: per group, the weight log(W_pred / n) of its exchanged slots

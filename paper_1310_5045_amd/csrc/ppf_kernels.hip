@@ -2230,8 +2230,8 @@ __device__ __forceinline__ int64_t rpa_at(const Model& m, const Buffers& b, int 
 // per tile of kSortTile positions the sum and the count present
 // (k_rpa_plan_tiles), their exclusive prefixes over the tiles
 // (k_rpa_plan_scan, one workgroup per side), then each position's prefixes
-// (k_rpa_plan_apply): the senders in order with the prefix of their surplus,
-// each receiver's first surplus particle.
+// (k_rpa_plan_apply): each sender's position in the sender order and the
+// prefix of the surplus before it, each receiver's first surplus particle.
 __global__ __launch_bounds__(256) void k_rpa_plan_tiles(Model m, Buffers b) {
   __shared__ uint64_t sh[4];
   const Ctrl* c = b.ctrl;
@@ -2310,8 +2310,8 @@ __global__ __launch_bounds__(256) void k_rpa_plan_apply(Model m, Buffers b) {
   for (int i = 0; i < 4; ++i) {
     if (v[i] > 0) {
       if (side == 0) {
-        b.rsend[pp] = (int32_t)g[i];
         b.rscum[pp] = (int64_t)pv;
+        b.rsidx[g[i]] = (int32_t)pp;
       } else {
         b.rdbase[g[i]] = (int64_t)pv;
       }
@@ -2321,36 +2321,77 @@ __global__ __launch_bounds__(256) void k_rpa_plan_apply(Model m, Buffers b) {
   }
 }
 
-// One thread per output slot.
+// The surplus stream: the q-th surplus offspring in schedule order is
+// offspring n + j of the sender at position i of the sender order, where q =
+// (surplus of the senders before i) + j. Each thread takes four consecutive
+// systematic slots t: slot t is offspring t - first(g) of the group g that
+// holds its ancestor (every load is issued before any store).
+__global__ __launch_bounds__(256) void k_rpa_stream(Model m, Buffers b) {
+  const Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int64_t t0 = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
+  const int64_t N = m.n;
+  if (t0 >= N) return;
+  const int64_t n = m.rpa_group;
+  const int32_t* __restrict__ asys = b.asys;
+  int32_t a[4];
+  if (t0 + 4 <= N && (reinterpret_cast<uintptr_t>(asys + t0) & 15) == 0) {
+    const int4 v = *reinterpret_cast<const int4*>(asys + t0);
+    a[0] = v.x;
+    a[1] = v.y;
+    a[2] = v.z;
+    a[3] = v.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = asys[min(t0 + i, N - 1)];
+  }
+  int64_t q[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    // ancestors are below N < 2^31: a 32-bit quotient
+    const int64_t g = (int64_t)((uint32_t)a[i] / (uint32_t)n);
+    const int64_t j = t0 + i - b.rfirst[g] - n;
+    q[i] = (t0 + i < N && j >= 0) ? b.rscum[b.rsidx[g]] + j : -1;  // -1: kept by its group
+  }
+  int32_t* __restrict__ out = b.rstream;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (q[i] >= 0 && q[i] < N) out[q[i]] = a[i];  // a balanced plan has q < N
+}
+
+// Four consecutive output slots per thread: each takes its group's own
+// offspring first, then the surplus stream from the receiver's first
+// surplus particle (every load is issued before any store).
 __global__ __launch_bounds__(256) void k_rpa_route(Model m, Buffers b) {
   const Ctrl* c = b.ctrl;
   if (!c->do_resample) return;
-  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t s0 = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
   const int64_t N = m.n;
-  if (s >= N) return;
+  if (s0 >= N) return;
   const int64_t n = m.rpa_group;
-  const int64_t g = (int64_t)((uint32_t)s / (uint32_t)n);
-  const int64_t p = s - g * n;
-  const int64_t f0 = b.rfirst[g];
-  const int64_t keep = min(b.rfirst[g + 1] - f0, n);
-  int64_t src;
-  if (p < keep) {
-    src = f0 + p;
-  } else {
-    // the q-th surplus particle in schedule order belongs to the last
-    // sender whose prefix is <= q
-    const int64_t q = b.rdbase[g] + (p - keep);
-    int64_t lo = 0, hi = max((int64_t)*b.rns - 1, (int64_t)0);
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (b.rscum[mid] <= q) lo = mid;
-      else hi = mid - 1;
-    }
-    const int64_t gs = min(max((int64_t)b.rsend[lo], (int64_t)0), m.rpa_G - 1);
-    src = b.rfirst[gs] + n + (q - b.rscum[lo]);
+  const int32_t* __restrict__ asys = b.asys;
+  const int32_t* __restrict__ stream = b.rstream;
+  int32_t v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t s = min(s0 + i, N - 1);
+    const int64_t g = (int64_t)((uint32_t)s / (uint32_t)n);
+    const int64_t p = s - g * n;
+    const int64_t f0 = b.rfirst[g];
+    const int64_t keep = min(b.rfirst[g + 1] - f0, n);
+    const int64_t q = min(max(b.rdbase[g] + (p - keep), (int64_t)0), N - 1);
+    // (both indices stay in [0, N) whichever way the choice goes; a balanced
+    // plan never clamps q)
+    v[i] = p < keep ? asys[min(f0 + p, N - 1)] : stream[q];
   }
-  src = min(max(src, (int64_t)0), N - 1);  // a balanced plan never clamps
-  b.anc[s] = b.asys[src];
+  int32_t* __restrict__ out = b.anc;
+  if (s0 + 4 <= N && (reinterpret_cast<uintptr_t>(out + s0) & 15) == 0) {
+    *reinterpret_cast<int4*>(out + s0) = make_int4(v[0], v[1], v[2], v[3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (s0 + i < N) out[s0 + i] = v[i];
+  }
 }
 
 // The DLB schedules of Section 4 for G <= kDlbMaxSorted groups, one
@@ -2881,7 +2922,9 @@ hipError_t launch_rpa(const Model& m, const Buffers& b, hipStream_t s) {
   if (e == hipSuccess) e = launch_k(k_rpa_plan_tiles, dim3(nt2, 2), dim3(256), s, m, b);
   if (e == hipSuccess) e = launch_k(k_rpa_plan_scan, dim3(2), dim3(256), s, m, b);
   if (e == hipSuccess) e = launch_k(k_rpa_plan_apply, dim3(nt2, 2), dim3(256), s, m, b);
-  if (e == hipSuccess) e = launch_k(k_rpa_route, dim3(grid_for(m.n, 256)), dim3(256), s, m, b);
+  const int64_t quads = (m.n + 3) / 4;
+  if (e == hipSuccess) e = launch_k(k_rpa_stream, dim3(grid_for(quads, 256)), dim3(256), s, m, b);
+  if (e == hipSuccess) e = launch_k(k_rpa_route, dim3(grid_for(quads, 256)), dim3(256), s, m, b);
   return e;
 }
 
