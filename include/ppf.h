@@ -63,7 +63,6 @@ enum { PPF_RESAMPLE_SYSTEMATIC = 0, PPF_RESAMPLE_RNA = 1, PPF_RESAMPLE_RPA = 2,
 /* DLB schedules of Section 4: Greedy (Alg. 2), Sorted Greedy (Alg. 3),
  * Largest Gradient (Alg. 4). */
 enum { PPF_DLB_GS = 0, PPF_DLB_SGS = 1, PPF_DLB_LGS = 2 };
-#define PPF_DLB_MAX_SORTED 4096 /* groups ppf_dlb_schedule accepts */
 enum { PPF_OBS_SPOT = 0, PPF_OBS_LINEAR_GAUSSIAN = 1 };
 enum { PPF_INIT_UNIFORM = 0, PPF_INIT_GAUSSIAN = 1, PPF_INIT_STRATIFIED = 2 };
 
@@ -478,8 +477,13 @@ int ppf_resample_rna(const float* logw_dev, int64_t n, int32_t group, int32_t mo
  *                two (Alg. 4, recording the count before zeroing it).
  * sched_dev: 3 int32 per entry (sender group, receiver group, particles),
  * at most cap entries; *n_entries_dev (int32, device) receives their number,
- * or -1 when cap is too small. EINVAL: G < 1, n < 0, an unknown kind, or G
- * above PPF_DLB_MAX_SORTED (all kinds run in one workgroup).
+ * or -1 when cap is too small (then no entry is written). Any number of
+ * groups: the lists are radix-sorted and the entries found in parallel (the
+ * greedy walk pairs each sender with the receivers whose deficit intervals
+ * overlap its surplus interval, both laid end to end in list order). The
+ * call allocates its device scratch on the stream (hipMallocAsync, about
+ * 80 bytes per group) and frees it there after its launches; async.
+ * EINVAL: G < 1, n < 0 or an unknown kind; ENOMEM: no scratch.
  */
 int ppf_dlb_schedule(int32_t kind, const int32_t* counts_dev, int32_t G, int32_t n,
                      int32_t* sched_dev, int32_t cap, int32_t* n_entries_dev, void* hip_stream);

@@ -26,7 +26,6 @@ PPF_OK, PPF_EINVAL, PPF_ENOMEM, PPF_EDEVICE, PPF_ESTATE, PPF_ENUMERIC, PPF_ENOTI
     0, -1, -2, -3, -4, -5, -6)
 RESAMPLE_SYSTEMATIC, RESAMPLE_RNA, RESAMPLE_RPA, RESAMPLE_ARNA = 0, 1, 2, 3
 DLB_GS, DLB_SGS, DLB_LGS = 0, 1, 2
-DLB_MAX_SORTED = 4096
 STATIC_MAX_N = 1 << 22  # weights the allocation-free resampler takes
 OBS_SPOT, OBS_LINEAR_GAUSSIAN = 0, 1
 INIT_UNIFORM, INIT_GAUSSIAN, INIT_STRATIFIED = 0, 1, 2

@@ -799,12 +799,16 @@ int ppf_philox4x32_10(uint64_t seed, const uint32_t* ctr_dev, uint32_t* out_dev,
 
 int ppf_dlb_schedule(int32_t kind, const int32_t* counts_dev, int32_t G, int32_t n,
                      int32_t* sched_dev, int32_t cap, int32_t* n_entries_dev, void* hip_stream) {
-  if (kind < PPF_DLB_GS || kind > PPF_DLB_LGS || G < 1 || G > PPF_DLB_MAX_SORTED || n < 0)
-    return PPF_EINVAL;
+  if (kind < PPF_DLB_GS || kind > PPF_DLB_LGS || G < 1 || n < 0) return PPF_EINVAL;
   if (!counts_dev || !n_entries_dev || cap < 0 || (cap > 0 && !sched_dev)) return PPF_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // stream-ordered scratch: freed on the stream after the schedule's launches
+  void* scratch = nullptr;
+  if (hipMallocAsync(&scratch, ppf::dlb_scratch_bytes(G), s) != hipSuccess) return PPF_ENOMEM;
   const hipError_t e = ppf::launch_dlb_schedule(kind, counts_dev, G, n, sched_dev, cap,
-                                                n_entries_dev, static_cast<hipStream_t>(hip_stream));
-  return e == hipSuccess ? PPF_OK : PPF_EDEVICE;
+                                                n_entries_dev, scratch, s);
+  const hipError_t ef = hipFreeAsync(scratch, s);
+  return e == hipSuccess && ef == hipSuccess ? PPF_OK : PPF_EDEVICE;
 }
 
 int ppf_resample_scratch_bytes(int64_t n, size_t* bytes) {

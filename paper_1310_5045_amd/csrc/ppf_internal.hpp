@@ -57,7 +57,6 @@ constexpr int kFillGridBatch = 2048;  // waves of a batched fill, over all track
 // Batched steps run every patch size up to this one in a single launch (the
 // sizes that fit five waves per SIMD); wider patches launch per size.
 constexpr int kFusedMaxP = 13;
-constexpr int kDlbMaxSorted = 4096;  // groups of a standalone DLB schedule (LDS sort)
 constexpr int kSortTile = 1024;      // pairs per tile of the radix sort and list scans
 // The allocation-free standalone resampler keeps its scratch in a device
 // array of this many bytes, one per device for the life of the process.
@@ -258,9 +257,12 @@ hipError_t launch_arna(const Model& m, const Buffers& b, hipStream_t s);
 
 // RPA: the balancing plan and the routed ancestors of one filter.
 hipError_t launch_rpa(const Model& m, const Buffers& b, hipStream_t s);
-// DLB schedule of G groups' counts (kind 0 GS, 1 SGS, 2 LGS; G <= kDlbMaxSorted).
+// DLB schedule of G groups' counts (kind 0 GS, 1 SGS, 2 LGS) with
+// dlb_scratch_bytes(G) bytes of device scratch (256-byte aligned).
+size_t dlb_scratch_bytes(int32_t G);
 hipError_t launch_dlb_schedule(int32_t kind, const int32_t* counts, int32_t G, int32_t n,
-                               int32_t* sched, int32_t cap, int32_t* n_entries, hipStream_t s);
+                               int32_t* sched, int32_t cap, int32_t* n_entries, void* scratch,
+                               hipStream_t s);
 
 // Batched launches over independent filters: ms and bs are device arrays of
 // the tracks' models and buffers, items the device list of work items.

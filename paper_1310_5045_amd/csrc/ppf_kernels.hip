@@ -2064,32 +2064,6 @@ __device__ __forceinline__ int64_t lower_bound_i32(const int32_t* a, int64_t n, 
   return lo;
 }
 
-// Ascending bitonic sort of key[0..size) in LDS (size a power of two) by the
-// whole workgroup.
-__device__ __forceinline__ void bitonic_sort(uint64_t* key, int size) {
-  for (int k = 2; k <= size; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < size; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const bool up = (i & k) == 0;
-          const uint64_t a = key[i], c = key[ixj];
-          if ((a > c) == up) {
-            key[i] = c;
-            key[ixj] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Key of a sort by value descending, ties by group ascending (~0: absent).
-__device__ __forceinline__ uint64_t desc_key(int64_t value, int64_t g) {
-  return value > 0 ? (((uint64_t)(0xffffffffu - (uint32_t)value) << 32) | (uint64_t)g) : ~0ull;
-}
-
 __device__ __forceinline__ int64_t rpa_count(const Buffers& b, int64_t g) {
   return b.rfirst[g + 1] - b.rfirst[g];
 }
@@ -2394,72 +2368,177 @@ __global__ __launch_bounds__(256) void k_rpa_route(Model m, Buffers b) {
   }
 }
 
-// The DLB schedules of Section 4 for G <= kDlbMaxSorted groups, one
-// workgroup: the lists (sorted for SGS and LGS by a bitonic sort in LDS),
-// then the matching by one thread in list order.
-__global__ __launch_bounds__(256) void k_dlb_schedule(int32_t kind, const int32_t* counts,
-                                                      int32_t G, int32_t n, int32_t* sched,
-                                                      int32_t cap, int32_t* n_entries) {
-  __shared__ uint64_t key[kDlbMaxSorted];
-  __shared__ int32_t S[kDlbMaxSorted];
-  __shared__ int32_t R[kDlbMaxSorted];
-  __shared__ int32_t nsr[2];
-  const int t = threadIdx.x;
-  int size = 1;
-  while (size < G) size <<= 1;
-  for (int side = 0; side < 2; ++side) {
-    for (int i = t; i < size; i += 256) {
-      int64_t v = 0;
-      if (i < G) v = side == 0 ? (int64_t)counts[i] - n : (int64_t)n - counts[i];
-      // GS keeps group order: the key is the group index alone
-      key[i] = v > 0 ? (kind == 0 ? (uint64_t)i : desc_key(v, i)) : ~0ull;
-    }
-    __syncthreads();
-    bitonic_sort(key, size);
-    for (int i = t; i < size; i += 256) {
-      if (key[i] != ~0ull) (side == 0 ? S : R)[i] = (int32_t)(key[i] & 0xffffffffu);
-      if (key[i] != ~0ull && (i + 1 == size || key[i + 1] == ~0ull)) nsr[side] = i + 1;
-      if (i == 0 && key[0] == ~0ull) nsr[side] = 0;
-    }
-    __syncthreads();
+// ------------------------------------------------ standalone DLB schedules
+// The DLB schedules of Section 4 for any number of groups. The lists: the
+// 2G entries (senders, then receivers) radix-sorted by key, where GS keys a
+// present entry by its group and SGS / LGS by the complement of its value
+// (descending, ties in group order); absent entries sort last in their side.
+__global__ __launch_bounds__(256) void k_dlb_keys(int32_t kind, const int32_t* __restrict__ counts,
+                                                  int32_t G, int32_t n, uint32_t* __restrict__ key,
+                                                  int32_t* __restrict__ val) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= 2 * (int64_t)G) return;
+  const int side = j >= G ? 1 : 0;
+  const int64_t g = j - side * (int64_t)G;
+  const int64_t v = side == 0 ? (int64_t)counts[g] - n : (int64_t)n - counts[g];
+  // values and groups are below 2^31
+  const uint32_t low = v <= 0 ? 0x7fffffffu
+                              : (kind == 0 ? (uint32_t)g : 0x7fffffffu - (uint32_t)min(v, (int64_t)0x7ffffffe));
+  key[j] = ((uint32_t)side << 31) | low;
+  val[j] = (int32_t)g;
+}
+
+__global__ __launch_bounds__(64) void k_zero_i32(int32_t* __restrict__ p, int32_t count) {
+  if ((int32_t)threadIdx.x < count) p[threadIdx.x] = 0;
+}
+
+// The surplus (side 0) or deficit (side 1) at each list position, 0 past
+// the present entries.
+__global__ __launch_bounds__(256) void k_dlb_values(const int32_t* __restrict__ counts, int32_t G,
+                                                    int32_t n, const int32_t* __restrict__ val,
+                                                    uint64_t* __restrict__ vals) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= 2 * (int64_t)G) return;
+  const int side = j >= G ? 1 : 0;
+  const int64_t c = counts[val[j]];
+  const int64_t v = side == 0 ? c - n : n - c;
+  vals[j] = v > 0 ? (uint64_t)v : 0;
+}
+
+// Exclusive prefix sums over `len` uint64 values (tiles of kSortTile: the
+// tiles' sums, their prefixes in one workgroup, then each value's prefix);
+// out[len] receives the total.
+__global__ __launch_bounds__(256) void k_scan_tiles(const uint64_t* __restrict__ in, int64_t len,
+                                                    uint64_t* __restrict__ tsum) {
+  __shared__ uint64_t sh[4];
+  const int64_t k0 = (int64_t)blockIdx.x * kSortTile + 4 * threadIdx.x;
+  uint64_t s = 0;
+  for (int i = 0; i < 4; ++i)
+    if (k0 + i < len) s += in[k0 + i];
+  uint64_t tot;
+  block_excl_sum(s, sh, &tot);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_top(uint64_t* __restrict__ tsum, int64_t ntiles,
+                                                  uint64_t* __restrict__ total) {
+  __shared__ uint64_t sh[4];
+  uint64_t carry = 0;
+  for (int64_t i0 = 0; i0 < ntiles; i0 += 256) {
+    const int64_t i = i0 + threadIdx.x;
+    const uint64_t v = i < ntiles ? tsum[i] : 0;
+    uint64_t t;
+    const uint64_t ex = block_excl_sum(v, sh, &t);
+    if (i < ntiles) tsum[i] = carry + ex;
+    carry += t;
   }
-  if (t != 0) return;
-  const int ns = nsr[0], nr = nsr[1];
-  int32_t m = 0;
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint64_t* __restrict__ in, int64_t len,
+                                                    const uint64_t* __restrict__ tsum,
+                                                    uint64_t* __restrict__ out) {
+  __shared__ uint64_t sh[4];
+  const int64_t k0 = (int64_t)blockIdx.x * kSortTile + 4 * threadIdx.x;
+  uint64_t v[4], s = 0;
+  for (int i = 0; i < 4; ++i) {
+    v[i] = k0 + i < len ? in[k0 + i] : 0;
+    s += v[i];
+  }
+  uint64_t tot;
+  uint64_t p = block_excl_sum(s, sh, &tot) + tsum[blockIdx.x];
+  for (int i = 0; i < 4; ++i) {
+    if (k0 + i < len) out[k0 + i] = p;
+    p += v[i];
+  }
+}
+
+// Number of the leading positive values of one side (its present entries).
+__global__ __launch_bounds__(256) void k_dlb_present(const uint64_t* __restrict__ vals, int32_t G,
+                                                     int32_t* __restrict__ nsr) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= 2 * (int64_t)G) return;
+  const int side = j >= G ? 1 : 0;
+  const int64_t k = j - side * (int64_t)G;
+  // present entries come first: the last one marks the count
+  if (vals[j] > 0 && (k + 1 == G || vals[j + 1] == 0)) nsr[side] = (int32_t)(k + 1);
+}
+
+// GS / SGS: the greedy walk of the two lists (Alg. 2, with filled receivers
+// skipped) pairs sender i with every receiver whose deficit interval
+// [cd_j, cd_j + de_j) overlaps its surplus interval [cs_i, cs_i + su_i),
+// both laid end to end in list order and cut at T = min(total surplus,
+// total deficit). Per sender: its first receiver and its number of entries.
+__global__ __launch_bounds__(256) void k_dlb_count(const uint64_t* __restrict__ cs,
+                                                   const uint64_t* __restrict__ cd,
+                                                   const int32_t* __restrict__ nsr, int32_t G,
+                                                   int32_t* __restrict__ jlo,
+                                                   uint64_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= G) return;
+  const int64_t ns = nsr[0], nr = nsr[1];
+  const uint64_t T = min(cs[ns], cd[nr]);
+  cnt[i] = 0;
+  if (i >= ns || cs[i] >= T) return;
+  const uint64_t* d = cd;
+  // last j with d[j] <= cs[i], then last j with d[j] < min(cs[i + 1], T)
+  int64_t lo = 0, hi = nr - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (d[mid] <= cs[i]) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint64_t end = min(cs[i + 1], T);
+  int64_t lo2 = lo, hi2 = nr - 1;
+  while (lo2 < hi2) {
+    const int64_t mid = (lo2 + hi2 + 1) >> 1;
+    if (d[mid] < end) lo2 = mid;
+    else hi2 = mid - 1;
+  }
+  jlo[i] = (int32_t)lo;
+  cnt[i] = (uint64_t)(lo2 - lo + 1);
+}
+
+// Entry e: GS / SGS its sender (the last with entry prefix <= e) and
+// receiver, the overlap of their intervals; LGS the e-th sender with the e-th
+// receiver and the smaller of their values (Alg. 4, the count recorded before
+// it is zeroed). Thread 0 writes the number of entries, or -1 past cap.
+__global__ __launch_bounds__(256) void k_dlb_entries(int32_t kind, const int32_t* __restrict__ val,
+                                                     const uint64_t* __restrict__ vals,
+                                                     const uint64_t* __restrict__ cs,
+                                                     const uint64_t* __restrict__ cd,
+                                                     const int32_t* __restrict__ nsr, int32_t G,
+                                                     const int32_t* __restrict__ jlo,
+                                                     const uint64_t* __restrict__ E,
+                                                     int32_t* __restrict__ sched, int32_t cap,
+                                                     int32_t* __restrict__ n_entries) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t ns = nsr[0], nr = nsr[1];
+  const int64_t M = kind == 2 ? min(ns, nr) : (int64_t)E[G];
+  if (e == 0) *n_entries = M <= cap ? (int32_t)M : -1;
+  if (e >= M || M > cap) return;  // nothing is written past the capacity
+  int64_t i, j;
+  uint64_t amount;
   if (kind == 2) {
-    for (int i = 0; i < min(ns, nr) && m >= 0; ++i) {
-      const int64_t su = (int64_t)counts[S[i]] - n, de = (int64_t)n - counts[R[i]];
-      if (m >= cap) {
-        m = -1;
-        break;
-      }
-      sched[3 * m] = S[i];
-      sched[3 * m + 1] = R[i];
-      sched[3 * m + 2] = (int32_t)min(su, de);
-      ++m;
-    }
+    i = e;
+    j = e;
+    amount = min(vals[i], vals[G + j]);
   } else {
-    int j = 0;
-    int64_t dj = nr > 0 ? (int64_t)n - counts[R[0]] : 0;  // remaining deficit of R[j]
-    for (int i = 0; i < ns && m >= 0; ++i) {
-      int64_t si = (int64_t)counts[S[i]] - n;
-      while (si > 0 && j < nr) {
-        const int64_t mv = min(si, dj);
-        if (m >= cap) {
-          m = -1;
-          break;
-        }
-        sched[3 * m] = S[i];
-        sched[3 * m + 1] = R[j];
-        sched[3 * m + 2] = (int32_t)mv;
-        ++m;
-        si -= mv;
-        dj -= mv;
-        if (dj == 0 && ++j < nr) dj = (int64_t)n - counts[R[j]];  // the next receiver
-      }
+    int64_t lo = 0, hi = ns - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (E[mid] <= (uint64_t)e) lo = mid;
+      else hi = mid - 1;
     }
+    i = lo;
+    j = jlo[i] + (e - (int64_t)E[i]);
+    const uint64_t* d = cd;
+    const uint64_t T = min(cs[ns], d[nr]);
+    amount = min(min(cs[i + 1], d[j + 1]), T) - max(cs[i], d[j]);
   }
-  *n_entries = m;
+  sched[3 * e] = val[i];
+  sched[3 * e + 1] = val[G + j];
+  sched[3 * e + 2] = (int32_t)amount;
 }
 
 // --------------------------------------------------------------- batches
@@ -2928,10 +3007,113 @@ hipError_t launch_rpa(const Model& m, const Buffers& b, hipStream_t s) {
   return e;
 }
 
+namespace {
+// Scratch of a standalone DLB schedule of G groups, carved from `base` (the
+// pointers stay null when it is null); returns its size in bytes.
+struct DlbScratch {
+  uint32_t* key0;
+  uint32_t* key1;
+  int32_t* val0;
+  int32_t* val1;
+  uint32_t* hist;
+  uint32_t* row;
+  uint64_t* vals;  // list values, 2G
+  uint64_t* cs;    // senders' prefixes, G + 1
+  uint64_t* cd;    // receivers' prefixes, G + 1
+  uint64_t* cnt;   // entries per sender, G
+  uint64_t* E;     // their prefixes, G + 1
+  int32_t* jlo;    // each sender's first receiver, G
+  uint64_t* tsum;  // scan tiles
+  int32_t* nsr;    // present entries per side, 2
+};
+
+size_t dlb_carve(int32_t G, char* base, DlbScratch* d) {
+  const size_t L = 2 * (size_t)G, nt = (L + kSortTile - 1) / kSortTile;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return q;
+  };
+  d->key0 = reinterpret_cast<uint32_t*>(take(L * 4));
+  d->key1 = reinterpret_cast<uint32_t*>(take(L * 4));
+  d->val0 = reinterpret_cast<int32_t*>(take(L * 4));
+  d->val1 = reinterpret_cast<int32_t*>(take(L * 4));
+  d->hist = reinterpret_cast<uint32_t*>(take(256 * nt * 4));
+  d->row = reinterpret_cast<uint32_t*>(take(256 * 4));
+  d->vals = reinterpret_cast<uint64_t*>(take(L * 8));
+  d->cs = reinterpret_cast<uint64_t*>(take(((size_t)G + 1) * 8));
+  d->cd = reinterpret_cast<uint64_t*>(take(((size_t)G + 1) * 8));
+  d->cnt = reinterpret_cast<uint64_t*>(take((size_t)G * 8));
+  d->E = reinterpret_cast<uint64_t*>(take(((size_t)G + 1) * 8));
+  d->jlo = reinterpret_cast<int32_t*>(take((size_t)G * 4));
+  d->tsum = reinterpret_cast<uint64_t*>(take((nt + 1) * 8));
+  d->nsr = reinterpret_cast<int32_t*>(take(2 * 4));
+  return off;
+}
+
+// Exclusive prefix sums of len values into out[0..len), the total into
+// out[len] (tsum: scan tiles).
+hipError_t scan_u64(const uint64_t* in, int64_t len, uint64_t* out, uint64_t* tsum, hipStream_t s) {
+  const unsigned nt = (unsigned)((len + kSortTile - 1) / kSortTile);
+  hipError_t e = launch_k(k_scan_tiles, dim3(nt), dim3(256), s, in, len, tsum);
+  if (e == hipSuccess) e = launch_k(k_scan_top, dim3(1), dim3(256), s, tsum, (int64_t)nt, out + len);
+  if (e == hipSuccess)
+    e = launch_k(k_scan_apply, dim3(nt), dim3(256), s, in, len, (const uint64_t*)tsum, out);
+  return e;
+}
+}  // namespace
+
+size_t dlb_scratch_bytes(int32_t G) {
+  DlbScratch d;
+  return dlb_carve(G, nullptr, &d);
+}
+
 hipError_t launch_dlb_schedule(int32_t kind, const int32_t* counts, int32_t G, int32_t n,
-                               int32_t* sched, int32_t cap, int32_t* n_entries, hipStream_t s) {
-  return launch_k(k_dlb_schedule, dim3(1), dim3(256), s, kind, counts, G, n, sched, cap,
-                  n_entries);
+                               int32_t* sched, int32_t cap, int32_t* n_entries, void* scratch,
+                               hipStream_t s) {
+  const int64_t L = 2 * (int64_t)G;
+  const int32_t nt = (int32_t)((L + kSortTile - 1) / kSortTile);
+  DlbScratch d;
+  dlb_carve(G, static_cast<char*>(scratch), &d);
+  const Ctrl* nogate = nullptr;
+  hipError_t e = launch_k(k_dlb_keys, dim3(grid_for(L, 256)), dim3(256), s, kind, counts, G, n,
+                          d.key0, d.val0);
+  for (int pass = 0; pass < 4 && e == hipSuccess; ++pass) {
+    // ping -> pong on even passes, back on odd ones: the lists land in ping
+    const uint32_t* kin = pass & 1 ? d.key1 : d.key0;
+    const int32_t* vin = pass & 1 ? d.val1 : d.val0;
+    uint32_t* kout = pass & 1 ? d.key0 : d.key1;
+    int32_t* vout = pass & 1 ? d.val0 : d.val1;
+    e = launch_k(k_radix_hist, dim3((unsigned)nt), dim3(256), s, kin, L, 8 * pass, d.hist, nt,
+                 nogate);
+    if (e == hipSuccess)
+      e = launch_k(k_radix_rowscan, dim3(256), dim3(256), s, d.hist, nt, d.row, nogate);
+    if (e == hipSuccess)
+      e = launch_k(k_radix_scatter, dim3((unsigned)nt), dim3(256), s, kin, vin, kout, vout, L,
+                   8 * pass, (const uint32_t*)d.hist, (const uint32_t*)d.row, nt, nogate);
+  }
+  if (e == hipSuccess)
+    e = launch_k(k_dlb_values, dim3(grid_for(L, 256)), dim3(256), s, counts, G, n,
+                 (const int32_t*)d.val0, d.vals);
+  if (e == hipSuccess) e = launch_k(k_zero_i32, dim3(1), dim3(64), s, d.nsr, 2);
+  if (e == hipSuccess)
+    e = launch_k(k_dlb_present, dim3(grid_for(L, 256)), dim3(256), s, (const uint64_t*)d.vals, G,
+                 d.nsr);
+  if (e == hipSuccess) e = scan_u64(d.vals, G, d.cs, d.tsum, s);
+  if (e == hipSuccess) e = scan_u64(d.vals + G, G, d.cd, d.tsum, s);
+  if (kind != 2) {
+    if (e == hipSuccess)
+      e = launch_k(k_dlb_count, dim3(grid_for(G, 256)), dim3(256), s, (const uint64_t*)d.cs,
+                   (const uint64_t*)d.cd, (const int32_t*)d.nsr, G, d.jlo, d.cnt);
+    if (e == hipSuccess) e = scan_u64(d.cnt, G, d.E, d.tsum, s);
+  }
+  if (e == hipSuccess)
+    e = launch_k(k_dlb_entries, dim3(grid_for(L, 256)), dim3(256), s, kind,
+                 (const int32_t*)d.val0, (const uint64_t*)d.vals, (const uint64_t*)d.cs,
+                 (const uint64_t*)d.cd, (const int32_t*)d.nsr, G, (const int32_t*)d.jlo,
+                 (const uint64_t*)d.E, sched, cap, n_entries);
+  return e;
 }
 
 hipError_t launch_merge(const Model& m, const Buffers& b, int standalone, double u_given,

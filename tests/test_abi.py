@@ -106,7 +106,6 @@ def test_standalone_argument_checks():
     dlb = L.ppf_dlb_schedule
     assert dlb(3, v, 10, 4, v, 10, v, None) == ppf.PPF_EINVAL      # unknown kind
     assert dlb(0, v, 0, 4, v, 10, v, None) == ppf.PPF_EINVAL       # no groups
-    assert dlb(1, v, 4097, 4, v, 10, v, None) == ppf.PPF_EINVAL    # above the sorted limit
     assert dlb(0, None, 10, 4, v, 10, v, None) == ppf.PPF_EINVAL   # null counts
     assert dlb(0, v, 10, -1, v, 10, v, None) == ppf.PPF_EINVAL     # negative n
     assert dlb(0, v, 10, 4, None, 10, v, None) == ppf.PPF_EINVAL   # null schedule

@@ -51,6 +51,37 @@ def test_dlb_schedules_match_oracle(ppf, G, n):
             assert np.array_equal(got, want), (G, n, trial, kind)
 
 
+@pytest.mark.parametrize("G,n", [(5000, 8), (152_000, 250)])
+def test_dlb_schedules_many_groups_match_oracle(ppf, G, n):
+    """Beyond one tile of the radix sort and of the scans: a systematic
+    allocation at 152,000 groups (the 38M workload with groups of 250), and
+    unbalanced counts."""
+    rng = np.random.default_rng(G)
+    w = rng.gamma(0.05, 1.0, G * n)
+    w /= w.sum()
+    balanced = oracle.rpa_counts(oracle.resample_systematic(w, float(rng.uniform())), n)
+    for counts in (balanced, rng.integers(0, 3 * n, G).astype(np.int32)):
+        ct = torch.from_numpy(counts.astype(np.int32)).cuda()
+        for kind in (ppf.DLB_GS, ppf.DLB_SGS, ppf.DLB_LGS):
+            got = ppf.dlb_schedule(kind, ct, n).cpu().numpy()
+            want = oracle.dlb_schedule(kind, counts, n)
+            assert np.array_equal(got, want), (G, n, kind, got.shape, want.shape)
+
+
+def test_dlb_schedule_capacity(ppf):
+    """Too small a capacity: the count reads -1 and no entry is written."""
+    import ctypes
+    counts = torch.tensor([9, 3, 7, 1, 4, 6, 2], dtype=torch.int32).cuda()
+    sched = torch.full((3, 3), -7, dtype=torch.int32).cuda()
+    m = torch.zeros(1, dtype=torch.int32).cuda()
+    s = torch.cuda.current_stream()
+    rc = ppf.lib().ppf_dlb_schedule(ppf.DLB_GS, ctypes.c_void_p(counts.data_ptr()), 7, 4,
+                                    ctypes.c_void_p(sched.data_ptr()), 3,
+                                    ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(s.cuda_stream))
+    assert rc == 0
+    assert int(m.cpu()) == -1 and bool(torch.all(sched == -7))
+
+
 @pytest.mark.parametrize("dlb", [0, 1])
 @pytest.mark.parametrize("n,group", [(4096, 256), (8192, 64), (3000, 1000)])
 def test_rpa_filter(ppf, dlb, n, group):
