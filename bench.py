@@ -174,8 +174,11 @@ WORKLOADS = {
                                        thr=float("inf"), scheme=(2, 250, 1)),
     "sir_128x128_n4096_p9": dict(W=128, H=128, T=10, n=4096, s=1.5, P=9, thr=float("inf")),
     # forward pass with the derivatives of log p^ in (s, b, sigma, q, I0)
+    # (the cloud starts within 5 px of the spot: at I = 25 and s = 1.7 a cloud
+    # spread over the frame locks onto empty patches, where low-intensity
+    # particles explain the pixels as well as the spot's own do)
     "grad_512x512_n262k_p11": dict(W=512, H=512, T=30, n=1 << 18, s=1.7, P=11, thr=float("inf"),
-                                   I=25.0, grad=1, box=(128, 384, 128, 384)),
+                                   I=25.0, grad=1, init_radius=5.0),
     "grad_1024x1024_n38m_p13": dict(W=1024, H=1024, T=20, n=38_000_000, s=2.0, P=13,
                                     thr=float("inf"), grad=1),
     # 256 spots, one independent filter each, stepped as one batch
@@ -798,6 +801,11 @@ def run(args):
     mv = synth.render_movie(w["W"], w["H"], T, intensity=w.get("I", 30.0), sigma=w["s"],
                             background=10.0, noise_sd=3.0, seed=1,
                             start_box=None if box is None else tuple(float(v) for v in box))
+    if w.get("init_radius"):
+        # the initial cloud's box around the spot's first position
+        x0, y0 = mv.truth[0, 0]
+        r = w["init_radius"]
+        w = dict(w, box=(x0 - r, x0 + r, y0 - r, y0 + r))
     torch.cuda.set_device(0)
     frames = torch.from_numpy(mv.frames).cuda()
     if args.copy_probe_mib:
