@@ -251,11 +251,14 @@ size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) 
     bb.rsidx = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * Gr));
     bb.rstream = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
   }
-  if (p->resample == PPF_RESAMPLE_ARNA) {
+  if (p->resample == PPF_RESAMPLE_RNA || p->resample == PPF_RESAMPLE_ARNA) {
+    // the local resampling of every group and its share W_g, read by the
+    // exchange launch
     bb.aloc = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
     bb.Wg = reinterpret_cast<double*>(take(sizeof(double) * G));
-    bb.lwt = reinterpret_cast<double*>(take(sizeof(double) * G));
   }
+  if (p->resample == PPF_RESAMPLE_ARNA)
+    bb.lwt = reinterpret_cast<double*>(take(sizeof(double) * G));
   if (p->grad) {
     bb.T0 = reinterpret_cast<float*>(take(sizeof(float) * ppf::kNTan * n));
     bb.T1 = reinterpret_cast<float*>(take(sizeof(float) * ppf::kNTan * n));
@@ -566,7 +569,7 @@ int enqueue_step(ppf_handle h, const float* obs_dev) {
   if (rc) return rc;
   const ppf::WeightSrc w = h->filter_weights();
   if (h->p.resample == PPF_RESAMPLE_RNA)
-    return h->run(kKRna, [&] { return ppf::launch_rna(h->m, h->b, w, nullptr, h->stream); });
+    return h->run(kKRna, [&] { return ppf::launch_rna_groups(h->m, h->b, h->stream); });
   if (h->p.resample == PPF_RESAMPLE_ARNA)
     return h->run(kKRna, [&] { return ppf::launch_arna(h->m, h->b, h->stream); });
   rc = h->run(kKAnc, [&] { return ppf::launch_anc(h->m, h->b, w, h->stream); });

@@ -253,6 +253,9 @@ hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int6
 hipError_t static_scratch(void** ptr, size_t* bytes);
 
 // ARNA: local resampling per group, then the exchange along the ring.
+// RNA of the filter's own weights in two launches: every group's local
+// resampling, then the exchange with group g-1.
+hipError_t launch_rna_groups(const Model& m, const Buffers& b, hipStream_t s);
 hipError_t launch_arna(const Model& m, const Buffers& b, hipStream_t s);
 
 // RPA: the balancing plan and the routed ancestors of one filter.

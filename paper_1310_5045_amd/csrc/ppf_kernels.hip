@@ -1988,7 +1988,10 @@ __device__ int64_t ring_pred(const Model& m, uint32_t key, int64_t G, int64_t g)
 
 // One workgroup per group: W_g, the local systematic resampling (global
 // indices into aloc), and the tracking count.
-__device__ __forceinline__ void arna_local_body(const Model& m, const Buffers& b, int64_t g) {
+// The local resampling of group g into aloc and its share W_g (RNA and
+// ARNA; ARNA also counts the tracking groups).
+template <bool ARNA>
+__device__ __forceinline__ void group_local_body(const Model& m, const Buffers& b, int64_t g) {
   __shared__ uint64_t C[kMaxGroup];
   __shared__ double dsum[4];
   __shared__ uint64_t wsum[4];
@@ -2006,7 +2009,7 @@ __device__ __forceinline__ void arna_local_body(const Model& m, const Buffers& b
     b.aloc[g * ng + l] = (int32_t)(g * ng + local_slot(C, ng, m.inv_group, W, u, l));
   if (threadIdx.x == 0) {
     b.Wg[g] = W;
-    if (W >= m.arna_share) atomicAdd(&c->arna_tracking, 1);
+    if (ARNA && W >= m.arna_share) atomicAdd(&c->arna_tracking, 1);
   }
 }
 
@@ -2034,7 +2037,28 @@ __device__ __forceinline__ void arna_exchange_body(const Model& m, const Buffers
 }
 
 __global__ __launch_bounds__(256) void k_arna_local(Model m, Buffers b) {
-  arna_local_body(m, b, blockIdx.x);
+  group_local_body<true>(m, b, blockIdx.x);
+}
+
+// RNA (Section 3) in two launches: the groups' local resampling
+// (k_rna_local), then each group's last `moved` slots from group g-1's
+// (k_rna_exchange); the same ancestors and weights as rna_body, which
+// recomputes group g-1's local resampling in every workgroup instead.
+__global__ __launch_bounds__(256) void k_rna_local(Model m, Buffers b) {
+  group_local_body<false>(m, b, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_rna_exchange(Model m, Buffers b) {
+  const Ctrl* c = b.ctrl;
+  if (!c->do_resample) return;
+  const int64_t g = blockIdx.x, G = m.G;
+  const int ng = m.group;
+  const int64_t prev = (g + G - 1) % G;
+  for (int l = threadIdx.x; l < ng; l += 256) {
+    const int64_t src = (l >= ng - m.moved) ? prev : g;
+    b.anc[g * ng + l] = b.aloc[src * ng + l];
+  }
+  if (threadIdx.x == 0) b.lwg[g] = log(b.Wg[g] / (double)ng);
 }
 
 __global__ __launch_bounds__(256) void k_arna_exchange(Model m, Buffers b) {
@@ -2966,6 +2990,12 @@ hipError_t launch_rna_batch(const Model* ms, const Buffers* bs, const BatchItem*
                             int64_t n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   return launch_k(k_rna_batch, dim3((unsigned)n_items), dim3(256), s, ms, bs, items);
+}
+
+hipError_t launch_rna_groups(const Model& m, const Buffers& b, hipStream_t s) {
+  const hipError_t e = launch_k(k_rna_local, dim3((unsigned)m.G), dim3(256), s, m, b);
+  if (e != hipSuccess) return e;
+  return launch_k(k_rna_exchange, dim3((unsigned)m.G), dim3(256), s, m, b);
 }
 
 hipError_t launch_arna(const Model& m, const Buffers& b, hipStream_t s) {
