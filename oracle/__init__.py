@@ -75,6 +75,12 @@ def lib():
         L.orc_rna_uniform.argtypes = [P(_Model), i64, i64]
         L.orc_rna_uniform.restype = d
         L.orc_init.argtypes = [P(_Model), vp, vp]
+        L.orc_init.restype = ctypes.c_int
+        L.orc_init_indexed.restype = ctypes.c_int
+        L.orc_zorder_key.argtypes = [u32, u32]
+        L.orc_zorder_key.restype = u32
+        L.orc_zorder_perm.argtypes = [P(_Model), i64, vp]
+        L.orc_zorder_perm.restype = ctypes.c_int
         L.orc_propagate.argtypes = [P(_Model), i64, vp, vp, vp]
         L.orc_init_indexed.argtypes = [P(_Model), i64, vp, vp]
         L.orc_propagate_indexed.argtypes = [P(_Model), i64, vp, vp, vp]
@@ -131,7 +137,8 @@ class Model:
     sigma: float = 3.0            # sigma_xi
     patch: int = 0                # 0: 2 floor(3 s) + 1
     q: Sequence[float] = (0.5, 0.5, 0.1, 0.1, 1.0)
-    init_kind: int = 0            # 0 uniform [a, b), 1 Gaussian N(a, b^2), 2 stratified
+    init_kind: int = 0            # 0 uniform [a, b), 1 Gaussian N(a, b^2), 2 stratified,
+                                  # 3 uniform in Z order
     init_a: Sequence[float] = (0.0, 0.0, -1.0, -1.0, 15.0)
     init_b: Sequence[float] = (128.0, 128.0, 1.0, 1.0, 45.0)
     lg_r: Sequence[float] = (1.0, 1.0, 1.0)
@@ -236,8 +243,23 @@ def init(m: Model):
     c = m.c()
     x = np.empty(5 * m.n)
     lw = np.empty(m.n)
-    lib().orc_init(ctypes.byref(c), _ptr(x), _ptr(lw))
+    if lib().orc_init(ctypes.byref(c), _ptr(x), _ptr(lw)) != 0:
+        raise MemoryError("orc_init")
     return x.reshape(5, m.n), lw
+
+
+def zorder_key(wx: int, wy: int) -> int:
+    """Init kind 3's key: the Morton code of the top 16 bits of two words."""
+    return int(lib().orc_zorder_key(wx, wy))
+
+
+def zorder_perm(m: Model, n: int) -> np.ndarray:
+    """Init kind 3: the draw index of the particle at each position."""
+    c = m.c()
+    out = np.empty(n, dtype=np.int64)
+    if lib().orc_zorder_perm(ctypes.byref(c), n, _ptr(out)) != 0:
+        raise MemoryError("orc_zorder_perm")
+    return out
 
 
 def propagate(m: Model, k: int, x_prev: np.ndarray, parent: Optional[np.ndarray] = None, c=None):
@@ -256,7 +278,8 @@ def init_indexed(m: Model, n_total: int, index: np.ndarray) -> np.ndarray:
     idx = np.ascontiguousarray(index, dtype=np.int64)
     assert idx.size == m.n
     x = np.empty((5, m.n))
-    lib().orc_init_indexed(ctypes.byref(c), n_total, _ptr(idx), _ptr(x))
+    if lib().orc_init_indexed(ctypes.byref(c), n_total, _ptr(idx), _ptr(x)) != 0:
+        raise MemoryError("orc_init_indexed")
     return x
 
 

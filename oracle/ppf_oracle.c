@@ -217,17 +217,77 @@ static void init_one(const orc_model* m, int64_t i, int64_t n, double* x, int64_
   for (int d = 0; d < 5; ++d) x[d * stride] = m->init_a[d] + (m->init_b[d] - m->init_a[d]) * f[d];
 }
 
-/* Algorithm 1, k = 0: w_0 = 1/N and x_0 drawn from the initial density. */
-void orc_init(const orc_model* m, double* x, double* lw) {
-  const int64_t n = m->n;
-  for (int64_t i = 0; i < n; ++i) {
-    init_one(m, i, n, x + i, n);
-    lw[i] = -log((double)n);
+/* Init kind 3: the uniform draws of kind 0, with the particles ordered by
+ * the Z-order (Morton) key of the top 16 bits of their x and y uniforms
+ * (x bits at the even positions), ties by draw index. Position is monotone
+ * in those bits, so neighbours in the order are neighbours in space; the
+ * cloud as a set is the uniform one. */
+uint32_t orc_zorder_key(uint32_t wx, uint32_t wy) {
+  uint32_t k = 0;
+  for (int j = 0; j < 16; ++j) {
+    k |= ((wx >> (16 + j)) & 1u) << (2 * j);
+    k |= ((wy >> (16 + j)) & 1u) << (2 * j + 1);
   }
+  return k;
 }
 
-void orc_init_indexed(const orc_model* m, int64_t n_total, const int64_t* index, double* x) {
-  for (int64_t j = 0; j < m->n; ++j) init_one(m, index[j], n_total, x + j, m->n);
+static int cmp_u64(const void* a, const void* b) {
+  const uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* order[j] = the draw index of the particle at position j (kind 3), from
+ * the composite keys (key << 32 | index), whose plain sort is the stable
+ * sort by key. Returns 0, or -1 without memory. */
+int orc_zorder_perm(const orc_model* m, int64_t n, int64_t* order) {
+  uint64_t* kk = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+  if (!kk) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t r0[4];
+    draw(m, (uint32_t)i, 0u, PURPOSE_INIT, 0u, r0);
+    kk[i] = ((uint64_t)orc_zorder_key(r0[0], r0[1]) << 32) | (uint64_t)i;
+  }
+  qsort(kk, (size_t)n, sizeof(uint64_t), cmp_u64);
+  for (int64_t j = 0; j < n; ++j) order[j] = (int64_t)(kk[j] & 0xffffffffu);
+  free(kk);
+  return 0;
+}
+
+/* Algorithm 1, k = 0: w_0 = 1/N and x_0 drawn from the initial density. */
+int orc_init(const orc_model* m, double* x, double* lw) {
+  const int64_t n = m->n;
+  int64_t* order = NULL;
+  if (m->init_kind == 3) {
+    order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!order || orc_zorder_perm(m, n, order) != 0) {
+      free(order);
+      return -1;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    init_one(m, order ? order[i] : i, n, x + i, n);
+    lw[i] = -log((double)n);
+  }
+  free(order);
+  return 0;
+}
+
+/* The initial states at the given positions of a cloud of n_total
+ * particles (kind 3 orders the whole cloud first). Returns 0, or -1
+ * without memory. */
+int orc_init_indexed(const orc_model* m, int64_t n_total, const int64_t* index, double* x) {
+  int64_t* order = NULL;
+  if (m->init_kind == 3) {
+    order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_total > 0 ? n_total : 1));
+    if (!order || orc_zorder_perm(m, n_total, order) != 0) {
+      free(order);
+      return -1;
+    }
+  }
+  for (int64_t j = 0; j < m->n; ++j)
+    init_one(m, order ? order[index[j]] : index[j], n_total, x + j, m->n);
+  free(order);
+  return 0;
 }
 
 /* ---------------------------------------------------------- propagate */
@@ -514,8 +574,8 @@ int orc_run(const orc_model* m, int32_t T, const float* obs, double* mean, doubl
   int have_parent = 0, status = 0;
   const int64_t frame_len = m->obs_model == 0 ? (int64_t)m->width * m->height : 3;
 
-  orc_init(m, x, lw);
-  for (int32_t k = 1; k <= T; ++k) {
+  if (orc_init(m, x, lw) != 0) status = -1;
+  for (int32_t k = 1; k <= T && status == 0; ++k) {
     const float* z = obs + (int64_t)(k - 1) * frame_len;
     orc_propagate(m, k, x, have_parent ? parent : NULL, xn);
     if (m->obs_model == 0)
@@ -713,8 +773,8 @@ int orc_run_grad(const orc_model* m, int32_t T, const float* obs, const int32_t*
   const int64_t frame_len = (int64_t)m->width * m->height;
   *cum = 0.0;
   for (int d = 0; d < 9; ++d) grad[d] = 0.0;
-  orc_init(m, x, lw);
-  for (int32_t k = 1; k <= T; ++k) {
+  if (orc_init(m, x, lw) != 0) status = -1;
+  for (int32_t k = 1; k <= T && status == 0; ++k) {
     const float* z = obs + (int64_t)(k - 1) * frame_len;
     orc_propagate(m, k, x, have_parent ? parent : NULL, xn);
     orc_propagate_tangent(m, k, t, have_parent ? parent : NULL, tn);

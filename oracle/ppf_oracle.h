@@ -29,7 +29,8 @@ typedef struct orc_model {
   double b;             /* I_bg (Eq. 3)                                       */
   double sigma;         /* sigma_xi (Eq. 4)                                   */
   double q[5];          /* process-noise sds of (x, y, vx, vy, I0)            */
-  int32_t init_kind;    /* 0 uniform [a,b), 1 Gaussian N(a,b^2), 2 stratified  */
+  int32_t init_kind;    /* 0 uniform [a,b), 1 Gaussian N(a,b^2), 2 stratified,
+                           3 uniform in Z order */
   int32_t resample;     /* 0 = systematic, 1 = RNA, 2 = ARNA                  */
   double init_a[5];
   double init_b[5];
@@ -67,12 +68,20 @@ void orc_box_muller(uint32_t rad, uint32_t ang, double* z0, double* z1);
 double orc_resample_uniform(const orc_model* m, int64_t k);
 double orc_rna_uniform(const orc_model* m, int64_t g, int64_t k);
 
-/* Algorithm 1 initialisation: x (5*n, SoA), lw (n) = -log N. */
-void orc_init(const orc_model* m, double* x, double* lw);
+/* Algorithm 1 initialisation: x (5*n, SoA), lw (n) = -log N. Returns 0,
+ * or -1 without memory (kind 3). */
+int orc_init(const orc_model* m, double* x, double* lw);
 
 /* Initial states of the particles index[0..m->n) of a run with n_total
- * particles (5 * m->n SoA). */
-void orc_init_indexed(const orc_model* m, int64_t n_total, const int64_t* index, double* x);
+ * particles (5 * m->n SoA). Returns 0, or -1 without memory (kind 3). */
+int orc_init_indexed(const orc_model* m, int64_t n_total, const int64_t* index, double* x);
+
+/* Init kind 3: the Morton key of the top 16 bits of the x and y uniform
+ * words, and the draw index of the particle at each position of the
+ * cloud (stable sort by key). orc_zorder_perm returns 0, or -1 without
+ * memory. */
+uint32_t orc_zorder_key(uint32_t wx, uint32_t wy);
+int orc_zorder_perm(const orc_model* m, int64_t n, int64_t* order);
 
 /* SIS draw of frame k under the bootstrap proposal: x_new[i] from parent
  * x_prev[parent[i]] (parent NULL: identity). SoA 5*n. */

@@ -215,7 +215,7 @@ def test_normalize_matches_exact_sums(orc):
     assert np.allclose(orc.estimate(w, x), np.average(x, axis=1, weights=w), rtol=1e-12, atol=1e-14)
 
 
-@pytest.mark.parametrize("init_kind", [0, 1, 2])
+@pytest.mark.parametrize("init_kind", [0, 1, 2, 3])
 def test_indexed_entry_points_agree_with_whole_run(orc, init_kind):
     n = 3001
     m = model(orc, n=n, init_kind=init_kind, init_a=(0, 0, -1, -1, 15), init_b=(64, 32, 1, 1, 45))
@@ -226,3 +226,54 @@ def test_indexed_entry_points_agree_with_whole_run(orc, init_kind):
     parent = np.sort(np.random.default_rng(0).integers(0, n, n)).astype(np.int32)
     xn = orc.propagate(m, 4, x, parent)
     assert np.array_equal(orc.propagate_indexed(ms, 4, idx, x[:, parent[idx]]), xn[:, idx])
+
+
+# ------------------------------------------------- init kind 3 (Z-ordered uniform)
+def test_zorder_key_hand_worked(orc):
+    """The Morton key interleaves the top 16 bits of the x word (even bit
+    positions) and of the y word (odd positions); the low 16 bits of each
+    word do not enter."""
+    assert orc.zorder_key(0xFFFF0000, 0) == 0x55555555
+    assert orc.zorder_key(0, 0xFFFF0000) == 0xAAAAAAAA
+    assert orc.zorder_key(0x00010000, 0) == 1
+    assert orc.zorder_key(0, 0x00010000) == 2
+    assert orc.zorder_key(0x80000000, 0x80000000) == 0xC0000000
+    assert orc.zorder_key(0x0000FFFF, 0x0000FFFF) == 0
+    assert orc.zorder_key(0x00030000, 0x00050000) == 0b100111  # x 011, y 101
+
+
+def _morton16(x, y):
+    k = 0
+    for j in range(16):
+        k |= ((x >> j) & 1) << (2 * j)
+        k |= ((y >> j) & 1) << (2 * j + 1)
+    return k
+
+
+def test_zorder_init_is_the_uniform_cloud_in_key_order(orc):
+    """Kind 3 equals kind 0's draws permuted: position j holds the draw
+    whose key is j-th in the stable sort by key, the keys re-derived here
+    from the generator's words with an interleave written independently."""
+    n = 5000
+    kw = dict(n=n, init_a=(0, 0, -1, -1, 15), init_b=(128, 96, 1, 1, 45), seed=11, track=3)
+    x0, _ = orc.init(model(orc, init_kind=0, **kw))
+    x3, lw3 = orc.init(model(orc, init_kind=3, **kw))
+    assert np.allclose(lw3, -np.log(n), rtol=0, atol=1e-15)
+    ctr = np.zeros((n, 4), dtype=np.uint32)
+    ctr[:, 0] = np.arange(n)
+    ctr[:, 2] = 1 << 24  # the init purpose, block 0
+    ctr[:, 3] = 3
+    words = orc.philox(11, ctr)
+    keys = np.array([_morton16(int(a) >> 16, int(b) >> 16) for a, b in words[:, :2]],
+                    dtype=np.int64)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(orc.zorder_perm(model(orc, init_kind=3, **kw), n), order)
+    assert np.array_equal(x3, x0[:, order])
+    # the order is spatial: keys non-decreasing, ties by draw index
+    k_sorted = keys[order]
+    assert np.all(np.diff(k_sorted) >= 0)
+    ties = np.diff(k_sorted) == 0
+    assert np.all(np.diff(order)[ties] > 0)
+    # neighbours in the order are neighbours in space (cells of 1/256 of the box)
+    step = np.hypot(np.diff(x3[0]) / 128, np.diff(x3[1]) / 96)
+    assert np.median(step) < 0.05
