@@ -18,7 +18,10 @@ invariants of the last step are checked on the GPU's output; the
 cpu_baseline leg then runs one more step and checks it against the oracle on
 sampled particles (propagation, log weights, every ancestor). The same
 workload is also timed from the other initial cloud (`init_alternative`:
-uniform when the headline uses the stratified cloud, and the reverse).
+stratified when the headline uses the uniform cloud, uniform otherwise). The
+uniform cloud is the paper's (i.i.d. uniform draws, Section 6.3) with the
+particles placed in the Z order of their draws, so that a workgroup's 256
+particles are neighbours in the image from the first frame on.
 `roofline` covers the dominant kernel (k_step) against the fp64 vector peak;
 `roofline_resample` covers the ancestor passes against HBM bandwidth; both
 use algorithmic work per launch / average launch time measured with HIP
@@ -278,7 +281,7 @@ def run_multitrack(args, w):
     pmv = synth.render_movie(pw["W"], pw["H"], pw["T"], intensity=30.0, sigma=pw["s"],
                              background=10.0, noise_sd=3.0, seed=1)
     pframes = torch.from_numpy(pmv.frames).cuda()
-    pf = ppf.Filter(make_params(ppf, pw, ppf.INIT_STRATIFIED))
+    pf = ppf.Filter(make_params(ppf, pw, ppf.INIT_UNIFORM_ZORDER))
     pms, _, _, _, _ = timed_steps(torch, pf, pframes, K, Wm, pw["T"], False, None)
     check_state(ppf, pf, pw, pmv, (K - 1) % pw["T"], 0)
     pf.close()
@@ -472,6 +475,12 @@ def run_grad_check(args):
                                     "true": track_err(mean_true)}},
     }
     print(json.dumps(out), flush=True)
+
+
+# --init: the library's init kind of each initial cloud
+INIT_KINDS = {"uniform": lambda ppf: ppf.INIT_UNIFORM_ZORDER,
+              "stratified": lambda ppf: ppf.INIT_STRATIFIED,
+              "uniform-unordered": lambda ppf: ppf.INIT_UNIFORM}
 
 
 def make_params(ppf, w, init_kind, grad=0):
@@ -724,7 +733,9 @@ def main():
     # averaged over 100 steps after 2)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="sir_1024x1024_n38m_p13", choices=sorted(WORKLOADS))
-    ap.add_argument("--init", default="stratified", choices=["stratified", "uniform"])
+    ap.add_argument("--init", default="uniform", choices=["uniform", "stratified", "uniform-unordered"],
+                    help="initial cloud: uniform (the paper's i.i.d. uniform draws, placed in Z "
+                         "order), stratified (Z-order strata), uniform-unordered (in draw order)")
     ap.add_argument("--no-alt-init", action="store_true",
                     help="skip the second measurement from the other initial cloud")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -794,7 +805,7 @@ def run(args):
     w = WORKLOADS[args.workload]
     if "tracks" in w:
         return run_multitrack(args, w)
-    init_kind = ppf.INIT_STRATIFIED if args.init == "stratified" else ppf.INIT_UNIFORM
+    init_kind = INIT_KINDS[args.init](ppf)
     K, Wm = args.steps, args.warmup
     T = max(K, w["T"])  # the warm-up steps cycle through these frames
     box = w.get("box")
@@ -907,8 +918,8 @@ def run(args):
         # the same workload from the other initial cloud (the paper's is
         # uniform; the stratified cloud gives each workgroup a compact
         # first-frame box)
-        alt = "uniform" if args.init == "stratified" else "stratified"
-        ak = ppf.INIT_UNIFORM if alt == "uniform" else ppf.INIT_STRATIFIED
+        alt = "stratified" if args.init == "uniform" else "uniform"
+        ak = INIT_KINDS[alt](ppf)
         fa = ppf.Filter(make_params(ppf, w, ak))
         a_ms, _, akt, _, _ = timed_steps(torch, fa, frames, K, 2, T, graph, ran)
         a_err, a_st = check_state(ppf, fa, w, mv, (K - 1) % T, scheme)
@@ -918,8 +929,12 @@ def run(args):
                                    "kernel_ms_total": {k: v[1] for k, v in akt.items()},
                                    "tracking_error_px": a_err, "final_ess": a_st["ess"]}
     if not args.no_cpu_baseline:
+        # (the oracle's run includes its initialisation; the Z-ordered cloud's
+        # sort would add to it, and the order does not change the oracle's
+        # per-particle work, so it times the same draws unordered)
+        ck = ppf.INIT_UNIFORM if init_kind == ppf.INIT_UNIFORM_ZORDER else init_kind
         out["cpu_baseline"] = cpu_baseline(w, mv.frames, min(args.cpu_sample, n), args.cpu_frames,
-                                           init_kind, cpu_threads(args))
+                                           ck, cpu_threads(args))
     print(json.dumps(out), flush=True)
 
 

@@ -64,7 +64,8 @@ enum { PPF_RESAMPLE_SYSTEMATIC = 0, PPF_RESAMPLE_RNA = 1, PPF_RESAMPLE_RPA = 2,
  * Largest Gradient (Alg. 4). */
 enum { PPF_DLB_GS = 0, PPF_DLB_SGS = 1, PPF_DLB_LGS = 2 };
 enum { PPF_OBS_SPOT = 0, PPF_OBS_LINEAR_GAUSSIAN = 1 };
-enum { PPF_INIT_UNIFORM = 0, PPF_INIT_GAUSSIAN = 1, PPF_INIT_STRATIFIED = 2 };
+enum { PPF_INIT_UNIFORM = 0, PPF_INIT_GAUSSIAN = 1, PPF_INIT_STRATIFIED = 2,
+       PPF_INIT_UNIFORM_ZORDER = 3 };
 
 /* Largest patch edge P the kernels are built for. */
 #define PPF_MAX_PATCH 25
@@ -100,7 +101,15 @@ typedef struct ppf_ctx* ppf_handle;
  *               ceil(t/2) bits, y floor(t/2)) visited in Z order; particle i
  *               lies uniformly inside cell floor(i 2^t / N). Consecutive
  *               indices are then neighbours in the image, which keeps the
- *               first frame's image tiles small.
+ *               first frame's image tiles small;
+ *               PPF_INIT_UNIFORM_ZORDER: the draws of PPF_INIT_UNIFORM, i.i.d.
+ *               uniform, with the particles placed in the stable order of the
+ *               Morton key of the top 16 bits of their x and y uniform words
+ *               (x bits at the even positions; ties by draw index): the same
+ *               cloud as a set, ordered so that neighbours in the index are
+ *               neighbours in the image. Its initialisation sorts N keys on
+ *               the device (about 17 N bytes more workspace). Single filters
+ *               only.
  * lg_r[3]       observation noise sds of the linear-Gaussian model (> 0).
  * resample      PPF_RESAMPLE_SYSTEMATIC, PPF_RESAMPLE_RNA, or PPF_RESAMPLE_RPA:
  *               resampling with proportional allocation (Section 3) over

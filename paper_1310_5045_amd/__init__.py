@@ -28,7 +28,7 @@ RESAMPLE_SYSTEMATIC, RESAMPLE_RNA, RESAMPLE_RPA, RESAMPLE_ARNA = 0, 1, 2, 3
 DLB_GS, DLB_SGS, DLB_LGS = 0, 1, 2
 STATIC_MAX_N = 1 << 22  # weights the allocation-free resampler takes
 OBS_SPOT, OBS_LINEAR_GAUSSIAN = 0, 1
-INIT_UNIFORM, INIT_GAUSSIAN, INIT_STRATIFIED = 0, 1, 2
+INIT_UNIFORM, INIT_GAUSSIAN, INIT_STRATIFIED, INIT_UNIFORM_ZORDER = 0, 1, 2, 3
 MAX_PATCH = 25
 NUM_SHAPES, TUNE_MAX = 2, 3  # step-kernel workgroup shapes; tuning candidates at most
 # theta of ppf_grad, in order

@@ -51,7 +51,7 @@ std::string validate(const ppf_params* p) {
   if (p->n_particles < 1 || p->n_particles > 2147483647LL) return "n_particles out of range";
   if (p->obs_model != PPF_OBS_SPOT && p->obs_model != PPF_OBS_LINEAR_GAUSSIAN)
     return "unknown obs_model";
-  if (p->init_kind < PPF_INIT_UNIFORM || p->init_kind > PPF_INIT_STRATIFIED)
+  if (p->init_kind < PPF_INIT_UNIFORM || p->init_kind > PPF_INIT_UNIFORM_ZORDER)
     return "unknown init_kind";
   if (p->resample != PPF_RESAMPLE_SYSTEMATIC && p->resample != PPF_RESAMPLE_RNA &&
       p->resample != PPF_RESAMPLE_RPA && p->resample != PPF_RESAMPLE_ARNA)
@@ -250,6 +250,16 @@ size_t carve(const ppf_params* p, char* base, Buffers* b, bool own_ctrl = true) 
     bb.rtsum = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * 4 * nt2));
     bb.rsidx = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * Gr));
     bb.rstream = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
+  }
+  if (p->init_kind == PPF_INIT_UNIFORM_ZORDER) {
+    // the initialisation's sort of the particles' keys
+    const int64_t nt = (n + ppf::kSortTile - 1) / ppf::kSortTile;
+    bb.zkey0 = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * n));
+    bb.zkey1 = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * n));
+    bb.zval0 = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
+    bb.zval1 = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * n));
+    bb.zhist = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 256 * nt));
+    bb.zrow = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 256));
   }
   if (p->resample == PPF_RESAMPLE_RNA || p->resample == PPF_RESAMPLE_ARNA) {
     // the local resampling of every group and its share W_g, read by the
@@ -930,6 +940,8 @@ std::string validate_batch(const ppf_params* p, int32_t count) {
     if (p[t].grad) return "track " + std::to_string(t) + ": batches do not take grad = 1";
     if (p[t].resample == PPF_RESAMPLE_RPA || p[t].resample == PPF_RESAMPLE_ARNA)
       return "track " + std::to_string(t) + ": batches do not take RPA or ARNA";
+    if (p[t].init_kind == PPF_INIT_UNIFORM_ZORDER)
+      return "track " + std::to_string(t) + ": batches do not take the Z-ordered init";
     if (p[t].width != p[0].width || p[t].height != p[0].height)
       return "track " + std::to_string(t) + ": frame size differs from track 0";
   }

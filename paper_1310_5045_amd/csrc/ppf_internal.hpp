@@ -206,6 +206,12 @@ struct Buffers {
   uint32_t* rhist;   // RPA with SGS: digit counts per sort tile (256 x tiles)
   uint32_t* rrow;    // RPA with SGS: digit totals (256)
   uint64_t* rtsum;   // RPA: per list tile, the sum of the values and the count present
+  uint32_t* zkey0;   // Z-ordered init: the particles' sort keys, ping
+  uint32_t* zkey1;   //   and pong
+  int32_t* zval0;    // Z-ordered init: their draw indices, ping (after the sort: the
+  int32_t* zval1;    //   draw index at each position) and pong
+  uint32_t* zhist;   // Z-ordered init: digit counts per sort tile
+  uint32_t* zrow;    // Z-ordered init: digit totals
   int32_t* rsidx;    // RPA: each sender group's position in the sender order (G)
   int32_t* rstream;  // RPA: the senders' surplus offspring in schedule order (N)
   int32_t* aloc;     // ARNA: each group's local resampling (n global indices)

@@ -386,6 +386,19 @@ __device__ __forceinline__ uint64_t block_excl_sum(uint64_t v, uint64_t* sh, uin
 }
 
 // ------------------------------------------------------------ k_init
+// The Morton key of the top 16 bits of two words: x's bits at the even
+// positions, y's at the odd ones (each spread by doubling its bit distance).
+__device__ __forceinline__ uint32_t spread16(uint32_t v) {
+  v &= 0xffffu;
+  v = (v | (v << 8)) & 0x00ff00ffu;
+  v = (v | (v << 4)) & 0x0f0f0f0fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  return (v | (v << 1)) & 0x55555555u;
+}
+__device__ __forceinline__ uint32_t zorder_key(uint32_t wx, uint32_t wy) {
+  return spread16(wx >> 16) | (spread16(wy >> 16) << 1);
+}
+__device__ __forceinline__ void init_state(const Model& m, int64_t i, float* xs);
 // Algorithm 1 initialisation, k = 0. The state is computed in fp64 and
 // rounded once to fp32.
 __device__ __forceinline__ void init_body(const Model& m, const Buffers& b, int64_t blk) {
@@ -413,6 +426,21 @@ __device__ __forceinline__ void init_body(const Model& m, const Buffers& b, int6
   if (i >= m.n) return;
   if (m.grad)
     for (int d = 0; d < kNTan; ++d) b.T0[(int64_t)d * m.n + i] = 0.0f;
+  if (m.init_kind == 3) {
+    // Z order: the sort key of draw i; k_init_place writes the states
+    const uint4 r0 = draw(m, (uint32_t)i, 0u, kInit, 0u);
+    b.zkey0[i] = zorder_key(r0.x, r0.y);
+    b.zval0[i] = (int32_t)i;
+    return;
+  }
+  float xs[5];
+  init_state(m, i, xs);
+#pragma unroll
+  for (int d = 0; d < 5; ++d) b.X0[(int64_t)d * m.n + i] = xs[d];
+}
+
+// The initial state of draw i (kinds 0-2; kind 3 draws as kind 0).
+__device__ __forceinline__ void init_state(const Model& m, int64_t i, float* xs) {
   const uint4 r0 = draw(m, (uint32_t)i, 0u, kInit, 0u);
   const uint4 r1 = draw(m, (uint32_t)i, 0u, kInit, 1u);
   double x[5];
@@ -454,10 +482,20 @@ __device__ __forceinline__ void init_body(const Model& m, const Buffers& b, int6
       x[d] = (double)m.init_a[d] + ((double)m.init_b[d] - (double)m.init_a[d]) * f[d];
   }
 #pragma unroll
-  for (int d = 0; d < 5; ++d) b.X0[(int64_t)d * m.n + i] = (float)x[d];
+  for (int d = 0; d < 5; ++d) xs[d] = (float)x[d];
 }
 
 __global__ __launch_bounds__(256) void k_init(Model m, Buffers b) { init_body(m, b, blockIdx.x); }
+
+// Z-ordered init: position p takes draw zval0[p] (the keys sorted, stably).
+__global__ __launch_bounds__(256) void k_init_place(Model m, Buffers b) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= m.n) return;
+  float xs[5];
+  init_state(m, (int64_t)b.zval0[p], xs);
+#pragma unroll
+  for (int d = 0; d < 5; ++d) b.X0[(int64_t)d * m.n + p] = xs[d];
+}
 
 // ------------------------------------------------------------ k_step
 // Parent, carried log weight and propagated state of particle i.
@@ -2911,7 +2949,26 @@ hipError_t static_scratch(void** ptr, size_t* bytes) {
 }
 
 hipError_t launch_init(const Model& m, const Buffers& b, hipStream_t s) {
-  return launch_k(k_init, dim3(grid_for(m.n, 256)), dim3(256), s, m, b);
+  hipError_t e = launch_k(k_init, dim3(grid_for(m.n, 256)), dim3(256), s, m, b);
+  if (e != hipSuccess || m.init_kind != 3) return e;
+  // Z order: sort the keys with their draw indices (stable), then place
+  const int32_t nt = (int32_t)((m.n + kSortTile - 1) / kSortTile);
+  const Ctrl* nogate = nullptr;
+  for (int pass = 0; pass < 4 && e == hipSuccess; ++pass) {
+    const uint32_t* kin = pass & 1 ? b.zkey1 : b.zkey0;
+    const int32_t* vin = pass & 1 ? b.zval1 : b.zval0;
+    uint32_t* kout = pass & 1 ? b.zkey0 : b.zkey1;
+    int32_t* vout = pass & 1 ? b.zval0 : b.zval1;
+    e = launch_k(k_radix_hist, dim3((unsigned)nt), dim3(256), s, kin, m.n, 8 * pass, b.zhist, nt,
+                 nogate);
+    if (e == hipSuccess)
+      e = launch_k(k_radix_rowscan, dim3(256), dim3(256), s, b.zhist, nt, b.zrow, nogate);
+    if (e == hipSuccess)
+      e = launch_k(k_radix_scatter, dim3((unsigned)nt), dim3(256), s, kin, vin, kout, vout, m.n,
+                   8 * pass, (const uint32_t*)b.zhist, (const uint32_t*)b.zrow, nt, nogate);
+  }
+  if (e == hipSuccess) e = launch_k(k_init_place, dim3(grid_for(m.n, 256)), dim3(256), s, m, b);
+  return e;
 }
 
 hipError_t launch_step(const Model& m, const Buffers& b, const float* obs, hipStream_t s) {

@@ -63,7 +63,7 @@ def test_philox_bit_exact(ppf):
         assert np.array_equal(out.view(np.uint32), oracle.philox(seed, ctr))
 
 
-@pytest.mark.parametrize("init_kind", [0, 1, 2])
+@pytest.mark.parametrize("init_kind", [0, 1, 2, 3])
 def test_init_matches_oracle(ppf, init_kind):
     kw = dict(SPOT, n=5000, init_kind=init_kind)
     if init_kind == 1:
@@ -78,6 +78,23 @@ def test_init_matches_oracle(ppf, init_kind):
     assert np.all(np.abs(x - xo) <= tol)
     assert np.allclose(lw, lwo, rtol=1e-15)
     assert np.array_equal(anc, np.arange(5000))
+    f.close()
+
+
+def test_zorder_init_many_tiles(ppf):
+    """The Z-ordered uniform cloud over many sort tiles and a ragged tail:
+    every particle equals the oracle's, and a reset draws it again."""
+    n = (1 << 20) + 37
+    p, m = pair(ppf, **dict(SPOT, n=n, init_kind=3, init_a=(0, 0, -1, -1, 15),
+                            init_b=(128, 128, 1, 1, 45)))
+    f = ppf.Filter(p)
+    x, _, _ = f.particles()
+    xo, _ = oracle.init(m)
+    assert np.all(np.abs(x - xo) <= np.spacing(np.abs(xo).astype(np.float32)))
+    f.step(torch.from_numpy(np.full((128, 128), 10.0, np.float32)).cuda())
+    f.reset()
+    x2, _, _ = f.particles()
+    assert np.array_equal(x, x2)
     f.close()
 
 
