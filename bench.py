@@ -85,6 +85,9 @@ TRAFFIC_GROUPS = {
     "k_step": dict(match=("k_step_spot",), per_shape=True),
     # the resampling pair: the ancestor pass and its long-run fill, per step
     "k_resample": dict(match=("k_anc", "k_fill"), per_shape=False),
+    # a batch's step launches: the fused one and the wide-patch one, per step
+    # (counter runs with --shape 1: one fused launch per step)
+    "k_step_batch": dict(match=("k_step_batch_fused", "k_step_batch_wide"), per_shape=False),
 }
 
 
@@ -228,6 +231,13 @@ def run_multitrack(args, w):
     T = w["T"]
     torch.cuda.set_device(0)
     frames = torch.from_numpy(mv.frames).cuda()
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     b = ppf.Batch(ps)
     graph = args.launch == "graph"
     gpu_ms, wall, kt, tuned, _ = timed_steps(torch, b, frames, K, Wm, T, graph, args.shape)
@@ -266,7 +276,8 @@ def run_multitrack(args, w):
                    "launch": args.launch, "autotune": tuned},
         "roofline": {"bound": "alu", "kernel": "k_step (all patch sizes)",
                      "achieved": achieved_tf, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": load_traffic("k_step_batch", args.workload, None),
                      "step_kernels_ms_per_step": step_ms},
         "kernel_ms_total": {k: v[1] for k, v in kt.items()},
         "kernel_launches": {k: v[0] for k, v in kt.items()},

@@ -107,6 +107,31 @@ def test_resampling_pair_traffic_record(tmp_path, records):
     assert bench.load_traffic("k_resample", "wl", 1) == rec["traffic_bytes_per_launch"]
 
 
+def test_batched_step_traffic_record(tmp_path, records):
+    """The batch's record sums its fused and wide-patch step launches per step."""
+    f = str(tmp_path / "fetch.db")
+    w = str(tmp_path / "write.db")
+    for path, counter, copy_kib in ((f, "FETCH_SIZE", 512.0 * 1024), (w, "WRITE_SIZE", 1024.0 * 1024)):
+        con = sqlite3.connect(path)
+        con.execute("create table counters_collection (dispatch_id integer, kernel_name text, "
+                    "counter_name text, value real)")
+        rows, d = [], 0
+        for k in range(3 + 4):
+            for name, kib in (("void ppf::k_step_batch_fused<1>(ppf::Model const*)", 30.0),
+                              ("void ppf::k_step_batch_wide<15>(ppf::Model const*)", 4.0),
+                              ("void ppf::k_anc_batch(ppf::Model const*)", 2.0)):
+                d += 1
+                rows.append((d, name, counter, kib if k >= 3 else 1.0))
+        rows.append((d + 1, "__amd_rocclr_copyBuffer", counter, copy_kib))
+        con.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
+        con.commit()
+        con.close()
+    rec = bench.traffic_from(f, w, "mt", 1024, 3, 4, 1, kernel="k_step_batch")
+    assert rec["shape"] is None
+    assert rec["traffic_bytes_per_launch"] == (34.0 * 2.0 + 34.0) * 1024
+    assert bench.load_traffic("k_step_batch", "mt", None) == rec["traffic_bytes_per_launch"]
+
+
 # ------------------------------------------------------- correctness gate
 class OracleFilter:
     """Stand-in for the library's Filter, stepped by the oracle on the host
