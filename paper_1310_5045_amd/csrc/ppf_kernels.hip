@@ -9,11 +9,14 @@
 //   k_merge_final  fixed-order merge of the chunks: the normaliser, ESS, MMSE
 //                  estimate, resampling decision and uniform; commits or rolls
 //                  back the step; the fixed-point CDF prefixes of the chunks
-//   k_anc          systematic resampling: per segment of 2048 particles, each
-//                  particle's run of output slots from the segment's CDF
+//   k_anc          systematic resampling: one wave per segment of 512
+//                  particles, each particle's run of output slots from the
+//                  segment's CDF
 //   k_fill         the slots of heavy segments queued by k_anc (concentrated
 //                  weights), in chunks of tiles
-//   (or k_rna      RNA of Section 3: one workgroup per group of particles)
+//   (or k_rna_local + k_rna_exchange: RNA of Section 3, one workgroup per
+//                  group of particles; k_arna_* for ARNA; k_rpa_* after k_fill
+//                  for RPA)
 #include "ppf_internal.hpp"
 
 #include <array>
