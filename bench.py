@@ -58,10 +58,18 @@ KERNEL_SOURCES = ("paper_1310_5045_amd/csrc/ppf_kernels.hip",
 
 
 def kernel_source_hash():
+    """sha256 of the kernel sources' code: comments, trailing blanks and empty
+    lines removed, so that only a change of the code itself invalidates a
+    traffic record (the sources hold no string literal with a comment
+    marker)."""
+    import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.split("\n")]
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()
 
 
