@@ -49,8 +49,10 @@ def same_filter(a, b):
     dict(n_particles=4096, ess_threshold=2000.0),
     dict(n_particles=2048, resample=1, rna_group=256, rna_exchange=0.1),
     dict(n_particles=4096, resample=2, rna_group=256, dlb=1),
+    dict(n_particles=1 << 16, resample=2, rna_group=4, dlb=1, ess_threshold=float(1 << 15)),
+    dict(n_particles=4096, resample=3, rna_group=256, rna_exchange=0.5, arna_min=0.05),
     dict(n_particles=3001, grad=1),
-], ids=["systematic", "ess", "rna", "rpa", "grad"])
+], ids=["systematic", "ess", "rna", "rpa", "rpa_many_groups_ess", "arna", "grad"])
 def test_graph_replays_equal_launches(ppf, frames, extra):
     p = ppf.params(**BASE, **extra)
     eager, graphed = ppf.Filter(p), ppf.Filter(p)

@@ -140,3 +140,43 @@ def test_rpa_filter_many_groups(ppf, dlb, group):
         routed = oracle.route_rpa(sys_anc, group, dlb)
         assert np.array_equal(anc, routed), (k, int(np.sum(anc != routed)))
     f.close()
+
+
+@pytest.mark.parametrize("dlb", [0, 1])
+def test_rpa_filter_ess_threshold_many_groups(ppf, dlb):
+    """16,384 groups with an ESS threshold: steps that do not resample leave
+    the ancestors and carried weights to the plain step (the routing kernels
+    do nothing), steps that do are routed as the oracle routes them."""
+    n, group = 1 << 16, 4
+    mv = synth.render_movie(128, 128, 6, intensity=30.0, sigma=1.5, start_box=(40, 88, 40, 88),
+                            seed=25)
+    p, m = pair(ppf, n=n, width=128, height=128, s=1.5, b=10.0, sigma=3.0,
+                init_a=(32, 32, -1, -1, 15), init_b=(96, 96, 1, 1, 45), resample=0, seed=8,
+                ess_threshold=float(n // 100))  # the oracle's run resamples at steps 1, 2, 4, 5
+    p.resample = ppf.RESAMPLE_RPA
+    p.rna_group = group
+    p.dlb = dlb
+    f = ppf.Filter(p)
+    frames = torch.from_numpy(mv.frames).cuda()
+    x, lw, anc = f.particles()
+    prev = GpuState(x, lw, anc, False, np.full(n, -math.log(n)))
+    seen = set()
+    for k in range(1, 7):
+        f.step(frames[k - 1])
+        x, lw, anc = f.particles()
+        st = f.stats()
+        cur = GpuState(x, lw, anc, bool(st["resampled"]), None)
+        check_propagate(m, k, prev, cur.x)
+        check_weights(m, mv.frames[k - 1], prev.lw_next, cur.x, cur.lw, st)
+        seen.add(cur.resampled)
+        if cur.resampled:
+            sys_anc = np.sort(cur.anc)
+            check_systematic(np.exp(cur.lw), oracle.resample_uniform(m, k), sys_anc)
+            assert np.array_equal(cur.anc, oracle.route_rpa(sys_anc, group, dlb)), k
+            cur.lw_next = np.full(n, -math.log(n))
+        else:
+            assert np.array_equal(cur.anc, np.arange(n))
+            cur.lw_next = cur.lw
+        prev = cur
+    f.close()
+    assert seen == {True, False}, seen
