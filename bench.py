@@ -874,9 +874,10 @@ def run(args):
     # weights, sum g_y^2, the table adds and two g_y recurrence products
     executed = 2 * P * (P - 1) + 2 * P + 2 * P + P + 2 * P
     # resampling: read 4 B log weight, write 4 B ancestor per particle; the
-    # ancestor pass and its overflow pass together, per step
-    res_ms = kt.get("k_anc", (0, 0.0))[1] + kt.get("k_fill", (0, 0.0))[1]
-    res_avg_s = res_ms / max(kt.get("k_anc", (0, 0.0))[0], 1) / 1e3
+    # library times the pass (k_anc, then k_fill for queued tile chunks)
+    # under one pair of events, per step
+    res_launches, res_ms = kt.get("k_resample", (0, 0.0))
+    res_avg_s = res_ms / max(res_launches, 1) / 1e3
     res_gbs = 8.0 * n / res_avg_s / 1e9 if res_avg_s > 0 else 0.0
     step_gbs = 48.0 * n / step_avg_s / 1e9
 

@@ -208,7 +208,12 @@ typedef struct ppf_stats_t {
   double mean[5];      /* MMSE estimate sum_i w_i x~_i (Section 2)           */
 } ppf_stats_t;
 
-/* Per-kernel timing accumulated while profiling is enabled. */
+/* Per-kernel timing accumulated while profiling is enabled. Entries are
+ * named for the step's timed units: "k_step", "k_merge" (both merge
+ * launches), "k_resample" (the systematic resampling pass: the segment
+ * launch and the launch that fills queued tile chunks, under one pair of
+ * events), "k_rna" (RNA and ARNA), "k_rpa", and "k_init", "k_gather",
+ * "k_logw" outside the step. */
 typedef struct ppf_kernel_time {
   char name[32];
   int64_t launches;

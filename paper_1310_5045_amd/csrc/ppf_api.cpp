@@ -23,11 +23,13 @@ using ppf::Model;
 
 namespace {
 
+// Timed units of a step. k_resample is the systematic resampling pass, its
+// two launches (segments, then queued tile chunks) under one pair of events.
 enum KernelId {
-  kKStep, kKMerge, kKAnc, kKFill, kKRna, kKInit, kKGather, kKLogw, kKRpa, kNumKernels
+  kKStep, kKMerge, kKResample, kKRna, kKInit, kKGather, kKLogw, kKRpa, kNumKernels
 };
-const char* const kKernelNames[kNumKernels] = {"k_step", "k_merge",  "k_anc",  "k_fill", "k_rna",
-                                               "k_init", "k_gather", "k_logw", "k_rpa"};
+const char* const kKernelNames[kNumKernels] = {"k_step",   "k_merge",  "k_resample", "k_rna",
+                                               "k_init",   "k_gather", "k_logw",     "k_rpa"};
 
 constexpr size_t kAlign = 256;
 
@@ -582,9 +584,10 @@ int enqueue_step(ppf_handle h, const float* obs_dev) {
     return h->run(kKRna, [&] { return ppf::launch_rna_groups(h->m, h->b, h->stream); });
   if (h->p.resample == PPF_RESAMPLE_ARNA)
     return h->run(kKRna, [&] { return ppf::launch_arna(h->m, h->b, h->stream); });
-  rc = h->run(kKAnc, [&] { return ppf::launch_anc(h->m, h->b, w, h->stream); });
-  if (rc) return rc;
-  rc = h->run(kKFill, [&] { return ppf::launch_fill(h->m, h->b, w, h->stream); });
+  rc = h->run(kKResample, [&] {
+    const hipError_t e = ppf::launch_anc(h->m, h->b, w, h->stream);
+    return e != hipSuccess ? e : ppf::launch_fill(h->m, h->b, w, h->stream);
+  });
   if (rc || !h->m.rpa) return rc;
   return h->run(kKRpa, [&] { return ppf::launch_rpa(h->m, h->b, h->stream); });
 }
@@ -1171,14 +1174,12 @@ int enqueue_batch_step(ppf_batch h, const float* obs_dev) {
   });
   if (rc) return rc;
   if (!bp.segs.empty()) {
-    rc = h->run(kKAnc, [&] {
-      return ppf::launch_anc_batch(h->d_models, h->d_bufs, h->d_segs, (int64_t)bp.segs.size(),
-                                   h->stream);
-    });
-    if (rc) return rc;
-    rc = h->run(kKFill, [&] {
-      return ppf::launch_fill_batch(h->d_models, h->d_bufs, h->d_sys,
-                                    (int32_t)bp.sys_tracks.size(), h->stream);
+    rc = h->run(kKResample, [&] {
+      const hipError_t e = ppf::launch_anc_batch(h->d_models, h->d_bufs, h->d_segs,
+                                                 (int64_t)bp.segs.size(), h->stream);
+      return e != hipSuccess ? e
+                             : ppf::launch_fill_batch(h->d_models, h->d_bufs, h->d_sys,
+                                                      (int32_t)bp.sys_tracks.size(), h->stream);
     });
     if (rc) return rc;
   }

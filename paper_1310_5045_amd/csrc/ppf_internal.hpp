@@ -47,11 +47,11 @@ constexpr double kItemToCdf = 0x1p18;
 // kSlotTile slots; a heavier segment queues its tiles in chunks of
 // kChunkTiles for k_fill (kFillGrid one-wave workgroups, each taking chunks
 // in turn).
-constexpr int kSegBlocks = 2;
+constexpr int kSegBlocks = 4;
 constexpr int kSegItems = kSegBlocks * kBlock;
 constexpr int kSlotTile = kSegItems;  // slots per LDS tile of the segment's writes
-constexpr int kCoopTiles = 8;
-constexpr int kChunkTiles = 4;
+constexpr int kCoopTiles = 4;
+constexpr int kChunkTiles = 2;
 constexpr int kFillGrid = 4096;
 constexpr int kFillGridBatch = 2048;  // waves of a batched fill, over all tracks' queues
 // Batched steps run every patch size up to this one in a single launch (the

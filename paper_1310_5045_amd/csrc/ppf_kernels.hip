@@ -875,7 +875,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
 
   Prop o;
   float tg[kNTan];  // gradient mode: the particle's new tangents
-  if (GRAD) {
+  if constexpr (GRAD) {
     float z[5];
     int64_t p;
     o = propagate(m, b, cur, mode, ia, k, z, &p);
@@ -1036,7 +1036,7 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
   const int col0 = cx - h - tx0;
   const double* p0 =
       tile + ((cy - h - ty0) * ts + (col0 & ~1) + ((col0 & 1) ? kCopy + kOffB : 0));
-  if (GRAD) {
+  if constexpr (GRAD) {
     Moments mo{};
     // frame row of the patch's first row; centres far outside are clamped,
     // as for the addresses (every row of such a patch is outside the frame)
@@ -1505,19 +1505,23 @@ __device__ __forceinline__ int slot_bound(double C, double u, double nd, int n) 
 
 // Systematic resampling runs one wavefront per segment of kSegItems
 // particles (kPerThread consecutive per lane, so the 256 particles of a
-// block are two rows of 16 lanes): every scan and maximum of the segment is
+// block are one row of 16 lanes): every scan and maximum of the segment is
 // a DPP operation within the wave and no barrier waits for other waves, so
-// each wave streams its weights and ancestors at its own pace.
+// each wave streams its weights and ancestors at its own pace. Four blocks
+// per wave spread the wave's fixed work (block records, the factor's exp,
+// the scans) over 1024 particles.
 constexpr int kWave = 64;
 constexpr int kPerThread = kSegItems / kWave;  // particles, and slots of a tile, per lane
-static_assert(kPerThread == 8 && kSlotTile == kSegItems && kSegBlocks == 2,
-              "a segment is two blocks, eight particles and slots per lane");
+static_assert(kPerThread == 16 && kSlotTile == kSegItems && kSegBlocks == 4 &&
+                  kBlock == 16 * kPerThread,
+              "a segment is four blocks of one row each, sixteen particles and slots per lane");
 // A tile's slot e lives at word slot_word(e) of the LDS tile, four spare
-// words after every eight, so that each lane reads its slots with two
-// 128-bit loads 48 bytes from its neighbour's (sixteen lanes then cover the
-// 64 banks once).
+// words after every sixteen, so that each lane reads its slots with four
+// 128-bit loads 80 bytes from its neighbour's (sixteen lanes then cover the
+// 64 banks once); the lane-contiguous accesses (slots 4 lane + q of a
+// block) meet at most two lanes on a bank.
 constexpr int kTileWords = kSlotTile / kPerThread * (kPerThread + 4);
-__device__ __forceinline__ int slot_word(int e) { return e + ((e >> 3) << 2); }
+__device__ __forceinline__ int slot_word(int e) { return e + ((e >> 4) << 2); }
 
 // Inclusive maximum scan over the wave of values >= 0 (each DPP step folds
 // into one v_max_i32: row shifts, whose lanes outside the row read 0, then
@@ -1536,14 +1540,14 @@ __device__ __forceinline__ int exclusive_of(int inclusive) {
 }
 
 // Inclusive sum of exact integers held in doubles over the lanes of one
-// block, two rows of 16 lanes (rows 1 and 3 add the last lane of rows 0 and
-// 2). Lanes outside a row read 0, the identity.
+// block, one row of 16 lanes. Lanes whose source is outside the row read 0,
+// the identity.
 __device__ __forceinline__ double block_scan_add(double v) {
   v += shr<1>(v);
   v += shr<2>(v);
   v += shr<4>(v);
   v += shr<8>(v);
-  return pair_rows(v, OpAdd(), 0.0);
+  return v;
 }
 
 // The resampling of one segment by one wave: the segment's slot range from
@@ -1562,11 +1566,19 @@ __device__ __forceinline__ double block_scan_add(double v) {
 // One segment's loads, raw: its lanes' weights and its block records. Every
 // lane loads (indices clamped into the arrays, values masked at use), so no
 // load sits in a divergent branch that would consume it at once.
+// The weights arrive lane-contiguous: x[4 h + q] is particle h kBlock +
+// 4 lane + q of the segment (each load instruction reads one contiguous
+// kWave x 16 bytes); anc_segment hands each lane its own kPerThread
+// consecutive particles through the LDS tile.
+typedef int V4i __attribute__((ext_vector_type(4)));  // for the nontemporal stores
+
 struct SegIn {
   float x[kPerThread];
-  uint64_t pfx;  // the block prefix of block b0 + min(lane, nbs) (clamped)
-  ChunkPre cp;   // its chunk's prefix and factor
-  double mbt;    // the record maximum of block b0 + min(lane, nbs - 1)
+  uint64_t pfx;      // the block prefix of the lane's block b0 + lane / 16 (clamped)
+  ChunkPre cp;       // its chunk's prefix and factor
+  double mbt;        // its record maximum
+  uint64_t pfx_end;  // the block prefix of block b0 + nbs, the first after the segment (clamped)
+  ChunkPre cp_end;   // its chunk's
 };
 
 __device__ __forceinline__ SegIn load_seg(const Model& m, const Buffers& b, const float* E,
@@ -1575,32 +1587,38 @@ __device__ __forceinline__ SegIn load_seg(const Model& m, const Buffers& b, cons
   const int lane = threadIdx.x;
   const int64_t b0 = seg * kSegBlocks;
   const int nbs = (int)min((int64_t)kSegBlocks, b.nb - b0);
-  const int64_t bp = min(b0 + min(lane, nbs), b.nb - 1);
-  // chunk = 256 per with per <= 8 and blk < 2^23: a 32-bit quotient
-  in.cp = b.cpre[(uint32_t)(bp >> 8) / (uint32_t)(b.chunk >> 8)];
-  in.pfx = b.pfx[bp];
-  in.mbt = rec[(b0 + min(lane, nbs - 1)) * kRec];
+  const int64_t bl = min(b0 + (lane >> 4), b.nb - 1);
+  const int64_t be = min(b0 + nbs, b.nb - 1);
+  // chunk = 256 per with per <= 8 and blk < 2^23: 32-bit quotients
+  const uint32_t cb = (uint32_t)(b.chunk >> 8);
+  in.cp = b.cpre[(uint32_t)(bl >> 8) / cb];
+  in.pfx = b.pfx[bl];
+  in.mbt = rec[bl * kRec];
+  in.cp_end = b.cpre[(uint32_t)(be >> 8) / cb];
+  in.pfx_end = b.pfx[be];
   const int64_t ib0 = b0 * kBlock;
   const int64_t ib1 = min(m.n, (b0 + nbs) * kBlock);
-  const int64_t j0 = ib0 + kPerThread * (int64_t)lane;
   if (ib1 - ib0 == kSegItems && (reinterpret_cast<uintptr_t>(E) & 15) == 0) {
     // a whole segment (uniform)
-    const float4* v = reinterpret_cast<const float4*>(E + j0);
+    const float4* v = reinterpret_cast<const float4*>(E + ib0);
 #pragma unroll
-    for (int q4 = 0; q4 < kPerThread / 4; ++q4) {
-      const float4 f = v[q4];
-      in.x[4 * q4] = f.x;
-      in.x[4 * q4 + 1] = f.y;
-      in.x[4 * q4 + 2] = f.z;
-      in.x[4 * q4 + 3] = f.w;
+    for (int h = 0; h < kSegBlocks; ++h) {
+      const float4 f = v[h * (kBlock / 4) + lane];
+      in.x[4 * h] = f.x;
+      in.x[4 * h + 1] = f.y;
+      in.x[4 * h + 2] = f.z;
+      in.x[4 * h + 3] = f.w;
     }
   } else {
     // the ragged end: weight 0 past the last particle
 #pragma unroll
-    for (int q = 0; q < kPerThread; ++q) {
-      const float v = E[min(j0 + q, ib1 - 1)];
-      in.x[q] = (j0 + q < ib1) ? v : (log_src ? -INFINITY : 0.0f);
-    }
+    for (int h = 0; h < kSegBlocks; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t j = ib0 + h * kBlock + 4 * lane + q;
+        const float v = E[min(j, ib1 - 1)];
+        in.x[4 * h + q] = (j < ib1) ? v : (log_src ? -INFINITY : 0.0f);
+      }
   }
   return in;
 }
@@ -1618,25 +1636,24 @@ __device__ __forceinline__ void anc_segment(const Model& m, const Buffers& b, co
   __shared__ __align__(16) int A[kTileWords];
   Ctrl* c = b.ctrl;
   const int lane = threadIdx.x;
+  const int lb = lane >> 4;  // this lane's block within the segment
   const int64_t b0 = seg * kSegBlocks;
   const int nbs = (int)min((int64_t)kSegBlocks, b.nb - b0);
   const int64_t ib0 = b0 * kBlock;
   const int64_t j0 = ib0 + kPerThread * (int64_t)lane;
   const double delta = ci.delta, u = ci.u;
-  // lanes 0..nbs: the CDF at the block starts (blocks past the data read as
-  // its end); lanes 0..nbs-1: the blocks' maximum log weights
-  const double pbt = (lane <= nbs && b0 + lane < b.nb) ? block_cdf(in.cp, in.pfx) : 1.0;
-  const double mbt = lane < nbs ? in.mbt : -INFINITY;
-  float x[kPerThread];
-#pragma unroll
-  for (int q = 0; q < kPerThread; ++q) x[q] = in.x[q];
-  // the blocks' factors from integer weights to the CDF (lanes 0 and 1)
-  const double fbt = (lane < nbs && mbt != -INFINITY) ? exp(mbt - delta) * (1.0 / kItemScale) : 0.0;
-  const double Pb0 = readlane(pbt, 0), Pb1 = readlane(pbt, 1), Pb2 = readlane(pbt, 2);
+  // the CDF at this lane's block start and at the block after the segment
+  // (blocks past the data read as its end), and the block's factor from
+  // integer weights to the CDF
+  const bool in_seg = lb < nbs;
+  const double Pblk = in_seg ? block_cdf(in.cp, in.pfx) : 1.0;
+  const double Pend = b0 + nbs < b.nb ? block_cdf(in.cp_end, in.pfx_end) : 1.0;
+  const double f =
+      (in_seg && in.mbt != -INFINITY) ? exp(in.mbt - delta) * (1.0 / kItemScale) : 0.0;
   const int n = (int)m.n;
   const double nd = (double)m.n;
-  const int fs = seg == 0 ? 0 : slot_bound(Pb0, u, nd, n);
-  const int fe = seg + 1 >= b.nseg ? n : slot_bound(nbs == 2 ? Pb2 : Pb1, u, nd, n);
+  const int fs = seg == 0 ? 0 : slot_bound(readlane(Pblk, 0), u, nd, n);
+  const int fe = seg + 1 >= b.nseg ? n : slot_bound(Pend, u, nd, n);
   if (fe <= fs) return;  // uniform: no slot falls in this segment
   const int T0 = fs & ~3;  // tiles start on 16 bytes of anc
   const int ntiles = (fe - T0 + kSlotTile - 1) / kSlotTile;
@@ -1653,16 +1670,36 @@ __device__ __forceinline__ void anc_segment(const Model& m, const Buffers& b, co
     return;
   }
 
-  const int lb = lane >> 5;  // this lane's block within the segment
-  // (readlane takes a lane index uniform across the wave)
-  const double mblk = LOG ? (lb ? readlane(mbt, 1) : readlane(mbt, 0)) : 0.0;
+  // each lane's kPerThread consecutive particles from the lane-contiguous
+  // loads, through the tile (the tile is free: every earlier call on this
+  // workgroup ended with its slots cleared and a barrier); the words a lane
+  // reads are then cleared by it, so the tile starts cleared
+  float x[kPerThread];
+  {
+    float4* A4 = reinterpret_cast<float4*>(A);
+#pragma unroll
+    for (int h = 0; h < kSegBlocks; ++h)
+      A4[slot_word(h * kBlock + 4 * lane) >> 2] =
+          make_float4(in.x[4 * h], in.x[4 * h + 1], in.x[4 * h + 2], in.x[4 * h + 3]);
+    __syncthreads();
+    float4* mine = A4 + (slot_word(kPerThread * lane) >> 2);
+#pragma unroll
+    for (int r = 0; r < kPerThread / 4; ++r) {
+      const float4 v = mine[r];
+      x[4 * r] = v.x;
+      x[4 * r + 1] = v.y;
+      x[4 * r + 2] = v.z;
+      x[4 * r + 3] = v.w;
+      mine[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  }
   double kl[kPerThread];
   double tsum = 0.0;
 #pragma unroll
   for (int q = 0; q < kPerThread; ++q) {
     double wi;
-    if (LOG)
-      wi = item_weight(x[q] == -INFINITY ? 0.0 : exp((double)x[q] - mblk));
+    if (LOG)  // particles past the data hold -inf
+      wi = item_weight(x[q] == -INFINITY ? 0.0 : exp((double)x[q] - in.mbt));
     else
       wi = item_weight((double)x[q]);
     tsum += wi;
@@ -1671,9 +1708,6 @@ __device__ __forceinline__ void anc_segment(const Model& m, const Buffers& b, co
   // prefix of the block's integer weights before this lane's particles
   // (exact: integers < 2^53)
   const double texcl = block_scan_add(tsum) - tsum;
-  const double fb0 = readlane(fbt, 0), fb1 = readlane(fbt, 1);
-  const double f = lb ? fb1 : fb0;
-  const double Pblk = lb ? Pb1 : Pb0;
   // each particle's slot bound at its CDF value C = Pblk + (texcl + kl) f,
   // ceil(C n - u) clamped to [fs, fe], evaluated as one fma per particle:
   // kl (n f) + (texcl (n f) + Pblk n - u). Rounding may move a bound by one
@@ -1730,13 +1764,8 @@ __device__ __forceinline__ void anc_segment(const Model& m, const Buffers& b, co
       if (mw[q] >= 0 && mw[q] < lim) carry = p0 + q;  // the largest such (mw increases with q)
     carry = readlane(wave_reduce_last(carry, OpMax(), 0), 63);
   }
-  // the tile starts cleared; each tile's reads clear it again
-  {
-    uint4* A4 = reinterpret_cast<uint4*>(A);
-#pragma unroll
-    for (int r = 0; r < kTileWords / 4 / kWave; ++r)
-      A4[r * kWave + lane] = make_uint4(0u, 0u, 0u, 0u);
-  }
+  uint4* A4 = reinterpret_cast<uint4*>(A);
+  uint4* mine = A4 + (slot_word(kPerThread * lane) >> 2);
   for (int j = jt0; j < jt1; ++j) {
     const int c0 = T0 + j * kSlotTile, wbase = j * kTileWords;
     __syncthreads();  // one wave: orders the LDS accesses of the lanes
@@ -1749,9 +1778,8 @@ __device__ __forceinline__ void anc_segment(const Model& m, const Buffers& b, co
     // this lane's slots, their running maximum (particles increase with
     // slots), then the maximum over the lanes before it; 0 (the cleared
     // tile, and DPP's fill) is below every mark that precedes a slot from fs
-    // on. Reading a slot clears it for the next tile.
+    // on.
     int v[kPerThread];
-    uint4* mine = reinterpret_cast<uint4*>(A + (kPerThread + 4) * lane);
 #pragma unroll
     for (int r = 0; r < kPerThread / 4; ++r) {
       const uint4 a = mine[r];
@@ -1761,25 +1789,34 @@ __device__ __forceinline__ void anc_segment(const Model& m, const Buffers& b, co
       v[4 * r + 3] = (int)a.w;
     }
 #pragma unroll
-    for (int r = 0; r < kPerThread / 4; ++r) mine[r] = make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
     for (int q = 1; q < kPerThread; ++q) v[q] = max(v[q], v[q - 1]);
     const int winc = wave_max_scan(v[kPerThread - 1]);
     const int before = max(carry, exclusive_of(winc));
     carry = max(carry, readlane(winc, 63));
+    // the slots' particles back into the tile, then out lane-contiguous
+    // (slots 4 lane + q of each block-sized quarter of the tile), streamed
+    // past the caches; a lane clears the words it reads for the next tile
 #pragma unroll
-    for (int q = 0; q < kPerThread; ++q) v[q] = max(before, v[q]);
-    const int s0 = c0 + kPerThread * lane;
-    int32_t* out = anc + s0;
-    if (vec && s0 >= fs && s0 + kPerThread <= fe) {
-      int4* o4 = reinterpret_cast<int4*>(out);
+    for (int r = 0; r < kPerThread / 4; ++r)
+      mine[r] = make_uint4((uint32_t)max(before, v[4 * r]), (uint32_t)max(before, v[4 * r + 1]),
+                           (uint32_t)max(before, v[4 * r + 2]), (uint32_t)max(before, v[4 * r + 3]));
+    __syncthreads();
 #pragma unroll
-      for (int r = 0; r < kPerThread / 4; ++r)
-        o4[r] = make_int4(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
-    } else {
+    for (int h = 0; h < kSegBlocks; ++h) {
+      uint4* src = A4 + (slot_word(h * kBlock + 4 * lane) >> 2);
+      const uint4 a = *src;
+      *src = make_uint4(0u, 0u, 0u, 0u);
+      const int s0 = c0 + h * kBlock + 4 * lane;
+      int32_t* out = anc + s0;
+      if (vec && s0 >= fs && s0 + 4 <= fe) {
+        __builtin_nontemporal_store(V4i{(int)a.x, (int)a.y, (int)a.z, (int)a.w},
+                                    reinterpret_cast<V4i*>(out));
+      } else {
+        const int w4[4] = {(int)a.x, (int)a.y, (int)a.z, (int)a.w};
 #pragma unroll
-      for (int q = 0; q < kPerThread; ++q)
-        if (s0 + q >= fs && s0 + q < fe) out[q] = v[q];
+        for (int q = 0; q < 4; ++q)
+          if (s0 + q >= fs && s0 + q < fe) out[q] = w4[q];
+      }
     }
   }
 }

@@ -205,11 +205,11 @@ def test_batch_heavy_fill_across_tracks(ppf, movie):
         for f in singles:
             f.step(ft[k])
         assert_same_as_single(b, singles)
-        # tracks with a 512-particle segment of more than 4 x 512 slots (queued)
+        # tracks with a 1024-particle segment of more than 4 x 1024 slots (queued)
         heavy = 0
         for t, (n, _) in enumerate(spec):
             _, _, anc = b.particles(t)
-            if b.stats()[t]["resampled"] and np.bincount(anc // 512).max() > 2048:
+            if b.stats()[t]["resampled"] and np.bincount(anc // 1024).max() > 4096:
                 heavy += 1
         heavy_steps += heavy >= 2
     assert heavy_steps >= 1, "no step queued chunks in two tracks"

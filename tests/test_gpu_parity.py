@@ -224,7 +224,7 @@ def test_systematic_standalone_vs_oracle(ppf, n, kind):
     elif kind == "onehot":
         l = np.full(n, -np.inf)
         l[n // 3] = 0.0
-    elif kind == "one_tile":  # nearly all weight in one 2048-particle tile: the heavy pass
+    elif kind == "one_tile":  # nearly all weight on 1000 particles of two segments: the heavy pass
         l = rng.normal(-60, 1, n)
         l[500_000:501_000] = rng.normal(0, 1, 1000)
     else:
