@@ -9,7 +9,7 @@
 //   k_merge_final  fixed-order merge of the chunks: the normaliser, ESS, MMSE
 //                  estimate, resampling decision and uniform; commits or rolls
 //                  back the step; the fixed-point CDF prefixes of the chunks
-//   k_anc          systematic resampling: one wave per segment of 512
+//   k_anc          systematic resampling: one wave per segment of 1024
 //                  particles, each particle's run of output slots from the
 //                  segment's CDF
 //   k_fill         the slots of heavy segments queued by k_anc (concentrated
