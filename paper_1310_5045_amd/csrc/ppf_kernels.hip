@@ -570,15 +570,19 @@ __device__ __forceinline__ Prop propagate(const Model& m, const Buffers& b, int 
   return o;
 }
 
+// The new states stream past the caches (non-temporal stores): the next
+// step gathers them through the ancestors long after, and left in the
+// caches as dirty lines their write-back would compete with the weight
+// stream of the resampling pass that follows.
 __device__ __forceinline__ void store_state(const Model& m, const Buffers& b, int cur, int64_t i,
                                             const Prop& o) {
   float* Xout = cur ? b.X0 : b.X1;
   const int64_t n = m.n;
-  Xout[i] = o.x;
-  Xout[n + i] = o.y;
-  Xout[2 * n + i] = o.vx;
-  Xout[3 * n + i] = o.vy;
-  Xout[4 * n + i] = o.I;
+  __builtin_nontemporal_store(o.x, Xout + i);
+  __builtin_nontemporal_store(o.y, Xout + n + i);
+  __builtin_nontemporal_store(o.vx, Xout + 2 * n + i);
+  __builtin_nontemporal_store(o.vy, Xout + 3 * n + i);
+  __builtin_nontemporal_store(o.I, Xout + 4 * n + i);
 }
 
 // Fixed-point weight of a particle whose weight relative to its block
@@ -893,9 +897,9 @@ __device__ __forceinline__ void step_spot(const Model& m, const Buffers& b,
     tg[4] = (float)((double)tp[4] + (double)z[3]);
     tg[5] = (float)((double)tp[5] + (double)tp[4]);
     tg[6] = (float)((double)tp[6] + (double)z[4]);
-    if (active)
+    if (active)  // streamed like the states
 #pragma unroll
-      for (int d = 0; d < kNTan; ++d) Tout[(int64_t)d * m.n + i] = tg[d];
+      for (int d = 0; d < kNTan; ++d) __builtin_nontemporal_store(tg[d], Tout + (int64_t)d * m.n + i);
   } else {
     o = propagate(m, b, cur, mode, ia, k);
   }

@@ -241,6 +241,41 @@ def test_systematic_standalone_vs_oracle(ppf, n, kind):
         assert o.sum() == n and np.all(o[w == 0] == 0)
 
 
+@pytest.mark.parametrize("slots", [2048, 3900, 4100, 6200, 9000])
+def test_systematic_heavy_segments_around_the_queue_limit(ppf, slots):
+    """Segments of 1024 particles whose slots span just under, at and over the
+    four tiles one wave writes itself (more go to the queued fill in chunks of
+    two tiles: odd and even chunk counts), two such segments side by side, and
+    a heavy ragged last segment; ancestors against the oracle (band rule)."""
+    S = 1024
+    n = 64 * S + 517
+    rng = np.random.default_rng(slots)
+    heavy = [5, 6, n // S]  # two neighbours and the ragged last segment
+    l = rng.normal(0.0, 1.0, n)
+    w_rest = np.exp(l).sum()
+    for s in heavy:
+        lo, hi = s * S, min(n, (s + 1) * S)
+        # this segment's weight for about `slots` of the n slots
+        a = slots / n * w_rest / (1.0 - len(heavy) * slots / n) / (hi - lo)
+        l[lo:hi] = np.log(a) + rng.normal(0.0, 0.3, hi - lo) - 0.045
+    l32 = l.astype(np.float32)
+    spans = set()
+    for u in (0.0, 0.37, 0.999):
+        anc = ppf.resample_systematic(torch.from_numpy(l32).cuda(), u).cpu().numpy()
+        w = np.exp(l32.astype(np.float64) - l32.max())
+        w /= w.sum()
+        nm, nm10 = check_systematic(w, u, anc)
+        assert nm10 == 0
+        assert np.bincount(anc, minlength=n).sum() == n
+        # tiles each heavy segment's slots span (tiles start on 4 slots)
+        for s in heavy:
+            idx = np.nonzero((anc >= s * S) & (anc < (s + 1) * S))[0]
+            fs, fe = int(idx.min()), int(idx.max()) + 1
+            spans.add(-(-(fe - (fs & ~3)) // S))
+    # the case exercises the wave's own limit (3900: four tiles) or the queue
+    assert (max(spans) <= 4) == (slots < 4000), spans
+
+
 def test_rna_standalone_vs_oracle(ppf):
     rng = np.random.default_rng(7)
     for n, group, moved in ((4096, 256, 25), (1024, 4, 1), (8192, 1024, 512), (512, 512, 0)):
