@@ -1677,107 +1677,142 @@ __device__ __forceinline__ void anc_segment(const Model& m, const Buffers& b, co
   // each lane's kPerThread consecutive particles from the lane-contiguous
   // loads, through the tile (the tile is free: every earlier call on this
   // workgroup ended with its slots cleared and a barrier); the words a lane
-  // reads are then cleared by it, so the tile starts cleared
-  float x[kPerThread];
-  {
-    float4* A4 = reinterpret_cast<float4*>(A);
+  // reads stay until it clears them before the first tile
+  float4* const Af = reinterpret_cast<float4*>(A);
+  float4* const minef = Af + (slot_word(kPerThread * lane) >> 2);
 #pragma unroll
-    for (int h = 0; h < kSegBlocks; ++h)
-      A4[slot_word(h * kBlock + 4 * lane) >> 2] =
-          make_float4(in.x[4 * h], in.x[4 * h + 1], in.x[4 * h + 2], in.x[4 * h + 3]);
-    __syncthreads();
-    float4* mine = A4 + (slot_word(kPerThread * lane) >> 2);
-#pragma unroll
-    for (int r = 0; r < kPerThread / 4; ++r) {
-      const float4 v = mine[r];
-      x[4 * r] = v.x;
-      x[4 * r + 1] = v.y;
-      x[4 * r + 2] = v.z;
-      x[4 * r + 3] = v.w;
-      mine[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
-  }
+  for (int h = 0; h < kSegBlocks; ++h)
+    Af[slot_word(h * kBlock + 4 * lane) >> 2] =
+        make_float4(in.x[4 * h], in.x[4 * h + 1], in.x[4 * h + 2], in.x[4 * h + 3]);
+  __syncthreads();
+  // a particle's fixed-point weight
+  auto weight = [&](float xq) {
+    if (LOG)  // particles past the data hold -inf
+      return item_weight(xq == -INFINITY ? 0.0 : exp((double)xq - in.mbt));
+    return item_weight((double)xq);
+  };
   double kl[kPerThread];
   double tsum = 0.0;
 #pragma unroll
-  for (int q = 0; q < kPerThread; ++q) {
-    double wi;
-    if (LOG)  // particles past the data hold -inf
-      wi = item_weight(x[q] == -INFINITY ? 0.0 : exp((double)x[q] - in.mbt));
-    else
-      wi = item_weight((double)x[q]);
-    tsum += wi;
-    kl[q] = tsum;
+  for (int r = 0; r < kPerThread / 4; ++r) {
+    const float4 v = minef[r];
+    const float xr[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) {
+      tsum += weight(xr[c4]);
+      kl[4 * r + c4] = tsum;
+    }
   }
   // prefix of the block's integer weights before this lane's particles
   // (exact: integers < 2^53)
   const double texcl = block_scan_add(tsum) - tsum;
-  // each particle's slot bound at its CDF value C = Pblk + (texcl + kl) f,
-  // ceil(C n - u) clamped to [fs, fe], evaluated as one fma per particle:
-  // kl (n f) + (texcl (n f) + Pblk n - u). Rounding may move a bound by one
-  // where C n - u is within a few ulps of an integer; the running maximum
-  // below keeps the runs disjoint and ordered regardless. A particle of zero
-  // weight gets 0, below every bound, so its run is empty (computing its
-  // bound would repeat its predecessor's, except across lanes, where the two
-  // fmas round apart).
+  // each particle's slot bound at its CDF value C = Pblk + K f, with K the
+  // block's integer weights up to and including the particle (exact):
+  // ceil(C n - u) = ceil(K (n f) + (Pblk n - u)), one fma, at most fe.
+  // Rounding may move a bound by one where C n - u is within a few ulps of
+  // an integer; the running maximum below keeps the runs disjoint and
+  // ordered regardless. Bounds are non-decreasing in K and equal K give
+  // equal bounds in every lane of the block, so a particle of zero weight
+  // after a positive one repeats its predecessor's bound and gets an empty
+  // run. A block's leading particles of zero weight (K = 0) get 0, below
+  // every bound: the previous block's CDF is computed apart and may round
+  // lower than this block's start.
   const double fn = f * nd;
-  const double g = fma(texcl, fn, fma(Pblk, nd, -u));
+  const double gb = fma(Pblk, nd, -u);
+  const int p0 = (int)j0;  // particle indices are below n < 2^31
   int rb[kPerThread];
-  int lp = -1;  // this lane's last particle of positive weight
 #pragma unroll
   for (int q = 0; q < kPerThread; ++q) {
+    const double K = texcl + kl[q];
     // |C n - u| stays far inside the int range (C in [0, 1], n < 2^31)
-    const int bq = (int)ceil(fma(kl[q], fn, g));
-    const bool pos = kl[q] > (q ? kl[q - 1] : 0.0);
-    rb[q] = pos ? min(max(bq, fs), fe) : 0;
-    lp = pos ? q : lp;
+    rb[q] = K > 0.0 ? min((int)ceil(fma(K, fn, gb)), fe) : 0;
   }
-  int tmax = 0;
-#pragma unroll
-  for (int q = 0; q < kPerThread; ++q) tmax = max(tmax, rb[q]);
-  const int h0 = max(fs, exclusive_of(wave_max_scan(tmax)));
-  // the segment's last particle of positive weight ends its runs at fe
+  // the largest bound before the lane (bounds are non-decreasing in a lane)
+  const int h0 = max(fs, exclusive_of(wave_max_scan(rb[kPerThread - 1])));
+  // The segment's last particle of positive weight ends its runs at fe
   // (those after it have zero weight and empty runs), so every slot has an
-  // owner whatever the rounding of the last bounds
-  const int last_pos =
-      readlane(wave_reduce_last(lp >= 0 ? kPerThread * lane + lp : -1, OpMax(), -1), 63);
-  const int lastq = last_pos - kPerThread * lane;
+  // owner whatever the rounding of the last bounds. Slots after its run's
+  // end already take its mark; only if its own run came out empty (its
+  // bound rounded to its predecessor's, below fe) does it need a mark, at
+  // the start of its extended run: xmb / xmp, uniform, from a replay of that
+  // lane's runs (rare: that lane's last bound then fell short of fe).
+  int xmb = -1, xmp = 0;
+  {
+    const uint64_t pos_lanes = __builtin_amdgcn_ballot_w64(tsum > 0.0);
+    const int L = 63 - __builtin_clzll(pos_lanes | 1ull);
+    if (pos_lanes != 0 && readlane(rb[kPerThread - 1], L) < fe) {
+      const double tl = readlane(texcl, L), fnl = readlane(fn, L), gbl = readlane(gb, L);
+      const double mL = LOG ? readlane(in.mbt, L) : 0.0;  // lane L's block maximum
+      const float* xl = reinterpret_cast<const float*>(A) + slot_word(kPerThread * L);
+      int pv = readlane(h0, L), lastq = -1, pstart = 0;
+      bool empty = false;
+      double kk = 0.0;
+#pragma nounroll
+      for (int q = 0; q < kPerThread; ++q) {
+        const float xq = xl[q];
+        const double wq = LOG ? item_weight(xq == -INFINITY ? 0.0 : exp((double)xq - mL))
+                              : item_weight((double)xq);
+        kk += wq;
+        const double K = tl + kk;
+        const int rbq = K > 0.0 ? min((int)ceil(fma(K, fnl, gbl)), fe) : 0;
+        const int e = max(pv, rbq);
+        if (wq > 0.0) {
+          lastq = q;
+          pstart = pv;
+          empty = !(e > pv);
+        }
+        pv = e;
+      }
+      if (lastq >= 0 && empty && pstart < fe) {
+        const int r = pstart - T0;
+        xmb = 4 * r + (r & ~15);
+        xmp = p0 - kPerThread * lane + kPerThread * L + lastq;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kPerThread / 4; ++r) minef[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   // particle kPerThread lane + q owns [e_{q-1}, e_q), e_q = max(e_{q-1},
-  // rb[q]) (fe for the last particle of positive weight), e_{-1} = h0. Each
-  // non-empty run marks its first slot with the particle; a slot's particle
-  // is then the largest mark at or before it. mw: the LDS word of the mark
-  // in tile coordinates from T0 (tile j: subtract j kTileWords), or -1.
-  int mw[kPerThread];
+  // rb[q]), e_{-1} = h0. Each non-empty run marks its first slot with the
+  // particle; a slot's particle is then the largest mark at or before it.
+  // mb: the LDS byte offset of the mark in tile coordinates from T0 (tile j:
+  // subtract j kTileWords 4), 4 slot_word(e) = 4 e + (e & ~15), or -1.
+  int mb[kPerThread];
   int prev = h0;
 #pragma unroll
   for (int q = 0; q < kPerThread; ++q) {
-    const int e = q == lastq ? fe : max(prev, rb[q]);
-    mw[q] = e > prev ? slot_word(prev - T0) : -1;
+    const int e = max(prev, rb[q]);
+    const int r = prev - T0;
+    mb[q] = e > prev ? 4 * r + (r & ~15) : -1;
     prev = e;
   }
+  static_assert(kPerThread == 16, "4 slot_word(e) = 4 e + (e & ~15) for four spare words per sixteen");
   int32_t* anc = m.rpa ? b.asys : b.anc;  // RPA routes the systematic result afterwards
   const bool vec = (reinterpret_cast<uintptr_t>(anc) & 15) == 0;
-  const int p0 = (int)j0;  // particle indices are below n < 2^31
   const int jt0 = queued ? tile_lo : 0, jt1 = queued ? min(tile_hi, ntiles) : ntiles;
   // the tiles before this call's first: the largest mark among them
   int carry = 0;
   if (jt0 > 0) {
-    const int lim = jt0 * kTileWords;  // marks at earlier words precede the first tile
+    const int lim = jt0 * kTileWords * 4;  // marks at earlier bytes precede the first tile
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q)
-      if (mw[q] >= 0 && mw[q] < lim) carry = p0 + q;  // the largest such (mw increases with q)
+      if (mb[q] >= 0 && mb[q] < lim) carry = p0 + q;  // the largest such (mb increases with q)
     carry = readlane(wave_reduce_last(carry, OpMax(), 0), 63);
+    if (xmb >= 0 && xmb < lim) carry = xmp;  // the segment's last particle of positive weight
   }
   uint4* A4 = reinterpret_cast<uint4*>(A);
   uint4* mine = A4 + (slot_word(kPerThread * lane) >> 2);
+  char* const Ab = reinterpret_cast<char*>(A);
   for (int j = jt0; j < jt1; ++j) {
-    const int c0 = T0 + j * kSlotTile, wbase = j * kTileWords;
+    const int c0 = T0 + j * kSlotTile, wbase = j * kTileWords * 4;
     __syncthreads();  // one wave: orders the LDS accesses of the lanes
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q) {
-      const int ew = mw[q] - wbase;
-      if ((unsigned)ew < (unsigned)kTileWords) A[ew] = p0 + q;
+      const int eb = mb[q] - wbase;
+      if ((unsigned)eb < (unsigned)(kTileWords * 4)) *reinterpret_cast<int*>(Ab + eb) = p0 + q;
     }
+    if (lane == 0 && (unsigned)(xmb - wbase) < (unsigned)(kTileWords * 4))
+      *reinterpret_cast<int*>(Ab + (xmb - wbase)) = xmp;
     __syncthreads();
     // this lane's slots, their running maximum (particles increase with
     // slots), then the maximum over the lanes before it; 0 (the cleared
