@@ -845,16 +845,17 @@ def run(args):
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    graph = args.launch == "graph"
     plain = None
     if w.get("grad"):
-        # the same configuration without derivatives, for the ratio
+        # the same configuration without derivatives, launched the same way,
+        # for the ratio
         pf = ppf.Filter(make_params(ppf, w, init_kind))
-        pms, _, pkt, _, _ = timed_steps(torch, pf, frames, K, Wm, T, False, args.shape)
+        pms, _, pkt, _, _ = timed_steps(torch, pf, frames, K, Wm, T, graph, args.shape)
         pf.close()
         plain = {"value": w["n"] * K / (pms / 1e3), "ms_per_step": pms / K,
                  "k_step_ms": pkt.get("k_step", (1, 0.0))[1] / K}
     f = ppf.Filter(make_params(ppf, w, init_kind, grad=w.get("grad", 0)))
-    graph = args.launch == "graph"
     scheme = w.get("scheme", (0,))[0]
     gpu_ms, wall, kt, tuned, ran = timed_steps(torch, f, frames, K, Wm, T, graph, args.shape)
     err, st = check_state(ppf, f, w, mv, (K - 1) % T, scheme)
