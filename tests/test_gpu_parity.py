@@ -214,7 +214,8 @@ def test_systematic_standalone_brute_force(ppf):
 
 
 @pytest.mark.parametrize("n,kind", [(1, "flat"), (2047, "flat"), (2049, "exp"), (100_000, "exp"),
-                                    (1 << 20, "onehot"), (1 << 20, "one_tile"), (300_001, "zeros")])
+                                    (1 << 20, "onehot"), (1 << 20, "one_tile"), (300_001, "zeros"),
+                                    ((1 << 24) + 77, "onehot")])
 def test_systematic_standalone_vs_oracle(ppf, n, kind):
     rng = np.random.default_rng(n)
     if kind == "flat":
